@@ -1,0 +1,470 @@
+"""Seeded synthetic inputs for the node-patch Poisson-Boltzmann solver.
+
+This module only *makes inputs*: closed triangulated surfaces, atom positions,
+charges and radii, and the physical parameters of each workload.  It holds none
+of the solver's arithmetic (no kernels, no patch geometry, no quadrature), so
+that both the FP64 CPU oracle and the GPU path can read the same inputs while
+sharing no code.
+
+Workloads (stand-ins for the paper's molecules; the paper's PQR files and
+TMSmesh meshes are not available):
+
+* ``born_ion``      -- one +1 e charge at the centre of an icosphere of radius
+                       2 A (level 4: 2,562 nodes / 5,120 triangles); the
+                       paper's analytic sphere test (Section 5) at small size.
+* ``globular``      -- 5,000 atoms by a seeded self-avoiding walk inside
+                       25 A, Gaussian-density isosurface meshed by marching
+                       tetrahedra on a 1.25 A grid (~100k triangles).
+* ``star_request``  -- the serving stream's star-shaped molecules
+                       r(x) = R max(0.3, 1 + sum a_lm Y_lm(x)).
+* ``complex_100k``  -- 100,000 atoms inside 90 A, same generator.
+
+Every generator uses ``numpy.random.Generator(PCG64(seed))`` with a fixed
+draw order.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Molecule", "icosphere", "born_ion", "saw_atoms", "gaussian_surface",
+    "globular", "complex_100k", "star_request", "check_closed_manifold",
+    "random_rigid_motion",
+]
+
+
+@dataclass
+class Molecule:
+    """One solve request: surface mesh + atoms + physical parameters."""
+    name: str
+    xyz: np.ndarray          # float64 [N,3] mesh nodes (A)
+    tri: np.ndarray          # int32  [M,3] triangles, CCW seen from the solvent
+    atom_xyz: np.ndarray     # float64 [K,3] (A)
+    charge: np.ndarray       # float64 [K]   (e)
+    radius: np.ndarray       # float64 [K]   (A), used only to make the surface
+    eps_p: float = 2.0
+    eps_s: float = 80.0
+    kappa: float = 0.1       # 1/A
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_unknowns(self) -> int:
+        return 2 * self.n_nodes
+
+
+# ---------------------------------------------------------------------------
+# Icosphere
+# ---------------------------------------------------------------------------
+
+def _icosahedron():
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    v = []
+    for a, b in itertools.product((-1.0, 1.0), repeat=2):
+        v.append((0.0, a, b * phi))
+        v.append((a, b * phi, 0.0))
+        v.append((b * phi, 0.0, a))
+    v = np.array(v, dtype=np.float64)
+    # Faces: all triples of mutually nearest vertices (edge length 2).
+    n = len(v)
+    d2 = ((v[:, None, :] - v[None, :, :]) ** 2).sum(-1)
+    adj = np.abs(d2 - 4.0) < 1e-9
+    faces = []
+    for i in range(n):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            for k in range(j + 1, n):
+                if adj[i, k] and adj[j, k]:
+                    f = [i, j, k]
+                    c = v[f].mean(0)
+                    nrm = np.cross(v[j] - v[i], v[k] - v[i])
+                    if nrm @ c < 0:
+                        f = [i, k, j]
+                    faces.append(f)
+    assert len(faces) == 20
+    return v, np.array(faces, dtype=np.int64)
+
+
+def icosphere(level: int, radius: float = 1.0):
+    """Icosahedron subdivided ``level`` times by edge midpoints, projected
+    onto the sphere of the given radius.  V = 10*4^L + 2, T = 20*4^L."""
+    v, f = _icosahedron()
+    verts = [tuple(p) for p in v]
+    for _ in range(level):
+        cache = {}
+        newf = []
+
+        def mid(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in cache:
+                pa, pb = verts[a], verts[b]
+                verts.append(((pa[0] + pb[0]) / 2, (pa[1] + pb[1]) / 2,
+                              (pa[2] + pb[2]) / 2))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        for a, b, c in f:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            newf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        f = np.array(newf, dtype=np.int64)
+    vv = np.array(verts, dtype=np.float64)
+    vv /= np.linalg.norm(vv, axis=1, keepdims=True)
+    return vv * radius, f.astype(np.int32)
+
+
+def born_ion(level: int = 4, radius: float = 2.0, charge: float = 1.0,
+             eps_p: float = 2.0, eps_s: float = 80.0, kappa: float = 0.1):
+    """Config 'Born ion': one charge at the centre of an icosphere."""
+    xyz, tri = icosphere(level, radius)
+    return Molecule(
+        name=f"born_ion_L{level}", xyz=xyz, tri=tri,
+        atom_xyz=np.zeros((1, 3)), charge=np.array([charge]),
+        radius=np.array([radius]), eps_p=eps_p, eps_s=eps_s, kappa=kappa,
+        meta={"level": level, "sphere_radius": radius})
+
+
+# ---------------------------------------------------------------------------
+# Self-avoiding walk atoms
+# ---------------------------------------------------------------------------
+
+def _unit_vectors(rng, n):
+    g = rng.standard_normal((n, 3))
+    return g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def saw_atoms(n: int, r_max: float, seed: int, step: float = 1.5,
+              min_sep: float = 1.2, max_reject: int = 64):
+    """Atoms by a seeded self-avoiding random walk inside a ball.
+
+    Each step proposes x_{i-1} + step*u (u uniform on the sphere) and accepts
+    it if |x| <= r_max and every other atom is at least ``min_sep`` away
+    (grid hash).  After ``max_reject`` rejections the walk restarts from a
+    uniformly chosen earlier atom.  Radii ~ U(1.2, 2.0); charges ~ N(0, 0.4)
+    shifted to net charge 0.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cell = min_sep
+    grid: dict[tuple, list] = {}
+    pos = np.zeros((n, 3))
+
+    def key(p):
+        return (int(math.floor(p[0] / cell)), int(math.floor(p[1] / cell)),
+                int(math.floor(p[2] / cell)))
+
+    def ok(p):
+        if p @ p > r_max * r_max:
+            return False
+        k = key(p)
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    for j in grid.get((k[0] + dx, k[1] + dy, k[2] + dz), ()):
+                        d = pos[j] - p
+                        if d @ d < min_sep * min_sep:
+                            return False
+        return True
+
+    grid.setdefault(key(pos[0]), []).append(0)
+    cur = 0
+    count = 1
+    rejects = 0
+    while count < n:
+        u = _unit_vectors(rng, 1)[0]
+        p = pos[cur] + step * u
+        if ok(p):
+            pos[count] = p
+            grid.setdefault(key(p), []).append(count)
+            cur = count
+            count += 1
+            rejects = 0
+        else:
+            rejects += 1
+            if rejects >= max_reject:
+                cur = int(rng.integers(0, count))
+                rejects = 0
+    radius = rng.uniform(1.2, 2.0, n)
+    q = rng.normal(0.0, 0.4, n)
+    q -= q.mean()
+    return pos, radius, q
+
+
+# ---------------------------------------------------------------------------
+# Gaussian-density isosurface by marching tetrahedra
+# ---------------------------------------------------------------------------
+
+# Freudenthal (Kuhn) split of the unit cube into 6 tetrahedra sharing the
+# main diagonal (0,0,0)-(1,1,1).  Adjacent cubes split their shared face along
+# the same diagonal, so the tetrahedra form one conforming complex and the
+# zero set of the piecewise-linear interpolant is a closed surface.
+def _kuhn_tets():
+    tets = []
+    for perm in itertools.permutations(range(3)):
+        c = [0, 0, 0]
+        t = [tuple(c)]
+        for ax in perm:
+            c[ax] = 1
+            t.append(tuple(c))
+        tets.append(t)
+    return np.array(tets, dtype=np.int64)  # [6,4,3]
+
+
+def _density(atoms, radii, lo, h, shape, beta, trunc=3.0):
+    """rho(x) = sum_k exp(-beta (|x-r_k|^2 / R_k^2 - 1)), truncated at 3 R_k."""
+    rho = np.zeros(shape, dtype=np.float64)
+    gx = lo[0] + h * np.arange(shape[0])
+    gy = lo[1] + h * np.arange(shape[1])
+    gz = lo[2] + h * np.arange(shape[2])
+    for (ax, ay, az), r in zip(atoms, radii):
+        rc = trunc * r
+        i0 = max(0, int(math.floor((ax - rc - lo[0]) / h)))
+        i1 = min(shape[0], int(math.ceil((ax + rc - lo[0]) / h)) + 1)
+        j0 = max(0, int(math.floor((ay - rc - lo[1]) / h)))
+        j1 = min(shape[1], int(math.ceil((ay + rc - lo[1]) / h)) + 1)
+        k0 = max(0, int(math.floor((az - rc - lo[2]) / h)))
+        k1 = min(shape[2], int(math.ceil((az + rc - lo[2]) / h)) + 1)
+        dx2 = (gx[i0:i1] - ax) ** 2
+        dy2 = (gy[j0:j1] - ay) ** 2
+        dz2 = (gz[k0:k1] - az) ** 2
+        d2 = dx2[:, None, None] + dy2[None, :, None] + dz2[None, None, :]
+        inv = 1.0 / (r * r)
+        val = np.exp(-beta * (d2 * inv - 1.0))
+        val[d2 > rc * rc] = 0.0
+        rho[i0:i1, j0:j1, k0:k1] += val
+    return rho
+
+
+def gaussian_surface(atoms, radii, h_grid: float, beta: float = 2.0,
+                     pad: float = 5.0, level: float = 1.0):
+    """Closed, outward-oriented triangulation of {rho = level}.
+
+    Marching tetrahedra over the Freudenthal split of the grid cubes; mesh
+    vertices sit on grid edges (welded by edge id) with the interpolation
+    parameter clamped to [0.01, 0.99], so no vertex lands on a grid point.
+    Triangles are oriented toward decreasing density (out of the molecule).
+    """
+    atoms = np.asarray(atoms, dtype=np.float64)
+    lo = atoms.min(0) - pad
+    hi = atoms.max(0) + pad
+    shape = tuple(int(math.ceil((hi[a] - lo[a]) / h_grid)) + 1 for a in range(3))
+    rho = _density(atoms, radii, lo, h_grid, shape, beta)
+    F = rho - level
+    F[F == 0.0] = 1e-300          # no grid value exactly on the level set
+    inside = F > 0.0
+    nx, ny, nz = shape
+    # cubes with mixed signs
+    c000 = inside[:-1, :-1, :-1]
+    anyin = np.zeros((nx - 1, ny - 1, nz - 1), bool)
+    allin = np.ones((nx - 1, ny - 1, nz - 1), bool)
+    for dx, dy, dz in itertools.product((0, 1), repeat=3):
+        s = inside[dx:nx - 1 + dx, dy:ny - 1 + dy, dz:nz - 1 + dz]
+        anyin |= s
+        allin &= s
+    del c000
+    ci, cj, ck = np.nonzero(anyin & ~allin)
+    tets = _kuhn_tets()                                        # [6,4,3]
+    # grid point ids of all tet corners: [ncube,6,4]
+    base = np.stack([ci, cj, ck], axis=1)                      # [nc,3]
+    corners = base[:, None, None, :] + tets[None, :, :, :]     # [nc,6,4,3]
+    corners = corners.reshape(-1, 4, 3)
+    gid = (corners[..., 0] * ny + corners[..., 1]) * nz + corners[..., 2]  # [nt,4]
+    Ff = F.reshape(-1)
+    val = Ff[gid]                                              # [nt,4]
+    ins = val > 0
+    nin = ins.sum(1)
+    keep = (nin > 0) & (nin < 4)
+    gid, val, ins, nin = gid[keep], val[keep], ins[keep], nin[keep]
+
+    edge_key_to_vid: dict[int, int] = {}
+    vert_list: list = []
+    npts = nx * ny * nz
+
+    def vid(a, b, fa, fb):
+        # a inside, b outside
+        lo_, hi_ = (a, b) if a < b else (b, a)
+        k = lo_ * npts + hi_
+        v = edge_key_to_vid.get(k)
+        if v is None:
+            t = fa / (fa - fb)
+            t = min(0.99, max(0.01, t))
+            pa = np.array(np.unravel_index(a, shape), dtype=np.float64)
+            pb = np.array(np.unravel_index(b, shape), dtype=np.float64)
+            p = lo + h_grid * (pa + t * (pb - pa))
+            v = len(vert_list)
+            vert_list.append(p)
+            edge_key_to_vid[k] = v
+        return v
+
+    tris = []
+    for g, f, s in zip(gid.tolist(), val.tolist(), ins.tolist()):
+        I = [i for i in range(4) if s[i]]
+        O = [i for i in range(4) if not s[i]]
+        if len(I) == 1 or len(O) == 1:
+            if len(I) == 1:
+                a = I[0]
+                vs = [vid(g[a], g[o], f[a], f[o]) for o in O]
+            else:
+                o = O[0]
+                vs = [vid(g[i], g[o], f[i], f[o]) for i in I]
+            tris.append((vs, g, s))
+        else:
+            i0, i1 = I
+            o0, o1 = O
+            q0 = vid(g[i0], g[o0], f[i0], f[o0])
+            q1 = vid(g[i0], g[o1], f[i0], f[o1])
+            q2 = vid(g[i1], g[o1], f[i1], f[o1])
+            q3 = vid(g[i1], g[o0], f[i1], f[o0])
+            tris.append(([q0, q1, q2], g, s))
+            tris.append(([q0, q2, q3], g, s))
+    V = np.array(vert_list, dtype=np.float64)
+    T = np.array([t[0] for t in tris], dtype=np.int64)
+    # orientation: normal must point from inside corners to outside corners
+    gpos = np.stack(np.unravel_index(np.array([t[1] for t in tris]), shape), -1)
+    sg = np.array([t[2] for t in tris])
+    cin = (gpos * sg[..., None]).sum(1) / sg.sum(1, keepdims=True)
+    cout = (gpos * (~sg)[..., None]).sum(1) / (~sg).sum(1, keepdims=True)
+    nrm = np.cross(V[T[:, 1]] - V[T[:, 0]], V[T[:, 2]] - V[T[:, 0]])
+    flip = (nrm * (cout - cin)).sum(1) < 0
+    T[flip] = T[flip][:, [0, 2, 1]]
+    T = _collapse_degenerate(V, T)
+    V, T = _compact(V, T)
+    return V, T.astype(np.int32), {"grid_shape": shape, "h_grid": h_grid,
+                                   "beta": beta}
+
+
+def _tri_area(V, T):
+    return 0.5 * np.linalg.norm(
+        np.cross(V[T[:, 1]] - V[T[:, 0]], V[T[:, 2]] - V[T[:, 0]]), axis=1)
+
+
+def _collapse_degenerate(V, T, rel=1e-12):
+    """Collapse the shortest edge of any triangle with area < rel*mean."""
+    for _ in range(100):
+        A = _tri_area(V, T)
+        bad = np.nonzero(A < rel * A.mean())[0]
+        if len(bad) == 0:
+            return T
+        t = T[bad[0]]
+        e = [(t[0], t[1]), (t[1], t[2]), (t[2], t[0])]
+        L = [np.linalg.norm(V[a] - V[b]) for a, b in e]
+        a, b = e[int(np.argmin(L))]
+        T = np.where(T == b, a, T)
+        keep = (T[:, 0] != T[:, 1]) & (T[:, 1] != T[:, 2]) & (T[:, 2] != T[:, 0])
+        T = T[keep]
+    return T
+
+
+def _compact(V, T):
+    used = np.unique(T)
+    remap = -np.ones(len(V), np.int64)
+    remap[used] = np.arange(len(used))
+    return V[used], remap[T]
+
+
+def check_closed_manifold(tri) -> bool:
+    """Every directed edge appears exactly once and its reverse exactly once."""
+    T = np.asarray(tri, np.int64)
+    e = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+    key = e[:, 0] * (T.max() + 1) + e[:, 1]
+    rkey = e[:, 1] * (T.max() + 1) + e[:, 0]
+    u, c = np.unique(key, return_counts=True)
+    if (c != 1).any():
+        return False
+    return bool(np.isin(rkey, u).all())
+
+
+def globular(seed: int = 2, n_atoms: int = 5000, r_max: float = 25.0,
+             h_grid: float = 1.25):
+    """Config 'synthetic globular molecule' (5,000 atoms, ~50k nodes).
+
+    Marching tetrahedra yields about six times the triangles of marching
+    cubes at equal spacing, so the grid is 1.25 A (not 0.5 A) to land on the
+    configuration's ~100k triangles / ~50k nodes."""
+    pos, rad, q = saw_atoms(n_atoms, r_max, seed)
+    V, T, meta = gaussian_surface(pos, rad, h_grid)
+    return Molecule(name=f"globular_{n_atoms}", xyz=V, tri=T, atom_xyz=pos,
+                    charge=q, radius=rad, meta=dict(meta, seed=seed))
+
+
+def complex_100k(seed: int = 3, n_atoms: int = 100000, r_max: float = 90.0,
+                 h_grid: float = 0.7):
+    """Config 'synthetic large protein complex' (100,000 atoms, ~1M nodes)."""
+    pos, rad, q = saw_atoms(n_atoms, r_max, seed)
+    V, T, meta = gaussian_surface(pos, rad, h_grid)
+    return Molecule(name=f"complex_{n_atoms}", xyz=V, tri=T, atom_xyz=pos,
+                    charge=q, radius=rad, meta=dict(meta, seed=seed))
+
+
+# ---------------------------------------------------------------------------
+# Serving stream: star-shaped molecules
+# ---------------------------------------------------------------------------
+
+def _real_sph_harm(lmax, xyz):
+    """Real orthonormal spherical harmonics Y_lm at unit vectors, l=1..lmax."""
+    from scipy.special import sph_harm_y
+    z = np.clip(xyz[:, 2], -1.0, 1.0)
+    theta = np.arccos(z)
+    phi = np.arctan2(xyz[:, 1], xyz[:, 0])
+    out = []
+    for l in range(1, lmax + 1):
+        for m in range(-l, l + 1):
+            Y = sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                out.append(math.sqrt(2.0) * (-1) ** m * Y.real)
+            elif m < 0:
+                out.append(math.sqrt(2.0) * (-1) ** m * Y.imag)
+            else:
+                out.append(Y.real)
+    return np.stack(out, 1)
+
+
+def star_request(i: int, level: int | None = None):
+    """Request i of the serving stream (seed 4000+i)."""
+    rng = np.random.Generator(np.random.PCG64(4000 + i))
+    R = rng.uniform(8.0, 40.0)
+    a = rng.normal(0.0, 0.05, 48)               # l=1..6: 3+5+...+13 = 48
+    L = int(rng.integers(3, 7)) if level is None else level
+    _ = level
+    nq = int(rng.integers(5, 501))
+    qv = rng.normal(0.0, 0.5, nq)
+    vhat, tri = icosphere(L, 1.0)
+
+    def rfun(u):
+        return R * np.maximum(0.3, 1.0 + _real_sph_harm(6, u) @ a)
+
+    xyz = vhat * rfun(vhat)[:, None]
+    pos = np.zeros((nq, 3))
+    k = 0
+    while k < nq:
+        w = _unit_vectors(rng, 1)
+        u = rng.uniform()
+        rw = float(rfun(w)[0])
+        rad = 0.7 * rw * u ** (1.0 / 3.0)
+        if rw - rad < 1.5:
+            continue
+        pos[k] = w[0] * rad
+        k += 1
+    return Molecule(name=f"star_{i}", xyz=xyz, tri=tri, atom_xyz=pos,
+                    charge=qv, radius=np.full(nq, 1.5),
+                    meta={"level": L, "R": R, "seed": 4000 + i})
+
+
+def random_rigid_motion(seed: int):
+    """A seeded random rotation matrix and translation vector."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    Rm = np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+    t = rng.uniform(-10, 10, 3)
+    return Rm, t
