@@ -1,0 +1,154 @@
+"""Benchmark of the node-patch FMM matvec on one MI355X.
+
+One step = one application of the boundary-integral operator of Eq. (5)
+(source gather, P2M, M2M, M2L, L2L, L2P, P2P, near-set corrections and the
+identity term) to a vector already resident in HBM, on the synthetic globular
+molecule (5,000 atoms, ~54k surface nodes, ~108k unknowns).  Setup (geometry,
+octree, lists, near-set quadrature, translation operators) happens once
+before the timed region and is reported separately.
+
+Prints ONE JSON line with the metric, a roofline entry for the dominant
+kernel (per-launch durations from HIP events on the library's stream over
+the timed region) and the FP64 CPU oracle timed on a bounded row sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per unit (measurement section).
+P2P_FLOPS_PER_PAIR = 60            # canonical count, FMA = 2, transcendentals excluded
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(mol, target_s):
+    """FP64 oracle (direct O(N^2) node-patch matvec) on a bounded row sample,
+    scaled to Munknowns/s of a full matvec."""
+    import oracle as O
+    n = mol.n_nodes
+    rng = np.random.default_rng(123)
+    x = rng.normal(size=2 * n)
+    nrows = 128
+    while True:
+        rows = np.sort(rng.choice(n, size=min(nrows, n), replace=False))
+        op = O.operator(mol.xyz, mol.tri, mol.eps_p, mol.eps_s, mol.kappa, rows=rows,
+                        validate=False)
+        t0 = time.perf_counter()
+        op.apply_rows(x)
+        dt = time.perf_counter() - t0
+        if dt * 4 > target_s or nrows >= n:
+            break
+        nrows = min(n, int(nrows * max(2.0, target_s / max(dt, 1e-3) * 0.9)))
+    t_full = dt * n / len(rows)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 2 * n / t_full / 1e6, "unit": "Munknowns/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{len(rows)} of {n} rows of one FP64 direct matvec "
+                      f"({dt:.2f} s, near-set quadrature of those rows excluded), "
+                      f"scaled by N/rows"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                                   "multi-GPU sharding is a design only (see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1710_06316_amd as A
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    mol = W.globular()
+    n = mol.n_nodes
+    prec = A.AFMPB_FP64 if a.precision == "fp64" else A.AFMPB_FP32_REFINED
+    s = A.Solver(0, stream.cuda_stream)
+    t0 = time.perf_counter()
+    s.load(mol, order_p=a.order, leaf_cap=a.leaf, precision=prec)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    info = s.tree_info()
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.randn(2 * n, dtype=torch.float64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    for _ in range(a.warmup):
+        s.matvec_dev(x.data_ptr(), y.data_ptr())
+    torch.cuda.synchronize()
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        s.matvec_dev(x.data_ptr(), y.data_ptr())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read()
+    s.profile(False)
+    ms = (t1 - t0) * 1e3 / a.steps
+    value = 2 * n / (ms * 1e-3) / 1e6
+    # dominant kernel
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    name, (tot_ms, cnt) = dom
+    avg_s = tot_ms / cnt * 1e-3
+    peak = PEAK_FP64_VECTOR_TFLOPS if a.precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
+    if name == "p2p":
+        achieved = info["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR / avg_s / 1e12
+        roof = {"kernel": "p2p", "bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "pairs_per_launch": info["n_p2p_pairs"], "avg_ms": avg_s * 1e3}
+    else:
+        roof = {"kernel": name, "bound": "alu", "achieved": None, "peak": peak,
+                "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_ms": avg_s * 1e3}
+    # one full solve, reported beside the matvec
+    torch.cuda.synchronize()
+    f, h, E, sinfo, _ = s.solve(allow_not_converged=True)
+    solve = {"energy_kcal_mol": E, "iterations": sinfo.iterations,
+             "converged": bool(sinfo.converged), "true_rel_residual": sinfo.true_rel_residual,
+             "ms_gmres": sinfo.ms_gmres, "ms_total": sinfo.ms_total}
+    s.close()
+    line = {
+        "metric": "FMM matvec Munknowns/s", "value": value, "unit": "Munknowns/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "globular_5000: SAW atoms in 25 A, Gaussian isosurface, "
+                               f"{n} nodes / {len(mol.tri)} triangles",
+                   "unknowns": 2 * n, "order_p": a.order, "leaf_cap": a.leaf,
+                   "precision": a.precision, "n_boxes": info["n_boxes"],
+                   "n_p2p_pairs": info["n_p2p_pairs"], "n_m2l_pairs": info["n_m2l_pairs"],
+                   "n_near": info["n_near"]},
+        "setup_ms": setup_ms,
+        "kernels_ms_per_step": {k: v[0] / max(v[1], 1) * (v[1] / a.steps) for k, v in prof.items()},
+        "roofline": roof,
+        "solve": solve,
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(mol, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

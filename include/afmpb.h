@@ -1,0 +1,210 @@
+/*
+ * afmpb.h -- C ABI of the MI355X node-patch Poisson-Boltzmann solver.
+ *
+ * The library applies and solves the boundary-integral system of the
+ * linearised Poisson-Boltzmann equation as discretised by the node-patch
+ * scheme (Zhang et al., Section 2):
+ *
+ *   [ alpha I + B    -A        ] [f]   1     [ sum_k q_k G_pk       ]
+ *   [ D              alpha I - C] [h] = ---- [ sum_k q_k dG_pk/dn_0 ]   (Eq. 5)
+ *                                      eps_s
+ *
+ * with alpha = 1/(2 ebar) + 1/2, ebar = eps_s/eps_p, and A, B, C, D the patch
+ * integrals of Eq. (6).  Far pairs use the integrand at the node times the
+ * patch area; pairs within the near set N(p) = {p} U {t : |x_p-x_t| <
+ * eta max(rho_p, rho_t)} (rho = patch radius) use the patch integrals.  The
+ * point-rule sums run through an adaptive fast multipole method (Laplace and
+ * screened-Coulomb kernels, P2P near field, P2M/M2M/M2L/L2L/L2P far field).
+ *
+ * Conventions
+ *  - Every function returns afmpb_status: 0 on success, < 0 on error.  No
+ *    C++ exception crosses the ABI.  afmpb_last_error() gives the message of
+ *    the last failing call on a context.
+ *  - Ownership: the caller owns every array it passes.  afmpb_set_molecule
+ *    copies its inputs before returning; the context owns all device state
+ *    (tree, lists, near coefficients, expansions, Krylov basis) until
+ *    afmpb_destroy or the next afmpb_set_molecule.
+ *  - Pointers are host pointers unless the name ends in _dev; _dev pointers
+ *    are device pointers on the context's device, used in order on the
+ *    context's stream.
+ *  - Node order in every input/output array is the caller's order (the
+ *    Morton permutation is internal).  Vectors are x = [f(0..N-1); h(0..N-1)].
+ *  - Units: coordinates in Angstrom, charges in e, kappa in 1/Angstrom.  The
+ *    matvec is unitless.  afmpb_solve returns f in kcal/(mol e), h in
+ *    kcal/(mol e A) and the energy in kcal/mol.
+ *  - A context is used by one host thread at a time.
+ *  - After any error other than AFMPB_E_DEVICE the context stays usable
+ *    (a failed afmpb_set_molecule leaves it with no molecule).
+ */
+#ifndef AFMPB_H
+#define AFMPB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AFMPB_OK = 0,
+    AFMPB_E_INVALID = -1,        /* bad argument (NULL, size, NaN, eps<=0, kappa<0 ...) */
+    AFMPB_E_MESH = -2,           /* mesh not closed, non-manifold, duplicate vertex,
+                                    degenerate triangle or inward orientation        */
+    AFMPB_E_OOM = -3,            /* device allocation failed; nothing half-built kept */
+    AFMPB_E_NOT_CONVERGED = -4,  /* solve: outputs hold the last iterate, info filled */
+    AFMPB_E_NUMERIC = -5,        /* NaN/Inf met in an iterate or input vector          */
+    AFMPB_E_DEVICE = -6,         /* HIP runtime error; the context must be destroyed   */
+    AFMPB_E_STATE = -7           /* call out of order (e.g. matvec before a molecule)  */
+} afmpb_status;
+
+typedef enum {
+    AFMPB_FP64 = 0,              /* every kernel in double precision                   */
+    AFMPB_FP32_REFINED = 1       /* FMM/P2P in single precision with compensated sums,
+                                    near correction, Arnoldi, residuals and energy in
+                                    double; iterative refinement restores the residual */
+} afmpb_precision;
+
+/* Problem and solver parameters (the problem statement of Section 2 and the
+ * GMRES settings of Sections 3.4 and 5). */
+typedef struct {
+    double eps_p;        /* interior dielectric constant (> 0)                      */
+    double eps_s;        /* exterior (solvent) dielectric constant (> 0)            */
+    double kappa;        /* Debye-Hueckel parameter, 1/A (>= 0; 0 = no salt)        */
+    int order_p;         /* multipole expansion order p (2..20); 0 selects 8        */
+    int leaf_cap;        /* max nodes per leaf box (>= 1); 0 selects 64;  a value
+                            >= N makes the root a leaf: every pair by direct P2P   */
+    int precision;       /* afmpb_precision                                         */
+    double rel_tol;      /* GMRES stops at ||r|| <= rel_tol ||b||_2 + abs_tol (Eq. 7) */
+    double abs_tol;
+    int restart;         /* Krylov vectors per GMRES cycle (>= 1); 0 selects 80     */
+    int max_restarts;    /* restarts after the first cycle (>= 0)                   */
+    double near_eta;     /* near-set radius factor eta (> 0); 0 selects 4           */
+} afmpb_params;
+
+typedef struct {
+    int iterations;              /* Arnoldi steps (matrix-vector products in GMRES) */
+    int restarts;
+    long long inner_products;    /* dot products and norms taken by the Arnoldi process */
+    double rel_residual_estimate;/* GMRES estimate / ||b|| at exit                    */
+    double true_rel_residual;    /* ||b - M x|| / ||b|| recomputed in FP64 at exit    */
+    int converged;
+    int refinement_steps;        /* outer refinement steps (FP32_REFINED only)        */
+    double ms_setup;             /* last afmpb_set_molecule: geometry, tree, lists,
+                                    near coefficients, translation operators          */
+    double ms_rhs, ms_gmres, ms_energy, ms_total;
+} afmpb_solve_info;
+
+/* Sizes of the internal tree, for afmpb_debug_tree. */
+typedef struct {
+    long long n_nodes, n_boxes, n_levels;
+    long long n_u, n_v, n_w, n_x;    /* entries of the U, V, W, X lists         */
+    long long n_near;                /* entries of the near set (incl. diagonal)*/
+    long long n_p2p_pairs;           /* point pairs evaluated by P2P per matvec  */
+    long long n_m2l_pairs;           /* V-list box pairs per matvec              */
+    int order_p, leaf_cap;
+} afmpb_tree_sizes;
+
+/* Caller-allocated host buffers for afmpb_debug_tree (sizes from
+ * afmpb_tree_info).  Any pointer may be NULL to skip that array.  Boxes are
+ * numbered by ascending (level, prefix); lists are CSR over boxes with
+ * entries ascending; point indices are positions in Morton order. */
+typedef struct {
+    unsigned long long *keys;        /* [n_nodes] sorted 63-bit Morton keys      */
+    int *perm;                       /* [n_nodes] Morton position -> caller index */
+    int *level, *parent, *child_begin, *n_child, *pt_begin, *pt_end;  /* [n_boxes] */
+    unsigned long long *prefix;      /* [n_boxes]                                 */
+    int *u_ptr, *u_idx;              /* [n_boxes+1], [n_u]                        */
+    int *v_ptr, *v_idx, *v_class;    /* [n_boxes+1], [n_v], [n_v] (0..315)        */
+    int *w_ptr, *w_idx;              /* [n_boxes+1], [n_w]                        */
+    int *x_ptr, *x_idx;              /* [n_boxes+1], [n_x]                        */
+    long long *near_ptr;             /* [n_nodes+1]                               */
+    int *near_col;                   /* [n_near]                                  */
+    double *near_delta;              /* [n_near][4]: patch minus point-rule value
+                                        of {A,B,C,D} (point value 0 on the diagonal) */
+} afmpb_tree_view;
+
+typedef struct afmpb_ctx afmpb_ctx;
+
+/* Fills *out with the defaults above (eps_p 2, eps_s 80, kappa 0.1, p 8,
+ * leaf 64, FP64, rel_tol 1e-6, abs_tol 0, restart 80, max_restarts 5,
+ * eta 4). */
+afmpb_status afmpb_default_params(afmpb_params *out);
+
+/* Creates a context on HIP device `device`.  hip_stream is a hipStream_t
+ * (NULL = the device's null stream) on which all work of this context is
+ * queued; it must outlive the context. */
+afmpb_status afmpb_create(int device, void *hip_stream, afmpb_ctx **out);
+
+/* Frees all device state of the context.  NULL is accepted. */
+afmpb_status afmpb_destroy(afmpb_ctx *ctx);
+
+/* Message of the last failing call on ctx ("" if none).  Valid until the
+ * next call on ctx. */
+const char *afmpb_last_error(const afmpb_ctx *ctx);
+
+/* Loads a molecule and builds everything that does not depend on the
+ * unknowns (Section 2 computation flow, steps 1-2; the phased tree/DAG
+ * construction of Section 3.3): validates the mesh, uploads it, computes
+ * patch geometry, Morton keys and the adaptive octree, the U/V/W/X lists,
+ * the near set with its patch-integral corrections, and the translation
+ * operators.  xyz: [n_nodes][3] node coordinates.  tri: [n_tri][3] 0-based
+ * node indices, counter-clockwise seen from the solvent (outward normal).
+ * atom_xyz [n_atoms][3], charge [n_atoms]; radius [n_atoms] may be NULL (not
+ * used by the solver).  Errors: AFMPB_E_INVALID, AFMPB_E_MESH, AFMPB_E_OOM,
+ * AFMPB_E_DEVICE. */
+afmpb_status afmpb_set_molecule(afmpb_ctx *ctx, long long n_nodes,
+                                const double *xyz, long long n_tri,
+                                const int *tri, long long n_atoms,
+                                const double *atom_xyz, const double *charge,
+                                const double *radius,
+                                const afmpb_params *params);
+
+/* y = M x for the left-hand side operator of Eq. (5), one FMM evaluation
+ * (the per-iteration matrix-vector product of Section 2, step 3).
+ * x, y: [2 n_nodes] host arrays, caller order.  Uses the precision chosen in
+ * the parameters.  Errors: AFMPB_E_STATE (no molecule), AFMPB_E_NUMERIC
+ * (non-finite x), AFMPB_E_DEVICE. */
+afmpb_status afmpb_matvec(afmpb_ctx *ctx, const double *x, double *y);
+
+/* As afmpb_matvec with device pointers, enqueued on the context's stream
+ * without host synchronisation.  x_dev and y_dev must not overlap.  No
+ * finiteness check. */
+afmpb_status afmpb_matvec_dev(afmpb_ctx *ctx, const double *x_dev,
+                              double *y_dev);
+
+/* Solves Eq. (5) by restarted GMRES (Section 3.4; stopping rule Eq. 7) and
+ * evaluates the polar energy 1/2 sum_k q_k phi_reac(r_k), phi_reac from the
+ * interior Green representation on the surface.  x0: optional warm start
+ * [2 n_nodes] in internal (unitless) form as returned by a previous solve
+ * divided by the unit factor, or NULL for zero.  f, h: [n_nodes] outputs
+ * (may be NULL); energy: scalar output (may be NULL); info may be NULL.
+ * On AFMPB_E_NOT_CONVERGED the outputs hold the last iterate. */
+afmpb_status afmpb_solve(afmpb_ctx *ctx, const double *x0, double *f,
+                         double *h, double *energy, afmpb_solve_info *info);
+
+/* Right-hand side of Eq. (5) in caller order ([2 n_nodes], unitless). */
+afmpb_status afmpb_rhs(afmpb_ctx *ctx, double *b);
+
+/* Polar energy (kcal/mol) for a given internal solution x = [f; h]
+ * (caller order, unitless). */
+afmpb_status afmpb_energy(afmpb_ctx *ctx, const double *x, double *energy);
+
+/* Sizes of the internal tree and lists of the loaded molecule. */
+afmpb_status afmpb_tree_info(afmpb_ctx *ctx, afmpb_tree_sizes *out);
+
+/* Copies the internal tree, lists and near set to caller buffers. */
+afmpb_status afmpb_debug_tree(afmpb_ctx *ctx, const afmpb_tree_view *out);
+
+/* Per-kernel timing with HIP events on the context's stream.  enable != 0
+ * starts recording (and clears the totals); 0 stops.  afmpb_profile_read
+ * returns, for entry idx (0-based), its name, total milliseconds and launch
+ * count; AFMPB_E_INVALID past the last entry.  Names stay valid until the
+ * context is destroyed. */
+afmpb_status afmpb_profile_enable(afmpb_ctx *ctx, int enable);
+afmpb_status afmpb_profile_read(afmpb_ctx *ctx, int idx, const char **name,
+                                double *total_ms, long long *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFMPB_H */

@@ -1,0 +1,330 @@
+"""MI355X node-patch Poisson-Boltzmann solver: Python binding of libafmpb.
+
+Argument marshalling only: every step of the method runs in the HIP library
+(``libafmpb.so``, C ABI declared in ``include/afmpb.h``).  The functions below
+carry the C names; ``Solver`` is a small convenience wrapper over them.  If the
+library has not been built, any call raises ``RuntimeError`` -- there is no
+fallback implementation.
+
+Device memory and streams may come from PyTorch: ``afmpb_create`` takes a
+``hipStream_t`` (``torch.cuda.current_stream().cuda_stream``) and
+``afmpb_matvec_dev`` takes raw device pointers (``tensor.data_ptr()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libafmpb.so")
+
+AFMPB_OK = 0
+AFMPB_E_INVALID = -1
+AFMPB_E_MESH = -2
+AFMPB_E_OOM = -3
+AFMPB_E_NOT_CONVERGED = -4
+AFMPB_E_NUMERIC = -5
+AFMPB_E_DEVICE = -6
+AFMPB_E_STATE = -7
+AFMPB_FP64 = 0
+AFMPB_FP32_REFINED = 1
+
+STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_MESH", -3: "E_OOM",
+                -4: "E_NOT_CONVERGED", -5: "E_NUMERIC", -6: "E_DEVICE", -7: "E_STATE"}
+
+ABI_FUNCTIONS = (
+    "afmpb_default_params", "afmpb_create", "afmpb_destroy", "afmpb_last_error",
+    "afmpb_set_molecule", "afmpb_matvec", "afmpb_matvec_dev", "afmpb_solve",
+    "afmpb_rhs", "afmpb_energy", "afmpb_tree_info", "afmpb_debug_tree",
+    "afmpb_profile_enable", "afmpb_profile_read",
+)
+
+
+class afmpb_params(ctypes.Structure):
+    _fields_ = [("eps_p", ctypes.c_double), ("eps_s", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("order_p", ctypes.c_int),
+                ("leaf_cap", ctypes.c_int), ("precision", ctypes.c_int),
+                ("rel_tol", ctypes.c_double), ("abs_tol", ctypes.c_double),
+                ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
+                ("near_eta", ctypes.c_double)]
+
+
+class afmpb_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("inner_products", ctypes.c_longlong),
+                ("rel_residual_estimate", ctypes.c_double),
+                ("true_rel_residual", ctypes.c_double), ("converged", ctypes.c_int),
+                ("refinement_steps", ctypes.c_int), ("ms_setup", ctypes.c_double),
+                ("ms_rhs", ctypes.c_double), ("ms_gmres", ctypes.c_double),
+                ("ms_energy", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class afmpb_tree_sizes(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_longlong) for k in
+                ("n_nodes", "n_boxes", "n_levels", "n_u", "n_v", "n_w", "n_x", "n_near",
+                 "n_p2p_pairs", "n_m2l_pairs")] + [("order_p", ctypes.c_int),
+                                                   ("leaf_cap", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_TREE_FIELDS = ("keys", "perm", "level", "parent", "child_begin", "n_child", "pt_begin",
+                "pt_end", "prefix", "u_ptr", "u_idx", "v_ptr", "v_idx", "v_class", "w_ptr",
+                "w_idx", "x_ptr", "x_idx", "near_ptr", "near_col", "near_delta")
+
+
+class afmpb_tree_view(ctypes.Structure):
+    _fields_ = [(k, _P) for k in _TREE_FIELDS]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises RuntimeError when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"libafmpb.so not found at {LIB_PATH}; build it with "
+                "`python -m paper_1710_06316_amd.build` (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        ll = ctypes.c_longlong
+        L.afmpb_default_params.argtypes = [ctypes.POINTER(afmpb_params)]
+        L.afmpb_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.afmpb_destroy.argtypes = [vp]
+        L.afmpb_last_error.argtypes = [vp]
+        L.afmpb_last_error.restype = ctypes.c_char_p
+        L.afmpb_set_molecule.argtypes = [vp, ll, dp, ll, ip, ll, dp, dp, dp,
+                                         ctypes.POINTER(afmpb_params)]
+        L.afmpb_matvec.argtypes = [vp, dp, dp]
+        L.afmpb_matvec_dev.argtypes = [vp, vp, vp]
+        L.afmpb_solve.argtypes = [vp, dp, dp, dp, dp, ctypes.POINTER(afmpb_solve_info)]
+        L.afmpb_rhs.argtypes = [vp, dp]
+        L.afmpb_energy.argtypes = [vp, dp, dp]
+        L.afmpb_tree_info.argtypes = [vp, ctypes.POINTER(afmpb_tree_sizes)]
+        L.afmpb_debug_tree.argtypes = [vp, ctypes.POINTER(afmpb_tree_view)]
+        L.afmpb_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.afmpb_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                         dp, ctypes.POINTER(ll)]
+        for name in ABI_FUNCTIONS:
+            if name != "afmpb_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class AfmpbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --- the C entry points, one marshalling wrapper each -------------------------
+
+def afmpb_default_params() -> afmpb_params:
+    p = afmpb_params()
+    lib().afmpb_default_params(ctypes.byref(p))
+    return p
+
+
+def afmpb_create(device: int = 0, stream: int | None = None):
+    h = ctypes.c_void_p()
+    st = lib().afmpb_create(int(device), ctypes.c_void_p(stream or 0), ctypes.byref(h))
+    if st != AFMPB_OK:
+        raise AfmpbError(st, "afmpb_create failed")
+    return h
+
+
+def afmpb_destroy(ctx) -> int:
+    return lib().afmpb_destroy(ctx)
+
+
+def afmpb_last_error(ctx) -> str:
+    return lib().afmpb_last_error(ctx).decode()
+
+
+def _check(ctx, st, allow=(AFMPB_OK,)):
+    if st not in allow:
+        raise AfmpbError(st, afmpb_last_error(ctx))
+    return st
+
+
+def afmpb_set_molecule(ctx, xyz, tri, atom_xyz, charge, radius, params: afmpb_params):
+    xyz = _f64(xyz).reshape(-1, 3)
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    ax = _f64(atom_xyz).reshape(-1, 3)
+    q = _f64(charge).reshape(-1)
+    rad = None if radius is None else _f64(radius).reshape(-1)
+    st = lib().afmpb_set_molecule(ctx, len(xyz), _dp(xyz), len(tri), _ip(tri), len(q), _dp(ax),
+                                  _dp(q), _dp(rad), ctypes.byref(params))
+    return _check(ctx, st)
+
+
+def afmpb_matvec(ctx, x):
+    x = _f64(x)
+    y = np.empty_like(x)
+    _check(ctx, lib().afmpb_matvec(ctx, _dp(x), _dp(y)))
+    return y
+
+
+def afmpb_matvec_dev(ctx, x_ptr: int, y_ptr: int):
+    return _check(ctx, lib().afmpb_matvec_dev(ctx, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr)))
+
+
+def afmpb_solve(ctx, n_nodes: int, x0=None, allow_not_converged=False):
+    f = np.empty(n_nodes)
+    h = np.empty(n_nodes)
+    e = ctypes.c_double()
+    info = afmpb_solve_info()
+    x0 = None if x0 is None else _f64(x0)
+    st = lib().afmpb_solve(ctx, _dp(x0), _dp(f), _dp(h), ctypes.byref(e), ctypes.byref(info))
+    allow = (AFMPB_OK, AFMPB_E_NOT_CONVERGED) if allow_not_converged else (AFMPB_OK,)
+    _check(ctx, st, allow)
+    return f, h, e.value, info, st
+
+
+def afmpb_rhs(ctx, n_nodes: int):
+    b = np.empty(2 * n_nodes)
+    _check(ctx, lib().afmpb_rhs(ctx, _dp(b)))
+    return b
+
+
+def afmpb_energy(ctx, x):
+    x = _f64(x)
+    e = ctypes.c_double()
+    _check(ctx, lib().afmpb_energy(ctx, _dp(x), ctypes.byref(e)))
+    return e.value
+
+
+def afmpb_tree_info(ctx) -> afmpb_tree_sizes:
+    s = afmpb_tree_sizes()
+    _check(ctx, lib().afmpb_tree_info(ctx, ctypes.byref(s)))
+    return s
+
+
+def afmpb_debug_tree(ctx) -> dict:
+    s = afmpb_tree_info(ctx)
+    n, nb = s.n_nodes, s.n_boxes
+    arr = {
+        "keys": np.zeros(n, np.uint64), "perm": np.zeros(n, np.int32),
+        "level": np.zeros(nb, np.int32), "parent": np.zeros(nb, np.int32),
+        "child_begin": np.zeros(nb, np.int32), "n_child": np.zeros(nb, np.int32),
+        "pt_begin": np.zeros(nb, np.int32), "pt_end": np.zeros(nb, np.int32),
+        "prefix": np.zeros(nb, np.uint64),
+        "u_ptr": np.zeros(nb + 1, np.int32), "u_idx": np.zeros(max(s.n_u, 1), np.int32),
+        "v_ptr": np.zeros(nb + 1, np.int32), "v_idx": np.zeros(max(s.n_v, 1), np.int32),
+        "v_class": np.zeros(max(s.n_v, 1), np.int32),
+        "w_ptr": np.zeros(nb + 1, np.int32), "w_idx": np.zeros(max(s.n_w, 1), np.int32),
+        "x_ptr": np.zeros(nb + 1, np.int32), "x_idx": np.zeros(max(s.n_x, 1), np.int32),
+        "near_ptr": np.zeros(n + 1, np.int64), "near_col": np.zeros(max(s.n_near, 1), np.int32),
+        "near_delta": np.zeros((max(s.n_near, 1), 4)),
+    }
+    view = afmpb_tree_view(**{k: arr[k].ctypes.data for k in _TREE_FIELDS})
+    _check(ctx, lib().afmpb_debug_tree(ctx, ctypes.byref(view)))
+    for k, cnt in (("u_idx", s.n_u), ("v_idx", s.n_v), ("v_class", s.n_v), ("w_idx", s.n_w),
+                   ("x_idx", s.n_x), ("near_col", s.n_near), ("near_delta", s.n_near)):
+        arr[k] = arr[k][:cnt]
+    arr["sizes"] = s.as_dict()
+    return arr
+
+
+def afmpb_profile_enable(ctx, enable: bool):
+    return _check(ctx, lib().afmpb_profile_enable(ctx, 1 if enable else 0))
+
+
+def afmpb_profile_read(ctx) -> dict:
+    out = {}
+    i = 0
+    name = ctypes.c_char_p()
+    ms = ctypes.c_double()
+    cnt = ctypes.c_longlong()
+    while lib().afmpb_profile_read(ctx, i, ctypes.byref(name), ctypes.byref(ms),
+                                   ctypes.byref(cnt)) == AFMPB_OK:
+        out[name.value.decode()] = (ms.value, cnt.value)
+        i += 1
+    return out
+
+
+# --- convenience wrapper --------------------------------------------------------
+
+class Solver:
+    """One context holding one molecule."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.ctx = afmpb_create(device, stream)
+        self.n = 0
+
+    def close(self):
+        if self.ctx is not None:
+            afmpb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def params(**kw) -> afmpb_params:
+        p = afmpb_default_params()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    def set_molecule(self, xyz, tri, atom_xyz, charge, radius=None, **params):
+        afmpb_set_molecule(self.ctx, xyz, tri, atom_xyz, charge, radius, self.params(**params))
+        self.n = int(np.asarray(xyz).reshape(-1, 3).shape[0])
+
+    def load(self, mol, **params):
+        kw = dict(eps_p=mol.eps_p, eps_s=mol.eps_s, kappa=mol.kappa)
+        kw.update(params)
+        self.set_molecule(mol.xyz, mol.tri, mol.atom_xyz, mol.charge, mol.radius, **kw)
+
+    def matvec(self, x):
+        return afmpb_matvec(self.ctx, x)
+
+    def matvec_dev(self, x_ptr, y_ptr):
+        return afmpb_matvec_dev(self.ctx, x_ptr, y_ptr)
+
+    def solve(self, x0=None, allow_not_converged=False):
+        return afmpb_solve(self.ctx, self.n, x0, allow_not_converged)
+
+    def rhs(self):
+        return afmpb_rhs(self.ctx, self.n)
+
+    def energy(self, x):
+        return afmpb_energy(self.ctx, x)
+
+    def tree_info(self):
+        return afmpb_tree_info(self.ctx).as_dict()
+
+    def debug_tree(self):
+        return afmpb_debug_tree(self.ctx)
+
+    def profile(self, enable: bool):
+        afmpb_profile_enable(self.ctx, enable)
+
+    def profile_read(self):
+        return afmpb_profile_read(self.ctx)

@@ -1,0 +1,753 @@
+// C ABI of libafmpb: context, molecule setup, matvec, GMRES solve, energy,
+// debug views and profiling.  See include/afmpb.h for the contract.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+#include <numeric>
+
+#include "../../include/afmpb.h"
+#include "krylov.h"
+#include "matvec.h"
+#include "prof.h"
+
+namespace afmpb {
+
+// ------------------------------- profiling ---------------------------------
+
+int Prof::id_of(const char *name) {
+    auto it = index.find(name);
+    if (it != index.end()) return it->second;
+    int id = (int)entries.size();
+    entries.push_back(Entry{name, 0.0, 0});
+    index[name] = id;
+    return id;
+}
+
+hipEvent_t Prof::take() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+void Prof::flush() {
+    for (auto &p : pending) {
+        int id;
+        hipEvent_t a, b;
+        std::tie(id, a, b) = p;
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        entries[id].ms += ms;
+        entries[id].count += 1;
+        pool.push_back(a);
+        pool.push_back(b);
+    }
+    pending.clear();
+}
+
+Prof::~Prof() {
+    for (auto &p : pending) {
+        (void)hipEventDestroy(std::get<1>(p));
+        (void)hipEventDestroy(std::get<2>(p));
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(Prof *p, const char *name, hipStream_t st) : prof(p), id(-1), s(st) {
+    if (!prof || !prof->on) { prof = nullptr; return; }
+    id = prof->id_of(name);
+    hipEvent_t a = prof->take(), b = prof->take();
+    HIPCHK(hipEventRecord(a, s));
+    prof->pending.emplace_back(id, a, b);
+}
+
+ProfScope::~ProfScope() {
+    if (!prof) return;
+    (void)hipEventRecord(std::get<2>(prof->pending.back()), s);
+    if (prof->pending.size() > 4096) {
+        try { prof->flush(); } catch (...) {}
+    }
+}
+
+// ------------------------------- helpers -----------------------------------
+
+constexpr double E_CHARGE = 1.602176634e-19;
+constexpr double AVOGADRO = 6.02214076e23;
+constexpr double EPS0 = 8.8541878128e-12;
+
+double unit_scale() {
+    // 4 pi * (e^2 N_A / (4 pi eps0)) in kcal A / mol
+    double ce = E_CHARGE * E_CHARGE * AVOGADRO / (4.0 * M_PI * EPS0) * 1e10 / 4184.0;
+    return 4.0 * M_PI * ce;
+}
+
+void validate_mesh(long long n, const double *V, long long m, const int *T) {
+    require(n >= 4 && m >= 4, ST_MESH, "mesh needs at least 4 nodes and 4 triangles");
+    for (long long i = 0; i < 3 * n; ++i)
+        require(std::isfinite(V[i]), ST_INVALID, "non-finite node coordinate");
+    std::vector<char> used(n, 0);
+    for (long long i = 0; i < 3 * m; ++i) {
+        require(T[i] >= 0 && T[i] < n, ST_MESH, "triangle index out of range");
+        used[T[i]] = 1;
+    }
+    for (long long i = 0; i < n; ++i) require(used[i], ST_MESH, "node not used by any triangle");
+    std::vector<long long> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](long long a, long long b) {
+        for (int d = 0; d < 3; ++d)
+            if (V[3 * a + d] != V[3 * b + d]) return V[3 * a + d] < V[3 * b + d];
+        return a < b;
+    });
+    for (long long i = 1; i < n; ++i) {
+        const double *a = V + 3 * ord[i - 1], *b = V + 3 * ord[i];
+        require(!(a[0] == b[0] && a[1] == b[1] && a[2] == b[2]), ST_MESH, "duplicate vertex");
+    }
+    std::vector<unsigned long long> e(3 * m);
+    for (long long k = 0; k < m; ++k)
+        for (int j = 0; j < 3; ++j) {
+            unsigned long long a = (unsigned)T[3 * k + j], b = (unsigned)T[3 * k + (j + 1) % 3];
+            require(a != b, ST_MESH, "degenerate triangle (repeated node)");
+            e[3 * k + j] = a * (unsigned long long)n + b;
+        }
+    std::sort(e.begin(), e.end());
+    for (size_t i = 1; i < e.size(); ++i)
+        require(e[i] != e[i - 1], ST_MESH, "edge used twice in one direction (non-manifold)");
+    for (auto x : e) {
+        unsigned long long a = x / n, b = x % n;
+        require(std::binary_search(e.begin(), e.end(), b * (unsigned long long)n + a), ST_MESH,
+                "open surface or inconsistent orientation");
+    }
+    double asum = 0.0, vol = 0.0;
+    std::vector<double> ar(m);
+    for (long long k = 0; k < m; ++k) {
+        const double *a = V + 3ll * T[3 * k], *b = V + 3ll * T[3 * k + 1], *c = V + 3ll * T[3 * k + 2];
+        double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                        e1[0] * e2[1] - e1[1] * e2[0]};
+        ar[k] = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        asum += ar[k];
+        vol += (a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
+                a[2] * (b[0] * c[1] - b[1] * c[0])) / 6.0;
+    }
+    double amean = asum / m;
+    for (long long k = 0; k < m; ++k)
+        require(ar[k] >= 1e-12 * amean, ST_MESH, "degenerate triangle (zero area)");
+    require(vol > 0.0, ST_MESH, "surface encloses non-positive volume (inward orientation?)");
+}
+
+}  // namespace afmpb
+
+using namespace afmpb;
+
+struct afmpb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool loaded = false;
+    afmpb_params prm{};
+    long long n = 0, m = 0, na = 0;
+    double ebar = 1, alpha = 1, inv_ebar = 1;
+    double ms_setup = 0;
+    DBuf<double> V, ax, aq, tri_area, tri_n, area_c, nrm_c, rho2_c;
+    DBuf<int> T, inc_ptr, inc_tri, perm;
+    DBuf<unsigned long long> keys;
+    DBuf<double> node64;      // 8n: x y z nx ny nz area rho2
+    DBuf<float> node32;       // 6n
+    double lo[3] = {0, 0, 0}, scale = 1;
+    Tree tree;
+    Lists lists;
+    NearSet near;
+    Fmm fmm;
+    DBuf<double> w64, far64;
+    DBuf<float> w32, far32;
+    MatvecPlan<double> mp64;
+    MatvecPlan<float> mp32;
+    // vectors in Morton order
+    DBuf<double> xa, ya, bvec, xsol, tmp, hbuf, dscratch, phi_at, dotv;
+    DBuf<double> krylov;
+    int krylov_m = 0;
+    Prof prof;
+
+    NodeSoA nodes() const {
+        double *b = node64.p;
+        long long N = n;
+        return NodeSoA{b, b + N, b + 2 * N, b + 3 * N, b + 4 * N, b + 5 * N, b + 6 * N, b + 7 * N};
+    }
+    void sync() { HIPCHK(hipStreamSynchronize(stream)); }
+    void matvec_m(const double *x, double *y, bool fp64) {
+        if (fp64 || prm.precision == AFMPB_FP64) apply_operator<double>(mp64, x, y, &prof, stream);
+        else apply_operator<float>(mp32, x, y, &prof, stream);
+    }
+};
+
+namespace {
+
+int fail(afmpb_ctx *ctx, const Error &e) {
+    if (ctx) ctx->err = e.what();
+    return e.code;
+}
+
+template <class F>
+afmpb_status guarded(afmpb_ctx *ctx, F &&f) {
+    try {
+        f();
+        if (ctx) ctx->err.clear();
+        return AFMPB_OK;
+    } catch (const Error &e) {
+        return (afmpb_status)fail(ctx, e);
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->err = "host allocation failed";
+        return AFMPB_E_OOM;
+    } catch (const std::exception &e) {
+        if (ctx) ctx->err = e.what();
+        return AFMPB_E_DEVICE;
+    }
+}
+
+void fill_defaults(afmpb_params &p) {
+    p.eps_p = 2.0;
+    p.eps_s = 80.0;
+    p.kappa = 0.1;
+    p.order_p = 8;
+    p.leaf_cap = 64;
+    p.precision = AFMPB_FP64;
+    p.rel_tol = 1e-6;
+    p.abs_tol = 0.0;
+    p.restart = 80;
+    p.max_restarts = 5;
+    p.near_eta = 4.0;
+}
+
+afmpb_params normalise(const afmpb_params &in) {
+    afmpb_params p = in;
+    auto fin = [](double v) { return std::isfinite(v); };
+    require(fin(p.eps_p) && p.eps_p > 0 && fin(p.eps_s) && p.eps_s > 0, ST_INVALID,
+            "dielectric constants must be finite and positive");
+    require(fin(p.kappa) && p.kappa >= 0, ST_INVALID, "kappa must be finite and >= 0");
+    if (p.order_p == 0) p.order_p = 8;
+    require(p.order_p >= 2 && p.order_p <= MAXP, ST_INVALID, "order_p must be in [2, 20]");
+    if (p.leaf_cap == 0) p.leaf_cap = 64;
+    require(p.leaf_cap >= 1, ST_INVALID, "leaf_cap must be >= 1");
+    require(p.precision == AFMPB_FP64 || p.precision == AFMPB_FP32_REFINED, ST_INVALID,
+            "unknown precision");
+    require(fin(p.rel_tol) && p.rel_tol >= 0 && fin(p.abs_tol) && p.abs_tol >= 0, ST_INVALID,
+            "tolerances must be finite and >= 0");
+    if (p.restart == 0) p.restart = 80;
+    require(p.restart >= 1 && p.restart <= 1000, ST_INVALID, "restart must be in [1, 1000]");
+    require(p.max_restarts >= 0, ST_INVALID, "max_restarts must be >= 0");
+    if (p.near_eta == 0) p.near_eta = 4.0;
+    require(fin(p.near_eta) && p.near_eta > 0, ST_INVALID, "near_eta must be > 0");
+    return p;
+}
+
+void ensure_loaded(afmpb_ctx *c) {
+    require(c != nullptr, ST_INVALID, "null context");
+    require(c->loaded, ST_STATE, "no molecule loaded");
+}
+
+__global__ void k_to_f32(const double *a, float *b, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+__global__ void k_finite(const double *a, long long n, int *bad) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(a[i])) atomicOr(bad, 1);
+}
+
+template <typename R>
+void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const R *ndR) {
+    const long long n = c->n, K = c->fmm.K, nb = c->tree.nbox, nv = c->lists.n_v;
+    w.alloc((size_t)4 * n);
+    far.alloc((size_t)(2 * nb * K) * 2 + (size_t)std::max(nv, 1ll) * 2 * K + 4 * n);
+    mp.n = n;
+    mp.tree = &c->tree;
+    mp.lists = &c->lists;
+    mp.fmm = &c->fmm;
+    mp.near = &c->near;
+    mp.nd64 = c->nodes();
+    mp.nd = NodeR<R>{ndR, ndR + n, ndR + 2 * n, ndR + 3 * n, ndR + 4 * n, ndR + 5 * n};
+    mp.area = c->nodes().area;
+    mp.kappa = c->prm.kappa;
+    mp.inv_ebar = c->inv_ebar;
+    mp.alpha = c->alpha;
+    mp.sf = w.p;
+    mp.sh = w.p + n;
+    mp.pf = w.p + 2 * n;
+    mp.ph = w.p + 3 * n;
+    R *f = far.p;
+    mp.far.M = f;
+    mp.far.Lc = f + 2 * nb * K;
+    mp.far.Z = f + 4 * nb * K;
+    mp.far.phi = f + 4 * nb * K + std::max(nv, 1ll) * 2 * K;
+}
+
+void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, const int *tri,
+                   long long na, const double *axyz, const double *q, const afmpb_params &prm) {
+    auto t0 = std::chrono::steady_clock::now();
+    c->loaded = false;
+    validate_mesh(n, xyz, m, tri);
+    require(n < (1ll << 30) && m < (1ll << 30), ST_INVALID, "mesh too large");
+    for (long long i = 0; i < 3 * na; ++i)
+        require(std::isfinite(axyz[i]), ST_INVALID, "non-finite atom coordinate");
+    for (long long i = 0; i < na; ++i) require(std::isfinite(q[i]), ST_INVALID, "non-finite charge");
+    hipStream_t s = c->stream;
+    c->prm = prm;
+    c->n = n; c->m = m; c->na = na;
+    c->ebar = prm.eps_s / prm.eps_p;
+    c->inv_ebar = 1.0 / c->ebar;
+    c->alpha = 0.5 / c->ebar + 0.5;
+    c->V.alloc(3 * n); c->V.upload(xyz, 3 * n, s);
+    c->T.alloc(3 * m); c->T.upload(tri, 3 * m, s);
+    c->ax.alloc(3 * std::max(na, 1ll)); c->ax.upload(axyz, 3 * na, s);
+    c->aq.alloc(std::max(na, 1ll)); c->aq.upload(q, na, s);
+    // a0 geometry (caller order)
+    c->tri_area.alloc(m); c->tri_n.alloc(3 * m);
+    c->inc_ptr.alloc(n + 1); c->inc_tri.alloc(3 * m);
+    c->area_c.alloc(n); c->nrm_c.alloc(3 * n); c->rho2_c.alloc(n);
+    compute_geometry(c->V.p, c->T.p, n, m, c->tri_area.p, c->tri_n.p, c->inc_ptr.p, c->inc_tri.p,
+                     c->area_c.p, c->nrm_c.p, c->rho2_c.p, s);
+    // a1 Morton keys and sort
+    c->keys.alloc(n); c->perm.alloc(n);
+    morton_sort(c->V.p, n, c->keys.p, c->perm.p, c->lo, &c->scale, s);
+    c->node64.alloc(8 * n);
+    gather_nodes(c->V.p, c->nrm_c.p, c->area_c.p, c->rho2_c.p, c->perm.p, n, c->nodes(), s);
+    c->node32.alloc(6 * n);
+    k_to_f32<<<grid_for(6 * n, 256), 256, 0, s>>>(c->node64.p, c->node32.p, 6 * n);
+    KCHK();
+    // a2 tree, a3 lists
+    c->tree = Tree();
+    build_tree(c->keys.p, n, prm.leaf_cap, c->lo, c->scale, c->tree, s);
+    c->lists = Lists();
+    build_lists(c->tree, c->lists, s);
+    // a4 near set and corrections
+    c->near = NearSet();
+    build_near(c->nodes(), n, prm.near_eta, c->V.p, c->T.p, c->tri_n.p, c->inc_ptr.p,
+               c->inc_tri.p, c->perm.p, prm.kappa, c->ebar, c->near, s);
+    // translation operators
+    c->fmm = Fmm();
+    build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa, c->fmm, s);
+    setup_plan<double>(c, c->mp64, c->w64, c->far64, c->node64.p);
+    setup_plan<float>(c, c->mp32, c->w32, c->far32, c->node32.p);
+    c->xa.alloc(2 * n); c->ya.alloc(2 * n); c->bvec.alloc(2 * n);
+    c->xsol.alloc(2 * n); c->tmp.alloc(2 * n);
+    c->hbuf.alloc(2 * 1024 + 8);
+    c->phi_at.alloc(std::max(na, 1ll));
+    c->krylov = DBuf<double>();
+    c->krylov_m = 0;
+    c->sync();
+    c->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    c->loaded = true;
+}
+
+struct Gmres {
+    int iterations = 0, restarts = 0;
+    long long inner = 0;
+    double est = 0, true_rel = 0;
+    bool converged = false;
+};
+
+double host_dot(afmpb_ctx *c, const double *a, const double *b, long long len) {
+    if (c->dotv.n < 1) c->dotv.alloc(1);
+    dots(a, 0, 1, b, len, c->dotv.p, c->dscratch, c->stream);
+    double v;
+    HIPCHK(hipMemcpyAsync(&v, c->dotv.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    return v;
+}
+
+// Restarted GMRES(m) on M x = b (Morton order).  Arnoldi by classical
+// Gram-Schmidt with one reorthogonalisation pass (two block projections per
+// step), Givens rotations on the host; stopping rule Eq. (7).
+Gmres gmres(afmpb_ctx *c, const double *b, double *x, bool x_zero, double rel_tol,
+            double abs_tol, int m, int max_restarts, bool fp64_matvec) {
+    const long long len = 2 * c->n;
+    hipStream_t s = c->stream;
+    if (c->krylov_m < m) {
+        c->krylov.alloc((size_t)(m + 1) * len);
+        c->krylov_m = m;
+    }
+    if (c->hbuf.n < (size_t)(2 * (m + 2))) c->hbuf.alloc(2 * (m + 2));
+    double *Vk = c->krylov.p;
+    Gmres g;
+    const double nb = std::sqrt(host_dot(c, b, b, len));
+    g.inner += 1;
+    const double tol = rel_tol * nb + abs_tol;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), h1(m + 1), h2(m + 1);
+    bool first = true;
+    if (x_zero) HIPCHK(hipMemsetAsync(x, 0, len * sizeof(double), s));
+    for (int cycle = 0; cycle <= max_restarts; ++cycle) {
+        if (first && x_zero) {
+            HIPCHK(hipMemcpyAsync(Vk, b, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+            c->matvec_m(x, c->tmp.p, fp64_matvec);
+            axpby(1.0, b, -1.0, c->tmp.p, len, Vk, s);
+        }
+        first = false;
+        double beta = std::sqrt(host_dot(c, Vk, Vk, len));
+        g.inner += 1;
+        g.est = beta;
+        require(std::isfinite(beta), ST_NUMERIC, "non-finite residual");
+        if (beta <= tol) { g.converged = true; break; }
+        if (cycle > 0) g.restarts += 1;
+        scale(Vk, 1.0 / beta, len, Vk, s);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int k = 0;
+        bool done = false;
+        for (int j = 0; j < m; ++j) {
+            double *w = Vk + (size_t)(j + 1) * len;
+            c->matvec_m(Vk + (size_t)j * len, w, fp64_matvec);
+            g.iterations += 1;
+            // two block Gram-Schmidt passes
+            dots(Vk, len, j + 1, w, len, c->hbuf.p, c->dscratch, s);
+            gemv(Vk, len, j + 1, c->hbuf.p, -1.0, len, w, s);
+            dots(Vk, len, j + 1, w, len, c->hbuf.p + (m + 2), c->dscratch, s);
+            gemv(Vk, len, j + 1, c->hbuf.p + (m + 2), -1.0, len, w, s);
+            HIPCHK(hipMemcpyAsync(h1.data(), c->hbuf.p, (j + 1) * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h2.data(), c->hbuf.p + (m + 2), (j + 1) * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            double hn = std::sqrt(host_dot(c, w, w, len));
+            g.inner += 2 * (j + 1) + 1;
+            require(std::isfinite(hn), ST_NUMERIC, "non-finite value in the Arnoldi process");
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h1[i] + h2[i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            double den = std::hypot(H[(size_t)j * m + j], hn);
+            cs[j] = H[(size_t)j * m + j] / den;
+            sn[j] = hn / den;
+            H[(size_t)j * m + j] = den;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            k = j + 1;
+            g.est = std::fabs(gv[j + 1]);
+            if (g.est <= tol || hn == 0.0) { done = true; break; }
+            scale(w, 1.0 / hn, len, w, s);
+        }
+        std::vector<double> y(k);
+        for (int i = k - 1; i >= 0; --i) {
+            double acc = gv[i];
+            for (int l = i + 1; l < k; ++l) acc -= H[(size_t)i * m + l] * y[l];
+            y[i] = acc / H[(size_t)i * m + i];
+        }
+        HIPCHK(hipMemcpyAsync(c->hbuf.p, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+        gemv(Vk, len, k, c->hbuf.p, 1.0, len, x, s);
+        c->sync();
+        if (done) { g.converged = true; break; }
+    }
+    // true residual in FP64
+    c->matvec_m(x, c->tmp.p, true);
+    axpby(1.0, b, -1.0, c->tmp.p, len, c->tmp.p, s);
+    double rn = std::sqrt(host_dot(c, c->tmp.p, c->tmp.p, len));
+    g.true_rel = nb > 0 ? rn / nb : rn;
+    return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+afmpb_status afmpb_default_params(afmpb_params *out) {
+    if (!out) return AFMPB_E_INVALID;
+    fill_defaults(*out);
+    return AFMPB_OK;
+}
+
+afmpb_status afmpb_create(int device, void *hip_stream, afmpb_ctx **out) {
+    if (!out) return AFMPB_E_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return AFMPB_E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return AFMPB_E_DEVICE;
+    afmpb_ctx *c = new (std::nothrow) afmpb_ctx();
+    if (!c) return AFMPB_E_OOM;
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return AFMPB_OK;
+}
+
+afmpb_status afmpb_destroy(afmpb_ctx *ctx) {
+    if (!ctx) return AFMPB_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return AFMPB_OK;
+}
+
+const char *afmpb_last_error(const afmpb_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+afmpb_status afmpb_set_molecule(afmpb_ctx *ctx, long long n_nodes, const double *xyz,
+                                long long n_tri, const int *tri, long long n_atoms,
+                                const double *atom_xyz, const double *charge,
+                                const double *radius, const afmpb_params *params) {
+    (void)radius;
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        HIPCHK(hipSetDevice(ctx->device));
+        ctx->loaded = false;
+        require(xyz && tri && params, ST_INVALID, "null argument");
+        require(n_atoms >= 0 && (n_atoms == 0 || (atom_xyz && charge)), ST_INVALID,
+                "bad atom arrays");
+        afmpb_params p = normalise(*params);
+        try {
+            load_molecule(ctx, n_nodes, xyz, n_tri, tri, n_atoms, atom_xyz, charge, p);
+        } catch (...) {
+            ctx->loaded = false;
+            throw;
+        }
+    });
+}
+
+afmpb_status afmpb_matvec_dev(afmpb_ctx *ctx, const double *x_dev, double *y_dev) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        require(x_dev && y_dev, ST_INVALID, "null argument");
+        to_morton(x_dev, ctx->perm.p, ctx->n, ctx->xa.p, ctx->stream);
+        ctx->matvec_m(ctx->xa.p, ctx->ya.p, false);
+        from_morton(ctx->ya.p, ctx->perm.p, ctx->n, y_dev, ctx->stream);
+    });
+}
+
+afmpb_status afmpb_matvec(afmpb_ctx *ctx, const double *x, double *y) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        require(x && y, ST_INVALID, "null argument");
+        const long long len = 2 * ctx->n;
+        for (long long i = 0; i < len; ++i)
+            require(std::isfinite(x[i]), ST_NUMERIC, "non-finite input vector");
+        ctx->tmp.upload(x, len, ctx->stream);
+        to_morton(ctx->tmp.p, ctx->perm.p, ctx->n, ctx->xa.p, ctx->stream);
+        ctx->matvec_m(ctx->xa.p, ctx->ya.p, false);
+        from_morton(ctx->ya.p, ctx->perm.p, ctx->n, ctx->tmp.p, ctx->stream);
+        ctx->tmp.download(y, len, ctx->stream);
+        ctx->sync();
+    });
+}
+
+afmpb_status afmpb_rhs(afmpb_ctx *ctx, double *b) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        require(b != nullptr, ST_INVALID, "null argument");
+        rhs(ctx->nodes(), ctx->n, ctx->ax.p, ctx->aq.p, ctx->na, ctx->prm.eps_s, ctx->bvec.p,
+            ctx->stream);
+        from_morton(ctx->bvec.p, ctx->perm.p, ctx->n, ctx->tmp.p, ctx->stream);
+        ctx->tmp.download(b, 2 * ctx->n, ctx->stream);
+        ctx->sync();
+    });
+}
+
+static double energy_of(afmpb_ctx *ctx, const double *x_morton) {
+    if (ctx->na == 0) return 0.0;
+    reaction_potential(ctx->nodes(), ctx->n, x_morton, ctx->ax.p, ctx->na, ctx->ebar,
+                       ctx->phi_at.p, ctx->stream);
+    std::vector<double> phi(ctx->na), q(ctx->na);
+    ctx->phi_at.download(phi.data(), ctx->na, ctx->stream);
+    ctx->aq.download(q.data(), ctx->na, ctx->stream);
+    ctx->sync();
+    double sum = 0.0;
+    for (long long k = 0; k < ctx->na; ++k) sum += q[k] * phi[k];
+    return 0.5 * sum * unit_scale();
+}
+
+afmpb_status afmpb_energy(afmpb_ctx *ctx, const double *x, double *energy) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        require(x && energy, ST_INVALID, "null argument");
+        ctx->tmp.upload(x, 2 * ctx->n, ctx->stream);
+        to_morton(ctx->tmp.p, ctx->perm.p, ctx->n, ctx->xa.p, ctx->stream);
+        *energy = energy_of(ctx, ctx->xa.p);
+    });
+}
+
+afmpb_status afmpb_solve(afmpb_ctx *ctx, const double *x0, double *f, double *h,
+                         double *energy, afmpb_solve_info *info) {
+    if (!ctx) return AFMPB_E_INVALID;
+    afmpb_solve_info inf{};
+    int conv_code = 0;
+    afmpb_status st = guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        auto t0 = std::chrono::steady_clock::now();
+        auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+        const long long n = ctx->n, len = 2 * n;
+        hipStream_t s = ctx->stream;
+        rhs(ctx->nodes(), n, ctx->ax.p, ctx->aq.p, ctx->na, ctx->prm.eps_s, ctx->bvec.p, s);
+        ctx->sync();
+        auto t1 = std::chrono::steady_clock::now();
+        bool xz = (x0 == nullptr);
+        if (!xz) {
+            for (long long i = 0; i < len; ++i)
+                require(std::isfinite(x0[i]), ST_NUMERIC, "non-finite warm start");
+            ctx->tmp.upload(x0, len, s);
+            to_morton(ctx->tmp.p, ctx->perm.p, n, ctx->xsol.p, s);
+        }
+        const afmpb_params &p = ctx->prm;
+        Gmres g;
+        if (p.precision == AFMPB_FP64) {
+            g = gmres(ctx, ctx->bvec.p, ctx->xsol.p, xz, p.rel_tol, p.abs_tol, p.restart,
+                      p.max_restarts, true);
+        } else {
+            // iterative refinement: single-precision operator inside, true
+            // residual of the double-precision operator outside
+            const double nb = std::sqrt(host_dot(ctx, ctx->bvec.p, ctx->bvec.p, len));
+            const double tol = p.rel_tol * nb + p.abs_tol;
+            if (xz) HIPCHK(hipMemsetAsync(ctx->xsol.p, 0, len * sizeof(double), s));
+            DBuf<double> r(len), d(len);
+            int steps = 0;
+            double rn = nb;
+            if (!xz) {
+                ctx->matvec_m(ctx->xsol.p, ctx->tmp.p, true);
+                axpby(1.0, ctx->bvec.p, -1.0, ctx->tmp.p, len, r.p, s);
+                rn = std::sqrt(host_dot(ctx, r.p, r.p, len));
+            } else {
+                HIPCHK(hipMemcpyAsync(r.p, ctx->bvec.p, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+            }
+            for (int it = 0; it < 8 && rn > tol; ++it) {
+                double inner_rel = std::max(tol / rn, 1e-6);
+                Gmres gi = gmres(ctx, r.p, d.p, true, inner_rel, 0.0, p.restart, p.max_restarts,
+                                 false);
+                g.iterations += gi.iterations;
+                g.restarts += gi.restarts;
+                g.inner += gi.inner;
+                axpby(1.0, ctx->xsol.p, 1.0, d.p, len, ctx->xsol.p, s);
+                ctx->matvec_m(ctx->xsol.p, ctx->tmp.p, true);
+                axpby(1.0, ctx->bvec.p, -1.0, ctx->tmp.p, len, r.p, s);
+                rn = std::sqrt(host_dot(ctx, r.p, r.p, len));
+                require(std::isfinite(rn), ST_NUMERIC, "non-finite residual");
+                ++steps;
+            }
+            g.converged = rn <= tol;
+            g.est = rn;
+            g.true_rel = nb > 0 ? rn / nb : rn;
+            inf.refinement_steps = steps;
+        }
+        auto t2 = std::chrono::steady_clock::now();
+        double E = energy_of(ctx, ctx->xsol.p);
+        auto t3 = std::chrono::steady_clock::now();
+        const double us = unit_scale();
+        from_morton(ctx->xsol.p, ctx->perm.p, n, ctx->tmp.p, s);
+        std::vector<double> xo(len);
+        ctx->tmp.download(xo.data(), len, s);
+        ctx->sync();
+        if (f) for (long long i = 0; i < n; ++i) f[i] = xo[i] * us;
+        if (h) for (long long i = 0; i < n; ++i) h[i] = xo[n + i] * us;
+        if (energy) *energy = E;
+        double nb = std::sqrt(host_dot(ctx, ctx->bvec.p, ctx->bvec.p, len));
+        inf.iterations = g.iterations;
+        inf.restarts = g.restarts;
+        inf.inner_products = g.inner;
+        inf.rel_residual_estimate = nb > 0 ? g.est / nb : g.est;
+        inf.true_rel_residual = g.true_rel;
+        inf.converged = g.converged ? 1 : 0;
+        inf.ms_setup = ctx->ms_setup;
+        inf.ms_rhs = ms(t0, t1);
+        inf.ms_gmres = ms(t1, t2);
+        inf.ms_energy = ms(t2, t3);
+        inf.ms_total = ms(t0, std::chrono::steady_clock::now());
+        if (!g.converged) conv_code = 1;
+    });
+    if (info) *info = inf;
+    if (st == AFMPB_OK && conv_code) {
+        ctx->err = "GMRES did not reach the tolerance";
+        return AFMPB_E_NOT_CONVERGED;
+    }
+    return st;
+}
+
+afmpb_status afmpb_tree_info(afmpb_ctx *ctx, afmpb_tree_sizes *out) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        require(out != nullptr, ST_INVALID, "null argument");
+        out->n_nodes = ctx->n;
+        out->n_boxes = ctx->tree.nbox;
+        out->n_levels = ctx->tree.nlev;
+        out->n_u = ctx->lists.n_u;
+        out->n_v = ctx->lists.n_v;
+        out->n_w = ctx->lists.n_w;
+        out->n_x = ctx->lists.n_x;
+        out->n_near = ctx->near.nnz;
+        out->n_p2p_pairs = ctx->lists.n_p2p_pairs;
+        out->n_m2l_pairs = ctx->lists.n_v;
+        out->order_p = ctx->prm.order_p;
+        out->leaf_cap = ctx->prm.leaf_cap;
+    });
+}
+
+afmpb_status afmpb_debug_tree(afmpb_ctx *ctx, const afmpb_tree_view *o) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        require(o != nullptr, ST_INVALID, "null argument");
+        hipStream_t s = ctx->stream;
+        const long long n = ctx->n, nb = ctx->tree.nbox;
+        const Tree &t = ctx->tree;
+        const Lists &L = ctx->lists;
+        if (o->keys) ctx->keys.download(o->keys, n, s);
+        if (o->perm) ctx->perm.download(o->perm, n, s);
+        if (o->level) t.level.download(o->level, nb, s);
+        if (o->parent) t.parent.download(o->parent, nb, s);
+        if (o->child_begin) t.child_begin.download(o->child_begin, nb, s);
+        if (o->n_child) t.n_child.download(o->n_child, nb, s);
+        if (o->pt_begin) t.pt_begin.download(o->pt_begin, nb, s);
+        if (o->pt_end) t.pt_end.download(o->pt_end, nb, s);
+        if (o->prefix) t.prefix.download(o->prefix, nb, s);
+        if (o->u_ptr) L.u_ptr.download(o->u_ptr, nb + 1, s);
+        if (o->u_idx) L.u_idx.download(o->u_idx, L.n_u, s);
+        if (o->v_ptr) L.v_ptr.download(o->v_ptr, nb + 1, s);
+        if (o->v_idx) L.v_idx.download(o->v_idx, L.n_v, s);
+        if (o->v_class) L.v_cls.download(o->v_class, L.n_v, s);
+        if (o->w_ptr) L.w_ptr.download(o->w_ptr, nb + 1, s);
+        if (o->w_idx) L.w_idx.download(o->w_idx, L.n_w, s);
+        if (o->x_ptr) L.x_ptr.download(o->x_ptr, nb + 1, s);
+        if (o->x_idx) L.x_idx.download(o->x_idx, L.n_x, s);
+        if (o->near_ptr) ctx->near.ptr.download(o->near_ptr, n + 1, s);
+        if (o->near_col) ctx->near.col.download(o->near_col, ctx->near.nnz, s);
+        if (o->near_delta) ctx->near.delta.download(o->near_delta, 4 * ctx->near.nnz, s);
+        ctx->sync();
+    });
+}
+
+afmpb_status afmpb_profile_enable(afmpb_ctx *ctx, int enable) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ctx->prof.flush();
+        if (enable) {
+            for (auto &e : ctx->prof.entries) { e.ms = 0; e.count = 0; }
+        }
+        ctx->prof.on = enable != 0;
+    });
+}
+
+afmpb_status afmpb_profile_read(afmpb_ctx *ctx, int idx, const char **name, double *total_ms,
+                                long long *launches) {
+    if (!ctx) return AFMPB_E_INVALID;
+    afmpb_status st = guarded(ctx, [&] { ctx->prof.flush(); });
+    if (st != AFMPB_OK) return st;
+    if (idx < 0 || idx >= (int)ctx->prof.entries.size()) return AFMPB_E_INVALID;
+    const auto &e = ctx->prof.entries[idx];
+    if (name) *name = e.name.c_str();
+    if (total_ms) *total_ms = e.ms;
+    if (launches) *launches = e.count;
+    return AFMPB_OK;
+}
+
+}  // extern "C"

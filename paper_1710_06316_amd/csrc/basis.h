@@ -1,0 +1,103 @@
+// Expansion bases of the FMM for the Laplace kernel 1/(4 pi r) and the
+// screened-Coulomb kernel e^{-kappa r}/(4 pi r) (Section 2, Eq. 3; the four
+// FMM calls of the Section 2 computation flow use these two kernels with
+// charge and dipole sources).
+//
+// Real orthonormal spherical harmonics Y_nm (m = -n..n, index k = n^2+n+m)
+// are generated as regular solid harmonics R_k(u) = |u|^n Y_nm(u/|u|) by the
+// three-term recurrence of the associated Legendre functions in Cartesian
+// form (no angles), starting from (x + i y)^m.
+//
+// Level-scaled bases at a level with box side s, u = v/s:
+//   Laplace   regular  Reg_k(v) = R_k(u)
+//             singular Sing_k(v) = R_k(u) / |u|^{2n+1}
+//   screened  regular  Reg_k(v) = [g_n(kappa|v|) / g_n(kappa s)] R_k(u),
+//                      g_n(x) = i_n(x)/x^n (i_n modified spherical Bessel,
+//                      first kind, i_0 = sinh(x)/x), an entire function of x^2
+//             singular Sing_k(v) = [k_n(kappa|v|) / k_n(kappa s)] R_k(u)/|u|^n,
+//                      k_0 = e^{-x}/x
+// Kernel expansions (|y-c| < |x-c|):
+//   1/(4 pi |x-y|)            = sum_k Reg_k(y-c) Sing_k(x-c) / ((2n+1) s)
+//   e^{-kappa|x-y|}/(4pi|x-y|)= sum_k Reg_k(y-c) Sing_k(x-c) kappa i_n(kappa s) k_n(kappa s)
+//
+// Every routine is templated on the scalar so that a dual number (value,
+// directional derivative) yields dipole moments and normal derivatives.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace afmpb {
+
+template <typename R>
+struct Dual {
+    R v, d;
+    __device__ Dual() : v(0), d(0) {}
+    __device__ Dual(R a) : v(a), d(0) {}
+    __device__ Dual(R a, R b) : v(a), d(b) {}
+};
+template <typename R> __device__ inline Dual<R> operator+(Dual<R> a, Dual<R> b) { return {a.v + b.v, a.d + b.d}; }
+template <typename R> __device__ inline Dual<R> operator-(Dual<R> a, Dual<R> b) { return {a.v - b.v, a.d - b.d}; }
+template <typename R> __device__ inline Dual<R> operator*(Dual<R> a, Dual<R> b) { return {a.v * b.v, a.v * b.d + a.d * b.v}; }
+template <typename R> __device__ inline Dual<R> operator*(R a, Dual<R> b) { return {a * b.v, a * b.d}; }
+template <typename R> __device__ inline Dual<R> operator*(Dual<R> b, R a) { return {a * b.v, a * b.d}; }
+template <typename R> __device__ inline Dual<R> operator/(Dual<R> a, R b) { return {a.v / b, a.d / b}; }
+
+template <typename R> __device__ inline R val(R a) { return a; }
+template <typename R> __device__ inline R val(Dual<R> a) { return a.v; }
+
+// Emits (k, n, value) for every regular solid harmonic of degree <= P, in
+// the order m = 0..P, n = m..P (for m > 0 the cosine entry k = n^2+n+m and
+// the sine entry k = n^2+n-m).  norm[k] are the orthonormalisation factors.
+template <typename R, typename S, typename F, typename NT>
+__device__ inline void for_each_regular(S x, S y, S z, int P, const NT *norm, F &&emit) {
+    S r2 = (x * x + y * y) + z * z;
+    S cm(R(1)), sm(R(0));   // Re/Im of (x + i y)^m
+    R dfact = R(1);         // (2m-1)!!
+    for (int m = 0; m <= P; ++m) {
+        S pc = cm * dfact, ps = sm * dfact;     // q_m^m
+        S qc(R(0)), qs(R(0));                   // q_{m-1}^m = 0
+        for (int n = m; n <= P; ++n) {
+            if (n > m) {
+                R a = R(2 * n - 1) / R(n - m), b = R(n + m - 1) / R(n - m);
+                S nc = a * (z * pc) - b * (r2 * qc);
+                S ns = a * (z * ps) - b * (r2 * qs);
+                qc = pc; qs = ps;
+                pc = nc; ps = ns;
+            }
+            int k0 = n * n + n;
+            if (m == 0) {
+                emit(k0, n, R(norm[k0]) * pc);
+            } else {
+                emit(k0 + m, n, R(norm[k0 + m]) * pc);
+                emit(k0 - m, n, R(norm[k0 - m]) * ps);
+            }
+        }
+        S c2 = cm * x - sm * y;
+        sm = cm * y + sm * x;
+        cm = c2;
+        dfact *= R(2 * m + 1);
+    }
+}
+
+// g_n(x) = i_n(x) / x^n for n = 0..P as functions of t = x^2: series for
+// n = P and P-1, then the downward recurrence g_{n-1} = t g_{n+1} + (2n+1) g_n.
+// inv_dfact[n] = 1/(2n+1)!!.
+template <typename R, typename S>
+__device__ inline S g_series(int n, S t, const R *inv_dfact) {
+    S sum(R(1)), term(R(1));
+    for (int k = 1; k < 200; ++k) {
+        term = term * t * (R(0.5) / (R(k) * R(2 * n + 2 * k + 1)));
+        sum = sum + term;
+        R tv = val(term), sv = val(sum);
+        if ((tv < R(0) ? -tv : tv) <= R(1e-17) * (sv < R(0) ? -sv : sv)) break;
+    }
+    return sum * inv_dfact[n];
+}
+
+template <typename R, typename S>
+__device__ inline void g_all(int P, S t, const R *inv_dfact, S *g) {
+    g[P] = g_series<R, S>(P, t, inv_dfact);
+    if (P >= 1) g[P - 1] = g_series<R, S>(P - 1, t, inv_dfact);
+    for (int n = P - 1; n >= 1; --n) g[n - 1] = t * g[n + 1] + R(2 * n + 1) * g[n];
+}
+
+}  // namespace afmpb

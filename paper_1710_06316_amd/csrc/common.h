@@ -1,0 +1,119 @@
+// Internal declarations shared by the HIP translation units of libafmpb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace afmpb {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+enum : int {
+    ST_INVALID = -1, ST_MESH = -2, ST_OOM = -3, ST_NOT_CONVERGED = -4,
+    ST_NUMERIC = -5, ST_DEVICE = -6, ST_STATE = -7
+};
+
+#define HIPCHK(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            throw ::afmpb::Error(e_ == hipErrorOutOfMemory ? ::afmpb::ST_OOM      \
+                                                           : ::afmpb::ST_DEVICE,  \
+                                 std::string(#call) + ": " + hipGetErrorString(e_)); \
+        }                                                                         \
+    } while (0)
+
+#define KCHK() HIPCHK(hipGetLastError())
+
+inline void require(bool ok, int code, const std::string &msg) {
+    if (!ok) throw Error(code, msg);
+}
+
+// ---------------------------------------------------------------------------
+// Device buffer (owning, move-only)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) count = 1;  // keep a valid pointer for empty arrays
+        HIPCHK(hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)));
+        n = count;
+    }
+    void release() {
+        if (p) { (void)hipFree(p); p = nullptr; n = 0; }
+    }
+    T *get() const { return p; }
+    void upload(const T *h, size_t count, hipStream_t s) {
+        if (count) HIPCHK(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    void download(T *h, size_t count, hipStream_t s) const {
+        if (count) HIPCHK(hipMemcpyAsync(h, p, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    }
+    void zero(size_t count, hipStream_t s) {
+        if (count) HIPCHK(hipMemsetAsync(p, 0, count * sizeof(T), s));
+    }
+};
+
+inline unsigned grid_for(long long n, int block) {
+    long long g = (n + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------------------
+// Primitives (prims.hip)
+// ---------------------------------------------------------------------------
+
+// Exclusive prefix sum of in[0..n) into out[0..n]; out[n] = total.  in and out
+// may alias.  Returns nothing; the caller reads out[n] when it needs the total.
+void exclusive_scan_i32(const int *in, int *out, long long n, hipStream_t s);
+void exclusive_scan_i64(const long long *in, long long *out, long long n, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
+// keys.  Sorted results end in keys/vals (the scratch buffers are used as
+// ping-pong storage and must hold n elements each).
+void radix_sort_pairs(unsigned long long *keys, int *vals,
+                      unsigned long long *tmp_keys, int *tmp_vals, long long n,
+                      int bits, hipStream_t s);
+
+// Sort each CSR row ascending (rows are short; one thread per row).
+void sort_rows_i32(const int *ptr, int *idx, long long nrows, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Profiling (api.hip)
+// ---------------------------------------------------------------------------
+
+struct Prof;
+struct ProfScope {
+    Prof *prof; int id; hipStream_t s;
+    ProfScope(Prof *p, const char *name, hipStream_t st);
+    ~ProfScope();
+};
+
+}  // namespace afmpb

@@ -1,0 +1,53 @@
+// Far field of the matvec: expansions, translation operators and the
+// P2M / M2M / M2L / L2L / L2P passes.
+#pragma once
+#include "geometry.h"
+
+namespace afmpb {
+
+constexpr int MAXP = 20;
+
+// Device-side view of the per-level basis constants.
+struct BasisDev {
+    int P, K;
+    int screened;              // 1: kernel 1 is e^{-kappa r}/(4 pi r); 0: both Laplace
+    double kappa;
+    const double *norm;        // [K]
+    const double *inv_dfact;   // [P+2]   1/(2n+1)!!
+    const double *ginv;        // [nlev][P+1]  1/g_n(kappa s_l)
+    const double *side;        // [nlev]
+};
+
+struct Fmm {
+    int P = 0, K = 0, nlev = 0;
+    double kappa = 0;
+    int screened = 0;
+    long long nkey = 0;                  // (nlev-2)*316 translation classes
+    DBuf<double> norm, inv_dfact, ginv, kinv, weight, side;
+    DBuf<double> T;                      // [2][nkey][K][K] M2L, row = local index
+    DBuf<double> Ut;                     // [2][nlev][8][K][K] transposed M2M operator
+    DBuf<float> T32, Ut32;               // single-precision copies
+    DBuf<int> pos_of;                    // V entry -> position in bucket order
+    BasisDev dev() const {
+        return BasisDev{P, K, screened, kappa, norm.p, inv_dfact.p, ginv.p, side.p};
+    }
+};
+
+void build_fmm_operators(const Tree &t, const Lists &L, int P, double kappa, Fmm &F,
+                         hipStream_t s);
+
+// Far-field evaluation for one matvec.  sf = a*f, sh = a*h per node (Morton
+// order).  Writes phi[4][n] = {Phi_L, dPhi_L/dn, Phi_Y, dPhi_Y/dn} at every
+// node (zero where no local expansion exists).
+template <typename R>
+struct FarWork {
+    R *M, *Lc, *Z, *phi;       // [nbox][2][K], [nbox][2][K], [n_v][2][K], [4][n]
+};
+
+template <typename R>
+void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd,
+               const R *px, const R *py, const R *pz, const R *pnx, const R *pny,
+               const R *pnz, const R *sf, const R *sh, double inv_ebar, long long n,
+               const FarWork<R> &w, struct Prof *prof, hipStream_t s);
+
+}  // namespace afmpb

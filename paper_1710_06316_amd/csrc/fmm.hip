@@ -1,0 +1,563 @@
+// Far field of the node-patch matvec (Section 2 computation flow, step 3b:
+// the single/double-layer Laplace and screened-Coulomb FMM evaluations, done
+// together in one traversal as the paper's ViewSet does, Section 3.1).
+//
+// Sources per node t: charge sigma_t = a_t h_t for both kernels, dipole
+// -a_t f_t n_t / ebar for the Laplace expansion and -a_t f_t n_t for the
+// screened one; targets: potential and normal derivative at every node.
+//
+// Translation operators are dense K x K matrices, one per (level, offset
+// class) for M2L and per (level, child octant) for M2M/L2L, obtained by
+// projecting the translated basis functions onto spherical harmonics with a
+// Gauss-Legendre x trapezoid product rule on a sphere and one batched GEMM.
+#include <algorithm>
+#include <cmath>
+
+#include "basis.h"
+#include "fmm.h"
+#include "prof.h"
+
+namespace afmpb {
+
+void gauss_legendre01(int nq, double *x, double *w);
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Regular level-scaled basis of kernel `kern` at v (box side s, level lev).
+template <typename R, typename S, typename F>
+__device__ inline void regular_basis(const BasisDev &B, int kern, int lev, S vx, S vy, S vz,
+                                     F &&emit) {
+    const R is = R(1.0 / B.side[lev]);
+    S ux = vx * is, uy = vy * is, uz = vz * is;
+    if (kern == 0 || !B.screened) {
+        for_each_regular<R>(ux, uy, uz, B.P, B.norm, [&](int k, int, S r) { emit(k, r); });
+    } else {
+        R ks = R(B.kappa * B.side[lev]);
+        S t = (ks * ks) * ((ux * ux + uy * uy) + uz * uz);
+        S g[MAXP + 1];
+        R inv_df[MAXP + 2];
+        for (int n = 0; n <= B.P + 1; ++n) inv_df[n] = R(B.inv_dfact[n]);
+        g_all<R, S>(B.P, t, inv_df, g);
+        const double *gi = B.ginv + (long long)lev * (B.P + 1);
+        for_each_regular<R>(ux, uy, uz, B.P, B.norm,
+                            [&](int k, int n, S r) { emit(k, r * (g[n] * R(gi[n]))); });
+    }
+}
+
+// ------------------------- operator construction ---------------------------
+
+struct MatDesc {
+    int kind;          // 0: M2L (singular source basis), 1: M2M/L2L (regular)
+    int kern, lev;     // kernel, basis level (M2L: box level; M2M: parent level)
+    double dx, dy, dz; // centre of the evaluation sphere relative to the basis origin
+    double rq;         // sphere radius
+    long long dst;     // offset of the K x K output
+};
+
+// Per-level constants: 1/g_n(kappa s), 1/k_n(kappa s) and the expansion
+// weights W_n (Laplace: 1/((2n+1) s); screened: kappa i_n(ks) k_n(ks)).
+__global__ void k_level_consts(BasisDev B, int nlev, double *ginv, double *kinv, double *W) {
+    int lev = blockIdx.x;
+    if (lev >= nlev || threadIdx.x != 0) return;
+    const int P = B.P;
+    const double s = B.side[lev];
+    for (int n = 0; n <= P; ++n) W[(0 * 64 + lev) * (P + 1) + n] = 1.0 / ((2.0 * n + 1.0) * s);
+    if (!B.screened) {
+        for (int n = 0; n <= P; ++n) {
+            ginv[lev * (P + 1) + n] = 1.0;
+            kinv[lev * (P + 1) + n] = 1.0;
+            W[(1 * 64 + lev) * (P + 1) + n] = 1.0 / ((2.0 * n + 1.0) * s);
+        }
+        return;
+    }
+    const double ks = B.kappa * s;
+    double g[MAXP + 1], kn[MAXP + 2];
+    g_all<double, double>(P, ks * ks, B.inv_dfact, g);
+    kn[0] = exp(-ks) / ks;
+    kn[1] = exp(-ks) * (1.0 + ks) / (ks * ks);
+    for (int n = 1; n < P; ++n) kn[n + 1] = kn[n - 1] + (2.0 * n + 1.0) / ks * kn[n];
+    for (int n = 0; n <= P; ++n) {
+        ginv[lev * (P + 1) + n] = 1.0 / g[n];
+        kinv[lev * (P + 1) + n] = 1.0 / kn[n];
+        W[(1 * 64 + lev) * (P + 1) + n] = B.kappa * (g[n] * pow(ks, (double)n)) * kn[n];
+    }
+}
+
+// Yw[q][k] = w_q Y_k(s_q) on the unit sphere.
+__global__ void k_sphere_table(BasisDev B, int Q, const double *dir, const double *wq,
+                               double *Yw) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q) return;
+    double x = dir[3 * q], y = dir[3 * q + 1], z = dir[3 * q + 2], w = wq[q];
+    const int K = B.K;
+    for_each_regular<double>(x, y, z, B.P, B.norm,
+                             [&](int k, int, double r) { Yw[(long long)q * K + k] = w * r; });
+}
+
+// B[m][q][j]: basis values of matrix m at quadrature point q, and row scales.
+__global__ void k_basis_samples(BasisDev B, const MatDesc *desc, int nmat, int Q,
+                                const double *dir, const double *kinv, const double *W,
+                                double *out, double *rowscale) {
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long long)nmat * Q) return;
+    int m = (int)(id / Q), q = (int)(id % Q);
+    const MatDesc d = desc[m];
+    const int K = B.K, P = B.P;
+    const double s = B.side[d.lev];
+    double vx = d.dx + d.rq * dir[3 * q], vy = d.dy + d.rq * dir[3 * q + 1],
+           vz = d.dz + d.rq * dir[3 * q + 2];
+    double *o = out + id * K;
+    if (d.kind == 1) {
+        regular_basis<double, double>(B, d.kern, d.lev, vx, vy, vz,
+                                      [&](int k, double r) { o[k] = r; });
+    } else {
+        double ux = vx / s, uy = vy / s, uz = vz / s;
+        double ru = sqrt((ux * ux + uy * uy) + uz * uz);
+        const double *Wl = W + ((long long)d.kern * 64 + d.lev) * (P + 1);
+        double rad[MAXP + 1];
+        if (d.kern == 0 || !B.screened) {
+            double ir = 1.0 / ru, f = ir;
+            for (int n = 0; n <= P; ++n) { rad[n] = f * Wl[n]; f *= ir * ir; }
+        } else {
+            double x = B.kappa * s * ru;
+            double k0 = exp(-x) / x, k1 = exp(-x) * (1.0 + x) / (x * x);
+            double km = k0, kc = k1, ir = 1.0 / ru, f = 1.0;
+            const double *ki = kinv + (long long)d.lev * (P + 1);
+            for (int n = 0; n <= P; ++n) {
+                double kn;
+                if (n == 0) kn = k0;
+                else if (n == 1) kn = k1;
+                else { double nx = km + (2.0 * (n - 1) + 1.0) / x * kc; km = kc; kc = nx; kn = kc; }
+                rad[n] = kn * ki[n] * f * Wl[n];
+                f *= ir;
+            }
+        }
+        for_each_regular<double>(ux, uy, uz, P, B.norm,
+                                 [&](int k, int n, double r) { o[k] = r * rad[n]; });
+    }
+    if (q == 0) {
+        // row scale 1/rho_n(rq) of the local basis (M2L only)
+        double g[MAXP + 1];
+        const bool scr = d.kind == 0 && d.kern == 1 && B.screened;
+        if (scr) g_all<double, double>(P, (B.kappa * d.rq) * (B.kappa * d.rq), B.inv_dfact, g);
+        for (int n = 0; n <= P; ++n) {
+            double sc = 1.0;
+            if (d.kind == 0) {
+                sc = 1.0 / pow(d.rq / s, (double)n);
+                if (scr) sc *= 1.0 / (g[n] * B.ginv[(long long)d.lev * (P + 1) + n]);
+            }
+            for (int mm = -n; mm <= n; ++mm) rowscale[(long long)m * K + n * n + n + mm] = sc;
+        }
+    }
+}
+
+// C[m][i][j] = rs[m][i] * sum_q A[q][i] Bm[m][q][j]  (16 x 16 LDS tiles).
+__global__ void k_project_gemm(const double *A, const double *Bm, const double *rs,
+                               const MatDesc *desc, int K, int Q, double *Tbase,
+                               double *Ubase) {
+    __shared__ double As[16][17], Bs[16][17];
+    int m = blockIdx.z;
+    int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+    int ty = threadIdx.y, tx = threadIdx.x;
+    const double *B = Bm + (long long)m * Q * K;
+    double acc = 0.0;
+    for (int q0 = 0; q0 < Q; q0 += 16) {
+        int q = q0 + ty;
+        As[ty][tx] = (q < Q && i0 + tx < K) ? A[(long long)q * K + i0 + tx] : 0.0;
+        Bs[ty][tx] = (q < Q && j0 + tx < K) ? B[(long long)q * K + j0 + tx] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) acc += As[kk][ty] * Bs[kk][tx];
+        __syncthreads();
+    }
+    int i = i0 + ty, j = j0 + tx;
+    double *C = desc[m].kind == 0 ? Tbase : Ubase;
+    if (i < K && j < K) C[desc[m].dst + (long long)i * K + j] = rs[(long long)m * K + i] * acc;
+}
+
+__global__ void k_to_float(const double *a, float *b, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+__global__ void k_inverse_perm(const int *perm, long long n, int *inv) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) inv[perm[i]] = (int)i;
+}
+
+// ------------------------------ far field ----------------------------------
+
+struct TreeDev {
+    const int *level, *parent, *cb, *nc, *ptb, *pte;
+    const unsigned long long *prefix;
+    const double *center;
+};
+
+template <typename R>
+__global__ void k_p2m(BasisDev B, TreeDev T, const int *leaf_ids, const R *px, const R *py,
+                      const R *pz, const R *pnx, const R *pny, const R *pnz, const R *sf,
+                      const R *sh, R inv_ebar, R *M) {
+    const int box = leaf_ids[blockIdx.x];
+    const int lev = T.level[box];
+    if (lev < 2) return;
+    const int lane = threadIdx.x, K = B.K;
+    const R cx = R(T.center[3 * box]), cy = R(T.center[3 * box + 1]), cz = R(T.center[3 * box + 2]);
+    const int b = T.ptb[box], e = T.pte[box];
+    for (int c0 = b; c0 < e; c0 += 64) {
+        int i = c0 + lane;
+        bool ok = i < e;
+        R vx = ok ? px[i] - cx : R(0), vy = ok ? py[i] - cy : R(0), vz = ok ? pz[i] - cz : R(0);
+        R nx = ok ? pnx[i] : R(0), ny = ok ? pny[i] : R(0), nz = ok ? pnz[i] : R(0);
+        R q = ok ? sh[i] : R(0);
+        R dmag = ok ? -sf[i] : R(0);
+        for (int kern = 0; kern < 2; ++kern) {
+            R dip = (kern == 0) ? dmag * inv_ebar : dmag;
+            R *Mb = M + ((long long)box * 2 + kern) * K;
+            regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, nx), Dual<R>(vy, ny),
+                                      Dual<R>(vz, nz), [&](int k, Dual<R> r) {
+                                          R tot = wave_sum(q * r.v + dip * r.d);
+                                          if (lane == 0) Mb[k] = (c0 == b) ? tot : Mb[k] + tot;
+                                      });
+        }
+    }
+}
+
+// M of non-leaf boxes of one level from their children: M_P[a] = sum_b U[a][b] M_c[b].
+template <typename R>
+__global__ void k_m2m(BasisDev B, TreeDev T, long long lb, long long le, const R *Ut,
+                      int nlev, R *M) {
+    long long box = lb + blockIdx.x;
+    if (box >= le || T.nc[box] == 0) return;
+    const int K = B.K, lev = T.level[box];
+    for (int kern = 0; kern < 2; ++kern) {
+        for (int a = threadIdx.x; a < K; a += blockDim.x) {
+            R acc = R(0);
+            for (int c = T.cb[box]; c < T.cb[box] + T.nc[box]; ++c) {
+                int oct = (int)(T.prefix[c] & 7ull);
+                const R *U = Ut + (((long long)kern * nlev + lev) * 8 + oct) * K * K;
+                const R *Mc = M + ((long long)c * 2 + kern) * K;
+                for (int bb = 0; bb < K; ++bb) acc += U[(long long)bb * K + a] * Mc[bb];
+            }
+            M[((long long)box * 2 + kern) * K + a] = acc;
+        }
+    }
+}
+
+// Batched M2L: one work item = up to 64 V entries of one (level, class).
+template <typename R>
+__global__ void k_m2l(int K, const int *item_key, const int *item_begin, const int *item_count,
+                      const int *pairs, const int *vidx, const R *Tops, long long nkey,
+                      const R *M, R *Z) {
+    extern __shared__ unsigned char smem_raw[];
+    R *Ms = reinterpret_cast<R *>(smem_raw);          // [K][64]
+    R *Tt = Ms + (long long)K * 64;                    // [16][K]
+    const int w = blockIdx.x, kern = blockIdx.y;
+    const int key = item_key[w], beg = item_begin[w], cnt = item_count[w];
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < K * 64; idx += blockDim.x) {
+        int k = idx / 64, i = idx % 64;
+        R v = R(0);
+        if (i < cnt) {
+            int src = vidx[pairs[beg + i]];
+            v = M[((long long)src * 2 + kern) * K + k];
+        }
+        Ms[idx] = v;
+    }
+    const R *Top = Tops + ((long long)kern * nkey + key) * K * K;
+    const int col = tid & 63, rg = tid >> 6;
+    for (int r0 = 0; r0 < K; r0 += 16) {
+        __syncthreads();
+        for (int idx = tid; idx < 16 * K; idx += blockDim.x) {
+            int rr = idx / K, k = idx % K;
+            Tt[idx] = (r0 + rr < K) ? Top[(long long)(r0 + rr) * K + k] : R(0);
+        }
+        __syncthreads();
+        R acc[4] = {R(0), R(0), R(0), R(0)};
+        for (int k = 0; k < K; ++k) {
+            R m = Ms[k * 64 + col];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] += Tt[(rg + 4 * j) * K + k] * m;
+        }
+        if (col < cnt) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int r = r0 + rg + 4 * j;
+                if (r < K) Z[((long long)(beg + col) * 2 + kern) * K + r] = acc[j];
+            }
+        }
+    }
+}
+
+// L[B] = sum over V(B) in list order of the M2L products (every box written).
+template <typename R>
+__global__ void k_m2l_reduce(int K, long long nbox, const int *vptr, const int *pos_of,
+                             const R *Z, R *L) {
+    long long box = blockIdx.x;
+    if (box >= nbox) return;
+    for (int idx = threadIdx.x; idx < 2 * K; idx += blockDim.x) {
+        R acc = R(0);
+        for (int q = vptr[box]; q < vptr[box + 1]; ++q) acc += Z[(long long)pos_of[q] * 2 * K + idx];
+        L[box * 2 * K + idx] = acc;
+    }
+}
+
+// Children of one level take their parent's local expansion:
+// L_c[b] += sum_a U[a][b] L_P[a].
+template <typename R>
+__global__ void k_l2l(BasisDev B, TreeDev T, long long lb, long long le, const R *Ut, int nlev,
+                      R *L) {
+    long long box = lb + blockIdx.x;
+    if (box >= le) return;
+    const int P = T.parent[box];
+    const int plev = T.level[P];
+    if (plev < 2) return;
+    const int K = B.K;
+    const int oct = (int)(T.prefix[box] & 7ull);
+    for (int kern = 0; kern < 2; ++kern) {
+        const R *U = Ut + (((long long)kern * nlev + plev) * 8 + oct) * K * K;
+        const R *Lp = L + ((long long)P * 2 + kern) * K;
+        for (int bb = threadIdx.x; bb < K; bb += blockDim.x) {
+            R acc = R(0);
+            for (int a = 0; a < K; ++a) acc += U[(long long)bb * K + a] * Lp[a];
+            L[((long long)box * 2 + kern) * K + bb] += acc;
+        }
+    }
+}
+
+template <typename R>
+__global__ void k_l2p(BasisDev B, TreeDev T, const int *leaf_ids, const R *px, const R *py,
+                      const R *pz, const R *pnx, const R *pny, const R *pnz, const R *L,
+                      long long n, R *phi) {
+    const int box = leaf_ids[blockIdx.x];
+    const int lev = T.level[box];
+    const int K = B.K;
+    const R cx = R(T.center[3 * box]), cy = R(T.center[3 * box + 1]), cz = R(T.center[3 * box + 2]);
+    for (int i = T.ptb[box] + threadIdx.x; i < T.pte[box]; i += blockDim.x) {
+        R out[4] = {R(0), R(0), R(0), R(0)};
+        if (lev >= 2) {
+            R vx = px[i] - cx, vy = py[i] - cy, vz = pz[i] - cz;
+            for (int kern = 0; kern < 2; ++kern) {
+                const R *Lb = L + ((long long)box * 2 + kern) * K;
+                R p = R(0), dp = R(0);
+                regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, pnx[i]), Dual<R>(vy, pny[i]),
+                                          Dual<R>(vz, pnz[i]), [&](int k, Dual<R> r) {
+                                              R l = Lb[k];
+                                              p += l * r.v;
+                                              dp += l * r.d;
+                                          });
+                out[2 * kern] = p;
+                out[2 * kern + 1] = dp;
+            }
+        }
+        for (int c = 0; c < 4; ++c) phi[c * n + i] = out[c];
+    }
+}
+
+}  // namespace
+
+void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, Fmm &F,
+                         hipStream_t s) {
+    require(P >= 2 && P <= MAXP, ST_INVALID, "expansion order must be in [2, 20]");
+    require(t.nlev <= 64, ST_INVALID, "too many tree levels");
+    F.P = P;
+    F.K = (P + 1) * (P + 1);
+    F.nlev = t.nlev;
+    F.kappa = kappa;
+    F.screened = kappa > 0.0;
+    const int K = F.K, nlev = t.nlev;
+    // orthonormalisation factors and 1/(2n+1)!!
+    std::vector<double> norm(K), idf(P + 2);
+    for (int n = 0; n <= P; ++n)
+        for (int m = -n; m <= n; ++m) {
+            int am = std::abs(m);
+            double r = 1.0;  // (n-|m|)!/(n+|m|)!
+            for (int j = n - am + 1; j <= n + am; ++j) r /= j;
+            double v = (2.0 * n + 1.0) / (4.0 * M_PI) * r;
+            norm[n * n + n + m] = std::sqrt(am == 0 ? v : 2.0 * v);
+        }
+    double df = 1.0;
+    for (int n = 0; n <= P + 1; ++n) { df *= (2.0 * n + 1.0); idf[n] = 1.0 / df; }
+    F.norm.alloc(K); F.norm.upload(norm.data(), K, s);
+    F.inv_dfact.alloc(P + 2); F.inv_dfact.upload(idf.data(), P + 2, s);
+    F.side.alloc(nlev); F.side.upload(t.side.data(), nlev, s);
+    F.ginv.alloc((size_t)nlev * (P + 1));
+    F.kinv.alloc((size_t)nlev * (P + 1));
+    F.weight.alloc((size_t)2 * 64 * (P + 1));
+    BasisDev B = F.dev();
+    k_level_consts<<<nlev, 1, 0, s>>>(B, nlev, F.ginv.p, F.kinv.p, F.weight.p);
+    KCHK();
+    // quadrature on the unit sphere: Gauss-Legendre in cos(theta) x trapezoid in phi
+    const int nth = (P + 57) / 2, nph = 2 * nth, Q = nth * nph;
+    std::vector<double> gx(nth), gw(nth), dir(3 * Q), wq(Q);
+    gauss_legendre01(nth, gx.data(), gw.data());
+    for (int i = 0; i < nth; ++i) {
+        double ct = 2.0 * gx[i] - 1.0, st = std::sqrt(std::fmax(0.0, 1.0 - ct * ct));
+        for (int j = 0; j < nph; ++j) {
+            double ph = 2.0 * M_PI * j / nph;
+            int q = i * nph + j;
+            dir[3 * q] = st * std::cos(ph);
+            dir[3 * q + 1] = st * std::sin(ph);
+            dir[3 * q + 2] = ct;
+            wq[q] = 2.0 * gw[i] * (2.0 * M_PI / nph);
+        }
+    }
+    DBuf<double> ddir(3 * Q), dwq(Q), Yw((size_t)Q * K);
+    ddir.upload(dir.data(), 3 * Q, s);
+    dwq.upload(wq.data(), Q, s);
+    k_sphere_table<<<grid_for(Q, 128), 128, 0, s>>>(B, Q, ddir.p, dwq.p, Yw.p);
+    KCHK();
+    // descriptors
+    std::vector<MatDesc> desc;
+    F.nkey = nlev > 2 ? (long long)(nlev - 2) * 316 : 0;
+    F.T.alloc((size_t)2 * std::max(F.nkey, 1ll) * K * K);
+    F.Ut.alloc((size_t)2 * nlev * 8 * K * K);
+    std::vector<int> offs;  // offset class -> (dx,dy,dz)
+    for (int dx = -3; dx <= 3; ++dx)
+        for (int dy = -3; dy <= 3; ++dy)
+            for (int dz = -3; dz <= 3; ++dz)
+                if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) > 1) {
+                    offs.push_back(dx); offs.push_back(dy); offs.push_back(dz);
+                }
+    for (int kern = 0; kern < 2; ++kern) {
+        for (int lev : Ls.levels_with_v) {
+            double sl = t.side[lev];
+            for (int c = 0; c < 316; ++c) {
+                // target centre minus source centre = -offset * side
+                double dx = -offs[3 * c] * sl, dy = -offs[3 * c + 1] * sl, dz = -offs[3 * c + 2] * sl;
+                double rq = 0.5 * std::sqrt(dx * dx + dy * dy + dz * dz);
+                long long key = (long long)(lev - 2) * 316 + c;
+                desc.push_back(MatDesc{0, kern, lev, dx, dy, dz, rq,
+                                       ((long long)kern * F.nkey + key) * K * K});
+            }
+        }
+        for (int lev = 2; lev + 1 < nlev; ++lev) {
+            double sc = t.side[lev + 1];
+            for (int o = 0; o < 8; ++o) {
+                double d[3];
+                for (int a = 0; a < 3; ++a) d[a] = 0.5 * sc * (((o >> a) & 1) ? 1.0 : -1.0);
+                desc.push_back(MatDesc{1, kern, lev, d[0], d[1], d[2], sc,
+                                       (((long long)kern * nlev + lev) * 8 + o) * K * K});
+            }
+        }
+    }
+    const long long per = (long long)Q * K;
+    const int batch = (int)std::max(1ll, std::min(256ll, (256ll << 20) / (per * 8)));
+    DBuf<double> samples((size_t)batch * per), rs((size_t)batch * K);
+    DBuf<MatDesc> ddesc(desc.size() + 1);
+    ddesc.upload(desc.data(), desc.size(), s);
+    for (size_t m0 = 0; m0 < desc.size(); m0 += batch) {
+        int nb = (int)std::min<size_t>(batch, desc.size() - m0);
+        k_basis_samples<<<grid_for((long long)nb * Q, 128), 128, 0, s>>>(
+            B, ddesc.p + m0, nb, Q, ddir.p, F.kinv.p, F.weight.p, samples.p, rs.p);
+        KCHK();
+        dim3 grid((K + 15) / 16, (K + 15) / 16, nb);
+        k_project_gemm<<<grid, dim3(16, 16), 0, s>>>(Yw.p, samples.p, rs.p, ddesc.p + m0, K, Q,
+                                                     F.T.p, F.Ut.p);
+        KCHK();
+    }
+    F.T32.alloc(F.T.n);
+    F.Ut32.alloc(F.Ut.n);
+    k_to_float<<<grid_for(F.T.n, 256), 256, 0, s>>>(F.T.p, F.T32.p, F.T.n);
+    KCHK();
+    k_to_float<<<grid_for(F.Ut.n, 256), 256, 0, s>>>(F.Ut.p, F.Ut32.p, F.Ut.n);
+    KCHK();
+    F.pos_of.alloc(Ls.n_v);
+    if (Ls.n_v) {
+        k_inverse_perm<<<grid_for(Ls.n_v, 256), 256, 0, s>>>(Ls.m2l_pairs.p, Ls.n_v, F.pos_of.p);
+        KCHK();
+    }
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+template <typename R>
+static const R *ops_T(const Fmm &F);
+template <>
+const double *ops_T<double>(const Fmm &F) { return F.T.p; }
+template <>
+const float *ops_T<float>(const Fmm &F) { return F.T32.p; }
+template <typename R>
+static const R *ops_U(const Fmm &F);
+template <>
+const double *ops_U<double>(const Fmm &F) { return F.Ut.p; }
+template <>
+const float *ops_U<float>(const Fmm &F) { return F.Ut32.p; }
+
+template <typename R>
+void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, const R *px,
+               const R *py, const R *pz, const R *pnx, const R *pny, const R *pnz, const R *sf,
+               const R *sh, double inv_ebar, long long n, const FarWork<R> &w, Prof *prof,
+               hipStream_t s) {
+    (void)nd;
+    BasisDev B = F.dev();
+    TreeDev T{t.level.p, t.parent.p, t.child_begin.p, t.n_child.p, t.pt_begin.p, t.pt_end.p,
+              t.prefix.p, t.center.p};
+    const int K = F.K;
+    if (L.n_v == 0) {
+        // no box has a far field: every pair is in a U/W/X list
+        HIPCHK(hipMemsetAsync(w.phi, 0, sizeof(R) * 4 * n, s));
+        return;
+    }
+    {
+        ProfScope ps(prof, "p2m", s);
+        k_p2m<R><<<(unsigned)L.n_leaves, 64, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
+                                                     sf, sh, R(inv_ebar), w.M);
+        KCHK();
+    }
+    {
+        ProfScope ps(prof, "m2m", s);
+        for (int lev = t.nlev - 2; lev >= 2; --lev) {
+            long long lb = t.level_start[lev], le = t.level_start[lev + 1];
+            k_m2m<R><<<(unsigned)(le - lb), 64, 0, s>>>(B, T, lb, le, ops_U<R>(F), F.nlev, w.M);
+            KCHK();
+        }
+    }
+    if (L.n_m2l_items > 0) {
+        ProfScope ps(prof, "m2l", s);
+        size_t sh_bytes = sizeof(R) * ((size_t)K * 64 + 16 * (size_t)K);
+        k_m2l<R><<<dim3((unsigned)L.n_m2l_items, 2), 256, sh_bytes, s>>>(
+            K, L.m2l_item_key.p, L.m2l_item_begin.p, L.m2l_item_count.p, L.m2l_pairs.p,
+            L.v_idx.p, ops_T<R>(F), F.nkey, w.M, w.Z);
+        KCHK();
+    }
+    {
+        ProfScope ps(prof, "m2l_reduce", s);
+        k_m2l_reduce<R><<<(unsigned)t.nbox, 128, 0, s>>>(K, t.nbox, L.v_ptr.p, F.pos_of.p, w.Z, w.Lc);
+        KCHK();
+    }
+    {
+        ProfScope ps(prof, "l2l", s);
+        for (int lev = 3; lev < t.nlev; ++lev) {
+            long long lb = t.level_start[lev], le = t.level_start[lev + 1];
+            k_l2l<R><<<(unsigned)(le - lb), 64, 0, s>>>(B, T, lb, le, ops_U<R>(F), F.nlev, w.Lc);
+            KCHK();
+        }
+    }
+    {
+        ProfScope ps(prof, "l2p", s);
+        k_l2p<R><<<(unsigned)L.n_leaves, 64, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
+                                                     w.Lc, n, w.phi);
+        KCHK();
+    }
+}
+
+template void far_field<double>(const Fmm &, const Tree &, const Lists &, const NodeSoA &,
+                                const double *, const double *, const double *, const double *,
+                                const double *, const double *, const double *, const double *,
+                                double, long long, const FarWork<double> &, Prof *, hipStream_t);
+template void far_field<float>(const Fmm &, const Tree &, const Lists &, const NodeSoA &,
+                               const float *, const float *, const float *, const float *,
+                               const float *, const float *, const float *, const float *,
+                               double, long long, const FarWork<float> &, Prof *, hipStream_t);
+
+}  // namespace afmpb

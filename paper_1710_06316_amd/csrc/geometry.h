@@ -1,0 +1,58 @@
+// Setup-phase declarations: patch geometry, Morton sort, octree and lists.
+#pragma once
+#include "common.h"
+
+namespace afmpb {
+
+// Node data in Morton order (structure of arrays).
+struct NodeSoA {
+    double *x, *y, *z, *nx, *ny, *nz, *area, *rho2;
+};
+
+void compute_geometry(const double *V, const int *T, long long n, long long m,
+                      double *tri_area, double *tri_n, int *inc_ptr, int *inc_tri,
+                      double *area, double *nrm, double *rho2, hipStream_t s);
+
+void morton_sort(const double *V, long long n, unsigned long long *keys, int *perm,
+                 double lo_out[3], double *scale_out, hipStream_t s);
+
+void gather_nodes(const double *V, const double *nrm, const double *area, const double *rho2,
+                  const int *perm, long long n, const NodeSoA &out, hipStream_t s);
+
+// Octree over Morton-sorted keys.  Boxes numbered by ascending (level,
+// prefix); level_start[l] is the first box of level l (size nlev + 1).
+struct Tree {
+    long long nbox = 0;
+    int nlev = 0;                      // number of levels present
+    std::vector<long long> level_start;
+    DBuf<int> level, parent, child_begin, n_child, pt_begin, pt_end;
+    DBuf<unsigned long long> prefix;
+    DBuf<double> center;               // [nbox][3] physical box centres
+    std::vector<double> side;          // physical side length per level
+};
+
+void build_tree(const unsigned long long *keys, long long n, int leaf_cap,
+                const double lo[3], double scale, Tree &t, hipStream_t s);
+
+// Interaction lists (CSR over boxes, entries ascending).
+struct Lists {
+    DBuf<int> coll, ncoll;             // [nbox][26] colleagues, count
+    DBuf<int> u_ptr, u_idx, v_ptr, v_idx, v_cls, w_ptr, w_idx, x_ptr, x_idx;
+    long long n_u = 0, n_v = 0, n_w = 0, n_x = 0;
+    // P2P: for each leaf the source boxes U(B) + W(B) + X(A), A = B and its
+    // ancestors; work items (leaf, first target point) of <= 64 targets.
+    DBuf<int> leaf_ids, p2p_ptr, p2p_src;
+    DBuf<int> item_box, item_begin;
+    long long n_leaves = 0, n_items = 0, n_p2p_src = 0;
+    long long n_p2p_pairs = 0;
+    // M2L: V entries grouped by (level, offset class) into chunks of <= 64.
+    DBuf<int> v_tgt;                   // [n_v] target box of each V entry
+    DBuf<int> m2l_pairs;               // [n_v] V-entry indices grouped by bucket
+    DBuf<int> m2l_item_key, m2l_item_begin, m2l_item_count;
+    long long n_m2l_items = 0;
+    std::vector<int> levels_with_v;    // levels that have V entries
+};
+
+void build_lists(const Tree &t, Lists &L, hipStream_t s);
+
+}  // namespace afmpb

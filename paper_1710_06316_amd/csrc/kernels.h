@@ -1,0 +1,84 @@
+// Point kernels of the boundary-integral equation (Section 2, Eq. 3) and the
+// four integrands of the patch coefficients (Eq. 6), for double and float.
+//
+// R = x - y with x the target node p (normal n_p = n0) and y the source point
+// on patch t (normal n_t = n).  G = 1/(4 pi r), u = e^{-kappa r}/(4 pi r).
+//   A-integrand  G - u                         = -expm1(-s)/(4 pi r)
+//   B-integrand  dG/dn/ebar - du/dn            = (R.n)/(4 pi r^3) (1/ebar - e(1+s))
+//   C-integrand  dG/dn0 - du/dn0/ebar          = -(R.n0)/(4 pi r^3) (1 - e(1+s)/ebar)
+//   D-integrand  (d2G/dn0dn - d2u/dn0dn)/ebar  = [(n0.n) a(s)/r^3 - (R.n0)(R.n) b(s)/r^5]
+//                                                / (4 pi ebar)
+// with s = kappa r, e = e^{-s}, a(s) = 1 - e(1+s), b(s) = 3 - e(3+3s+s^2).
+// a and b are taken from their Taylor series below s = 0.1 and from
+// expm1-based forms above, so the Laplace/screened difference never cancels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace afmpb {
+
+constexpr double INV_4PI = 0.079577471545947667884441881686257181;
+
+// Taylor coefficients: a(s) = sum_{k>=2} (-1)^k (k-1) s^k/k!,
+//                      b(s) = -sum_{k>=2} (-1)^k (k-1)(k-3) s^k/k!.
+struct DiffSeries {
+    double a[11], b[11];
+    constexpr DiffSeries() : a(), b() {
+        double fact = 1.0;
+        for (int k = 1; k <= 10; ++k) {
+            fact *= k;
+            double sg = (k & 1) ? -1.0 : 1.0;
+            a[k] = (k >= 2) ? sg * (k - 1) / fact : 0.0;
+            b[k] = (k >= 2) ? -sg * (double)((k - 1) * (k - 3)) / fact : 0.0;
+        }
+    }
+};
+
+template <typename R>
+__device__ inline void diff_factors(R s, R e, R &fa, R &fb) {
+    constexpr DiffSeries S;
+    if (s < R(0.1)) {
+        R pa = R(S.a[10]), pb = R(S.b[10]);
+#pragma unroll
+        for (int k = 9; k >= 2; --k) {
+            pa = pa * s + R(S.a[k]);
+            pb = pb * s + R(S.b[k]);
+        }
+        fa = pa * s * s;
+        fb = pb * s * s;
+    } else {
+        R em1 = -expm1(-s);                  // 1 - e
+        fa = em1 - s * e;                    // 1 - e - s e
+        fb = R(3) * em1 - e * (R(3) * s + s * s);
+    }
+}
+
+// The four integrands (without the patch area / quadrature weight).
+template <typename R>
+struct Abcd {
+    R A, B, C, D;
+};
+
+template <typename R>
+__device__ inline Abcd<R> abcd_point(R rx, R ry, R rz, R n0x, R n0y, R n0z, R nx, R ny,
+                                     R nz, R kappa, R inv_ebar) {
+    R r2 = (rx * rx + ry * ry) + rz * rz;
+    R r = sqrt(r2);
+    R ir = R(1) / r;
+    R ir3 = ir * ir * ir;
+    R s = kappa * r;
+    R e = exp(-s);
+    R Rn = (rx * nx + ry * ny) + rz * nz;
+    R Rn0 = (rx * n0x + ry * n0y) + rz * n0z;
+    R n0n = (n0x * nx + n0y * ny) + n0z * nz;
+    R fa, fb;
+    diff_factors(s, e, fa, fb);
+    R e1 = e * (R(1) + s);
+    Abcd<R> o;
+    o.A = -expm1(-s) * ir * R(INV_4PI);
+    o.B = Rn * ir3 * R(INV_4PI) * (inv_ebar - e1);
+    o.C = -Rn0 * ir3 * R(INV_4PI) * (R(1) - e1 * inv_ebar);
+    o.D = (n0n * fa * ir3 - Rn0 * Rn * fb * ir3 * ir * ir) * R(INV_4PI) * inv_ebar;
+    return o;
+}
+
+}  // namespace afmpb

@@ -1,0 +1,37 @@
+// The per-iteration operator y = M x of Eq. (5), assembled from the far
+// field (fmm.hip), P2P, the near-set corrections and the identity term.
+#pragma once
+#include "fmm.h"
+#include "near.h"
+
+namespace afmpb {
+
+template <typename R>
+struct NodeR {
+    const R *x, *y, *z, *nx, *ny, *nz;
+};
+
+template <typename R>
+struct MatvecPlan {
+    long long n = 0;
+    const Tree *tree = nullptr;
+    const Lists *lists = nullptr;
+    const Fmm *fmm = nullptr;
+    const NearSet *near = nullptr;
+    NodeSoA nd64{};            // double node data (Morton order)
+    NodeR<R> nd{};             // node data in the working precision
+    const double *area = nullptr;
+    double kappa = 0, inv_ebar = 0, alpha = 0;
+    R *sf = nullptr, *sh = nullptr, *pf = nullptr, *ph = nullptr;
+    FarWork<R> far{};
+};
+
+// x, y: [2n] in Morton order, double.  y must not alias x.
+template <typename R>
+void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *prof,
+                    hipStream_t s);
+
+void to_morton(const double *in, const int *perm, long long n, double *out, hipStream_t s);
+void from_morton(const double *in, const int *perm, long long n, double *out, hipStream_t s);
+
+}  // namespace afmpb

@@ -1,0 +1,18 @@
+// Near set (CSR over Morton-ordered rows) with patch-minus-point corrections.
+#pragma once
+#include "geometry.h"
+
+namespace afmpb {
+
+struct NearSet {
+    DBuf<long long> ptr;     // [n+1]
+    DBuf<int> col;           // [nnz] ascending per row, Morton positions
+    DBuf<double> delta;      // [nnz][4] corrections of {A, B, C, D}
+    long long nnz = 0;
+};
+
+void build_near(const NodeSoA &nd, long long n, double eta, const double *V, const int *T,
+                const double *tri_n, const int *inc_ptr, const int *inc_tri, const int *perm,
+                double kappa, double ebar, NearSet &out, hipStream_t s);
+
+}  // namespace afmpb

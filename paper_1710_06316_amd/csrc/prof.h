@@ -1,0 +1,29 @@
+// Per-phase timing with HIP events on the context stream.
+#pragma once
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace afmpb {
+
+struct Prof {
+    bool on = false;
+    struct Entry {
+        std::string name;
+        double ms = 0;
+        long long count = 0;
+    };
+    std::vector<Entry> entries;
+    std::map<std::string, int> index;
+    // (entry, start, stop) events awaiting readout
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
+    std::vector<hipEvent_t> pool;
+    int id_of(const char *name);
+    hipEvent_t take();
+    void flush();   // synchronises on pending events and accumulates
+    ~Prof();
+};
+
+}  // namespace afmpb

@@ -1,0 +1,527 @@
+// Adaptive octree over Morton-sorted points and the four interaction lists of
+// the adaptive FMM (list-1 U, list-2 V, list-3 W, list-4 X; Section 3.2 of
+// the paper handles list-3 like list-1 by direct evaluation, as done here for
+// both W and X).  Level-synchronous construction, integer geometry only.
+#include <algorithm>
+
+#include "geometry.h"
+
+namespace afmpb {
+
+namespace {
+
+constexpr int MAXLEVEL = 21;
+constexpr int MAXCOLL = 26;
+constexpr int DFS_STACK = 128;
+
+// ----------------------------- split ---------------------------------------
+
+__global__ void k_split_flags(const unsigned long long *__restrict__ keys, long long n,
+                              const int *__restrict__ box_of, const int *__restrict__ ptb,
+                              const int *__restrict__ pte, int level, int cap,
+                              int *__restrict__ flag) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = box_of[i];
+    int f = 0;
+    if (b >= 0 && level < MAXLEVEL && pte[b] - ptb[b] > cap) {
+        int sh = 3 * (MAXLEVEL - level - 1);
+        f = (i == ptb[b]) || ((keys[i] >> sh) != (keys[i - 1] >> sh));
+    }
+    flag[i] = f;
+}
+
+__global__ void k_make_children(const unsigned long long *__restrict__ keys, long long n,
+                                int *__restrict__ box_of, const int *__restrict__ flag,
+                                const int *__restrict__ pos, const int *__restrict__ ptb_old,
+                                const int *__restrict__ pte_old, int level, int cap,
+                                long long base, int *lev, unsigned long long *prefix,
+                                int *parent, int *ptb, int *child_begin, int *n_child) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = box_of[i];
+    bool split = b >= 0 && level < MAXLEVEL && pte_old[b] - ptb_old[b] > cap;
+    if (!split) {
+        box_of[i] = -1;
+        return;
+    }
+    int sh = 3 * (MAXLEVEL - level - 1);
+    long long id = base + pos[i] + flag[i] - 1;
+    if (flag[i]) {
+        lev[id] = level + 1;
+        prefix[id] = keys[i] >> sh;
+        parent[id] = b;
+        ptb[id] = (int)i;
+        child_begin[id] = -1;
+        n_child[id] = 0;
+    }
+    box_of[i] = (int)id;
+}
+
+__global__ void k_finish_children(long long base, long long cnt, const int *__restrict__ parent,
+                                  const int *__restrict__ ptb, int *pte, int *child_begin,
+                                  int *n_child) {
+    long long k = base + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= base + cnt) return;
+    int p = parent[k];
+    bool last = (k + 1 == base + cnt) || parent[k + 1] != p;
+    pte[k] = last ? pte[p] : ptb[k + 1];
+    if (k == base || parent[k - 1] != p) {
+        child_begin[p] = (int)k;
+        int c = 1;
+        while (k + c < base + cnt && parent[k + c] == p) ++c;
+        n_child[p] = c;
+    }
+}
+
+__global__ void k_box_centers(long long nbox, const int *__restrict__ lev,
+                              const unsigned long long *__restrict__ prefix, double lx, double ly,
+                              double lz, double inv_scale, double *center) {
+    long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    int l = lev[b];
+    unsigned long long p = prefix[b];
+    long long ia[3] = {0, 0, 0};
+    for (int k = 0; k < l; ++k)
+        for (int a = 0; a < 3; ++a) ia[a] |= (long long)((p >> (3 * k + a)) & 1ull) << k;
+    long long side = 1ll << (MAXLEVEL - l);
+    const double lo[3] = {lx, ly, lz};
+    for (int a = 0; a < 3; ++a)
+        center[3 * b + a] = lo[a] + ((double)(ia[a] * side) + 0.5 * (double)side) * inv_scale;
+}
+
+template <typename T>
+void grow(DBuf<T> &buf, size_t need, size_t used, hipStream_t s) {
+    if (buf.n >= need) return;
+    DBuf<T> nb(std::max(need, buf.n * 2));
+    if (used) HIPCHK(hipMemcpyAsync(nb.p, buf.p, used * sizeof(T), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    buf = std::move(nb);
+}
+
+// ----------------------------- lists ---------------------------------------
+
+struct TreeView {
+    const int *lev, *parent, *cb, *nc, *ptb, *pte;
+    const unsigned long long *prefix;
+    const int *coll, *ncoll;
+};
+
+__device__ inline void anchor_of(const TreeView &t, int b, long long a[3]) {
+    int l = t.lev[b];
+    unsigned long long p = t.prefix[b];
+    a[0] = a[1] = a[2] = 0;
+    for (int k = 0; k < l; ++k)
+        for (int d = 0; d < 3; ++d) a[d] |= (long long)((p >> (3 * k + d)) & 1ull) << k;
+    for (int d = 0; d < 3; ++d) a[d] <<= (MAXLEVEL - l);
+}
+
+__device__ inline bool is_ancestor(const TreeView &t, int a, int b) {
+    int la = t.lev[a], lb = t.lev[b];
+    return la < lb && (t.prefix[b] >> (3 * (lb - la))) == t.prefix[a];
+}
+
+// Distinct boxes, neither an ancestor of the other, closed cubes touching.
+__device__ inline bool adj(const TreeView &t, int a, int b) {
+    if (a == b || is_ancestor(t, a, b) || is_ancestor(t, b, a)) return false;
+    long long pa[3], pb[3];
+    anchor_of(t, a, pa);
+    anchor_of(t, b, pb);
+    long long sa = 1ll << (MAXLEVEL - t.lev[a]), sb = 1ll << (MAXLEVEL - t.lev[b]);
+    for (int d = 0; d < 3; ++d)
+        if (!(pa[d] <= pb[d] + sb && pb[d] <= pa[d] + sa)) return false;
+    return true;
+}
+
+__device__ inline bool is_leaf(const TreeView &t, int b) { return t.nc[b] == 0; }
+
+__global__ void k_colleagues(TreeView t, long long begin, long long end, int *coll, int *ncoll) {
+    long long B = begin + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= end) return;
+    int c[MAXCOLL];
+    int nc = 0;
+    int P = t.parent[B];
+    if (P >= 0) {
+        // siblings, then children of the parent's colleagues
+        for (int k = -1; k < t.ncoll[P]; ++k) {
+            int Q = (k < 0) ? P : t.coll[(long long)P * MAXCOLL + k];
+            for (int j = 0; j < t.nc[Q]; ++j) {
+                int C = t.cb[Q] + j;
+                if (C != B && adj(t, (int)B, C) && nc < MAXCOLL) c[nc++] = C;
+            }
+        }
+    }
+    for (int i = 1; i < nc; ++i) {
+        int v = c[i], j = i - 1;
+        while (j >= 0 && c[j] > v) { c[j + 1] = c[j]; --j; }
+        c[j + 1] = v;
+    }
+    for (int i = 0; i < nc; ++i) coll[B * MAXCOLL + i] = c[i];
+    ncoll[B] = nc;
+}
+
+struct CountEmit {
+    int u = 0, v = 0, w = 0;
+    __device__ void U(int) { ++u; }
+    __device__ void V(int) { ++v; }
+    __device__ void W(int) { ++w; }
+};
+
+struct FillEmit {
+    int *u, *v, *w;
+    __device__ void U(int c) { *u++ = c; }
+    __device__ void V(int c) { *v++ = c; }
+    __device__ void W(int c) { *w++ = c; }
+};
+
+// Enumerates U(B) (leaf), W(B) (leaf) and V(B) (level >= 2) in an arbitrary
+// order; rows are sorted afterwards.  Returns false on stack overflow.
+template <class E>
+__device__ bool enumerate(const TreeView &t, int B, E &e) {
+    bool ok = true;
+    if (is_leaf(t, B)) {
+        e.U(B);
+        int stack[DFS_STACK];
+        for (int k = 0; k < t.ncoll[B]; ++k) {
+            int C = t.coll[(long long)B * MAXCOLL + k];
+            if (is_leaf(t, C)) { e.U(C); continue; }
+            int sp = 0;
+            stack[sp++] = C;
+            while (sp > 0) {
+                int Q = stack[--sp];
+                for (int j = 0; j < t.nc[Q]; ++j) {
+                    int D = t.cb[Q] + j;
+                    if (adj(t, B, D)) {
+                        if (is_leaf(t, D)) e.U(D);
+                        else if (sp < DFS_STACK) stack[sp++] = D;
+                        else ok = false;
+                    } else {
+                        e.W(D);
+                    }
+                }
+            }
+        }
+        // coarser adjacent leaves: leaf colleagues of proper ancestors
+        for (int A = t.parent[B]; A >= 0; A = t.parent[A])
+            for (int k = 0; k < t.ncoll[A]; ++k) {
+                int C = t.coll[(long long)A * MAXCOLL + k];
+                if (is_leaf(t, C) && adj(t, B, C)) e.U(C);
+            }
+    }
+    if (t.lev[B] >= 2) {
+        int P = t.parent[B];
+        for (int k = 0; k < t.ncoll[P]; ++k) {
+            int Q = t.coll[(long long)P * MAXCOLL + k];
+            for (int j = 0; j < t.nc[Q]; ++j) {
+                int C = t.cb[Q] + j;
+                if (!adj(t, B, C)) e.V(C);
+            }
+        }
+    }
+    return ok;
+}
+
+__global__ void k_list_count(TreeView t, long long nbox, int *cu, int *cv, int *cw, int *err) {
+    long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nbox) return;
+    CountEmit e;
+    if (!enumerate(t, (int)B, e)) atomicOr(err, 1);
+    cu[B] = e.u;
+    cv[B] = e.v;
+    cw[B] = e.w;
+}
+
+__global__ void k_list_fill(TreeView t, long long nbox, const int *pu, const int *pv,
+                            const int *pw, int *iu, int *iv, int *iw) {
+    long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nbox) return;
+    FillEmit e{iu + pu[B], iv + pv[B], iw + pw[B]};
+    enumerate(t, (int)B, e);
+}
+
+// Offset class of C relative to B: rank of (anchor_C - anchor_B)/side in
+// [-3,3]^3 minus [-1,1]^3, ascending lexicographic (dx, dy, dz).
+__global__ void k_v_class(TreeView t, long long nbox, const int *vptr, const int *vidx,
+                          int *vcls, int *vtgt) {
+    long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nbox) return;
+    long long ab[3];
+    anchor_of(t, (int)B, ab);
+    long long side = 1ll << (MAXLEVEL - t.lev[B]);
+    for (int q = vptr[B]; q < vptr[B + 1]; ++q) {
+        long long ac[3];
+        anchor_of(t, vidx[q], ac);
+        int d[3];
+        for (int a = 0; a < 3; ++a) d[a] = (int)((ac[a] - ab[a]) / side);
+        int full = ((d[0] + 3) * 7 + (d[1] + 3)) * 7 + (d[2] + 3);
+        // number of excluded (|d|_inf <= 1) positions that precede `full`
+        int excl = 0;
+        for (int x = -1; x <= 1; ++x)
+            for (int y = -1; y <= 1; ++y)
+                for (int z = -1; z <= 1; ++z)
+                    if (((x + 3) * 7 + (y + 3)) * 7 + (z + 3) < full) ++excl;
+        vcls[q] = full - excl;
+        vtgt[q] = (int)B;
+    }
+}
+
+__global__ void k_x_count(long long nbox, const int *wptr, const int *widx, int *cnt) {
+    long long C = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (C >= nbox) return;
+    for (int q = wptr[C]; q < wptr[C + 1]; ++q) atomicAdd(&cnt[widx[q]], 1);
+}
+
+__global__ void k_x_fill(long long nbox, const int *wptr, const int *widx, const int *xptr,
+                         int *cursor, int *xidx) {
+    long long C = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (C >= nbox) return;
+    for (int q = wptr[C]; q < wptr[C + 1]; ++q) {
+        int B = widx[q];
+        xidx[xptr[B] + atomicAdd(&cursor[B], 1)] = (int)C;
+    }
+}
+
+__global__ void k_leaf_flags(TreeView t, long long nbox, int *flag) {
+    long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nbox) return;
+    flag[B] = is_leaf(t, (int)B);
+}
+
+__global__ void k_leaf_collect(long long nbox, const int *flag, const int *pos, int *leaf_ids) {
+    long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nbox) return;
+    if (flag[B]) leaf_ids[pos[B]] = (int)B;
+}
+
+// Per leaf: number of P2P source boxes, work items, and point pairs.
+__global__ void k_p2p_count(TreeView t, long long nleaf, const int *leaf_ids, const int *uptr,
+                            const int *uidx, const int *wptr, const int *widx, const int *xptr,
+                            const int *xidx, int *nsrc, int *nitem, long long *npairs) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaf) return;
+    int B = leaf_ids[i];
+    int cnt = (uptr[B + 1] - uptr[B]) + (wptr[B + 1] - wptr[B]);
+    long long src_pts = 0;
+    for (int q = uptr[B]; q < uptr[B + 1]; ++q) src_pts += t.pte[uidx[q]] - t.ptb[uidx[q]];
+    for (int q = wptr[B]; q < wptr[B + 1]; ++q) src_pts += t.pte[widx[q]] - t.ptb[widx[q]];
+    for (int A = B; A >= 0; A = t.parent[A]) {
+        cnt += xptr[A + 1] - xptr[A];
+        for (int q = xptr[A]; q < xptr[A + 1]; ++q) src_pts += t.pte[xidx[q]] - t.ptb[xidx[q]];
+    }
+    long long npt = t.pte[B] - t.ptb[B];
+    nsrc[i] = cnt;
+    nitem[i] = (int)((npt + 63) / 64);
+    npairs[i] = npt * src_pts - npt;
+}
+
+__global__ void k_p2p_fill(TreeView t, long long nleaf, const int *leaf_ids, const int *uptr,
+                           const int *uidx, const int *wptr, const int *widx, const int *xptr,
+                           const int *xidx, const int *sptr, int *src, const int *iptr,
+                           int *item_box, int *item_begin) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaf) return;
+    int B = leaf_ids[i];
+    int o = sptr[i];
+    for (int q = uptr[B]; q < uptr[B + 1]; ++q) src[o++] = uidx[q];
+    for (int q = wptr[B]; q < wptr[B + 1]; ++q) src[o++] = widx[q];
+    for (int A = B; A >= 0; A = t.parent[A])
+        for (int q = xptr[A]; q < xptr[A + 1]; ++q) src[o++] = xidx[q];
+    int k = iptr[i];
+    for (int b = t.ptb[B]; b < t.pte[B]; b += 64) {
+        item_box[k] = (int)i;
+        item_begin[k] = b;
+        ++k;
+    }
+}
+
+__global__ void k_m2l_keys(long long nv, const int *vtgt, const int *vcls, const int *lev,
+                           unsigned long long *keys, int *idx) {
+    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nv) return;
+    keys[q] = (unsigned long long)((lev[vtgt[q]] - 2) * 316 + vcls[q]);
+    idx[q] = (int)q;
+}
+
+template <typename T>
+T read_scalar(const T *p, hipStream_t s) {
+    T v;
+    HIPCHK(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return v;
+}
+
+}  // namespace
+
+void build_tree(const unsigned long long *keys, long long n, int cap, const double lo[3],
+                double scale, Tree &t, hipStream_t s) {
+    size_t capb = (size_t)(2 * n / std::max(cap, 1) + 64);
+    t.level.alloc(capb); t.parent.alloc(capb); t.child_begin.alloc(capb);
+    t.n_child.alloc(capb); t.pt_begin.alloc(capb); t.pt_end.alloc(capb);
+    t.prefix.alloc(capb);
+    {
+        int root_i[6] = {0, -1, -1, 0, 0, (int)n};  // level parent cb nc ptb pte
+        unsigned long long z = 0;
+        t.level.upload(&root_i[0], 1, s); t.parent.upload(&root_i[1], 1, s);
+        t.child_begin.upload(&root_i[2], 1, s); t.n_child.upload(&root_i[3], 1, s);
+        t.pt_begin.upload(&root_i[4], 1, s); t.pt_end.upload(&root_i[5], 1, s);
+        t.prefix.upload(&z, 1, s);
+    }
+    DBuf<int> box_of(n), flag(n + 1), pos(n + 1);
+    box_of.zero(n, s);
+    t.level_start.assign(1, 0);
+    t.level_start.push_back(1);
+    long long nbox = 1;
+    for (int l = 0; l < MAXLEVEL; ++l) {
+        k_split_flags<<<grid_for(n, 256), 256, 0, s>>>(keys, n, box_of.p, t.pt_begin.p,
+                                                       t.pt_end.p, l, cap, flag.p);
+        KCHK();
+        exclusive_scan_i32(flag.p, pos.p, n, s);
+        long long cnt = read_scalar(pos.p + n, s);
+        if (cnt == 0) break;
+        size_t need = (size_t)(nbox + cnt);
+        grow(t.level, need, nbox, s); grow(t.parent, need, nbox, s);
+        grow(t.child_begin, need, nbox, s); grow(t.n_child, need, nbox, s);
+        grow(t.pt_begin, need, nbox, s); grow(t.pt_end, need, nbox, s);
+        grow(t.prefix, need, nbox, s);
+        k_make_children<<<grid_for(n, 256), 256, 0, s>>>(
+            keys, n, box_of.p, flag.p, pos.p, t.pt_begin.p, t.pt_end.p, l, cap, nbox,
+            t.level.p, t.prefix.p, t.parent.p, t.pt_begin.p, t.child_begin.p, t.n_child.p);
+        KCHK();
+        k_finish_children<<<grid_for(cnt, 256), 256, 0, s>>>(nbox, cnt, t.parent.p, t.pt_begin.p,
+                                                             t.pt_end.p, t.child_begin.p,
+                                                             t.n_child.p);
+        KCHK();
+        nbox += cnt;
+        t.level_start.push_back(nbox);
+    }
+    t.nbox = nbox;
+    t.nlev = (int)t.level_start.size() - 1;
+    t.center.alloc(3 * nbox);
+    k_box_centers<<<grid_for(nbox, 256), 256, 0, s>>>(nbox, t.level.p, t.prefix.p, lo[0], lo[1],
+                                                      lo[2], 1.0 / scale, t.center.p);
+    KCHK();
+    t.side.resize(t.nlev);
+    for (int l = 0; l < t.nlev; ++l) t.side[l] = (double)(1ll << (MAXLEVEL - l)) / scale;
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+void build_lists(const Tree &t, Lists &L, hipStream_t s) {
+    const long long nb = t.nbox;
+    L.coll.alloc((size_t)nb * MAXCOLL);
+    L.ncoll.alloc(nb);
+    L.ncoll.zero(nb, s);
+    TreeView tv{t.level.p, t.parent.p, t.child_begin.p, t.n_child.p, t.pt_begin.p, t.pt_end.p,
+                t.prefix.p, L.coll.p, L.ncoll.p};
+    for (int l = 1; l < t.nlev; ++l) {
+        long long b = t.level_start[l], e = t.level_start[l + 1];
+        k_colleagues<<<grid_for(e - b, 128), 128, 0, s>>>(tv, b, e, L.coll.p, L.ncoll.p);
+        KCHK();
+    }
+    DBuf<int> cu(nb + 1), cv(nb + 1), cw(nb + 1), err(1);
+    err.zero(1, s);
+    k_list_count<<<grid_for(nb, 128), 128, 0, s>>>(tv, nb, cu.p, cv.p, cw.p, err.p);
+    KCHK();
+    require(read_scalar(err.p, s) == 0, ST_INVALID, "tree too deep for list traversal");
+    L.u_ptr.alloc(nb + 1); L.v_ptr.alloc(nb + 1); L.w_ptr.alloc(nb + 1);
+    exclusive_scan_i32(cu.p, L.u_ptr.p, nb, s);
+    exclusive_scan_i32(cv.p, L.v_ptr.p, nb, s);
+    exclusive_scan_i32(cw.p, L.w_ptr.p, nb, s);
+    L.n_u = read_scalar(L.u_ptr.p + nb, s);
+    L.n_v = read_scalar(L.v_ptr.p + nb, s);
+    L.n_w = read_scalar(L.w_ptr.p + nb, s);
+    L.u_idx.alloc(L.n_u); L.v_idx.alloc(L.n_v); L.w_idx.alloc(L.n_w);
+    L.v_cls.alloc(L.n_v); L.v_tgt.alloc(L.n_v);
+    k_list_fill<<<grid_for(nb, 128), 128, 0, s>>>(tv, nb, L.u_ptr.p, L.v_ptr.p, L.w_ptr.p,
+                                                  L.u_idx.p, L.v_idx.p, L.w_idx.p);
+    KCHK();
+    sort_rows_i32(L.u_ptr.p, L.u_idx.p, nb, s);
+    sort_rows_i32(L.v_ptr.p, L.v_idx.p, nb, s);
+    sort_rows_i32(L.w_ptr.p, L.w_idx.p, nb, s);
+    k_v_class<<<grid_for(nb, 128), 128, 0, s>>>(tv, nb, L.v_ptr.p, L.v_idx.p, L.v_cls.p,
+                                                L.v_tgt.p);
+    KCHK();
+    // X = transpose of W
+    DBuf<int> cx(nb + 1), cur(nb + 1);
+    cx.zero(nb + 1, s);
+    cur.zero(nb + 1, s);
+    k_x_count<<<grid_for(nb, 256), 256, 0, s>>>(nb, L.w_ptr.p, L.w_idx.p, cx.p);
+    KCHK();
+    L.x_ptr.alloc(nb + 1);
+    exclusive_scan_i32(cx.p, L.x_ptr.p, nb, s);
+    L.n_x = read_scalar(L.x_ptr.p + nb, s);
+    L.x_idx.alloc(L.n_x);
+    k_x_fill<<<grid_for(nb, 256), 256, 0, s>>>(nb, L.w_ptr.p, L.w_idx.p, L.x_ptr.p, cur.p,
+                                               L.x_idx.p);
+    KCHK();
+    sort_rows_i32(L.x_ptr.p, L.x_idx.p, nb, s);
+    // leaves and P2P work
+    DBuf<int> lflag(nb + 1), lpos(nb + 1);
+    k_leaf_flags<<<grid_for(nb, 256), 256, 0, s>>>(tv, nb, lflag.p);
+    KCHK();
+    exclusive_scan_i32(lflag.p, lpos.p, nb, s);
+    L.n_leaves = read_scalar(lpos.p + nb, s);
+    L.leaf_ids.alloc(L.n_leaves);
+    k_leaf_collect<<<grid_for(nb, 256), 256, 0, s>>>(nb, lflag.p, lpos.p, L.leaf_ids.p);
+    KCHK();
+    const long long nl = L.n_leaves;
+    DBuf<int> nsrc(nl + 1), nitem(nl + 1), iptr(nl + 1);
+    DBuf<long long> npairs(nl + 1);
+    k_p2p_count<<<grid_for(nl, 128), 128, 0, s>>>(tv, nl, L.leaf_ids.p, L.u_ptr.p, L.u_idx.p,
+                                                  L.w_ptr.p, L.w_idx.p, L.x_ptr.p, L.x_idx.p,
+                                                  nsrc.p, nitem.p, npairs.p);
+    KCHK();
+    L.p2p_ptr.alloc(nl + 1);
+    exclusive_scan_i32(nsrc.p, L.p2p_ptr.p, nl, s);
+    exclusive_scan_i32(nitem.p, iptr.p, nl, s);
+    exclusive_scan_i64(npairs.p, npairs.p, nl, s);
+    L.n_p2p_src = read_scalar(L.p2p_ptr.p + nl, s);
+    L.n_items = read_scalar(iptr.p + nl, s);
+    L.n_p2p_pairs = read_scalar(npairs.p + nl, s);
+    L.p2p_src.alloc(L.n_p2p_src);
+    L.item_box.alloc(L.n_items);
+    L.item_begin.alloc(L.n_items);
+    k_p2p_fill<<<grid_for(nl, 128), 128, 0, s>>>(tv, nl, L.leaf_ids.p, L.u_ptr.p, L.u_idx.p,
+                                                 L.w_ptr.p, L.w_idx.p, L.x_ptr.p, L.x_idx.p,
+                                                 L.p2p_ptr.p, L.p2p_src.p, iptr.p,
+                                                 L.item_box.p, L.item_begin.p);
+    KCHK();
+    // M2L buckets by (level, class), chunks of <= 64 entries
+    const long long nv = L.n_v;
+    L.m2l_pairs.alloc(nv);
+    L.levels_with_v.clear();
+    L.n_m2l_items = 0;
+    if (nv > 0) {
+        DBuf<unsigned long long> keys(nv), tk(nv);
+        DBuf<int> tvv(nv);
+        k_m2l_keys<<<grid_for(nv, 256), 256, 0, s>>>(nv, L.v_tgt.p, L.v_cls.p, t.level.p,
+                                                     keys.p, L.m2l_pairs.p);
+        KCHK();
+        radix_sort_pairs(keys.p, L.m2l_pairs.p, tk.p, tvv.p, nv, 16, s);
+        std::vector<unsigned long long> hk(nv);
+        keys.download(hk.data(), nv, s);
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<int> ik, ib, ic;
+        long long i = 0;
+        while (i < nv) {
+            long long j = i;
+            while (j < nv && hk[j] == hk[i] && j - i < 64) ++j;
+            ik.push_back((int)hk[i]);
+            ib.push_back((int)i);
+            ic.push_back((int)(j - i));
+            int lev = (int)(hk[i] / 316) + 2;
+            if (L.levels_with_v.empty() || L.levels_with_v.back() != lev)
+                L.levels_with_v.push_back(lev);
+            i = j;
+        }
+        L.n_m2l_items = (long long)ik.size();
+        L.m2l_item_key.alloc(ik.size());
+        L.m2l_item_begin.alloc(ik.size());
+        L.m2l_item_count.alloc(ik.size());
+        L.m2l_item_key.upload(ik.data(), ik.size(), s);
+        L.m2l_item_begin.upload(ib.data(), ib.size(), s);
+        L.m2l_item_count.upload(ic.data(), ic.size(), s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+}  // namespace afmpb

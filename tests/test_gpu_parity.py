@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bit-exact: Morton keys, permutation, boxes, U/V/W/X lists and offset classes,
+near-set structure.  Floating point: near corrections (1e-12 of scale), the
+direct (all-P2P) matvec (1e-12 rel-L2), the FMM matvec at p = 8 (1e-5 rel-L2,
+the tolerance the method states for the FP64 matvec), RHS and energy kernels
+(1e-12), solvation energies (1e-4 relative)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import tree as OT
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _solver(mol, **params):
+    import paper_1710_06316_amd as A
+    s = A.Solver(0)
+    _say(f"set_molecule {mol.name} n={mol.n_nodes} {params}")
+    s.load(mol, **params)
+    return s
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+MOLS = {
+    "born3": lambda: W.born_ion(3),
+    "born4": lambda: W.born_ion(4),
+    "star3": lambda: W.star_request(11, level=3),
+    "star4": lambda: W.star_request(12, level=4),
+}
+
+
+# ------------------------------- tree ---------------------------------------
+
+@pytest.mark.parametrize("name,cap", [("born4", 64), ("star3", 16), ("star4", 32), ("star4", 5)])
+def test_tree_and_lists_bit_exact(name, cap):
+    mol = MOLS[name]()
+    s = _solver(mol, leaf_cap=cap)
+    g = s.debug_tree()
+    key, perm, _, _ = OT.morton_keys(mol.xyz)
+    assert (g["keys"].astype(np.int64) == key[perm]).all()
+    assert (g["perm"] == perm).all()
+    t = OT.build_tree(mol.xyz, cap)
+    assert g["sizes"]["n_boxes"] == t.nbox
+    for a, b in (("level", t.level), ("parent", t.parent), ("pt_begin", t.pt_begin),
+                 ("pt_end", t.pt_end), ("n_child", t.n_child)):
+        assert (g[a] == b).all(), a
+    assert (g["prefix"].astype(np.int64) == t.prefix).all()
+    nc = t.n_child > 0
+    assert (g["child_begin"][nc] == t.child_begin[nc]).all()
+    L = OT.build_lists(t)
+    for lst, pk, ik in ((L.U, "u_ptr", "u_idx"), (L.V, "v_ptr", "v_idx"), (L.W, "w_ptr", "w_idx"),
+                        (L.X, "x_ptr", "x_idx")):
+        ptr = np.r_[0, np.cumsum([len(r) for r in lst])]
+        flat = np.array([c for r in lst for c in r], dtype=np.int64)
+        assert (g[pk] == ptr).all(), pk
+        assert (g[ik] == flat).all(), ik
+    vc = np.array([c for r in L.V_class for c in r], dtype=np.int64)
+    assert (g["v_class"] == vc).all()
+    s.close()
+
+
+def test_near_set_bit_exact_and_corrections():
+    mol = MOLS["star3"]()
+    s = _solver(mol)
+    g = s.debug_tree()
+    perm = g["perm"].astype(np.int64)
+    geo = O.geometry(mol.xyz, mol.tri)
+    rows, ptr, col = O.near_set(geo, 4.0)
+    inv = np.argsort(perm)
+    # GPU rows/cols are Morton positions; map to caller indices
+    gp = g["near_ptr"]
+    gc = perm[g["near_col"]]
+    for m in range(mol.n_nodes):
+        p = perm[m]
+        assert sorted(gc[gp[m]:gp[m + 1]]) == list(col[ptr[p]:ptr[p + 1]])
+        assert (np.diff(g["near_col"][gp[m]:gp[m + 1]]) > 0).all()
+    # corrections: GPU delta + oracle point rule == oracle patch integral
+    P = np.repeat(perm[np.arange(mol.n_nodes)], np.diff(gp))
+    T = gc
+    ebar = mol.eps_s / mol.eps_p
+    patch = O.patch_coeffs(geo, mol.kappa, ebar, P, T)
+    point = O.point_coeffs(geo, mol.kappa, ebar, P, T)
+    point[P == T] = 0.0
+    scale = np.abs(patch).max(axis=0)
+    err = np.abs(g["near_delta"] + point - patch).max(axis=0) / scale
+    assert (err < 1e-12).all(), err
+    _ = inv
+    s.close()
+
+
+# ------------------------------- matvec -------------------------------------
+
+def _oracle_op(mol):
+    return O.operator(mol.xyz, mol.tri, mol.eps_p, mol.eps_s, mol.kappa)
+
+
+@pytest.mark.parametrize("name", ["born3", "star3", "star4"])
+def test_direct_matvec_matches_oracle(name):
+    mol = MOLS[name]()
+    op = _oracle_op(mol)
+    x = np.random.default_rng(3).normal(size=2 * mol.n_nodes)
+    ref = op.matvec(x)
+    s = _solver(mol, leaf_cap=mol.n_nodes)            # root is a leaf: every pair by P2P
+    y = s.matvec(x)
+    assert _rel(y, ref) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["born4", "star4"])
+def test_fmm_matvec_matches_oracle_and_converges_in_p(name):
+    mol = MOLS[name]()
+    op = _oracle_op(mol)
+    x = np.random.default_rng(4).normal(size=2 * mol.n_nodes)
+    ref = op.matvec(x)
+    errs = {}
+    for p, cap in ((4, 32), (8, 32), (12, 32)):
+        s = _solver(mol, order_p=p, leaf_cap=cap)
+        info = s.tree_info()
+        assert info["n_v"] > 0                          # the far field is exercised
+        errs[p] = _rel(s.matvec(x), ref)
+        s.close()
+    _say(f"fmm errors {errs}")
+    assert errs[8] < 1e-5
+    assert errs[4] > errs[8] > errs[12]
+
+
+def test_fmm_matvec_kappa_zero_and_identity_case():
+    mol = MOLS["star3"]()
+    x = np.random.default_rng(5).normal(size=2 * mol.n_nodes)
+    m0 = W.Molecule("k0", mol.xyz, mol.tri, mol.atom_xyz, mol.charge, mol.radius, 2.0, 80.0, 0.0)
+    ref = _oracle_op(m0).matvec(x)
+    s = _solver(m0, leaf_cap=16)
+    assert _rel(s.matvec(x), ref) < 1e-5
+    s.close()
+    mi = W.Molecule("id", mol.xyz, mol.tri, mol.atom_xyz, mol.charge, mol.radius, 3.0, 3.0, 0.0)
+    s = _solver(mi, leaf_cap=16)
+    assert _rel(s.matvec(x), x) < 1e-13
+    s.close()
+
+
+def test_rhs_and_energy_kernels():
+    mol = MOLS["star3"]()
+    s = _solver(mol)
+    geo = O.geometry(mol.xyz, mol.tri)
+    b_ref = O.rhs(geo, mol.atom_xyz, mol.charge, mol.eps_s)
+    assert _rel(s.rhs(), b_ref) < 1e-13
+    x = np.random.default_rng(6).normal(size=2 * mol.n_nodes)
+    e_ref, _ = O.reaction_energy(geo, mol.atom_xyz, mol.charge, mol.eps_s / mol.eps_p,
+                                 x[:mol.n_nodes], x[mol.n_nodes:])
+    assert s.energy(x) == pytest.approx(e_ref, rel=1e-12)
+    s.close()
+
+
+# ------------------------------- solve --------------------------------------
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_born_ion_solve_energy(precision):
+    from oracle.closed_forms import born_energy
+    mol = W.born_ion(4)
+    ref = O.solve(mol)
+    s = _solver(mol, precision=precision)
+    f, h, E, info, st = s.solve()
+    _say(f"born solve precision={precision} E={E} oracle={ref.energy} info={info.as_dict()}")
+    assert info.converged and info.true_rel_residual < 2e-6
+    assert E == pytest.approx(ref.energy, rel=1e-4)
+    assert E == pytest.approx(born_energy(1.0, 2.0, 2.0, 80.0, 0.1), rel=0.01)
+    assert _rel(f, ref.f) < 1e-4 and _rel(h, ref.h) < 1e-4
+    s.close()
+
+
+def test_star_solve_energy_matches_oracle():
+    mol = MOLS["star4"]()
+    ref = O.solve(mol)
+    s = _solver(mol, leaf_cap=32)
+    f, h, E, info, st = s.solve()
+    assert E == pytest.approx(ref.energy, rel=1e-4)
+    s.close()
+
+
+def test_globular_sampled_rows():
+    mol = W.globular()
+    n = mol.n_nodes
+    rng = np.random.default_rng(7)
+    rows = np.sort(rng.choice(n, size=192, replace=False))
+    op = O.operator(mol.xyz, mol.tri, mol.eps_p, mol.eps_s, mol.kappa, rows=rows)
+    x = rng.normal(size=2 * n)
+    yf, yh = op.apply_rows(x)
+    s = _solver(mol)
+    y = s.matvec(x)
+    err = np.linalg.norm(np.r_[y[rows] - yf, y[n + rows] - yh]) / np.linalg.norm(np.r_[yf, yh])
+    _say(f"globular sampled-row error {err}")
+    assert err < 1e-5
+    s.close()
+
+
+# ------------------------------- errors -------------------------------------
+
+def test_error_contract():
+    import paper_1710_06316_amd as A
+    s = A.Solver(0)
+    with pytest.raises(A.AfmpbError) as e:
+        s.matvec(np.zeros(10))
+    assert e.value.status == A.AFMPB_E_STATE
+    v, t = W.icosphere(2, 1.0)
+    with pytest.raises(A.AfmpbError) as e:
+        s.set_molecule(v, t[1:], np.zeros((1, 3)), [1.0])
+    assert e.value.status == A.AFMPB_E_MESH
+    with pytest.raises(A.AfmpbError) as e:
+        s.set_molecule(v, t[:, [0, 2, 1]], np.zeros((1, 3)), [1.0])
+    assert e.value.status == A.AFMPB_E_MESH
+    with pytest.raises(A.AfmpbError) as e:
+        s.set_molecule(v, t, np.zeros((1, 3)), [1.0], eps_p=-1.0)
+    assert e.value.status == A.AFMPB_E_INVALID
+    with pytest.raises(A.AfmpbError) as e:
+        s.set_molecule(v, t, np.zeros((1, 3)), [1.0], order_p=40)
+    assert e.value.status == A.AFMPB_E_INVALID
+    s.set_molecule(v, t, np.zeros((1, 3)), [1.0])
+    x = np.zeros(2 * len(v))
+    x[3] = np.nan
+    with pytest.raises(A.AfmpbError) as e:
+        s.matvec(x)
+    assert e.value.status == A.AFMPB_E_NUMERIC
+    s.set_molecule(v, t, np.zeros((1, 3)), [1.0], restart=1, max_restarts=0, rel_tol=1e-14)
+    f, h, E, info, st = s.solve(allow_not_converged=True)
+    assert st == A.AFMPB_E_NOT_CONVERGED and info.iterations == 1 and np.isfinite(E)
+    s.close()
