@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <cstdlib>
 #include <numeric>
 
 #include "../../include/afmpb.h"
@@ -289,6 +290,8 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.far.phi = f + 4 * nb * K + std::max(nv, 1ll) * 2 * K;
 }
 
+void check_setup(afmpb_ctx *c);
+
 void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, const int *tri,
                    long long na, const double *axyz, const double *q, const afmpb_params &prm) {
     auto t0 = std::chrono::steady_clock::now();
@@ -343,8 +346,121 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
     c->krylov = DBuf<double>();
     c->krylov_m = 0;
     c->sync();
+    check_setup(c);
     c->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     c->loaded = true;
+}
+
+// Structural checks of every array the matvec kernels index with; a failure
+// raises an error here instead of an out-of-range access later.
+template <typename T>
+std::vector<T> host_copy(const DBuf<T> &b, size_t n, hipStream_t s) {
+    std::vector<T> h(n);
+    if (n) b.download(h.data(), n, s);
+    return h;
+}
+
+void check_setup(afmpb_ctx *c) {
+    const char *env = std::getenv("AFMPB_CHECK");
+    if (env && env[0] == '0') return;
+    hipStream_t s = c->stream;
+    const long long n = c->n, nb = c->tree.nbox;
+    const Tree &t = c->tree;
+    const Lists &L = c->lists;
+    auto keys = host_copy(c->keys, n, s);
+    auto perm = host_copy(c->perm, n, s);
+    auto lev = host_copy(t.level, nb, s), par = host_copy(t.parent, nb, s);
+    auto cb = host_copy(t.child_begin, nb, s), nc = host_copy(t.n_child, nb, s);
+    auto ptb = host_copy(t.pt_begin, nb, s), pte = host_copy(t.pt_end, nb, s);
+    c->sync();
+    auto bad = [](const char *what) { throw Error(ST_DEVICE, std::string("setup check: ") + what); };
+    std::vector<char> seen(n, 0);
+    for (long long i = 0; i < n; ++i) {
+        if (perm[i] < 0 || perm[i] >= n || seen[perm[i]]) bad("perm is not a permutation");
+        seen[perm[i]] = 1;
+        if (i && keys[i] < keys[i - 1]) bad("keys not sorted");
+    }
+    if (nb < 1 || ptb[0] != 0 || pte[0] != n || par[0] != -1 || lev[0] != 0) bad("root box");
+    for (long long b = 0; b < nb; ++b) {
+        if (ptb[b] < 0 || pte[b] > n || ptb[b] >= pte[b]) bad("box point range");
+        if (lev[b] < 0 || lev[b] > 21) bad("box level");
+        if (b > 0 && (par[b] < 0 || par[b] >= b || lev[par[b]] != lev[b] - 1)) bad("box parent");
+        if (b > 0 && (ptb[b] < ptb[par[b]] || pte[b] > pte[par[b]])) bad("box not inside parent");
+        if (nc[b] < 0 || nc[b] > 8) bad("child count");
+        if (nc[b] > 0) {
+            if (cb[b] <= b || cb[b] + nc[b] > nb) bad("child range");
+            if (ptb[cb[b]] != ptb[b] || pte[cb[b] + nc[b] - 1] != pte[b]) bad("children cover");
+            for (int k = 0; k < nc[b]; ++k)
+                if (par[cb[b] + k] != b) bad("child parent");
+        }
+    }
+    if ((long long)t.level_start.size() != t.nlev + 1 || t.level_start.back() != nb) bad("levels");
+    auto csr = [&](const DBuf<int> &ptr, const DBuf<int> &idx, long long cnt, long long lim,
+                   const char *what) {
+        auto p = host_copy(ptr, nb + 1, s);
+        auto ix = host_copy(idx, cnt, s);
+        c->sync();
+        if (p[0] != 0 || p[nb] != cnt) bad(what);
+        for (long long b = 0; b < nb; ++b)
+            if (p[b + 1] < p[b]) bad(what);
+        for (long long q = 0; q < cnt; ++q)
+            if (ix[q] < 0 || ix[q] >= lim) bad(what);
+    };
+    csr(L.u_ptr, L.u_idx, L.n_u, nb, "U list");
+    csr(L.v_ptr, L.v_idx, L.n_v, nb, "V list");
+    csr(L.w_ptr, L.w_idx, L.n_w, nb, "W list");
+    csr(L.x_ptr, L.x_idx, L.n_x, nb, "X list");
+    auto vcls = host_copy(L.v_cls, L.n_v, s);
+    auto leaf = host_copy(L.leaf_ids, L.n_leaves, s);
+    auto sp = host_copy(L.p2p_ptr, L.n_leaves + 1, s);
+    auto src = host_copy(L.p2p_src, L.n_p2p_src, s);
+    auto ib = host_copy(L.item_box, L.n_items, s), ibeg = host_copy(L.item_begin, L.n_items, s);
+    c->sync();
+    for (auto v : vcls) if (v < 0 || v >= 316) bad("V class");
+    for (auto b : leaf) if (b < 0 || b >= nb || nc[b] != 0) bad("leaf ids");
+    if (sp[0] != 0 || sp[L.n_leaves] != L.n_p2p_src) bad("P2P ptr");
+    for (long long i = 0; i < L.n_leaves; ++i) if (sp[i + 1] < sp[i]) bad("P2P ptr");
+    for (auto b : src) if (b < 0 || b >= nb) bad("P2P source box");
+    for (long long k = 0; k < L.n_items; ++k) {
+        if (ib[k] < 0 || ib[k] >= L.n_leaves) bad("P2P item leaf");
+        int B = leaf[ib[k]];
+        if (ibeg[k] < ptb[B] || ibeg[k] >= pte[B]) bad("P2P item begin");
+    }
+    if (L.n_m2l_items > 0) {
+        auto ik = host_copy(L.m2l_item_key, L.n_m2l_items, s);
+        auto ibg = host_copy(L.m2l_item_begin, L.n_m2l_items, s);
+        auto icn = host_copy(L.m2l_item_count, L.n_m2l_items, s);
+        auto pairs = host_copy(L.m2l_pairs, L.n_v, s);
+        auto pos = host_copy(c->fmm.pos_of, L.n_v, s);
+        c->sync();
+        long long covered = 0;
+        for (long long w = 0; w < L.n_m2l_items; ++w) {
+            if (ik[w] < 0 || ik[w] >= c->fmm.nkey) bad("M2L item key");
+            if (icn[w] < 1 || icn[w] > 64 || ibg[w] < 0 || ibg[w] + icn[w] > L.n_v) bad("M2L item range");
+            covered += icn[w];
+        }
+        if (covered != L.n_v) bad("M2L items do not cover V");
+        std::vector<char> sv(L.n_v, 0);
+        for (long long q = 0; q < L.n_v; ++q) {
+            if (pairs[q] < 0 || pairs[q] >= L.n_v || sv[pairs[q]]) bad("M2L pair permutation");
+            sv[pairs[q]] = 1;
+            if (pos[pairs[q]] != q) bad("M2L inverse permutation");
+        }
+    }
+    auto nptr = host_copy(c->near.ptr, n + 1, s);
+    auto ncol = host_copy(c->near.col, c->near.nnz, s);
+    c->sync();
+    if (nptr[0] != 0 || nptr[n] != c->near.nnz) bad("near ptr");
+    for (long long p = 0; p < n; ++p) {
+        if (nptr[p + 1] <= nptr[p]) bad("near row empty");
+        bool self = false;
+        for (long long e = nptr[p]; e < nptr[p + 1]; ++e) {
+            if (ncol[e] < 0 || ncol[e] >= n) bad("near column");
+            if (e > nptr[p] && ncol[e] <= ncol[e - 1]) bad("near row not ascending");
+            self |= ncol[e] == p;
+        }
+        if (!self) bad("near row lacks the diagonal");
+    }
 }
 
 struct Gmres {

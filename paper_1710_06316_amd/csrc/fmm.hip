@@ -255,45 +255,49 @@ __global__ void k_m2m(BasisDev B, TreeDev T, long long lb, long long le, const R
 }
 
 // Batched M2L: one work item = up to 64 V entries of one (level, class).
-template <typename R>
-__global__ void k_m2l(int K, const int *item_key, const int *item_begin, const int *item_count,
-                      const int *pairs, const int *vidx, const R *Tops, long long nkey,
-                      const R *M, R *Z) {
+// The gathered multipoles of CC entries at a time sit in LDS ([K][CC]); each
+// thread owns one entry (column) and a strided set of output rows, so the
+// operator rows are read wave-uniformly (broadcast) from cache.
+template <typename R, int CC>
+__global__ void __launch_bounds__(256) k_m2l(int K, const int *item_key, const int *item_begin,
+                                             const int *item_count, const int *pairs,
+                                             const int *vidx, const R *Tops, long long nkey,
+                                             const R *M, R *Z) {
     extern __shared__ unsigned char smem_raw[];
-    R *Ms = reinterpret_cast<R *>(smem_raw);          // [K][64]
-    R *Tt = Ms + (long long)K * 64;                    // [16][K]
+    R *Ms = reinterpret_cast<R *>(smem_raw);          // [K][CC]
+    constexpr int G = 256 / CC;                       // row groups
     const int w = blockIdx.x, kern = blockIdx.y;
     const int key = item_key[w], beg = item_begin[w], cnt = item_count[w];
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < K * 64; idx += blockDim.x) {
-        int k = idx / 64, i = idx % 64;
-        R v = R(0);
-        if (i < cnt) {
-            int src = vidx[pairs[beg + i]];
-            v = M[((long long)src * 2 + kern) * K + k];
-        }
-        Ms[idx] = v;
-    }
+    const int tid = threadIdx.x, col = tid % CC, rg = tid / CC;
     const R *Top = Tops + ((long long)kern * nkey + key) * K * K;
-    const int col = tid & 63, rg = tid >> 6;
-    for (int r0 = 0; r0 < K; r0 += 16) {
+    for (int c0 = 0; c0 < cnt; c0 += CC) {
         __syncthreads();
-        for (int idx = tid; idx < 16 * K; idx += blockDim.x) {
-            int rr = idx / K, k = idx % K;
-            Tt[idx] = (r0 + rr < K) ? Top[(long long)(r0 + rr) * K + k] : R(0);
+        for (int idx = tid; idx < K * CC; idx += 256) {
+            int k = idx / CC, i = idx % CC;
+            R v = R(0);
+            if (c0 + i < cnt) {
+                int src = vidx[pairs[beg + c0 + i]];
+                v = M[((long long)src * 2 + kern) * K + k];
+            }
+            Ms[idx] = v;
         }
         __syncthreads();
-        R acc[4] = {R(0), R(0), R(0), R(0)};
-        for (int k = 0; k < K; ++k) {
-            R m = Ms[k * 64 + col];
+        const bool live = c0 + col < cnt;
+        for (int r0 = rg; r0 < K; r0 += 4 * G) {
+            R acc[4] = {R(0), R(0), R(0), R(0)};
+            const R *T0 = Top + (long long)r0 * K;
+            for (int k = 0; k < K; ++k) {
+                R m = Ms[k * CC + col];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[j] += Tt[(rg + 4 * j) * K + k] * m;
-        }
-        if (col < cnt) {
+                for (int j = 0; j < 4; ++j)
+                    if (r0 + j * G < K) acc[j] += T0[(long long)j * G * K + k] * m;
+            }
+            if (live) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                int r = r0 + rg + 4 * j;
-                if (r < K) Z[((long long)(beg + col) * 2 + kern) * K + r] = acc[j];
+                for (int j = 0; j < 4; ++j) {
+                    int r = r0 + j * G;
+                    if (r < K) Z[((long long)(beg + c0 + col) * 2 + kern) * K + r] = acc[j];
+                }
             }
         }
     }
@@ -524,10 +528,21 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     if (L.n_m2l_items > 0) {
         ProfScope ps(prof, "m2l", s);
-        size_t sh_bytes = sizeof(R) * ((size_t)K * 64 + 16 * (size_t)K);
-        k_m2l<R><<<dim3((unsigned)L.n_m2l_items, 2), 256, sh_bytes, s>>>(
-            K, L.m2l_item_key.p, L.m2l_item_begin.p, L.m2l_item_count.p, L.m2l_pairs.p,
-            L.v_idx.p, ops_T<R>(F), F.nkey, w.M, w.Z);
+        dim3 grid((unsigned)L.n_m2l_items, 2);
+        const size_t lim = 64 * 1024;
+        if ((size_t)K * 64 * sizeof(R) <= lim) {
+            k_m2l<R, 64><<<grid, 256, (size_t)K * 64 * sizeof(R), s>>>(
+                K, L.m2l_item_key.p, L.m2l_item_begin.p, L.m2l_item_count.p, L.m2l_pairs.p,
+                L.v_idx.p, ops_T<R>(F), F.nkey, w.M, w.Z);
+        } else if ((size_t)K * 32 * sizeof(R) <= lim) {
+            k_m2l<R, 32><<<grid, 256, (size_t)K * 32 * sizeof(R), s>>>(
+                K, L.m2l_item_key.p, L.m2l_item_begin.p, L.m2l_item_count.p, L.m2l_pairs.p,
+                L.v_idx.p, ops_T<R>(F), F.nkey, w.M, w.Z);
+        } else {
+            k_m2l<R, 16><<<grid, 256, (size_t)K * 16 * sizeof(R), s>>>(
+                K, L.m2l_item_key.p, L.m2l_item_begin.p, L.m2l_item_count.p, L.m2l_pairs.p,
+                L.v_idx.p, ops_T<R>(F), F.nkey, w.M, w.Z);
+        }
         KCHK();
     }
     {

@@ -34,11 +34,12 @@ __global__ void k_count_incidence(const int *__restrict__ T, long long m, int *c
 }
 
 __global__ void k_fill_incidence(const int *__restrict__ T, long long m,
-                                 const int *__restrict__ ptr, int *cursor, int *inc) {
+                                 const int *__restrict__ ptr, int *cursor, int *inc, int *err) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 3 * m) return;
     int v = T[i];
     int slot = atomicAdd(&cursor[v], 1);
+    if (ptr[v] + slot >= ptr[v + 1]) { atomicOr(err, 1); return; }
     inc[ptr[v] + slot] = (int)(i / 3);
 }
 
@@ -155,7 +156,8 @@ __global__ void k_gather_nodes(const double *__restrict__ V, const double *__res
 void compute_geometry(const double *V, const int *T, long long n, long long m,
                       double *tri_area, double *tri_n, int *inc_ptr, int *inc_tri,
                       double *area, double *nrm, double *rho2, hipStream_t s) {
-    DBuf<int> cnt(n + 1), cursor(n + 1);
+    DBuf<int> cnt(n + 1), cursor(n + 1), err(1);
+    err.zero(1, s);
     cnt.zero(n + 1, s);
     cursor.zero(n + 1, s);
     k_tri_geometry<<<grid_for(m, 256), 256, 0, s>>>(V, T, m, tri_area, tri_n);
@@ -163,13 +165,16 @@ void compute_geometry(const double *V, const int *T, long long n, long long m,
     k_count_incidence<<<grid_for(3 * m, 256), 256, 0, s>>>(T, m, cnt.p);
     KCHK();
     exclusive_scan_i32(cnt.p, inc_ptr, n, s);
-    k_fill_incidence<<<grid_for(3 * m, 256), 256, 0, s>>>(T, m, inc_ptr, cursor.p, inc_tri);
+    k_fill_incidence<<<grid_for(3 * m, 256), 256, 0, s>>>(T, m, inc_ptr, cursor.p, inc_tri, err.p);
     KCHK();
     sort_rows_i32(inc_ptr, inc_tri, n, s);
     k_node_geometry<<<grid_for(n, 256), 256, 0, s>>>(V, T, tri_area, tri_n, inc_ptr, inc_tri,
                                                       n, area, nrm, rho2);
     KCHK();
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    require(herr == 0, ST_DEVICE, "incidence fill out of range");
 }
 
 void morton_sort(const double *V, long long n, unsigned long long *keys, int *perm,

@@ -56,7 +56,7 @@ template <bool FILL>
 __global__ void k_near(NodeSoA nd, long long n, double lx, double ly, double lz,
                        double inv_cell, long long nx_, long long ny_, long long nz_,
                        const unsigned long long *__restrict__ ckeys, const int *__restrict__ cidx,
-                       double eta2, int *cnt, const long long *ptr, int *col) {
+                       double eta2, int *cnt, const long long *ptr, int *col, int *err) {
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const double px = nd.x[p], py = nd.y[p], pz = nd.z[p], rp = nd.rho2[p];
@@ -84,7 +84,10 @@ __global__ void k_near(NodeSoA nd, long long n, double lx, double ly, double lz,
                         near = dd < eta2 * r2;
                     }
                     if (near) {
-                        if (FILL) col[o + c] = t;
+                        if (FILL) {
+                            if (o + c < ptr[p + 1]) col[o + c] = t;
+                            else atomicOr(err, 1);
+                        }
                         ++c;
                     }
                 }
@@ -92,6 +95,7 @@ __global__ void k_near(NodeSoA nd, long long n, double lx, double ly, double lz,
         }
     }
     if (!FILL) cnt[p] = c;
+    else if (o + c != ptr[p + 1]) atomicOr(err, 1);
 }
 
 __global__ void k_sort_rows64(const long long *ptr, int *idx, long long nrows) {
@@ -347,11 +351,12 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
     while (bits < 64 && (maxkey >> bits)) ++bits;
     radix_sort_pairs(ck.p, ci.p, tk.p, ti.p, n, bits, s);
     double eta2 = eta * eta;
-    DBuf<int> cnt(n + 1);
+    DBuf<int> cnt(n + 1), nerr(1);
+    nerr.zero(1, s);
     DBuf<long long> cnt64(n + 1);
     k_near<false><<<grid_for(n, 128), 128, 0, s>>>(nd, n, lo[0], lo[1], lo[2], inv_cell, dims[0],
                                                    dims[1], dims[2], ck.p, ci.p, eta2, cnt.p,
-                                                   nullptr, nullptr);
+                                                   nullptr, nullptr, nullptr);
     KCHK();
     k_count_to_i64<<<grid_for(n, 256), 256, 0, s>>>(cnt.p, cnt64.p, n);
     KCHK();
@@ -362,8 +367,14 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
     out.col.alloc(out.nnz);
     k_near<true><<<grid_for(n, 128), 128, 0, s>>>(nd, n, lo[0], lo[1], lo[2], inv_cell, dims[0],
                                                   dims[1], dims[2], ck.p, ci.p, eta2, nullptr,
-                                                  out.ptr.p, out.col.p);
+                                                  out.ptr.p, out.col.p, nerr.p);
     KCHK();
+    {
+        int herr = 0;
+        HIPCHK(hipMemcpyAsync(&herr, nerr.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        require(herr == 0, ST_DEVICE, "near-set fill out of range");
+    }
     k_sort_rows64<<<grid_for(n, 256), 256, 0, s>>>(out.ptr.p, out.col.p, n);
     KCHK();
     // patch-integral corrections

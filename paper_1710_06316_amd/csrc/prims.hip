@@ -123,7 +123,7 @@ __global__ void k_rs_hist(const unsigned long long *keys, long long n, int shift
 // digit counts.
 __global__ void k_rs_scatter(const unsigned long long *kin, const int *vin,
                              unsigned long long *kout, int *vout, long long n,
-                             int shift, const int *offs, int nblk) {
+                             int shift, const int *offs, int nblk, int *err) {
     __shared__ int run[256];
     __shared__ int wcnt[RS_WAVES][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -153,8 +153,12 @@ __global__ void k_rs_scatter(const unsigned long long *kin, const int *vin,
             int pre = 0;
             for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
             int pos = run[d] + pre + rank;
-            kout[pos] = k;
-            vout[pos] = v;
+            if (pos < 0 || pos >= n) {
+                atomicOr(err, 1);
+            } else {
+                kout[pos] = k;
+                vout[pos] = v;
+            }
         }
         __syncthreads();
         int add = 0;
@@ -190,7 +194,8 @@ void radix_sort_pairs(unsigned long long *keys, int *vals, unsigned long long *t
     if (n <= 1) return;
     require(n < (1ll << 31), ST_INVALID, "radix sort: too many elements");
     int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
-    DBuf<int> hist((size_t)256 * nblk + 1);
+    DBuf<int> hist((size_t)256 * nblk + 1), err(1);
+    err.zero(1, s);
     int passes = (bits + 7) / 8;
     unsigned long long *ka = keys, *kb = tk;
     int *va = vals, *vb = tv;
@@ -199,7 +204,7 @@ void radix_sort_pairs(unsigned long long *keys, int *vals, unsigned long long *t
         k_rs_hist<<<nblk, RS_BLOCK, 0, s>>>(ka, n, shift, hist.p, nblk);
         KCHK();
         exclusive_scan_i32(hist.p, hist.p, (long long)256 * nblk, s);
-        k_rs_scatter<<<nblk, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, hist.p, nblk);
+        k_rs_scatter<<<nblk, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, hist.p, nblk, err.p);
         KCHK();
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -208,7 +213,10 @@ void radix_sort_pairs(unsigned long long *keys, int *vals, unsigned long long *t
         HIPCHK(hipMemcpyAsync(keys, ka, n * sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemcpyAsync(vals, va, n * sizeof(int), hipMemcpyDeviceToDevice, s));
     }
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));  // hist is freed on return
+    require(herr == 0, ST_DEVICE, "radix sort: scatter index out of range");
 }
 
 void sort_rows_i32(const int *ptr, int *idx, long long nrows, hipStream_t s) {

@@ -35,8 +35,9 @@ __global__ void k_make_children(const unsigned long long *__restrict__ keys, lon
                                 int *__restrict__ box_of, const int *__restrict__ flag,
                                 const int *__restrict__ pos, const int *__restrict__ ptb_old,
                                 const int *__restrict__ pte_old, int level, int cap,
-                                long long base, int *lev, unsigned long long *prefix,
-                                int *parent, int *ptb, int *child_begin, int *n_child) {
+                                long long base, long long capb, int *lev,
+                                unsigned long long *prefix, int *parent, int *ptb,
+                                int *child_begin, int *n_child, int *err) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int b = box_of[i];
@@ -47,6 +48,11 @@ __global__ void k_make_children(const unsigned long long *__restrict__ keys, lon
     }
     int sh = 3 * (MAXLEVEL - level - 1);
     long long id = base + pos[i] + flag[i] - 1;
+    if (id < base || id >= capb) {
+        atomicOr(err, 1);
+        box_of[i] = -1;
+        return;
+    }
     if (flag[i]) {
         lev[id] = level + 1;
         prefix[id] = keys[i] >> sh;
@@ -168,10 +174,11 @@ struct CountEmit {
 };
 
 struct FillEmit {
-    int *u, *v, *w;
-    __device__ void U(int c) { *u++ = c; }
-    __device__ void V(int c) { *v++ = c; }
-    __device__ void W(int c) { *w++ = c; }
+    int *u, *v, *w, *ue, *ve, *we;
+    int *err;
+    __device__ void U(int c) { if (u < ue) *u++ = c; else atomicOr(err, 1); }
+    __device__ void V(int c) { if (v < ve) *v++ = c; else atomicOr(err, 1); }
+    __device__ void W(int c) { if (w < we) *w++ = c; else atomicOr(err, 1); }
 };
 
 // Enumerates U(B) (leaf), W(B) (leaf) and V(B) (level >= 2) in an arbitrary
@@ -232,11 +239,13 @@ __global__ void k_list_count(TreeView t, long long nbox, int *cu, int *cv, int *
 }
 
 __global__ void k_list_fill(TreeView t, long long nbox, const int *pu, const int *pv,
-                            const int *pw, int *iu, int *iv, int *iw) {
+                            const int *pw, int *iu, int *iv, int *iw, int *err) {
     long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (B >= nbox) return;
-    FillEmit e{iu + pu[B], iv + pv[B], iw + pw[B]};
+    FillEmit e{iu + pu[B], iv + pv[B], iw + pw[B], iu + pu[B + 1], iv + pv[B + 1],
+               iw + pw[B + 1], err};
     enumerate(t, (int)B, e);
+    if (e.u != e.ue || e.v != e.ve || e.w != e.we) atomicOr(err, 2);
 }
 
 // Offset class of C relative to B: rank of (anchor_C - anchor_B)/side in
@@ -272,12 +281,15 @@ __global__ void k_x_count(long long nbox, const int *wptr, const int *widx, int 
 }
 
 __global__ void k_x_fill(long long nbox, const int *wptr, const int *widx, const int *xptr,
-                         int *cursor, int *xidx) {
+                         int *cursor, int *xidx, int *err) {
     long long C = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (C >= nbox) return;
     for (int q = wptr[C]; q < wptr[C + 1]; ++q) {
         int B = widx[q];
-        xidx[xptr[B] + atomicAdd(&cursor[B], 1)] = (int)C;
+        if (B < 0 || B >= nbox) { atomicOr(err, 4); continue; }
+        int o = xptr[B] + atomicAdd(&cursor[B], 1);
+        if (o >= xptr[B + 1]) { atomicOr(err, 4); continue; }
+        xidx[o] = (int)C;
     }
 }
 
@@ -317,21 +329,24 @@ __global__ void k_p2p_count(TreeView t, long long nleaf, const int *leaf_ids, co
 __global__ void k_p2p_fill(TreeView t, long long nleaf, const int *leaf_ids, const int *uptr,
                            const int *uidx, const int *wptr, const int *widx, const int *xptr,
                            const int *xidx, const int *sptr, int *src, const int *iptr,
-                           int *item_box, int *item_begin) {
+                           int *item_box, int *item_begin, int *err) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nleaf) return;
     int B = leaf_ids[i];
     int o = sptr[i];
-    for (int q = uptr[B]; q < uptr[B + 1]; ++q) src[o++] = uidx[q];
-    for (int q = wptr[B]; q < wptr[B + 1]; ++q) src[o++] = widx[q];
+    const int oe = sptr[i + 1];
+    for (int q = uptr[B]; q < uptr[B + 1]; ++q) { if (o < oe) src[o] = uidx[q]; ++o; }
+    for (int q = wptr[B]; q < wptr[B + 1]; ++q) { if (o < oe) src[o] = widx[q]; ++o; }
     for (int A = B; A >= 0; A = t.parent[A])
-        for (int q = xptr[A]; q < xptr[A + 1]; ++q) src[o++] = xidx[q];
+        for (int q = xptr[A]; q < xptr[A + 1]; ++q) { if (o < oe) src[o] = xidx[q]; ++o; }
+    if (o != oe) atomicOr(err, 8);
     int k = iptr[i];
+    const int ke = iptr[i + 1];
     for (int b = t.ptb[B]; b < t.pte[B]; b += 64) {
-        item_box[k] = (int)i;
-        item_begin[k] = b;
+        if (k < ke) { item_box[k] = (int)i; item_begin[k] = b; }
         ++k;
     }
+    if (k != ke) atomicOr(err, 8);
 }
 
 __global__ void k_m2l_keys(long long nv, const int *vtgt, const int *vcls, const int *lev,
@@ -359,15 +374,20 @@ void build_tree(const unsigned long long *keys, long long n, int cap, const doub
     t.n_child.alloc(capb); t.pt_begin.alloc(capb); t.pt_end.alloc(capb);
     t.prefix.alloc(capb);
     {
-        int root_i[6] = {0, -1, -1, 0, 0, (int)n};  // level parent cb nc ptb pte
-        unsigned long long z = 0;
-        t.level.upload(&root_i[0], 1, s); t.parent.upload(&root_i[1], 1, s);
-        t.child_begin.upload(&root_i[2], 1, s); t.n_child.upload(&root_i[3], 1, s);
-        t.pt_begin.upload(&root_i[4], 1, s); t.pt_end.upload(&root_i[5], 1, s);
-        t.prefix.upload(&z, 1, s);
+        // synchronous copies: the host values live on this stack frame only
+        const int root_i[6] = {0, -1, -1, 0, 0, (int)n};  // level parent cb nc ptb pte
+        const unsigned long long z = 0;
+        HIPCHK(hipMemcpy(t.level.p, &root_i[0], sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(t.parent.p, &root_i[1], sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(t.child_begin.p, &root_i[2], sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(t.n_child.p, &root_i[3], sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(t.pt_begin.p, &root_i[4], sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(t.pt_end.p, &root_i[5], sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(t.prefix.p, &z, sizeof(z), hipMemcpyHostToDevice));
     }
-    DBuf<int> box_of(n), flag(n + 1), pos(n + 1);
+    DBuf<int> box_of(n), flag(n + 1), pos(n + 1), gerr(1);
     box_of.zero(n, s);
+    gerr.zero(1, s);
     t.level_start.assign(1, 0);
     t.level_start.push_back(1);
     long long nbox = 1;
@@ -385,7 +405,10 @@ void build_tree(const unsigned long long *keys, long long n, int cap, const doub
         grow(t.prefix, need, nbox, s);
         k_make_children<<<grid_for(n, 256), 256, 0, s>>>(
             keys, n, box_of.p, flag.p, pos.p, t.pt_begin.p, t.pt_end.p, l, cap, nbox,
-            t.level.p, t.prefix.p, t.parent.p, t.pt_begin.p, t.child_begin.p, t.n_child.p);
+            (long long)std::min({t.level.n, t.prefix.n, t.parent.n, t.pt_begin.n, t.pt_end.n,
+                                 t.child_begin.n, t.n_child.n}),
+            t.level.p, t.prefix.p, t.parent.p, t.pt_begin.p, t.child_begin.p, t.n_child.p,
+            gerr.p);
         KCHK();
         k_finish_children<<<grid_for(cnt, 256), 256, 0, s>>>(nbox, cnt, t.parent.p, t.pt_begin.p,
                                                              t.pt_end.p, t.child_begin.p,
@@ -394,6 +417,7 @@ void build_tree(const unsigned long long *keys, long long n, int cap, const doub
         nbox += cnt;
         t.level_start.push_back(nbox);
     }
+    require(read_scalar(gerr.p, s) == 0, ST_DEVICE, "tree split: box index out of range");
     t.nbox = nbox;
     t.nlev = (int)t.level_start.size() - 1;
     t.center.alloc(3 * nbox);
@@ -432,8 +456,9 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
     L.u_idx.alloc(L.n_u); L.v_idx.alloc(L.n_v); L.w_idx.alloc(L.n_w);
     L.v_cls.alloc(L.n_v); L.v_tgt.alloc(L.n_v);
     k_list_fill<<<grid_for(nb, 128), 128, 0, s>>>(tv, nb, L.u_ptr.p, L.v_ptr.p, L.w_ptr.p,
-                                                  L.u_idx.p, L.v_idx.p, L.w_idx.p);
+                                                  L.u_idx.p, L.v_idx.p, L.w_idx.p, err.p);
     KCHK();
+    require(read_scalar(err.p, s) == 0, ST_DEVICE, "list fill out of range");
     sort_rows_i32(L.u_ptr.p, L.u_idx.p, nb, s);
     sort_rows_i32(L.v_ptr.p, L.v_idx.p, nb, s);
     sort_rows_i32(L.w_ptr.p, L.w_idx.p, nb, s);
@@ -451,8 +476,9 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
     L.n_x = read_scalar(L.x_ptr.p + nb, s);
     L.x_idx.alloc(L.n_x);
     k_x_fill<<<grid_for(nb, 256), 256, 0, s>>>(nb, L.w_ptr.p, L.w_idx.p, L.x_ptr.p, cur.p,
-                                               L.x_idx.p);
+                                               L.x_idx.p, err.p);
     KCHK();
+    require(read_scalar(err.p, s) == 0, ST_DEVICE, "X-list fill out of range");
     sort_rows_i32(L.x_ptr.p, L.x_idx.p, nb, s);
     // leaves and P2P work
     DBuf<int> lflag(nb + 1), lpos(nb + 1);
@@ -483,8 +509,9 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
     k_p2p_fill<<<grid_for(nl, 128), 128, 0, s>>>(tv, nl, L.leaf_ids.p, L.u_ptr.p, L.u_idx.p,
                                                  L.w_ptr.p, L.w_idx.p, L.x_ptr.p, L.x_idx.p,
                                                  L.p2p_ptr.p, L.p2p_src.p, iptr.p,
-                                                 L.item_box.p, L.item_begin.p);
+                                                 L.item_box.p, L.item_begin.p, err.p);
     KCHK();
+    require(read_scalar(err.p, s) == 0, ST_DEVICE, "P2P task fill out of range");
     // M2L buckets by (level, class), chunks of <= 64 entries
     const long long nv = L.n_v;
     L.m2l_pairs.alloc(nv);
@@ -520,6 +547,7 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
         L.m2l_item_key.upload(ik.data(), ik.size(), s);
         L.m2l_item_begin.upload(ib.data(), ib.size(), s);
         L.m2l_item_count.upload(ic.data(), ic.size(), s);
+        HIPCHK(hipStreamSynchronize(s));   // ik/ib/ic must outlive the copies
     }
     HIPCHK(hipStreamSynchronize(s));
 }
