@@ -166,7 +166,7 @@ struct afmpb_ctx {
     Lists lists;
     NearSet near;
     Fmm fmm;
-    DBuf<double> w64, far64;
+    DBuf<double> w64, far64, p2p64;
     DBuf<float> w32, far32;
     MatvecPlan<double> mp64;
     MatvecPlan<float> mp32;
@@ -266,7 +266,8 @@ __global__ void k_finite(const double *a, long long n, int *bad) {
 template <typename R>
 void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const R *ndR) {
     const long long n = c->n, K = c->fmm.K, nb = c->tree.nbox, nv = c->lists.n_v;
-    w.alloc((size_t)4 * n);
+    w.alloc((size_t)2 * n);
+    if (c->p2p64.n < (size_t)2 * n) c->p2p64.alloc((size_t)2 * n);
     far.alloc((size_t)(2 * nb * K) * 2 + (size_t)std::max(nv, 1ll) * 2 * K + 4 * n);
     mp.n = n;
     mp.tree = &c->tree;
@@ -281,8 +282,8 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.alpha = c->alpha;
     mp.sf = w.p;
     mp.sh = w.p + n;
-    mp.pf = w.p + 2 * n;
-    mp.ph = w.p + 3 * n;
+    mp.pf = c->p2p64.p;
+    mp.ph = c->p2p64.p + n;
     R *f = far.p;
     mp.far.M = f;
     mp.far.Lc = f + 2 * nb * K;
@@ -336,6 +337,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
                c->inc_tri.p, c->perm.p, prm.kappa, c->ebar, c->near, s);
     // translation operators
     c->fmm = Fmm();
+    c->p2p64 = DBuf<double>();
     build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa, c->fmm, s);
     setup_plan<double>(c, c->mp64, c->w64, c->far64, c->node64.p);
     setup_plan<float>(c, c->mp32, c->w32, c->far32, c->node32.p);

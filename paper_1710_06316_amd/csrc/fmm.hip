@@ -233,74 +233,193 @@ __global__ void k_p2m(BasisDev B, TreeDev T, const int *leaf_ids, const R *px, c
     }
 }
 
-// M of non-leaf boxes of one level from their children: M_P[a] = sum_b U[a][b] M_c[b].
-template <typename R>
-__global__ void k_m2m(BasisDev B, TreeDev T, long long lb, long long le, const R *Ut,
-                      int nlev, R *M) {
-    long long box = lb + blockIdx.x;
-    if (box >= le || T.nc[box] == 0) return;
-    const int K = B.K, lev = T.level[box];
-    for (int kern = 0; kern < 2; ++kern) {
-        for (int a = threadIdx.x; a < K; a += blockDim.x) {
-            R acc = R(0);
-            for (int c = T.cb[box]; c < T.cb[box] + T.nc[box]; ++c) {
-                int oct = (int)(T.prefix[c] & 7ull);
-                const R *U = Ut + (((long long)kern * nlev + lev) * 8 + oct) * K * K;
-                const R *Mc = M + ((long long)c * 2 + kern) * K;
-                for (int bb = 0; bb < K; ++bb) acc += U[(long long)bb * K + a] * Mc[bb];
-            }
-            M[((long long)box * 2 + kern) * K + a] = acc;
-        }
-    }
-}
+// ---------------------------------------------------------------------------
+// Batched K x K translations on the matrix cores.  One block (4 waves) owns a
+// set of up to CC output columns; each wave owns a fixed subset of the
+// 16 x 16 output tiles and runs v_mfma_*_16x16x4 over the (zero-padded) K
+// dimension.  Operands: A = translation operator rows (read from cache),
+// B = gathered expansions in LDS ([KK][CC]).
+//   MODE 0  M2L  one operator per work item (level, offset class);
+//                column c = one V entry; result -> Z (bucket order)
+//   MODE 1  M2M  eight operators (child octants) accumulated;
+//                column c = one parent box; result -> M[parent]
+//   MODE 2  L2L  eight operators, shared input L[parent];
+//                result added to L[child of octant o]
+// Operand layout of the 16x16x4 instructions (64 lanes, lane l, measured on
+// gfx950):  A[i][k]: i = l % 16, k = l / 16;  B[k][j]: k = l / 16, j = l % 16;
+//   D[i][j]: j = l % 16 and, for result register r = 0..3,
+//            f32: i = 4 (l / 16) + r        f64: i = (l / 16) + 4 r.
+// ---------------------------------------------------------------------------
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <typename R> struct Acc4;
+template <> struct Acc4<double> { typedef d4v T; };
+template <> struct Acc4<float> { typedef f4v T; };
 
-// Batched M2L: one work item = up to 64 V entries of one (level, class).
-// The gathered multipoles of CC entries at a time sit in LDS ([K][CC]); each
-// thread owns one entry (column) and a strided set of output rows, so the
-// operator rows are read wave-uniformly (broadcast) from cache.
-template <typename R, int CC>
-__global__ void __launch_bounds__(256) k_m2l(int K, const int *item_key, const int *item_begin,
-                                             const int *item_count, const int *pairs,
-                                             const int *vidx, const R *Tops, long long nkey,
-                                             const R *M, R *Z) {
+__device__ inline d4v mfma16(double a, double b, d4v c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4v mfma16(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// output row (within the 16-row tile) of result register r
+template <typename R> __device__ inline int drow(int lane, int r);
+template <> __device__ inline int drow<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+template <> __device__ inline int drow<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+struct TransArgs {
+    int K, KK, nlev;
+    long long nkey;
+    // M2L
+    const int *item_key, *item_begin, *item_count, *pairs, *vidx;
+    // M2M / L2L
+    long long lb, le;            // boxes of the parent level
+    const int *cb, *nc;          // child begin / count
+    const unsigned long long *prefix;
+};
+
+template <typename R, int CC, int MODE>
+__global__ void __launch_bounds__(256) k_trans(TransArgs a, const R *__restrict__ ops,
+                                               const R *__restrict__ in, R *__restrict__ out,
+                                               int lev) {
     extern __shared__ unsigned char smem_raw[];
-    R *Ms = reinterpret_cast<R *>(smem_raw);          // [K][CC]
-    constexpr int G = 256 / CC;                       // row groups
-    const int w = blockIdx.x, kern = blockIdx.y;
-    const int key = item_key[w], beg = item_begin[w], cnt = item_count[w];
-    const int tid = threadIdx.x, col = tid % CC, rg = tid / CC;
-    const R *Top = Tops + ((long long)kern * nkey + key) * K * K;
-    for (int c0 = 0; c0 < cnt; c0 += CC) {
-        __syncthreads();
-        for (int idx = tid; idx < K * CC; idx += 256) {
-            int k = idx / CC, i = idx % CC;
+    R *Ms = reinterpret_cast<R *>(smem_raw);         // [KK][CC] (modes 0 and 2)
+    __shared__ int colbox[CC];                         // column -> bucket position / box
+    __shared__ int child[8][CC];                       // modes 1, 2: child of octant o
+    typedef typename Acc4<R>::T V4;
+    const int K = a.K, KK = a.KK;
+    const int kern = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int NRT = (K + 15) / 16, NCT = CC / 16, NT = NRT * NCT;
+    const long long KK2 = (long long)K * K;
+    int ncols;
+    const R *op0;
+    if (MODE == 0) {
+        // work item blockIdx.x, columns [blockIdx.z * CC, +CC) of its <= 64 entries
+        const int w = blockIdx.x;
+        const int off = blockIdx.z * CC;
+        ncols = min(CC, a.item_count[w] - off);
+        if (ncols <= 0) return;                          // uniform for the block
+        const int beg = a.item_begin[w] + off;
+        if (tid < CC) colbox[tid] = tid < ncols ? beg + tid : -1;
+        op0 = ops + ((long long)kern * a.nkey + a.item_key[w]) * KK2;
+    } else {
+        const long long c0 = a.lb + (long long)blockIdx.x * CC;
+        ncols = (int)min((long long)CC, a.le - c0);
+        if (tid < CC) {
+            colbox[tid] = tid < ncols ? (int)(c0 + tid) : -1;
+            for (int o = 0; o < 8; ++o) child[o][tid] = -1;
+            if (tid < ncols) {
+                const int P = (int)(c0 + tid);
+                for (int c = a.cb[P]; c < a.cb[P] + a.nc[P]; ++c)
+                    child[(int)(a.prefix[c] & 7ull)][tid] = c;
+            }
+        }
+        op0 = ops + (((long long)kern * a.nlev + lev) * 8) * KK2;
+    }
+    __syncthreads();
+    if (MODE != 1) {
+        for (int idx = tid; idx < KK * CC; idx += 256) {
+            const int k = idx / CC, c = idx % CC;
             R v = R(0);
-            if (c0 + i < cnt) {
-                int src = vidx[pairs[beg + c0 + i]];
-                v = M[((long long)src * 2 + kern) * K + k];
+            if (k < K && c < ncols) {
+                const int src = (MODE == 0) ? a.vidx[a.pairs[colbox[c]]] : colbox[c];
+                v = in[((long long)src * 2 + kern) * K + k];
             }
             Ms[idx] = v;
         }
         __syncthreads();
-        const bool live = c0 + col < cnt;
-        for (int r0 = rg; r0 < K; r0 += 4 * G) {
-            R acc[4] = {R(0), R(0), R(0), R(0)};
-            const R *T0 = Top + (long long)r0 * K;
-            for (int k = 0; k < K; ++k) {
-                R m = Ms[k * CC + col];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (r0 + j * G < K) acc[j] += T0[(long long)j * G * K + k] * m;
+    }
+    for (int t = wave; t < NT; t += 4) {
+        const int rt = t / NCT, ct = t % NCT;
+        const int row = rt * 16 + (lane & 15);
+        const int col = ct * 16 + (lane & 15);       // B column / output column of this lane
+        if (MODE == 0) {
+            V4 c4 = V4{0, 0, 0, 0};
+            for (int k0 = 0; k0 < KK; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                const R av = (row < K && k < K) ? op0[(long long)row * K + k] : R(0);
+                c4 = mfma16(av, Ms[k * CC + col], c4);
             }
-            if (live) {
+            if (col < ncols) {
+                const long long dst = ((long long)colbox[col] * 2 + kern) * K;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    int r = r0 + j * G;
-                    if (r < K) Z[((long long)(beg + c0 + col) * 2 + kern) * K + r] = acc[j];
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = rt * 16 + drow<R>(lane, r);
+                    if (rr < K) out[dst + rr] = c4[r];
+                }
+            }
+        } else if (MODE == 1) {
+            // M_P[row] = sum_o sum_k U_o[row][k] M_{child o}[k],  U_o[row][k] = Ut_o[k][row]
+            V4 c4 = V4{0, 0, 0, 0};
+            for (int o = 0; o < 8; ++o) {
+                const int ch = col < ncols ? child[o][col] : -1;
+                const R *op = op0 + o * KK2;
+                const R *Mc = in + ((long long)(ch < 0 ? 0 : ch) * 2 + kern) * K;
+                for (int k0 = 0; k0 < KK; k0 += 4) {
+                    const int k = k0 + (lane >> 4);
+                    const R av = (row < K && k < K) ? op[(long long)k * K + row] : R(0);
+                    const R bv = (ch >= 0 && k < K) ? Mc[k] : R(0);
+                    c4 = mfma16(av, bv, c4);
+                }
+            }
+            const int P = col < ncols ? colbox[col] : -1;
+            if (P >= 0 && a.nc[P] > 0) {                 // leaves keep their P2M moments
+                const long long dst = ((long long)P * 2 + kern) * K;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = rt * 16 + drow<R>(lane, r);
+                    if (rr < K) out[dst + rr] = c4[r];
+                }
+            }
+        } else {
+            // L_{child o}[row] += sum_k Ut_o[row][k] L_P[k]
+            for (int o = 0; o < 8; ++o) {
+                const R *op = op0 + o * KK2;
+                V4 c4 = V4{0, 0, 0, 0};
+                for (int k0 = 0; k0 < KK; k0 += 4) {
+                    const int k = k0 + (lane >> 4);
+                    const R av = (row < K && k < K) ? op[(long long)row * K + k] : R(0);
+                    c4 = mfma16(av, Ms[k * CC + col], c4);
+                }
+                const int ch = col < ncols ? child[o][col] : -1;
+                if (ch >= 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int rr = rt * 16 + drow<R>(lane, r);
+                        if (rr < K) out[((long long)ch * 2 + kern) * K + rr] += c4[r];
+                    }
                 }
             }
         }
     }
+}
+
+template <typename R, int MODE>
+void launch_trans(const TransArgs &ta, dim3 grid_items, const R *ops, const R *in, R *out,
+                  int lev, hipStream_t s) {
+    // columns per block so that the B operand fits the LDS budget
+    const size_t lim = 60 * 1024;
+    const int NRT = (ta.K + 15) / 16;
+    (void)NRT;
+    auto fits = [&](int cc) { return MODE == 1 || (size_t)ta.KK * cc * sizeof(R) <= lim; };
+    auto shmem = [&](int cc) { return MODE == 1 ? (size_t)0 : (size_t)ta.KK * cc * sizeof(R); };
+    auto grid = [&](int cc) {
+        dim3 g = grid_items;
+        if (MODE == 0) g.z = 64 / cc;
+        else g.x = (unsigned)((ta.le - ta.lb + cc - 1) / cc);
+        return g;
+    };
+    if (fits(64)) {
+        k_trans<R, 64, MODE><<<grid(64), 256, shmem(64), s>>>(ta, ops, in, out, lev);
+    } else if (fits(32)) {
+        k_trans<R, 32, MODE><<<grid(32), 256, shmem(32), s>>>(ta, ops, in, out, lev);
+    } else if (fits(16)) {
+        k_trans<R, 16, MODE><<<grid(16), 256, shmem(16), s>>>(ta, ops, in, out, lev);
+    } else {
+        throw Error(ST_INVALID, "expansion order too large for the translation kernels");
+    }
+    KCHK();
 }
 
 // L[B] = sum over V(B) in list order of the M2L products (every box written).
@@ -313,29 +432,6 @@ __global__ void k_m2l_reduce(int K, long long nbox, const int *vptr, const int *
         R acc = R(0);
         for (int q = vptr[box]; q < vptr[box + 1]; ++q) acc += Z[(long long)pos_of[q] * 2 * K + idx];
         L[box * 2 * K + idx] = acc;
-    }
-}
-
-// Children of one level take their parent's local expansion:
-// L_c[b] += sum_a U[a][b] L_P[a].
-template <typename R>
-__global__ void k_l2l(BasisDev B, TreeDev T, long long lb, long long le, const R *Ut, int nlev,
-                      R *L) {
-    long long box = lb + blockIdx.x;
-    if (box >= le) return;
-    const int P = T.parent[box];
-    const int plev = T.level[P];
-    if (plev < 2) return;
-    const int K = B.K;
-    const int oct = (int)(T.prefix[box] & 7ull);
-    for (int kern = 0; kern < 2; ++kern) {
-        const R *U = Ut + (((long long)kern * nlev + plev) * 8 + oct) * K * K;
-        const R *Lp = L + ((long long)P * 2 + kern) * K;
-        for (int bb = threadIdx.x; bb < K; bb += blockDim.x) {
-            R acc = R(0);
-            for (int a = 0; a < K; ++a) acc += U[(long long)bb * K + a] * Lp[a];
-            L[((long long)box * 2 + kern) * K + bb] += acc;
-        }
     }
 }
 
@@ -518,32 +614,30 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
                                                      sf, sh, R(inv_ebar), w.M);
         KCHK();
     }
+    TransArgs ta{};
+    ta.K = K;
+    ta.KK = (K + 3) / 4 * 4;
+    ta.nlev = F.nlev;
+    ta.nkey = F.nkey;
+    ta.item_key = L.m2l_item_key.p;
+    ta.item_begin = L.m2l_item_begin.p;
+    ta.item_count = L.m2l_item_count.p;
+    ta.pairs = L.m2l_pairs.p;
+    ta.vidx = L.v_idx.p;
+    ta.cb = t.child_begin.p;
+    ta.nc = t.n_child.p;
+    ta.prefix = t.prefix.p;
     {
         ProfScope ps(prof, "m2m", s);
         for (int lev = t.nlev - 2; lev >= 2; --lev) {
-            long long lb = t.level_start[lev], le = t.level_start[lev + 1];
-            k_m2m<R><<<(unsigned)(le - lb), 64, 0, s>>>(B, T, lb, le, ops_U<R>(F), F.nlev, w.M);
-            KCHK();
+            ta.lb = t.level_start[lev];
+            ta.le = t.level_start[lev + 1];
+            launch_trans<R, 1>(ta, dim3(1, 2), ops_U<R>(F), w.M, w.M, lev, s);
         }
     }
     if (L.n_m2l_items > 0) {
         ProfScope ps(prof, "m2l", s);
-        dim3 grid((unsigned)L.n_m2l_items, 2);
-        const size_t lim = 64 * 1024;
-        if ((size_t)K * 64 * sizeof(R) <= lim) {
-            k_m2l<R, 64><<<grid, 256, (size_t)K * 64 * sizeof(R), s>>>(
-                K, L.m2l_item_key.p, L.m2l_item_begin.p, L.m2l_item_count.p, L.m2l_pairs.p,
-                L.v_idx.p, ops_T<R>(F), F.nkey, w.M, w.Z);
-        } else if ((size_t)K * 32 * sizeof(R) <= lim) {
-            k_m2l<R, 32><<<grid, 256, (size_t)K * 32 * sizeof(R), s>>>(
-                K, L.m2l_item_key.p, L.m2l_item_begin.p, L.m2l_item_count.p, L.m2l_pairs.p,
-                L.v_idx.p, ops_T<R>(F), F.nkey, w.M, w.Z);
-        } else {
-            k_m2l<R, 16><<<grid, 256, (size_t)K * 16 * sizeof(R), s>>>(
-                K, L.m2l_item_key.p, L.m2l_item_begin.p, L.m2l_item_count.p, L.m2l_pairs.p,
-                L.v_idx.p, ops_T<R>(F), F.nkey, w.M, w.Z);
-        }
-        KCHK();
+        launch_trans<R, 0>(ta, dim3((unsigned)L.n_m2l_items, 2), ops_T<R>(F), w.M, w.Z, 0, s);
     }
     {
         ProfScope ps(prof, "m2l_reduce", s);
@@ -552,10 +646,10 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "l2l", s);
-        for (int lev = 3; lev < t.nlev; ++lev) {
-            long long lb = t.level_start[lev], le = t.level_start[lev + 1];
-            k_l2l<R><<<(unsigned)(le - lb), 64, 0, s>>>(B, T, lb, le, ops_U<R>(F), F.nlev, w.Lc);
-            KCHK();
+        for (int lev = 2; lev + 1 < t.nlev; ++lev) {
+            ta.lb = t.level_start[lev];
+            ta.le = t.level_start[lev + 1];
+            launch_trans<R, 2>(ta, dim3(1, 2), ops_U<R>(F), w.Lc, w.Lc, lev, s);
         }
     }
     {

@@ -22,7 +22,8 @@ struct MatvecPlan {
     NodeR<R> nd{};             // node data in the working precision
     const double *area = nullptr;
     double kappa = 0, inv_ebar = 0, alpha = 0;
-    R *sf = nullptr, *sh = nullptr, *pf = nullptr, *ph = nullptr;
+    R *sf = nullptr, *sh = nullptr;
+    double *pf = nullptr, *ph = nullptr;   // P2P sums (double in both precisions)
     FarWork<R> far{};
 };
 

@@ -13,66 +13,114 @@ namespace afmpb {
 
 namespace {
 
-// Two-sum compensated accumulator (used for single precision).
-template <typename R>
-struct CompSum {
-    R s = R(0), c = R(0);
-    __device__ void add(R v) {
-        R t = s + v;
-        R bp = t - s;
-        c += (s - (t - bp)) + (v - bp);
-        s = t;
-    }
-    __device__ R value() const { return s + c; }
+// Per-pair arithmetic of the P2P kernel.  The 1/(4 pi) factor is applied to
+// the final sums.  1 - e^{-s}, a(s), b(s) come from their Taylor series below
+// s = 0.1, from e^{-s} above (no cancellation either way).
+template <typename R> struct Fast;
+template <> struct Fast<double> {
+    static __device__ inline double rsq(double x) { return 1.0 / sqrt(x); }
+    static __device__ inline double ex(double x) { return exp(x); }
+    static constexpr int NSER = 10;
+};
+template <> struct Fast<float> {
+    static __device__ inline float rsq(float x) { return rsqrtf(x); }
+    static __device__ inline float ex(float x) { return __expf(x); }
+    static constexpr int NSER = 6;
 };
 
-template <typename R>
-__global__ void __launch_bounds__(64) k_p2p(const int *__restrict__ item_leaf,
-                                            const int *__restrict__ item_begin,
-                                            const int *__restrict__ leaf_ids,
-                                            const int *__restrict__ src_ptr,
-                                            const int *__restrict__ src_box,
-                                            const int *__restrict__ ptb, const int *__restrict__ pte,
-                                            NodeR<R> nd, const R *__restrict__ sf,
-                                            const R *__restrict__ sh, R kappa, R inv_ebar,
-                                            R *__restrict__ out_f, R *__restrict__ out_h) {
-    __shared__ R S[8][64];
-    const int w = blockIdx.x, lane = threadIdx.x;
-    const int li = item_leaf[w];
-    const int box = leaf_ids[li];
-    const int i = item_begin[w] + lane;
-    const bool act = i < pte[box];
-    const R x = act ? nd.x[i] : R(0), y = act ? nd.y[i] : R(0), z = act ? nd.z[i] : R(0);
-    const R n0x = act ? nd.nx[i] : R(0), n0y = act ? nd.ny[i] : R(0), n0z = act ? nd.nz[i] : R(0);
-    CompSum<R> af, ah;
-    for (int q = src_ptr[li]; q < src_ptr[li + 1]; ++q) {
-        const int C = src_box[q];
-        const int cb = ptb[C], ce = pte[C];
-        for (int s0 = cb; s0 < ce; s0 += 64) {
-            const int j = s0 + lane;
-            __syncthreads();
-            if (j < ce) {
-                S[0][lane] = nd.x[j]; S[1][lane] = nd.y[j]; S[2][lane] = nd.z[j];
-                S[3][lane] = nd.nx[j]; S[4][lane] = nd.ny[j]; S[5][lane] = nd.nz[j];
-                S[6][lane] = sf[j]; S[7][lane] = sh[j];
-            }
-            __syncthreads();
-            const int cnt = min(64, ce - s0);
-            if (act) {
-                for (int jj = 0; jj < cnt; ++jj) {
-                    if (s0 + jj == i) continue;
-                    Abcd<R> k = abcd_point(x - S[0][jj], y - S[1][jj], z - S[2][jj], n0x, n0y,
-                                           n0z, S[3][jj], S[4][jj], S[5][jj], kappa, inv_ebar);
-                    const R f = S[6][jj], h = S[7][jj];
-                    af.add(k.B * f - k.A * h);
-                    ah.add(k.D * f - k.C * h);
-                }
-            }
+// Taylor coefficients of om(s) = 1 - e^{-s}, a(s), b(s) (see kernels.h)
+struct P2PSeries {
+    double om[11], a[11], b[11];
+    constexpr P2PSeries() : om(), a(), b() {
+        double fact = 1.0;
+        for (int k = 1; k <= 10; ++k) {
+            fact *= k;
+            double sg = (k & 1) ? -1.0 : 1.0;
+            om[k] = -sg / fact;
+            a[k] = (k >= 2) ? sg * (k - 1) / fact : 0.0;
+            b[k] = (k >= 2) ? -sg * (double)((k - 1) * (k - 3)) / fact : 0.0;
         }
     }
-    if (act) {
-        out_f[i] = af.value();
-        out_h[i] = ah.value();
+};
+
+template <typename R, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_p2p(
+    const int *__restrict__ item_leaf, const int *__restrict__ item_begin,
+    const int *__restrict__ leaf_ids, const int *__restrict__ src_ptr,
+    const int *__restrict__ src_box, const int *__restrict__ ptb, const int *__restrict__ pte,
+    NodeR<R> nd, const R *__restrict__ sf, const R *__restrict__ sh, R kappa, R inv_ebar,
+    double *__restrict__ out_f, double *__restrict__ out_h) {
+    constexpr P2PSeries S;
+    __shared__ double red[2][WAVES][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int w = blockIdx.x;
+    const int li = item_leaf[w];
+    const int box = leaf_ids[li];
+    const int i0 = item_begin[w];
+    const int i = i0 + lane;
+    const bool act = i < pte[box];
+    const int ii = act ? i : i0;
+    const R x = nd.x[ii], y = nd.y[ii], z = nd.z[ii];
+    const R n0x = nd.nx[ii], n0y = nd.ny[ii], n0z = nd.nz[ii];
+    double af = 0.0, ah = 0.0;
+    for (int q = src_ptr[li] + wave; q < src_ptr[li + 1]; q += WAVES) {
+        const int C = src_box[q];
+        const int cb = ptb[C], ce = pte[C];
+        R bf = R(0), bh = R(0);
+        for (int j = cb; j < ce; ++j) {
+            const R rx = x - nd.x[j], ry = y - nd.y[j], rz = z - nd.z[j];
+            const R snx = nd.nx[j], sny = nd.ny[j], snz = nd.nz[j];
+            const R f = sf[j], h = sh[j];
+            const bool self = (j == i);
+            R r2 = (rx * rx + ry * ry) + rz * rz;
+            r2 = self ? R(1) : r2;
+            const R ir = Fast<R>::rsq(r2);
+            const R r = r2 * ir;
+            const R s = kappa * r;
+            const R e = Fast<R>::ex(-s);
+            R om, fa, fb;
+            if (s < R(0.1)) {
+                constexpr int N = Fast<R>::NSER;
+                R po = R(S.om[N]), pa = R(S.a[N]), pb = R(S.b[N]);
+#pragma unroll
+                for (int k = N - 1; k >= 2; --k) {
+                    po = po * s + R(S.om[k]);
+                    pa = pa * s + R(S.a[k]);
+                    pb = pb * s + R(S.b[k]);
+                }
+                om = (po * s + R(1)) * s;
+                fa = pa * s * s;
+                fb = pb * s * s;
+            } else {
+                om = R(1) - e;
+                fa = om - s * e;
+                fb = R(3) * om - e * s * (R(3) + s);
+            }
+            const R Rn = (rx * snx + ry * sny) + rz * snz;
+            const R Rn0 = (rx * n0x + ry * n0y) + rz * n0z;
+            const R n0n = (n0x * snx + n0y * sny) + n0z * snz;
+            const R ir3 = ir * ir * ir;
+            const R e1 = e * (R(1) + s);
+            const R A = om * ir;
+            const R B = Rn * ir3 * (inv_ebar - e1);
+            const R Cc = Rn0 * ir3 * (e1 * inv_ebar - R(1));
+            const R D = inv_ebar * ir3 * (n0n * fa - Rn0 * Rn * fb * ir * ir);
+            const R m = self ? R(0) : R(1);
+            bf += m * (B * f - A * h);
+            bh += m * (D * f - Cc * h);
+        }
+        af += (double)bf;
+        ah += (double)bh;
+    }
+    red[0][wave][lane] = af;
+    red[1][wave][lane] = ah;
+    __syncthreads();
+    if (wave == 0 && act) {
+        double tf = 0.0, th = 0.0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) { tf += red[0][k][lane]; th += red[1][k][lane]; }
+        out_f[i] = tf * INV_4PI;
+        out_h[i] = th * INV_4PI;
     }
 }
 
@@ -88,8 +136,8 @@ __global__ void k_gather_sources(const double *__restrict__ x, const double *__r
 // One group of 8 lanes per row for the near correction; the row's result is
 // combined with every other part of the matvec.
 template <typename R>
-__global__ void k_combine(long long n, const double *__restrict__ x, const R *__restrict__ pf,
-                          const R *__restrict__ ph, const R *__restrict__ phi,
+__global__ void k_combine(long long n, const double *__restrict__ x, const double *__restrict__ pf,
+                          const double *__restrict__ ph, const R *__restrict__ phi,
                           const long long *__restrict__ nptr, const int *__restrict__ ncol,
                           const double *__restrict__ nd, double alpha, double inv_ebar,
                           double *__restrict__ y) {
@@ -114,8 +162,8 @@ __global__ void k_combine(long long n, const double *__restrict__ x, const R *__
     if (p < n && sub == 0) {
         double far_f = -(double)phi[p] + (double)phi[2 * n + p];
         double far_h = -(double)phi[n + p] + inv_ebar * (double)phi[3 * n + p];
-        y[p] = alpha * x[p] + (double)pf[p] + far_f + cf;
-        y[n + p] = alpha * x[n + p] + (double)ph[p] + far_h + ch;
+        y[p] = alpha * x[p] + pf[p] + far_f + cf;
+        y[n + p] = alpha * x[n + p] + ph[p] + far_h + ch;
     }
 }
 
@@ -162,10 +210,10 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
     {
         ProfScope ps(prof, "p2p", s);
         const Lists &L = *mp.lists;
-        k_p2p<R><<<(unsigned)L.n_items, 64, 0, s>>>(L.item_box.p, L.item_begin.p, L.leaf_ids.p,
-                                                    L.p2p_ptr.p, L.p2p_src.p, mp.tree->pt_begin.p,
-                                                    mp.tree->pt_end.p, mp.nd, mp.sf, mp.sh,
-                                                    R(mp.kappa), R(mp.inv_ebar), mp.pf, mp.ph);
+        k_p2p<R, 4><<<(unsigned)L.n_items, 256, 0, s>>>(
+            L.item_box.p, L.item_begin.p, L.leaf_ids.p, L.p2p_ptr.p, L.p2p_src.p,
+            mp.tree->pt_begin.p, mp.tree->pt_end.p, mp.nd, mp.sf, mp.sh, R(mp.kappa),
+            R(mp.inv_ebar), mp.pf, mp.ph);
         KCHK();
     }
     {

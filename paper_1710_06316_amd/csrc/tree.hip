@@ -308,7 +308,8 @@ __global__ void k_leaf_collect(long long nbox, const int *flag, const int *pos, 
 // Per leaf: number of P2P source boxes, work items, and point pairs.
 __global__ void k_p2p_count(TreeView t, long long nleaf, const int *leaf_ids, const int *uptr,
                             const int *uidx, const int *wptr, const int *widx, const int *xptr,
-                            const int *xidx, int *nsrc, int *nitem, long long *npairs) {
+                            const int *xidx, int *nsrc, int *nitem, long long *npairs,
+                            long long *srcpts) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nleaf) return;
     int B = leaf_ids[i];
@@ -324,6 +325,7 @@ __global__ void k_p2p_count(TreeView t, long long nleaf, const int *leaf_ids, co
     nsrc[i] = cnt;
     nitem[i] = (int)((npt + 63) / 64);
     npairs[i] = npt * src_pts - npt;
+    srcpts[i] = src_pts;
 }
 
 __global__ void k_p2p_fill(TreeView t, long long nleaf, const int *leaf_ids, const int *uptr,
@@ -491,10 +493,10 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
     KCHK();
     const long long nl = L.n_leaves;
     DBuf<int> nsrc(nl + 1), nitem(nl + 1), iptr(nl + 1);
-    DBuf<long long> npairs(nl + 1);
+    DBuf<long long> npairs(nl + 1), srcpts(nl + 1);
     k_p2p_count<<<grid_for(nl, 128), 128, 0, s>>>(tv, nl, L.leaf_ids.p, L.u_ptr.p, L.u_idx.p,
                                                   L.w_ptr.p, L.w_idx.p, L.x_ptr.p, L.x_idx.p,
-                                                  nsrc.p, nitem.p, npairs.p);
+                                                  nsrc.p, nitem.p, npairs.p, srcpts.p);
     KCHK();
     L.p2p_ptr.alloc(nl + 1);
     exclusive_scan_i32(nsrc.p, L.p2p_ptr.p, nl, s);
@@ -512,6 +514,31 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
                                                  L.item_box.p, L.item_begin.p, err.p);
     KCHK();
     require(read_scalar(err.p, s) == 0, ST_DEVICE, "P2P task fill out of range");
+    {
+        // heaviest work items first (targets x source points), stable
+        std::vector<int> ib(L.n_items), ibeg(L.n_items), leaf(nl);
+        std::vector<long long> sp(nl);
+        std::vector<int> pte_h(nb);
+        L.item_box.download(ib.data(), L.n_items, s);
+        L.item_begin.download(ibeg.data(), L.n_items, s);
+        L.leaf_ids.download(leaf.data(), nl, s);
+        srcpts.download(sp.data(), nl, s);
+        t.pt_end.download(pte_h.data(), nb, s);
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<long long> cost(L.n_items);
+        for (long long k = 0; k < L.n_items; ++k) {
+            long long tg = std::min(64, pte_h[leaf[ib[k]]] - ibeg[k]);
+            cost[k] = tg * sp[ib[k]];
+        }
+        std::vector<int> ord(L.n_items);
+        for (long long k = 0; k < L.n_items; ++k) ord[k] = (int)k;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        std::vector<int> ib2(L.n_items), ibeg2(L.n_items);
+        for (long long k = 0; k < L.n_items; ++k) { ib2[k] = ib[ord[k]]; ibeg2[k] = ibeg[ord[k]]; }
+        L.item_box.upload(ib2.data(), L.n_items, s);
+        L.item_begin.upload(ibeg2.data(), L.n_items, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
     // M2L buckets by (level, class), chunks of <= 64 entries
     const long long nv = L.n_v;
     L.m2l_pairs.alloc(nv);

@@ -242,12 +242,15 @@ def _density(atoms, radii, lo, h, shape, beta, trunc=3.0):
 
 
 def gaussian_surface(atoms, radii, h_grid: float, beta: float = 2.0,
-                     pad: float = 5.0, level: float = 1.0):
+                     pad: float = 5.0, level: float = 1.0, clamp: float = 0.25):
     """Closed, outward-oriented triangulation of {rho = level}.
 
     Marching tetrahedra over the Freudenthal split of the grid cubes; mesh
     vertices sit on grid edges (welded by edge id) with the interpolation
-    parameter clamped to [0.01, 0.99], so no vertex lands on a grid point.
+    parameter clamped to [0.25, 0.75]: every vertex stays a quarter edge away
+    from the grid points, which bounds the triangle quality from below
+    (slivers from vertices next to a grid point make the node-patch system
+    ill-conditioned and inaccurate).
     Triangles are oriented toward decreasing density (out of the molecule).
     """
     atoms = np.asarray(atoms, dtype=np.float64)
@@ -293,7 +296,7 @@ def gaussian_surface(atoms, radii, h_grid: float, beta: float = 2.0,
         v = edge_key_to_vid.get(k)
         if v is None:
             t = fa / (fa - fb)
-            t = min(0.99, max(0.01, t))
+            t = min(1.0 - clamp, max(clamp, t))
             pa = np.array(np.unravel_index(a, shape), dtype=np.float64)
             pb = np.array(np.unravel_index(b, shape), dtype=np.float64)
             p = lo + h_grid * (pa + t * (pb - pa))
