@@ -12,7 +12,9 @@ LIB = os.path.join(HERE, "libafmpb.so")
 SOURCES = ["prims", "geometry", "tree", "near", "fmm", "matvec", "krylov", "api"]
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",
          # no packed FP32 instructions anywhere in the device code
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # keep matrix-core accumulators in VGPRs (no per-step AGPR copies)
+         "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def build(verbose: bool = False) -> str:

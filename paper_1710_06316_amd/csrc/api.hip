@@ -166,7 +166,7 @@ struct afmpb_ctx {
     Lists lists;
     NearSet near;
     Fmm fmm;
-    DBuf<double> w64, far64, p2p64;
+    DBuf<double> w64, far64, p2p64, p2p_part;
     DBuf<float> w32, far32;
     MatvecPlan<double> mp64;
     MatvecPlan<float> mp32;
@@ -268,7 +268,14 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     const long long n = c->n, K = c->fmm.K, nb = c->tree.nbox, nv = c->lists.n_v;
     w.alloc((size_t)2 * n);
     if (c->p2p64.n < (size_t)2 * n) c->p2p64.alloc((size_t)2 * n);
-    far.alloc((size_t)(2 * nb * K) * 2 + (size_t)std::max(nv, 1ll) * 2 * K + 4 * n);
+    if (c->p2p_part.n < (size_t)c->lists.n_chunks * 128)
+        c->p2p_part.alloc((size_t)std::max(c->lists.n_chunks, 1ll) * 128);
+    mp.part = c->p2p_part.p;
+    long long widest = 1;
+    for (int l = 0; l < c->tree.nlev; ++l)
+        widest = std::max(widest, c->tree.level_start[l + 1] - c->tree.level_start[l]);
+    far.alloc((size_t)(2 * nb * K) * 2 + (size_t)std::max(nv, 1ll) * 2 * K + 4 * n +
+              (size_t)8 * widest * 2 * K);
     mp.n = n;
     mp.tree = &c->tree;
     mp.lists = &c->lists;
@@ -289,6 +296,7 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.far.Lc = f + 2 * nb * K;
     mp.far.Z = f + 4 * nb * K;
     mp.far.phi = f + 4 * nb * K + std::max(nv, 1ll) * 2 * K;
+    mp.far.Mt = mp.far.phi + 4 * n;
 }
 
 void check_setup(afmpb_ctx *c);
@@ -338,6 +346,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
     // translation operators
     c->fmm = Fmm();
     c->p2p64 = DBuf<double>();
+    c->p2p_part = DBuf<double>();
     build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa, c->fmm, s);
     setup_plan<double>(c, c->mp64, c->w64, c->far64, c->node64.p);
     setup_plan<float>(c, c->mp32, c->w32, c->far32, c->node32.p);
@@ -427,6 +436,25 @@ void check_setup(afmpb_ctx *c) {
         if (ib[k] < 0 || ib[k] >= L.n_leaves) bad("P2P item leaf");
         int B = leaf[ib[k]];
         if (ibeg[k] < ptb[B] || ibeg[k] >= pte[B]) bad("P2P item begin");
+    }
+    {
+        auto clo = host_copy(L.ch_lo, L.n_chunks, s), chi = host_copy(L.ch_hi, L.n_chunks, s);
+        auto cg = host_copy(L.ch_grp, L.n_chunks, s);
+        auto rb = host_copy(L.rng_b, L.n_rng, s), re = host_copy(L.rng_e, L.n_rng, s);
+        auto gp = host_copy(L.grp_ptr, L.n_groups + 1, s);
+        auto gb = host_copy(L.grp_tbeg, L.n_groups, s), ge = host_copy(L.grp_tend, L.n_groups, s);
+        c->sync();
+        for (long long k = 0; k < L.n_rng; ++k)
+            if (rb[k] < 0 || re[k] > n || rb[k] >= re[k]) bad("P2P source range");
+        for (long long k = 0; k < L.n_chunks; ++k) {
+            if (clo[k] < 0 || chi[k] > L.n_rng || clo[k] >= chi[k]) bad("P2P chunk span");
+            if (cg[k] < 0 || cg[k] >= L.n_groups || k < gp[cg[k]] || k >= gp[cg[k] + 1]) bad("P2P chunk group");
+        }
+        if (gp[0] != 0 || gp[L.n_groups] != L.n_chunks) bad("P2P group ptr");
+        for (long long g = 0; g < L.n_groups; ++g) {
+            if (gp[g + 1] <= gp[g]) bad("P2P group without chunks");
+            if (gb[g] < 0 || ge[g] > n || gb[g] >= ge[g] || ge[g] - gb[g] > 64) bad("P2P group targets");
+        }
     }
     if (L.n_m2l_items > 0) {
         auto ik = host_copy(L.m2l_item_key, L.n_m2l_items, s);

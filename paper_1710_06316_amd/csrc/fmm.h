@@ -26,7 +26,13 @@ struct Fmm {
     DBuf<double> norm, inv_dfact, ginv, kinv, weight, side;
     DBuf<double> T;                      // [2][nkey][K][K] M2L, row = local index
     DBuf<double> Ut;                     // [2][nlev][8][K][K] transposed M2M operator
-    DBuf<float> T32, Ut32;               // single-precision copies
+    // Operators in matrix-core operand order: per matrix [K/16 row tiles]
+    // [KK/4 k-steps][64 lanes], lane l holding A[16 rt + l%16][4 ks + l/16]
+    // (zero padded); PM elements per matrix.
+    long long PM = 0;
+    int KK = 0;
+    DBuf<double> Tp, Up, Lp;             // M2L, M2M (A = U), L2L (A = U^T)
+    DBuf<float> Tp32, Up32, Lp32;
     DBuf<int> pos_of;                    // V entry -> position in bucket order
     BasisDev dev() const {
         return BasisDev{P, K, screened, kappa, norm.p, inv_dfact.p, ginv.p, side.p};
@@ -42,6 +48,7 @@ void build_fmm_operators(const Tree &t, const Lists &L, int P, double kappa, Fmm
 template <typename R>
 struct FarWork {
     R *M, *Lc, *Z, *phi;       // [nbox][2][K], [nbox][2][K], [n_v][2][K], [4][n]
+    R *Mt;                     // [8][widest level][2][K] per-octant M2M products
 };
 
 template <typename R>

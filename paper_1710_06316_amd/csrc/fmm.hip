@@ -186,6 +186,26 @@ __global__ void k_project_gemm(const double *A, const double *Bm, const double *
     if (i < K && j < K) C[desc[m].dst + (long long)i * K + j] = rs[(long long)m * K + i] * acc;
 }
 
+// packed[m][rt][ks][l] = A_m[16 rt + l % 16][4 ks + l / 16], A_m = op_m or its
+// transpose, zero outside K x K.
+__global__ void k_pack(const double *__restrict__ src, long long nmat, int K, int KK, int NRT,
+                       int transpose, double *__restrict__ dst, float *__restrict__ dst32) {
+    const long long PM = (long long)NRT * 16 * KK;
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nmat * PM) return;
+    const long long m = id / PM;
+    const long long r = id % PM;
+    const int l = (int)(r % 64);
+    const long long tk = r / 64;
+    const int ks = (int)(tk % (KK / 4)), rt = (int)(tk / (KK / 4));
+    const int row = rt * 16 + (l & 15), k = ks * 4 + (l >> 4);
+    double v = 0.0;
+    if (row < K && k < K)
+        v = transpose ? src[m * K * K + (long long)k * K + row] : src[m * K * K + (long long)row * K + k];
+    dst[id] = v;
+    dst32[id] = (float)v;
+}
+
 __global__ void k_to_float(const double *a, float *b, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = (float)a[i];
@@ -269,11 +289,12 @@ template <> __device__ inline int drow<float>(int lane, int r) { return 4 * (lan
 
 struct TransArgs {
     int K, KK, nlev;
-    long long nkey;
+    long long nkey, PM;
     // M2L
     const int *item_key, *item_begin, *item_count, *pairs, *vidx;
     // M2M / L2L
     long long lb, le;            // boxes of the parent level
+    long long ncap;              // mode 1: capacity (boxes) of one octant slice of the scratch
     const int *cb, *nc;          // child begin / count
     const unsigned long long *prefix;
 };
@@ -283,15 +304,17 @@ __global__ void __launch_bounds__(256) k_trans(TransArgs a, const R *__restrict_
                                                const R *__restrict__ in, R *__restrict__ out,
                                                int lev) {
     extern __shared__ unsigned char smem_raw[];
-    R *Ms = reinterpret_cast<R *>(smem_raw);         // [KK][CC] (modes 0 and 2)
+    R *Ms = reinterpret_cast<R *>(smem_raw);         // [CC][KK|1]
     __shared__ int colbox[CC];                         // column -> bucket position / box
     __shared__ int child[8][CC];                       // modes 1, 2: child of octant o
     typedef typename Acc4<R>::T V4;
-    const int K = a.K, KK = a.KK;
+    constexpr int NCT = CC / 16;
+    const int K = a.K, KK = a.KK, KS = KK / 4, KKp = KK | 1;
     const int kern = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int NRT = (K + 15) / 16, NCT = CC / 16, NT = NRT * NCT;
-    const long long KK2 = (long long)K * K;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int NRT = (K + 15) / 16;
+    const int o = (MODE == 0) ? 0 : (int)blockIdx.z;  // child octant (modes 1, 2)
     int ncols;
     const R *op0;
     if (MODE == 0) {
@@ -302,122 +325,127 @@ __global__ void __launch_bounds__(256) k_trans(TransArgs a, const R *__restrict_
         if (ncols <= 0) return;                          // uniform for the block
         const int beg = a.item_begin[w] + off;
         if (tid < CC) colbox[tid] = tid < ncols ? beg + tid : -1;
-        op0 = ops + ((long long)kern * a.nkey + a.item_key[w]) * KK2;
+        op0 = ops + ((long long)kern * a.nkey + a.item_key[w]) * a.PM;
     } else {
         const long long c0 = a.lb + (long long)blockIdx.x * CC;
         ncols = (int)min((long long)CC, a.le - c0);
         if (tid < CC) {
             colbox[tid] = tid < ncols ? (int)(c0 + tid) : -1;
-            for (int o = 0; o < 8; ++o) child[o][tid] = -1;
+            for (int q = 0; q < 8; ++q) child[q][tid] = -1;
             if (tid < ncols) {
                 const int P = (int)(c0 + tid);
                 for (int c = a.cb[P]; c < a.cb[P] + a.nc[P]; ++c)
                     child[(int)(a.prefix[c] & 7ull)][tid] = c;
             }
         }
-        op0 = ops + (((long long)kern * a.nlev + lev) * 8) * KK2;
+        op0 = ops + ((((long long)kern * a.nlev + lev) * 8) + o) * a.PM;
     }
     __syncthreads();
-    if (MODE != 1) {
-        for (int idx = tid; idx < KK * CC; idx += 256) {
-            const int k = idx / CC, c = idx % CC;
-            R v = R(0);
-            if (k < K && c < ncols) {
-                const int src = (MODE == 0) ? a.vidx[a.pairs[colbox[c]]] : colbox[c];
-                v = in[((long long)src * 2 + kern) * K + k];
-            }
-            Ms[idx] = v;
+    // gather the B operand column-major (consecutive threads read consecutive
+    // coefficients of one expansion); missing columns are zero
+    for (int idx = tid; idx < KK * CC; idx += 256) {
+        const int c = idx / KK, k = idx % KK;
+        R v = R(0);
+        if (k < K && c < ncols) {
+            const int src = (MODE == 0) ? a.vidx[a.pairs[colbox[c]]]
+                          : (MODE == 1) ? child[o][c] : colbox[c];
+            if (src >= 0) v = in[((long long)src * 2 + kern) * K + k];
         }
-        __syncthreads();
+        Ms[c * KKp + k] = v;
     }
-    for (int t = wave; t < NT; t += 4) {
-        const int rt = t / NCT, ct = t % NCT;
-        const int row = rt * 16 + (lane & 15);
-        const int col = ct * 16 + (lane & 15);       // B column / output column of this lane
-        if (MODE == 0) {
-            V4 c4 = V4{0, 0, 0, 0};
-            for (int k0 = 0; k0 < KK; k0 += 4) {
-                const int k = k0 + (lane >> 4);
-                const R av = (row < K && k < K) ? op0[(long long)row * K + k] : R(0);
-                c4 = mfma16(av, Ms[k * CC + col], c4);
-            }
-            if (col < ncols) {
-                const long long dst = ((long long)colbox[col] * 2 + kern) * K;
+    __syncthreads();
+    // one row tile per pass over all column tiles: each operator fragment is
+    // loaded once (four k-steps ahead) and used NCT times
+    const R *Bp = Ms + (lane & 15) * KKp + (lane >> 4);
+    for (int rt = wave; rt < NRT; rt += 4) {
+        const R *A = op0 + (long long)rt * KS * 64 + lane;
+        V4 acc[NCT];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int rr = rt * 16 + drow<R>(lane, r);
-                    if (rr < K) out[dst + rr] = c4[r];
-                }
-            }
-        } else if (MODE == 1) {
-            // M_P[row] = sum_o sum_k U_o[row][k] M_{child o}[k],  U_o[row][k] = Ut_o[k][row]
-            V4 c4 = V4{0, 0, 0, 0};
-            for (int o = 0; o < 8; ++o) {
-                const int ch = col < ncols ? child[o][col] : -1;
-                const R *op = op0 + o * KK2;
-                const R *Mc = in + ((long long)(ch < 0 ? 0 : ch) * 2 + kern) * K;
-                for (int k0 = 0; k0 < KK; k0 += 4) {
-                    const int k = k0 + (lane >> 4);
-                    const R av = (row < K && k < K) ? op[(long long)k * K + row] : R(0);
-                    const R bv = (ch >= 0 && k < K) ? Mc[k] : R(0);
-                    c4 = mfma16(av, bv, c4);
-                }
-            }
-            const int P = col < ncols ? colbox[col] : -1;
-            if (P >= 0 && a.nc[P] > 0) {                 // leaves keep their P2M moments
-                const long long dst = ((long long)P * 2 + kern) * K;
+        for (int ct = 0; ct < NCT; ++ct) acc[ct] = V4{0, 0, 0, 0};
+        R pre[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int rr = rt * 16 + drow<R>(lane, r);
-                    if (rr < K) out[dst + rr] = c4[r];
+        for (int j = 0; j < 4; ++j) pre[j] = A[j * 64];
+        for (int ks = 0; ks < KS; ks += 4) {
+            R cur[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                cur[j] = pre[j];
+                pre[j] = A[(ks + 4 + j) * 64];   // in bounds: operators carry a tail pad
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (ks + j < KS) {
+#pragma unroll
+                    for (int ct = 0; ct < NCT; ++ct)
+                        acc[ct] = mfma16(cur[j], Bp[ct * 16 * KKp + (ks + j) * 4], acc[ct]);
                 }
             }
-        } else {
-            // L_{child o}[row] += sum_k Ut_o[row][k] L_P[k]
-            for (int o = 0; o < 8; ++o) {
-                const R *op = op0 + o * KK2;
-                V4 c4 = V4{0, 0, 0, 0};
-                for (int k0 = 0; k0 < KK; k0 += 4) {
-                    const int k = k0 + (lane >> 4);
-                    const R av = (row < K && k < K) ? op[(long long)row * K + k] : R(0);
-                    c4 = mfma16(av, Ms[k * CC + col], c4);
-                }
-                const int ch = col < ncols ? child[o][col] : -1;
-                if (ch >= 0) {
+        }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int rr = rt * 16 + drow<R>(lane, r);
-                        if (rr < K) out[((long long)ch * 2 + kern) * K + rr] += c4[r];
-                    }
+        for (int ct = 0; ct < NCT; ++ct) {
+            const int col = ct * 16 + (lane & 15);
+            if (col >= ncols) continue;
+            long long dst;
+            if (MODE == 0) {
+                dst = ((long long)colbox[col] * 2 + kern) * K;
+            } else if (MODE == 1) {
+                // per-octant product of parent column col (summed by k_m2m_sum)
+                dst = (((long long)o * a.ncap + (colbox[col] - a.lb)) * 2 + kern) * K;
+            } else {
+                const int ch = child[o][col];
+                if (ch < 0) continue;
+                dst = ((long long)ch * 2 + kern) * K;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = rt * 16 + drow<R>(lane, r);
+                if (rr < K) {
+                    if (MODE == 2) out[dst + rr] += acc[ct][r];
+                    else out[dst + rr] = acc[ct][r];
                 }
             }
         }
     }
 }
 
+// M of the non-leaf boxes of one level = sum over the 8 octant products.
+template <typename R>
+__global__ void k_m2m_sum(int K, long long lb, long long le, long long ncap,
+                          const int *__restrict__ nc, const R *__restrict__ part,
+                          R *__restrict__ M) {
+    const long long P = lb + blockIdx.x;
+    if (P >= le || nc[P] == 0) return;
+    for (int idx = threadIdx.x; idx < 2 * K; idx += blockDim.x) {
+        R acc = R(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += part[((long long)q * ncap + (P - lb)) * 2 * K + idx];
+        M[P * 2 * K + idx] = acc;
+    }
+}
+
 template <typename R, int MODE>
 void launch_trans(const TransArgs &ta, dim3 grid_items, const R *ops, const R *in, R *out,
                   int lev, hipStream_t s) {
-    // columns per block so that the B operand fits the LDS budget
     const size_t lim = 60 * 1024;
-    const int NRT = (ta.K + 15) / 16;
-    (void)NRT;
-    auto fits = [&](int cc) { return MODE == 1 || (size_t)ta.KK * cc * sizeof(R) <= lim; };
-    auto shmem = [&](int cc) { return MODE == 1 ? (size_t)0 : (size_t)ta.KK * cc * sizeof(R); };
-    auto grid = [&](int cc) {
+    auto shmem = [&](int cc) { return (size_t)(ta.KK | 1) * cc * sizeof(R); };
+    if (MODE == 0) {
         dim3 g = grid_items;
-        if (MODE == 0) g.z = 64 / cc;
-        else g.x = (unsigned)((ta.le - ta.lb + cc - 1) / cc);
-        return g;
-    };
-    if (fits(64)) {
-        k_trans<R, 64, MODE><<<grid(64), 256, shmem(64), s>>>(ta, ops, in, out, lev);
-    } else if (fits(32)) {
-        k_trans<R, 32, MODE><<<grid(32), 256, shmem(32), s>>>(ta, ops, in, out, lev);
-    } else if (fits(16)) {
-        k_trans<R, 16, MODE><<<grid(16), 256, shmem(16), s>>>(ta, ops, in, out, lev);
+        if (shmem(64) <= lim) {
+            g.z = 1;
+            k_trans<R, 64, 0><<<g, 256, shmem(64), s>>>(ta, ops, in, out, lev);
+        } else if (shmem(32) <= lim) {
+            g.z = 2;
+            k_trans<R, 32, 0><<<g, 256, shmem(32), s>>>(ta, ops, in, out, lev);
+        } else if (shmem(16) <= lim) {
+            g.z = 4;
+            k_trans<R, 16, 0><<<g, 256, shmem(16), s>>>(ta, ops, in, out, lev);
+        } else {
+            throw Error(ST_INVALID, "expansion order too large for the translation kernels");
+        }
     } else {
-        throw Error(ST_INVALID, "expansion order too large for the translation kernels");
+        require(shmem(16) <= lim, ST_INVALID, "expansion order too large for the translation kernels");
+        dim3 g((unsigned)((ta.le - ta.lb + 15) / 16), 2, 8);
+        k_trans<R, 16, MODE><<<g, 256, shmem(16), s>>>(ta, ops, in, out, lev);
     }
     KCHK();
 }
@@ -566,12 +594,28 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, Fm
                                                      F.T.p, F.Ut.p);
         KCHK();
     }
-    F.T32.alloc(F.T.n);
-    F.Ut32.alloc(F.Ut.n);
-    k_to_float<<<grid_for(F.T.n, 256), 256, 0, s>>>(F.T.p, F.T32.p, F.T.n);
-    KCHK();
-    k_to_float<<<grid_for(F.Ut.n, 256), 256, 0, s>>>(F.Ut.p, F.Ut32.p, F.Ut.n);
-    KCHK();
+    // operand-order packing (FP64 and FP32), then drop the plain copies
+    F.KK = (K + 3) / 4 * 4;
+    const int NRT = (K + 15) / 16;
+    F.PM = (long long)NRT * 16 * F.KK;
+    auto pack = [&](const DBuf<double> &src, long long nmat, int transpose, DBuf<double> &d,
+                    DBuf<float> &d32) {
+        // tail pad: the translation kernels prefetch up to 8 fragments past a
+        // matrix (values unused)
+        d.alloc((size_t)nmat * F.PM + 512);
+        d32.alloc((size_t)nmat * F.PM + 512);
+        HIPCHK(hipMemsetAsync(d.p, 0, ((size_t)nmat * F.PM + 512) * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(d32.p, 0, ((size_t)nmat * F.PM + 512) * sizeof(float), s));
+        k_pack<<<grid_for(nmat * F.PM, 256), 256, 0, s>>>(src.p, nmat, K, F.KK, NRT, transpose,
+                                                          d.p, d32.p);
+        KCHK();
+    };
+    pack(F.T, 2 * std::max(F.nkey, 1ll), 0, F.Tp, F.Tp32);
+    pack(F.Ut, 2ll * nlev * 8, 1, F.Up, F.Up32);
+    pack(F.Ut, 2ll * nlev * 8, 0, F.Lp, F.Lp32);
+    HIPCHK(hipStreamSynchronize(s));
+    F.T.release();
+    F.Ut.release();
     F.pos_of.alloc(Ls.n_v);
     if (Ls.n_v) {
         k_inverse_perm<<<grid_for(Ls.n_v, 256), 256, 0, s>>>(Ls.m2l_pairs.p, Ls.n_v, F.pos_of.p);
@@ -580,18 +624,17 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, Fm
     HIPCHK(hipStreamSynchronize(s));
 }
 
-template <typename R>
-static const R *ops_T(const Fmm &F);
-template <>
-const double *ops_T<double>(const Fmm &F) { return F.T.p; }
-template <>
-const float *ops_T<float>(const Fmm &F) { return F.T32.p; }
-template <typename R>
-static const R *ops_U(const Fmm &F);
-template <>
-const double *ops_U<double>(const Fmm &F) { return F.Ut.p; }
-template <>
-const float *ops_U<float>(const Fmm &F) { return F.Ut32.p; }
+template <typename R> struct Ops;
+template <> struct Ops<double> {
+    static const double *T(const Fmm &F) { return F.Tp.p; }
+    static const double *U(const Fmm &F) { return F.Up.p; }
+    static const double *L(const Fmm &F) { return F.Lp.p; }
+};
+template <> struct Ops<float> {
+    static const float *T(const Fmm &F) { return F.Tp32.p; }
+    static const float *U(const Fmm &F) { return F.Up32.p; }
+    static const float *L(const Fmm &F) { return F.Lp32.p; }
+};
 
 template <typename R>
 void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, const R *px,
@@ -616,7 +659,8 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     TransArgs ta{};
     ta.K = K;
-    ta.KK = (K + 3) / 4 * 4;
+    ta.KK = F.KK;
+    ta.PM = F.PM;
     ta.nlev = F.nlev;
     ta.nkey = F.nkey;
     ta.item_key = L.m2l_item_key.p;
@@ -632,12 +676,16 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
         for (int lev = t.nlev - 2; lev >= 2; --lev) {
             ta.lb = t.level_start[lev];
             ta.le = t.level_start[lev + 1];
-            launch_trans<R, 1>(ta, dim3(1, 2), ops_U<R>(F), w.M, w.M, lev, s);
+            ta.ncap = ta.le - ta.lb;
+            launch_trans<R, 1>(ta, dim3(1, 2), Ops<R>::U(F), w.M, w.Mt, lev, s);
+            k_m2m_sum<R><<<(unsigned)(ta.le - ta.lb), 64, 0, s>>>(K, ta.lb, ta.le, ta.ncap,
+                                                                  t.n_child.p, w.Mt, w.M);
+            KCHK();
         }
     }
     if (L.n_m2l_items > 0) {
         ProfScope ps(prof, "m2l", s);
-        launch_trans<R, 0>(ta, dim3((unsigned)L.n_m2l_items, 2), ops_T<R>(F), w.M, w.Z, 0, s);
+        launch_trans<R, 0>(ta, dim3((unsigned)L.n_m2l_items, 2), Ops<R>::T(F), w.M, w.Z, 0, s);
     }
     {
         ProfScope ps(prof, "m2l_reduce", s);
@@ -649,7 +697,7 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
         for (int lev = 2; lev + 1 < t.nlev; ++lev) {
             ta.lb = t.level_start[lev];
             ta.le = t.level_start[lev + 1];
-            launch_trans<R, 2>(ta, dim3(1, 2), ops_U<R>(F), w.Lc, w.Lc, lev, s);
+            launch_trans<R, 2>(ta, dim3(1, 2), Ops<R>::L(F), w.Lc, w.Lc, lev, s);
         }
     }
     {

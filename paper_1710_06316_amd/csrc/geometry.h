@@ -45,6 +45,14 @@ struct Lists {
     DBuf<int> item_box, item_begin;
     long long n_leaves = 0, n_items = 0, n_p2p_src = 0;
     long long n_p2p_pairs = 0;
+    // Balanced P2P work: chunk c = (group, source-range span) with at most
+    // P2P_CHUNK source points; group g = (leaf, first of <= 64 targets);
+    // chunks of a group are contiguous [grp_ptr[g], grp_ptr[g+1]).
+    DBuf<int> ch_lo, ch_hi;              // [n_chunks] range span [lo, hi) in rng
+    DBuf<int> rng_b, rng_e;              // [n_rng] source point ranges
+    DBuf<int> grp_ptr, grp_tbeg, grp_tend;  // [n_groups+1], [n_groups], [n_groups]
+    DBuf<int> ch_grp;                    // [n_chunks] owning group
+    long long n_chunks = 0, n_groups = 0, n_rng = 0;
     // M2L: V entries grouped by (level, offset class) into chunks of <= 64.
     DBuf<int> v_tgt;                   // [n_v] target box of each V entry
     DBuf<int> m2l_pairs;               // [n_v] V-entry indices grouped by bucket

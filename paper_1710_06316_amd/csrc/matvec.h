@@ -24,6 +24,7 @@ struct MatvecPlan {
     double kappa = 0, inv_ebar = 0, alpha = 0;
     R *sf = nullptr, *sh = nullptr;
     double *pf = nullptr, *ph = nullptr;   // P2P sums (double in both precisions)
+    double *part = nullptr;                // P2P chunk partial sums [chunks][2][64]
     FarWork<R> far{};
 };
 

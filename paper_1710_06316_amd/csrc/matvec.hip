@@ -18,12 +18,17 @@ namespace {
 // s = 0.1, from e^{-s} above (no cancellation either way).
 template <typename R> struct Fast;
 template <> struct Fast<double> {
-    static __device__ inline double rsq(double x) { return 1.0 / sqrt(x); }
+    // hardware reciprocal square root refined by two Newton steps
+    static __device__ inline double rsq(double x) {
+        double y = __builtin_amdgcn_rsq(x);
+        y = y * (1.5 - 0.5 * x * y * y);
+        return y * (1.5 - 0.5 * x * y * y);
+    }
     static __device__ inline double ex(double x) { return exp(x); }
     static constexpr int NSER = 10;
 };
 template <> struct Fast<float> {
-    static __device__ inline float rsq(float x) { return rsqrtf(x); }
+    static __device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ inline float ex(float x) { return __expf(x); }
     static constexpr int NSER = 6;
 };
@@ -43,85 +48,112 @@ struct P2PSeries {
     }
 };
 
-template <typename R, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) k_p2p(
-    const int *__restrict__ item_leaf, const int *__restrict__ item_begin,
-    const int *__restrict__ leaf_ids, const int *__restrict__ src_ptr,
-    const int *__restrict__ src_box, const int *__restrict__ ptb, const int *__restrict__ pte,
-    NodeR<R> nd, const R *__restrict__ sf, const R *__restrict__ sh, R kappa, R inv_ebar,
-    double *__restrict__ out_f, double *__restrict__ out_h) {
+// One wave per work chunk: <= 64 targets of one leaf (one lane each) against
+// <= 256 source points given as point ranges.  Sources are staged 64 at a
+// time in LDS (coalesced loads) and read back as broadcasts; the chunk's
+// partial sums go to part[chunk][2][64] and are added per target, in chunk
+// order, by k_p2p_reduce (deterministic).
+template <typename R>
+__global__ void __launch_bounds__(64) k_p2p(
+    const int *__restrict__ ch_lo, const int *__restrict__ ch_hi, const int *__restrict__ ch_grp,
+    const int *__restrict__ grp_tbeg, const int *__restrict__ grp_tend,
+    const int *__restrict__ rng_b, const int *__restrict__ rng_e, NodeR<R> nd,
+    const R *__restrict__ sf, const R *__restrict__ sh, R kappa, R inv_ebar,
+    double *__restrict__ part) {
     constexpr P2PSeries S;
-    __shared__ double red[2][WAVES][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int w = blockIdx.x;
-    const int li = item_leaf[w];
-    const int box = leaf_ids[li];
-    const int i0 = item_begin[w];
-    const int i = i0 + lane;
-    const bool act = i < pte[box];
-    const int ii = act ? i : i0;
+    __shared__ R T[64][8];
+    const int lane = threadIdx.x;
+    const int c = blockIdx.x;
+    const int g = ch_grp[c];
+    const int tb = grp_tbeg[g], te = grp_tend[g];
+    const int i = tb + lane;
+    const bool act = i < te;
+    const int ii = act ? i : tb;
     const R x = nd.x[ii], y = nd.y[ii], z = nd.z[ii];
     const R n0x = nd.nx[ii], n0y = nd.ny[ii], n0z = nd.nz[ii];
     double af = 0.0, ah = 0.0;
-    for (int q = src_ptr[li] + wave; q < src_ptr[li + 1]; q += WAVES) {
-        const int C = src_box[q];
-        const int cb = ptb[C], ce = pte[C];
-        R bf = R(0), bh = R(0);
-        for (int j = cb; j < ce; ++j) {
-            const R rx = x - nd.x[j], ry = y - nd.y[j], rz = z - nd.z[j];
-            const R snx = nd.nx[j], sny = nd.ny[j], snz = nd.nz[j];
-            const R f = sf[j], h = sh[j];
-            const bool self = (j == i);
-            R r2 = (rx * rx + ry * ry) + rz * rz;
-            r2 = self ? R(1) : r2;
-            const R ir = Fast<R>::rsq(r2);
-            const R r = r2 * ir;
-            const R s = kappa * r;
-            const R e = Fast<R>::ex(-s);
-            R om, fa, fb;
-            if (s < R(0.1)) {
-                constexpr int N = Fast<R>::NSER;
-                R po = R(S.om[N]), pa = R(S.a[N]), pb = R(S.b[N]);
-#pragma unroll
-                for (int k = N - 1; k >= 2; --k) {
-                    po = po * s + R(S.om[k]);
-                    pa = pa * s + R(S.a[k]);
-                    pb = pb * s + R(S.b[k]);
-                }
-                om = (po * s + R(1)) * s;
-                fa = pa * s * s;
-                fb = pb * s * s;
-            } else {
-                om = R(1) - e;
-                fa = om - s * e;
-                fb = R(3) * om - e * s * (R(3) + s);
+    const int rhi = ch_hi[c];
+    for (int r = ch_lo[c]; r < rhi; ++r) {
+        const int cb = rng_b[r], ce = rng_e[r];
+        for (int s0 = cb; s0 < ce; s0 += 64) {
+            const int j = s0 + lane;
+            __builtin_amdgcn_wave_barrier();
+            if (j < ce) {
+                T[lane][0] = nd.x[j]; T[lane][1] = nd.y[j]; T[lane][2] = nd.z[j];
+                T[lane][3] = nd.nx[j]; T[lane][4] = nd.ny[j]; T[lane][5] = nd.nz[j];
+                T[lane][6] = sf[j]; T[lane][7] = sh[j];
             }
-            const R Rn = (rx * snx + ry * sny) + rz * snz;
-            const R Rn0 = (rx * n0x + ry * n0y) + rz * n0z;
-            const R n0n = (n0x * snx + n0y * sny) + n0z * snz;
-            const R ir3 = ir * ir * ir;
-            const R e1 = e * (R(1) + s);
-            const R A = om * ir;
-            const R B = Rn * ir3 * (inv_ebar - e1);
-            const R Cc = Rn0 * ir3 * (e1 * inv_ebar - R(1));
-            const R D = inv_ebar * ir3 * (n0n * fa - Rn0 * Rn * fb * ir * ir);
-            const R m = self ? R(0) : R(1);
-            bf += m * (B * f - A * h);
-            bh += m * (D * f - Cc * h);
-        }
-        af += (double)bf;
-        ah += (double)bh;
-    }
-    red[0][wave][lane] = af;
-    red[1][wave][lane] = ah;
-    __syncthreads();
-    if (wave == 0 && act) {
-        double tf = 0.0, th = 0.0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int cnt = min(64, ce - s0);
+            R bf = R(0), bh = R(0);
+            for (int jj = 0; jj < cnt; ++jj) {
+                const R rx = x - T[jj][0], ry = y - T[jj][1], rz = z - T[jj][2];
+                const R snx = T[jj][3], sny = T[jj][4], snz = T[jj][5];
+                const R f = T[jj][6], h = T[jj][7];
+                const bool self = (s0 + jj == i);
+                R r2 = (rx * rx + ry * ry) + rz * rz;
+                r2 = self ? R(1) : r2;
+                const R ir = Fast<R>::rsq(r2);
+                const R r = r2 * ir;
+                const R s = kappa * r;
+                const R e = Fast<R>::ex(-s);
+                R om, fa, fb;
+                if (s < R(0.1)) {
+                    constexpr int N = Fast<R>::NSER;
+                    R po = R(S.om[N]), pa = R(S.a[N]), pb = R(S.b[N]);
 #pragma unroll
-        for (int k = 0; k < WAVES; ++k) { tf += red[0][k][lane]; th += red[1][k][lane]; }
-        out_f[i] = tf * INV_4PI;
-        out_h[i] = th * INV_4PI;
+                    for (int k = N - 1; k >= 2; --k) {
+                        po = po * s + R(S.om[k]);
+                        pa = pa * s + R(S.a[k]);
+                        pb = pb * s + R(S.b[k]);
+                    }
+                    om = (po * s + R(1)) * s;
+                    fa = pa * s * s;
+                    fb = pb * s * s;
+                } else {
+                    om = R(1) - e;
+                    fa = om - s * e;
+                    fb = R(3) * om - e * s * (R(3) + s);
+                }
+                const R Rn = (rx * snx + ry * sny) + rz * snz;
+                const R Rn0 = (rx * n0x + ry * n0y) + rz * n0z;
+                const R n0n = (n0x * snx + n0y * sny) + n0z * snz;
+                const R ir3 = ir * ir * ir;
+                const R e1 = e * (R(1) + s);
+                const R A = om * ir;
+                const R B = Rn * ir3 * (inv_ebar - e1);
+                const R Cc = Rn0 * ir3 * (e1 * inv_ebar - R(1));
+                const R D = inv_ebar * ir3 * (n0n * fa - Rn0 * Rn * fb * ir * ir);
+                const R m = self ? R(0) : R(1);
+                bf += m * (B * f - A * h);
+                bh += m * (D * f - Cc * h);
+            }
+            af += (double)bf;
+            ah += (double)bh;
+        }
     }
+    part[((long long)c * 2) * 64 + lane] = af;
+    part[((long long)c * 2 + 1) * 64 + lane] = ah;
+}
+
+__global__ void __launch_bounds__(64) k_p2p_reduce(const int *__restrict__ grp_ptr,
+                                                   const int *__restrict__ grp_tbeg,
+                                                   const int *__restrict__ grp_tend,
+                                                   const double *__restrict__ part,
+                                                   double *__restrict__ out_f,
+                                                   double *__restrict__ out_h) {
+    const int g = blockIdx.x, lane = threadIdx.x;
+    const int i = grp_tbeg[g] + lane;
+    if (i >= grp_tend[g]) return;
+    double tf = 0.0, th = 0.0;
+    for (int c = grp_ptr[g]; c < grp_ptr[g + 1]; ++c) {
+        tf += part[((long long)c * 2) * 64 + lane];
+        th += part[((long long)c * 2 + 1) * 64 + lane];
+    }
+    out_f[i] = tf * INV_4PI;
+    out_h[i] = th * INV_4PI;
 }
 
 template <typename R>
@@ -210,10 +242,12 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
     {
         ProfScope ps(prof, "p2p", s);
         const Lists &L = *mp.lists;
-        k_p2p<R, 4><<<(unsigned)L.n_items, 256, 0, s>>>(
-            L.item_box.p, L.item_begin.p, L.leaf_ids.p, L.p2p_ptr.p, L.p2p_src.p,
-            mp.tree->pt_begin.p, mp.tree->pt_end.p, mp.nd, mp.sf, mp.sh, R(mp.kappa),
-            R(mp.inv_ebar), mp.pf, mp.ph);
+        k_p2p<R><<<(unsigned)L.n_chunks, 64, 0, s>>>(
+            L.ch_lo.p, L.ch_hi.p, L.ch_grp.p, L.grp_tbeg.p, L.grp_tend.p, L.rng_b.p, L.rng_e.p,
+            mp.nd, mp.sf, mp.sh, R(mp.kappa), R(mp.inv_ebar), mp.part);
+        KCHK();
+        k_p2p_reduce<<<(unsigned)L.n_groups, 64, 0, s>>>(L.grp_ptr.p, L.grp_tbeg.p, L.grp_tend.p,
+                                                          mp.part, mp.pf, mp.ph);
         KCHK();
     }
     {

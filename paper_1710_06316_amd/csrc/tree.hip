@@ -494,6 +494,7 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
     const long long nl = L.n_leaves;
     DBuf<int> nsrc(nl + 1), nitem(nl + 1), iptr(nl + 1);
     DBuf<long long> npairs(nl + 1), srcpts(nl + 1);
+    (void)srcpts;
     k_p2p_count<<<grid_for(nl, 128), 128, 0, s>>>(tv, nl, L.leaf_ids.p, L.u_ptr.p, L.u_idx.p,
                                                   L.w_ptr.p, L.w_idx.p, L.x_ptr.p, L.x_idx.p,
                                                   nsrc.p, nitem.p, npairs.p, srcpts.p);
@@ -515,29 +516,70 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
     KCHK();
     require(read_scalar(err.p, s) == 0, ST_DEVICE, "P2P task fill out of range");
     {
-        // heaviest work items first (targets x source points), stable
-        std::vector<int> ib(L.n_items), ibeg(L.n_items), leaf(nl);
-        std::vector<long long> sp(nl);
-        std::vector<int> pte_h(nb);
-        L.item_box.download(ib.data(), L.n_items, s);
-        L.item_begin.download(ibeg.data(), L.n_items, s);
+        // balanced P2P chunks: per leaf, the source boxes' point ranges (adjacent
+        // ranges merged), cut into spans of at most P2P_CHUNK points; every
+        // (target group, span) is one work item
+        constexpr int P2P_CHUNK = 256;
+        std::vector<int> sptr(nl + 1), src(L.n_p2p_src), leaf(nl), ptb_h(nb), pte_h(nb);
+        L.p2p_ptr.download(sptr.data(), nl + 1, s);
+        L.p2p_src.download(src.data(), L.n_p2p_src, s);
         L.leaf_ids.download(leaf.data(), nl, s);
-        srcpts.download(sp.data(), nl, s);
+        t.pt_begin.download(ptb_h.data(), nb, s);
         t.pt_end.download(pte_h.data(), nb, s);
         HIPCHK(hipStreamSynchronize(s));
-        std::vector<long long> cost(L.n_items);
-        for (long long k = 0; k < L.n_items; ++k) {
-            long long tg = std::min(64, pte_h[leaf[ib[k]]] - ibeg[k]);
-            cost[k] = tg * sp[ib[k]];
+        std::vector<int> rb, re, clo, chi, cgrp, gptr, gtb, gte;
+        std::vector<std::pair<int, int>> r;
+        for (long long i = 0; i < nl; ++i) {
+            r.clear();
+            for (int q = sptr[i]; q < sptr[i + 1]; ++q) r.emplace_back(ptb_h[src[q]], pte_h[src[q]]);
+            std::sort(r.begin(), r.end());
+            // merge touching ranges, then cut into spans of <= P2P_CHUNK points
+            std::vector<std::pair<int, int>> m;
+            for (auto &x : r) {
+                if (!m.empty() && x.first <= m.back().second) m.back().second = std::max(m.back().second, x.second);
+                else m.push_back(x);
+            }
+            const long long r0 = (long long)rb.size();
+            long long acc = 0;
+            std::vector<long long> cut{r0};
+            for (auto &x : m) {
+                int b = x.first;
+                while (b < x.second) {
+                    int e = (int)std::min<long long>(x.second, b + (P2P_CHUNK - acc));
+                    rb.push_back(b);
+                    re.push_back(e);
+                    acc += e - b;
+                    b = e;
+                    if (acc == P2P_CHUNK) { cut.push_back((long long)rb.size()); acc = 0; }
+                }
+            }
+            if ((long long)rb.size() > cut.back()) cut.push_back((long long)rb.size());
+            const int B = leaf[i];
+            for (int tb = ptb_h[B]; tb < pte_h[B]; tb += 64) {
+                gptr.push_back((int)clo.size());
+                gtb.push_back(tb);
+                gte.push_back(std::min(tb + 64, pte_h[B]));
+                for (size_t k = 0; k + 1 < cut.size(); ++k) {
+                    clo.push_back((int)cut[k]);
+                    chi.push_back((int)cut[k + 1]);
+                    cgrp.push_back((int)gtb.size() - 1);
+                }
+            }
         }
-        std::vector<int> ord(L.n_items);
-        for (long long k = 0; k < L.n_items; ++k) ord[k] = (int)k;
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        std::vector<int> ib2(L.n_items), ibeg2(L.n_items);
-        for (long long k = 0; k < L.n_items; ++k) { ib2[k] = ib[ord[k]]; ibeg2[k] = ibeg[ord[k]]; }
-        L.item_box.upload(ib2.data(), L.n_items, s);
-        L.item_begin.upload(ibeg2.data(), L.n_items, s);
-        HIPCHK(hipStreamSynchronize(s));
+        gptr.push_back((int)clo.size());
+        require(rb.size() < (1ull << 31) && clo.size() < (1ull << 31), ST_INVALID, "too many P2P chunks");
+        L.n_rng = (long long)rb.size();
+        L.n_chunks = (long long)clo.size();
+        L.n_groups = (long long)gtb.size();
+        L.rng_b.alloc(L.n_rng); L.rng_e.alloc(L.n_rng);
+        L.ch_lo.alloc(L.n_chunks); L.ch_hi.alloc(L.n_chunks); L.ch_grp.alloc(L.n_chunks);
+        L.grp_ptr.alloc(L.n_groups + 1); L.grp_tbeg.alloc(L.n_groups); L.grp_tend.alloc(L.n_groups);
+        L.rng_b.upload(rb.data(), rb.size(), s); L.rng_e.upload(re.data(), re.size(), s);
+        L.ch_lo.upload(clo.data(), clo.size(), s); L.ch_hi.upload(chi.data(), chi.size(), s);
+        L.ch_grp.upload(cgrp.data(), cgrp.size(), s);
+        L.grp_ptr.upload(gptr.data(), gptr.size(), s);
+        L.grp_tbeg.upload(gtb.data(), gtb.size(), s); L.grp_tend.upload(gte.data(), gte.size(), s);
+        HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
     }
     // M2L buckets by (level, class), chunks of <= 64 entries
     const long long nv = L.n_v;
