@@ -3,13 +3,17 @@
 One step = one application of the boundary-integral operator of Eq. (5)
 (source gather, P2M, M2M, M2L, L2L, L2P, P2P, near-set corrections and the
 identity term) to a vector already resident in HBM, on the synthetic globular
-molecule (5,000 atoms, ~54k surface nodes, ~108k unknowns).  Setup (geometry,
-octree, lists, near-set quadrature, translation operators) happens once
-before the timed region and is reported separately.
+molecule (5,000 atoms, 49,190 surface nodes, 98,380 unknowns).  Setup
+(geometry, octree, lists, near-set quadrature, translation operators) happens
+once before the timed region and is reported separately.
 
-Prints ONE JSON line with the metric, a roofline entry for the dominant
-kernel (per-launch durations from HIP events on the library's stream over
-the timed region) and the FP64 CPU oracle timed on a bounded row sample.
+The headline form is the mixed-precision one (FP32 far and near field, FP64
+accumulation, combine and Krylov vectors) at expansion order 10; the plain
+FP64 form is timed on the same workload beside it.  Prints ONE JSON line with
+the metric, a roofline entry for the dominant kernel (per-launch durations
+from HIP events on the library's stream over the timed region), the FP64 CPU
+oracle timed on a bounded row sample, and the error of each GPU matvec
+against the oracle on those rows.
 """
 import argparse
 import json
@@ -36,85 +40,92 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
+    ap.add_argument("--order", type=int, default=10)
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the plain FP64 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
 
-def cpu_baseline(mol, target_s):
+def cpu_baseline(mol, target_s, x, y_gpu):
     """FP64 oracle (direct O(N^2) node-patch matvec) on a bounded row sample,
-    scaled to Munknowns/s of a full matvec."""
+    scaled to Munknowns/s of a full matvec.  The same rows give the error of
+    each GPU matvec in y_gpu (caller order, input x) against the oracle."""
     import oracle as O
     n = mol.n_nodes
     rng = np.random.default_rng(123)
-    x = rng.normal(size=2 * n)
     nrows = 128
     while True:
         rows = np.sort(rng.choice(n, size=min(nrows, n), replace=False))
         op = O.operator(mol.xyz, mol.tri, mol.eps_p, mol.eps_s, mol.kappa, rows=rows,
                         validate=False)
         t0 = time.perf_counter()
-        op.apply_rows(x)
+        yf, yh = op.apply_rows(x)
         dt = time.perf_counter() - t0
         if dt * 4 > target_s or nrows >= n:
             break
         nrows = min(n, int(nrows * max(2.0, target_s / max(dt, 1e-3) * 0.9)))
     t_full = dt * n / len(rows)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 2 * n / t_full / 1e6, "unit": "Munknowns/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{len(rows)} of {n} rows of one FP64 direct matvec "
-                      f"({dt:.2f} s, near-set quadrature of those rows excluded), "
-                      f"scaled by N/rows"}
+    ref = np.r_[yf, yh]
+    acc = {k: float(np.linalg.norm(np.r_[y[rows], y[n + rows]] - ref) / np.linalg.norm(ref))
+           for k, y in y_gpu.items()}
+    return ({"value": 2 * n / t_full / 1e6, "unit": "Munknowns/s", "cores": cores,
+             "kind": "oracle",
+             "sample": f"{len(rows)} of {n} rows of one FP64 direct matvec "
+                       f"({dt:.2f} s, near-set quadrature of those rows excluded), "
+                       f"scaled by N/rows"},
+            {"matvec_rel_l2_vs_oracle": acc, "rows": int(len(rows))})
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                                   "multi-GPU sharding is a design only (see DESIGN.md)"}))
-        sys.exit(2)
-    import torch
-
-    import paper_1710_06316_amd as A
-    import workloads as W
-
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    mol = W.globular()
+def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host):
+    """Setup, warm-up, K timed matvecs (device-resident vectors), one solve."""
     n = mol.n_nodes
-    prec = A.AFMPB_FP64 if a.precision == "fp64" else A.AFMPB_FP32_REFINED
+    stream = torch.cuda.current_stream()
+    prec = A.AFMPB_FP64 if precision == "fp64" else A.AFMPB_FP32_REFINED
     s = A.Solver(0, stream.cuda_stream)
     t0 = time.perf_counter()
-    s.load(mol, order_p=a.order, leaf_cap=a.leaf, precision=prec)
+    s.load(mol, order_p=order, leaf_cap=leaf, precision=prec)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
     info = s.tree_info()
     g = torch.Generator(device="cuda").manual_seed(1)
     x = torch.randn(2 * n, dtype=torch.float64, device="cuda", generator=g)
     y = torch.empty_like(x)
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         s.matvec_dev(x.data_ptr(), y.data_ptr())
     torch.cuda.synchronize()
     s.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(steps):
         s.matvec_dev(x.data_ptr(), y.data_ptr())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = s.profile_read()
     s.profile(False)
-    ms = (t1 - t0) * 1e3 / a.steps
-    value = 2 * n / (ms * 1e-3) / 1e6
-    # roofline entries: P2P (vector ALU) and M2L (matrix cores); the dominant
-    # kernel of the step (largest total time) is reported as "roofline"
-    K = (a.order + 1) ** 2
-    peak = PEAK_FP64_VECTOR_TFLOPS if a.precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
-    peak_mfma = PEAK_FP64_MFMA_TFLOPS if a.precision == "fp64" else PEAK_FP32_MFMA_TFLOPS
+    ms = (t1 - t0) * 1e3 / steps
+    y_host = s.matvec(x_host)
+    torch.cuda.synchronize()
+    f, h, E, sinfo, _ = s.solve(allow_not_converged=True)
+    solve = {"energy_kcal_mol": E, "iterations": sinfo.iterations,
+             "converged": bool(sinfo.converged), "true_rel_residual": sinfo.true_rel_residual,
+             "ms_gmres": sinfo.ms_gmres, "ms_total": sinfo.ms_total}
+    s.close()
+    return {"ms": ms, "value": 2 * n / (ms * 1e-3) / 1e6, "prof": prof, "info": info,
+            "setup_ms": setup_ms, "solve": solve, "y_host": y_host}
+
+
+def roofline(r, order, precision):
+    """Roofline entries for P2P (vector ALU) and M2L (matrix cores); the
+    dominant kernel of the step (largest total time) is the headline one."""
+    info, prof = r["info"], r["prof"]
+    K = (order + 1) ** 2
+    peak = PEAK_FP64_VECTOR_TFLOPS if precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
+    peak_mfma = PEAK_FP64_MFMA_TFLOPS if precision == "fp64" else PEAK_FP32_MFMA_TFLOPS
     work = {
         "p2p": ("alu", info["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR, peak),
         "m2l": ("mfma", info["n_m2l_pairs"] * 4 * K * K, peak_mfma),
@@ -130,17 +141,31 @@ def main():
                        "unit": "TFLOP/s", "frac": achieved / pk, "traffic": None,
                        "flops_per_launch": flops, "avg_ms": avg_s * 1e3}
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
-    roof = roofs.get(dom) or max(roofs.values(), key=lambda r: r["avg_ms"])
-    # one full solve, reported beside the matvec
-    torch.cuda.synchronize()
-    f, h, E, sinfo, _ = s.solve(allow_not_converged=True)
-    solve = {"energy_kcal_mol": E, "iterations": sinfo.iterations,
-             "converged": bool(sinfo.converged), "true_rel_residual": sinfo.true_rel_residual,
-             "ms_gmres": sinfo.ms_gmres, "ms_total": sinfo.ms_total}
-    s.close()
+    roof = roofs.get(dom) or max(roofs.values(), key=lambda q: q["avg_ms"])
+    return roof, roofs, dom
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                                   "multi-GPU sharding is a design only (see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1710_06316_amd as A
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    mol = W.globular()
+    n = mol.n_nodes
+    x_host = np.random.default_rng(99).normal(size=2 * n)
+    r = run_config(A, torch, mol, a.precision, a.order, a.leaf, a.steps, a.warmup, x_host)
+    roof, roofs, dom = roofline(r, a.order, a.precision)
+    info = r["info"]
     line = {
-        "metric": "FMM matvec Munknowns/s", "value": value, "unit": "Munknowns/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
+        "metric": "FMM matvec Munknowns/s", "value": r["value"], "unit": "Munknowns/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
@@ -150,15 +175,25 @@ def main():
                    "precision": a.precision, "n_boxes": info["n_boxes"],
                    "n_p2p_pairs": info["n_p2p_pairs"], "n_m2l_pairs": info["n_m2l_pairs"],
                    "n_near": info["n_near"]},
-        "setup_ms": setup_ms,
-        "kernels_ms_per_step": {k: v[0] / max(v[1], 1) * (v[1] / a.steps) for k, v in prof.items()},
+        "setup_ms": r["setup_ms"],
+        "kernels_ms_per_step": {k: v[0] / a.steps for k, v in r["prof"].items()},
         "roofline": roof,
         "roofline_all": roofs,
         "dominant_phase": dom,
-        "solve": solve,
+        "solve": r["solve"],
     }
+    y_gpu = {f"{a.precision}_p{a.order}": r["y_host"]}
+    if a.precision != "fp64" and not a.no_fp64:
+        # the plain FP64 path on the same workload, for comparison
+        r64 = run_config(A, torch, mol, "fp64", a.order, a.leaf, a.steps, a.warmup, x_host)
+        line["fp64_plain"] = {"value": r64["value"], "ms_per_step": r64["ms"],
+                              "kernels_ms_per_step": {k: v[0] / a.steps
+                                                      for k, v in r64["prof"].items()},
+                              "roofline_all": roofline(r64, a.order, "fp64")[1],
+                              "solve": r64["solve"]}
+        y_gpu[f"fp64_p{a.order}"] = r64["y_host"]
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(mol, a.cpu_seconds)
+        line["cpu_baseline"], line["accuracy"] = cpu_baseline(mol, a.cpu_seconds, x_host, y_gpu)
     print(json.dumps(line), flush=True)
 
 

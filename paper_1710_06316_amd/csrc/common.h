@@ -81,6 +81,12 @@ struct DBuf {
     }
 };
 
+// P2P lane replication: a target group of n points runs as f copies of
+// 64/f lanes, each copy taking every f-th source (f = 8, 4, 2, 1).
+__host__ __device__ inline int p2p_replicas(int ntarget) {
+    return ntarget <= 8 ? 8 : ntarget <= 16 ? 4 : ntarget <= 32 ? 2 : 1;
+}
+
 inline unsigned grid_for(long long n, int block) {
     long long g = (n + block - 1) / block;
     return (unsigned)(g < 1 ? 1 : g);

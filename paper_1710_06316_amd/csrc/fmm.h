@@ -33,7 +33,6 @@ struct Fmm {
     int KK = 0;
     DBuf<double> Tp, Up, Lp;             // M2L, M2M (A = U), L2L (A = U^T)
     DBuf<float> Tp32, Up32, Lp32;
-    DBuf<int> pos_of;                    // V entry -> position in bucket order
     BasisDev dev() const {
         return BasisDev{P, K, screened, kappa, norm.p, inv_dfact.p, ginv.p, side.p};
     }

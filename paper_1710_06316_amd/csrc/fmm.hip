@@ -211,10 +211,6 @@ __global__ void k_to_float(const double *a, float *b, long long n) {
     if (i < n) b[i] = (float)a[i];
 }
 
-__global__ void k_inverse_perm(const int *perm, long long n, int *inv) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) inv[perm[i]] = (int)i;
-}
 
 // ------------------------------ far field ----------------------------------
 
@@ -300,7 +296,7 @@ struct TransArgs {
 };
 
 template <typename R, int CC, int MODE>
-__global__ void __launch_bounds__(256) k_trans(TransArgs a, const R *__restrict__ ops,
+__global__ void __launch_bounds__(512) k_trans(TransArgs a, const R *__restrict__ ops,
                                                const R *__restrict__ in, R *__restrict__ out,
                                                int lev) {
     extern __shared__ unsigned char smem_raw[];
@@ -343,7 +339,7 @@ __global__ void __launch_bounds__(256) k_trans(TransArgs a, const R *__restrict_
     __syncthreads();
     // gather the B operand column-major (consecutive threads read consecutive
     // coefficients of one expansion); missing columns are zero
-    for (int idx = tid; idx < KK * CC; idx += 256) {
+    for (int idx = tid; idx < KK * CC; idx += (int)blockDim.x) {
         const int c = idx / KK, k = idx % KK;
         R v = R(0);
         if (k < K && c < ncols) {
@@ -354,10 +350,12 @@ __global__ void __launch_bounds__(256) k_trans(TransArgs a, const R *__restrict_
         Ms[c * KKp + k] = v;
     }
     __syncthreads();
-    // one row tile per pass over all column tiles: each operator fragment is
+    // waves take row tiles in turn; one row tile per pass over all column
+    // tiles, so each operator fragment is
     // loaded once (four k-steps ahead) and used NCT times
     const R *Bp = Ms + (lane & 15) * KKp + (lane >> 4);
-    for (int rt = wave; rt < NRT; rt += 4) {
+    const int nwave = (int)(blockDim.x >> 6);
+    for (int rt = wave; rt < NRT; rt += nwave) {
         const R *A = op0 + (long long)rt * KS * 64 + lane;
         V4 acc[NCT];
 #pragma unroll
@@ -387,7 +385,8 @@ __global__ void __launch_bounds__(256) k_trans(TransArgs a, const R *__restrict_
             if (col >= ncols) continue;
             long long dst;
             if (MODE == 0) {
-                dst = ((long long)colbox[col] * 2 + kern) * K;
+                // slot of the V entry (target-major list order)
+                dst = ((long long)a.pairs[colbox[col]] * 2 + kern) * K;
             } else if (MODE == 1) {
                 // per-octant product of parent column col (summed by k_m2m_sum)
                 dst = (((long long)o * a.ncap + (colbox[col] - a.lb)) * 2 + kern) * K;
@@ -427,40 +426,60 @@ template <typename R, int MODE>
 void launch_trans(const TransArgs &ta, dim3 grid_items, const R *ops, const R *in, R *out,
                   int lev, hipStream_t s) {
     const size_t lim = 60 * 1024;
+    // one wave per 16-row tile of the operator, at most 8 waves (balanced passes)
+    const int nrt = (ta.K + 15) / 16, passes = (nrt + 7) / 8;
+    const unsigned nthr = 64u * (unsigned)((nrt + passes - 1) / passes);
     auto shmem = [&](int cc) { return (size_t)(ta.KK | 1) * cc * sizeof(R); };
     if (MODE == 0) {
         dim3 g = grid_items;
         if (shmem(64) <= lim) {
             g.z = 1;
-            k_trans<R, 64, 0><<<g, 256, shmem(64), s>>>(ta, ops, in, out, lev);
+            k_trans<R, 64, 0><<<g, nthr, shmem(64), s>>>(ta, ops, in, out, lev);
         } else if (shmem(32) <= lim) {
             g.z = 2;
-            k_trans<R, 32, 0><<<g, 256, shmem(32), s>>>(ta, ops, in, out, lev);
+            k_trans<R, 32, 0><<<g, nthr, shmem(32), s>>>(ta, ops, in, out, lev);
         } else if (shmem(16) <= lim) {
             g.z = 4;
-            k_trans<R, 16, 0><<<g, 256, shmem(16), s>>>(ta, ops, in, out, lev);
+            k_trans<R, 16, 0><<<g, nthr, shmem(16), s>>>(ta, ops, in, out, lev);
         } else {
             throw Error(ST_INVALID, "expansion order too large for the translation kernels");
         }
     } else {
         require(shmem(16) <= lim, ST_INVALID, "expansion order too large for the translation kernels");
         dim3 g((unsigned)((ta.le - ta.lb + 15) / 16), 2, 8);
-        k_trans<R, 16, MODE><<<g, 256, shmem(16), s>>>(ta, ops, in, out, lev);
+        k_trans<R, 16, MODE><<<g, nthr, shmem(16), s>>>(ta, ops, in, out, lev);
     }
     KCHK();
 }
 
 // L[B] = sum over V(B) in list order of the M2L products (every box written).
+// L[B] = sum of the M2L products of the entries of V(B), stored in list
+// order as rows [v_ptr[B], v_ptr[B+1]) of Z (2K values each).  Four waves
+// take every fourth row; their partial sums are added in wave order.
 template <typename R>
-__global__ void k_m2l_reduce(int K, long long nbox, const int *vptr, const int *pos_of,
-                             const R *Z, R *L) {
-    long long box = blockIdx.x;
+__global__ void __launch_bounds__(256) k_m2l_reduce(int K, long long nbox, const int *vptr,
+                                                    const R *__restrict__ Z, R *__restrict__ L) {
+    __shared__ R red[4][2 * (MAXP + 1) * (MAXP + 1)];
+    const long long box = blockIdx.x;
     if (box >= nbox) return;
-    for (int idx = threadIdx.x; idx < 2 * K; idx += blockDim.x) {
-        R acc = R(0);
-        for (int q = vptr[box]; q < vptr[box + 1]; ++q) acc += Z[(long long)pos_of[q] * 2 * K + idx];
-        L[box * 2 * K + idx] = acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int W = 2 * K, NJ = (W + 63) / 64;
+    const long long q0 = vptr[box], q1 = vptr[box + 1];
+    R acc[14];
+#pragma unroll
+    for (int j = 0; j < 14; ++j) acc[j] = R(0);
+    for (long long q = q0 + wave; q < q1; q += 4) {
+        const R *z = Z + q * W;
+#pragma unroll
+        for (int j = 0; j < 14; ++j)
+            if (j < NJ && lane + 64 * j < W) acc[j] += z[lane + 64 * j];
     }
+#pragma unroll
+    for (int j = 0; j < 14; ++j)
+        if (j < NJ && lane + 64 * j < W) red[wave][lane + 64 * j] = acc[j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < W; i += 256)
+        L[box * W + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
 template <typename R>
@@ -616,12 +635,6 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, Fm
     HIPCHK(hipStreamSynchronize(s));
     F.T.release();
     F.Ut.release();
-    F.pos_of.alloc(Ls.n_v);
-    if (Ls.n_v) {
-        k_inverse_perm<<<grid_for(Ls.n_v, 256), 256, 0, s>>>(Ls.m2l_pairs.p, Ls.n_v, F.pos_of.p);
-        KCHK();
-    }
-    HIPCHK(hipStreamSynchronize(s));
 }
 
 template <typename R> struct Ops;
@@ -689,7 +702,7 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "m2l_reduce", s);
-        k_m2l_reduce<R><<<(unsigned)t.nbox, 128, 0, s>>>(K, t.nbox, L.v_ptr.p, F.pos_of.p, w.Z, w.Lc);
+        k_m2l_reduce<R><<<(unsigned)t.nbox, 256, 0, s>>>(K, t.nbox, L.v_ptr.p, w.Z, w.Lc);
         KCHK();
     }
     {

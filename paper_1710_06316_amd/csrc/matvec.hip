@@ -48,11 +48,13 @@ struct P2PSeries {
     }
 };
 
-// One wave per work chunk: <= 64 targets of one leaf (one lane each) against
-// <= 256 source points given as point ranges.  Sources are staged 64 at a
-// time in LDS (coalesced loads) and read back as broadcasts; the chunk's
-// partial sums go to part[chunk][2][64] and are added per target, in chunk
-// order, by k_p2p_reduce (deterministic).
+// One wave per work chunk: <= 64 targets of one leaf against the chunk's
+// source point ranges.  A group of <= 32 (16, 8) targets runs as 2 (4, 8)
+// copies of 32 (16, 8) lanes, copy r taking sources r, r+f, r+2f, ... of each
+// staged tile, so that small leaves still fill the wave.  Sources are staged
+// 64 at a time in LDS (coalesced loads, zero fill past the range); the copies
+// are added in copy order and the chunk's partial sums go to part[chunk][2][64],
+// which k_p2p_reduce adds per target in chunk order (deterministic).
 template <typename R>
 __global__ void __launch_bounds__(64) k_p2p(
     const int *__restrict__ ch_lo, const int *__restrict__ ch_hi, const int *__restrict__ ch_grp,
@@ -62,11 +64,14 @@ __global__ void __launch_bounds__(64) k_p2p(
     double *__restrict__ part) {
     constexpr P2PSeries S;
     __shared__ R T[64][8];
+    __shared__ double red[2][64];
     const int lane = threadIdx.x;
     const int c = blockIdx.x;
     const int g = ch_grp[c];
     const int tb = grp_tbeg[g], te = grp_tend[g];
-    const int i = tb + lane;
+    const int f = p2p_replicas(te - tb);              // uniform for the wave
+    const int W = 64 / f, rep = lane / W, ti = lane % W;
+    const int i = tb + ti;
     const bool act = i < te;
     const int ii = act ? i : tb;
     const R x = nd.x[ii], y = nd.y[ii], z = nd.z[ii];
@@ -78,26 +83,28 @@ __global__ void __launch_bounds__(64) k_p2p(
         for (int s0 = cb; s0 < ce; s0 += 64) {
             const int j = s0 + lane;
             __builtin_amdgcn_wave_barrier();
-            if (j < ce) {
-                T[lane][0] = nd.x[j]; T[lane][1] = nd.y[j]; T[lane][2] = nd.z[j];
-                T[lane][3] = nd.nx[j]; T[lane][4] = nd.ny[j]; T[lane][5] = nd.nz[j];
-                T[lane][6] = sf[j]; T[lane][7] = sh[j];
-            }
+            const bool in = j < ce;
+            T[lane][0] = in ? nd.x[j] : R(0); T[lane][1] = in ? nd.y[j] : R(0);
+            T[lane][2] = in ? nd.z[j] : R(0); T[lane][3] = in ? nd.nx[j] : R(0);
+            T[lane][4] = in ? nd.ny[j] : R(0); T[lane][5] = in ? nd.nz[j] : R(0);
+            T[lane][6] = in ? sf[j] : R(0);   T[lane][7] = in ? sh[j] : R(0);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int cnt = min(64, ce - s0);
             R bf = R(0), bh = R(0);
-            for (int jj = 0; jj < cnt; ++jj) {
+            // jb + rep <= 63: jb is a multiple of f below cnt <= 64 and f | 64
+            for (int jb = 0; jb < cnt; jb += f) {
+                const int jj = jb + rep;
                 const R rx = x - T[jj][0], ry = y - T[jj][1], rz = z - T[jj][2];
                 const R snx = T[jj][3], sny = T[jj][4], snz = T[jj][5];
-                const R f = T[jj][6], h = T[jj][7];
-                const bool self = (s0 + jj == i);
+                const R sfv = T[jj][6], shv = T[jj][7];
+                const bool ok = act && jj < cnt && s0 + jj != i;
                 R r2 = (rx * rx + ry * ry) + rz * rz;
-                r2 = self ? R(1) : r2;
+                r2 = ok ? r2 : R(1);
                 const R ir = Fast<R>::rsq(r2);
-                const R r = r2 * ir;
-                const R s = kappa * r;
+                const R rr = r2 * ir;
+                const R s = kappa * rr;
                 const R e = Fast<R>::ex(-s);
                 R om, fa, fb;
                 if (s < R(0.1)) {
@@ -126,16 +133,27 @@ __global__ void __launch_bounds__(64) k_p2p(
                 const R B = Rn * ir3 * (inv_ebar - e1);
                 const R Cc = Rn0 * ir3 * (e1 * inv_ebar - R(1));
                 const R D = inv_ebar * ir3 * (n0n * fa - Rn0 * Rn * fb * ir * ir);
-                const R m = self ? R(0) : R(1);
-                bf += m * (B * f - A * h);
-                bh += m * (D * f - Cc * h);
+                bf += ok ? (B * sfv - A * shv) : R(0);
+                bh += ok ? (D * sfv - Cc * shv) : R(0);
             }
             af += (double)bf;
             ah += (double)bh;
         }
     }
-    part[((long long)c * 2) * 64 + lane] = af;
-    part[((long long)c * 2 + 1) * 64 + lane] = ah;
+    red[0][lane] = af;
+    red[1][lane] = ah;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double tf = 0.0, th = 0.0;
+    if (lane < W) {
+        for (int q = 0; q < f; ++q) {
+            tf += red[0][q * W + lane];
+            th += red[1][q * W + lane];
+        }
+    }
+    part[((long long)c * 2) * 64 + lane] = tf;
+    part[((long long)c * 2 + 1) * 64 + lane] = th;
 }
 
 __global__ void __launch_bounds__(64) k_p2p_reduce(const int *__restrict__ grp_ptr,

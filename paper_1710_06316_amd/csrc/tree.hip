@@ -517,8 +517,8 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
     require(read_scalar(err.p, s) == 0, ST_DEVICE, "P2P task fill out of range");
     {
         // balanced P2P chunks: per leaf, the source boxes' point ranges (adjacent
-        // ranges merged), cut into spans of at most P2P_CHUNK points; every
-        // (target group, span) is one work item
+        // ranges merged), cut into spans of at most P2P_CHUNK points per lane
+        // copy; every (target group, span) is one work item
         constexpr int P2P_CHUNK = 256;
         std::vector<int> sptr(nl + 1), src(L.n_p2p_src), leaf(nl), ptb_h(nb), pte_h(nb);
         L.p2p_ptr.download(sptr.data(), nl + 1, s);
@@ -540,21 +540,24 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
                 else m.push_back(x);
             }
             const long long r0 = (long long)rb.size();
+            const int B = leaf[i];
+            // replicated lanes take proportionally more sources per chunk
+            const long long budget =
+                (long long)P2P_CHUNK * p2p_replicas(std::min(64, pte_h[B] - ptb_h[B]));
             long long acc = 0;
             std::vector<long long> cut{r0};
             for (auto &x : m) {
                 int b = x.first;
                 while (b < x.second) {
-                    int e = (int)std::min<long long>(x.second, b + (P2P_CHUNK - acc));
+                    int e = (int)std::min<long long>(x.second, b + (budget - acc));
                     rb.push_back(b);
                     re.push_back(e);
                     acc += e - b;
                     b = e;
-                    if (acc == P2P_CHUNK) { cut.push_back((long long)rb.size()); acc = 0; }
+                    if (acc == budget) { cut.push_back((long long)rb.size()); acc = 0; }
                 }
             }
             if ((long long)rb.size() > cut.back()) cut.push_back((long long)rb.size());
-            const int B = leaf[i];
             for (int tb = ptb_h[B]; tb < pte_h[B]; tb += 64) {
                 gptr.push_back((int)clo.size());
                 gtb.push_back(tb);
