@@ -281,6 +281,8 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.lists = &c->lists;
     mp.fmm = &c->fmm;
     mp.near = &c->near;
+    if constexpr (sizeof(R) == sizeof(double)) mp.delta = c->near.delta.p;
+    else mp.delta = c->near.delta32.p;
     mp.nd64 = c->nodes();
     mp.nd = NodeR<R>{ndR, ndR + n, ndR + 2 * n, ndR + 3 * n, ndR + 4 * n, ndR + 5 * n};
     mp.area = c->nodes().area;

@@ -46,9 +46,12 @@ template <typename R> __device__ inline R val(Dual<R> a) { return a.v; }
 
 // Emits (k, n, value) for every regular solid harmonic of degree <= P, in
 // the order m = 0..P, n = m..P (for m > 0 the cosine entry k = n^2+n+m and
-// the sine entry k = n^2+n-m).  norm[k] are the orthonormalisation factors.
+// the sine entry k = n^2+n-m).  norm[k] are the orthonormalisation factors;
+// rec[2 (n (P+1) + m) + {0, 1}] = {(2n-1)/(n-m), (n+m-1)/(n-m)} are the
+// recurrence coefficients (a table, so no division runs per point).
 template <typename R, typename S, typename F, typename NT>
-__device__ inline void for_each_regular(S x, S y, S z, int P, const NT *norm, F &&emit) {
+__device__ inline void for_each_regular(S x, S y, S z, int P, const NT *norm, const NT *rec,
+                                        F &&emit) {
     S r2 = (x * x + y * y) + z * z;
     S cm(R(1)), sm(R(0));   // Re/Im of (x + i y)^m
     R dfact = R(1);         // (2m-1)!!
@@ -57,7 +60,8 @@ __device__ inline void for_each_regular(S x, S y, S z, int P, const NT *norm, F 
         S qc(R(0)), qs(R(0));                   // q_{m-1}^m = 0
         for (int n = m; n <= P; ++n) {
             if (n > m) {
-                R a = R(2 * n - 1) / R(n - m), b = R(n + m - 1) / R(n - m);
+                const NT *ab = rec + 2 * (n * (P + 1) + m);
+                const R a = R(ab[0]), b = R(ab[1]);
                 S nc = a * (z * pc) - b * (r2 * qc);
                 S ns = a * (z * ps) - b * (r2 * qs);
                 qc = pc; qs = ps;
@@ -80,12 +84,15 @@ __device__ inline void for_each_regular(S x, S y, S z, int P, const NT *norm, F 
 
 // g_n(x) = i_n(x) / x^n for n = 0..P as functions of t = x^2: series for
 // n = P and P-1, then the downward recurrence g_{n-1} = t g_{n+1} + (2n+1) g_n.
-// inv_dfact[n] = 1/(2n+1)!!.
+// inv_dfact[n] = 1/(2n+1)!!; ser[k] = 1/(2 k (2n+2k+1)) is the ratio of
+// consecutive series terms over t (row 0: n = P, row 1: n = P-1).
+constexpr int GSER = 200;
+
 template <typename R, typename S>
-__device__ inline S g_series(int n, S t, const R *inv_dfact) {
+__device__ inline S g_series(int n, S t, const R *inv_dfact, const double *ser) {
     S sum(R(1)), term(R(1));
-    for (int k = 1; k < 200; ++k) {
-        term = term * t * (R(0.5) / (R(k) * R(2 * n + 2 * k + 1)));
+    for (int k = 1; k < GSER; ++k) {
+        term = term * t * R(ser[k]);
         sum = sum + term;
         R tv = val(term), sv = val(sum);
         if ((tv < R(0) ? -tv : tv) <= R(1e-17) * (sv < R(0) ? -sv : sv)) break;
@@ -94,9 +101,9 @@ __device__ inline S g_series(int n, S t, const R *inv_dfact) {
 }
 
 template <typename R, typename S>
-__device__ inline void g_all(int P, S t, const R *inv_dfact, S *g) {
-    g[P] = g_series<R, S>(P, t, inv_dfact);
-    if (P >= 1) g[P - 1] = g_series<R, S>(P - 1, t, inv_dfact);
+__device__ inline void g_all(int P, S t, const R *inv_dfact, const double *ser, S *g) {
+    g[P] = g_series<R, S>(P, t, inv_dfact, ser);
+    if (P >= 1) g[P - 1] = g_series<R, S>(P - 1, t, inv_dfact, ser + GSER);
     for (int n = P - 1; n >= 1; --n) g[n - 1] = t * g[n + 1] + R(2 * n + 1) * g[n];
 }
 

@@ -16,6 +16,8 @@ struct BasisDev {
     const double *inv_dfact;   // [P+2]   1/(2n+1)!!
     const double *ginv;        // [nlev][P+1]  1/g_n(kappa s_l)
     const double *side;        // [nlev]
+    const double *rec;         // [P+1][P+1][2] recurrence coefficients of the harmonics
+    const double *gser;        // [2][GSER] term ratios of the g_n series (n = P, P-1)
 };
 
 struct Fmm {
@@ -23,7 +25,7 @@ struct Fmm {
     double kappa = 0;
     int screened = 0;
     long long nkey = 0;                  // (nlev-2)*316 translation classes
-    DBuf<double> norm, inv_dfact, ginv, kinv, weight, side;
+    DBuf<double> norm, inv_dfact, ginv, kinv, weight, side, rec, gser;
     DBuf<double> T;                      // [2][nkey][K][K] M2L, row = local index
     DBuf<double> Ut;                     // [2][nlev][8][K][K] transposed M2M operator
     // Operators in matrix-core operand order: per matrix [K/16 row tiles]
@@ -34,7 +36,7 @@ struct Fmm {
     DBuf<double> Tp, Up, Lp;             // M2L, M2M (A = U), L2L (A = U^T)
     DBuf<float> Tp32, Up32, Lp32;
     BasisDev dev() const {
-        return BasisDev{P, K, screened, kappa, norm.p, inv_dfact.p, ginv.p, side.p};
+        return BasisDev{P, K, screened, kappa, norm.p, inv_dfact.p, ginv.p, side.p, rec.p, gser.p};
     }
 };
 

@@ -41,16 +41,16 @@ __device__ inline void regular_basis(const BasisDev &B, int kern, int lev, S vx,
     const R is = R(1.0 / B.side[lev]);
     S ux = vx * is, uy = vy * is, uz = vz * is;
     if (kern == 0 || !B.screened) {
-        for_each_regular<R>(ux, uy, uz, B.P, B.norm, [&](int k, int, S r) { emit(k, r); });
+        for_each_regular<R>(ux, uy, uz, B.P, B.norm, B.rec, [&](int k, int, S r) { emit(k, r); });
     } else {
         R ks = R(B.kappa * B.side[lev]);
         S t = (ks * ks) * ((ux * ux + uy * uy) + uz * uz);
         S g[MAXP + 1];
         R inv_df[MAXP + 2];
         for (int n = 0; n <= B.P + 1; ++n) inv_df[n] = R(B.inv_dfact[n]);
-        g_all<R, S>(B.P, t, inv_df, g);
+        g_all<R, S>(B.P, t, inv_df, B.gser, g);
         const double *gi = B.ginv + (long long)lev * (B.P + 1);
-        for_each_regular<R>(ux, uy, uz, B.P, B.norm,
+        for_each_regular<R>(ux, uy, uz, B.P, B.norm, B.rec,
                             [&](int k, int n, S r) { emit(k, r * (g[n] * R(gi[n]))); });
     }
 }
@@ -83,7 +83,7 @@ __global__ void k_level_consts(BasisDev B, int nlev, double *ginv, double *kinv,
     }
     const double ks = B.kappa * s;
     double g[MAXP + 1], kn[MAXP + 2];
-    g_all<double, double>(P, ks * ks, B.inv_dfact, g);
+    g_all<double, double>(P, ks * ks, B.inv_dfact, B.gser, g);
     kn[0] = exp(-ks) / ks;
     kn[1] = exp(-ks) * (1.0 + ks) / (ks * ks);
     for (int n = 1; n < P; ++n) kn[n + 1] = kn[n - 1] + (2.0 * n + 1.0) / ks * kn[n];
@@ -101,7 +101,7 @@ __global__ void k_sphere_table(BasisDev B, int Q, const double *dir, const doubl
     if (q >= Q) return;
     double x = dir[3 * q], y = dir[3 * q + 1], z = dir[3 * q + 2], w = wq[q];
     const int K = B.K;
-    for_each_regular<double>(x, y, z, B.P, B.norm,
+    for_each_regular<double>(x, y, z, B.P, B.norm, B.rec,
                              [&](int k, int, double r) { Yw[(long long)q * K + k] = w * r; });
 }
 
@@ -143,14 +143,14 @@ __global__ void k_basis_samples(BasisDev B, const MatDesc *desc, int nmat, int Q
                 f *= ir;
             }
         }
-        for_each_regular<double>(ux, uy, uz, P, B.norm,
+        for_each_regular<double>(ux, uy, uz, P, B.norm, B.rec,
                                  [&](int k, int n, double r) { o[k] = r * rad[n]; });
     }
     if (q == 0) {
         // row scale 1/rho_n(rq) of the local basis (M2L only)
         double g[MAXP + 1];
         const bool scr = d.kind == 0 && d.kern == 1 && B.screened;
-        if (scr) g_all<double, double>(P, (B.kappa * d.rq) * (B.kappa * d.rq), B.inv_dfact, g);
+        if (scr) g_all<double, double>(P, (B.kappa * d.rq) * (B.kappa * d.rq), B.inv_dfact, B.gser, g);
         for (int n = 0; n <= P; ++n) {
             double sc = 1.0;
             if (d.kind == 0) {
@@ -220,32 +220,62 @@ struct TreeDev {
     const double *center;
 };
 
+// P2M: one block per leaf, wave w computes the expansion of kernel w.  Each
+// lane evaluates the regular basis at one source point; the coefficients are
+// emitted 16 at a time into LDS and summed over the points by 16 groups of 4
+// lanes (fixed order, so the result is deterministic).
 template <typename R>
-__global__ void k_p2m(BasisDev B, TreeDev T, const int *leaf_ids, const R *px, const R *py,
-                      const R *pz, const R *pnx, const R *pny, const R *pnz, const R *sf,
-                      const R *sh, R inv_ebar, R *M) {
+__global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *leaf_ids,
+                                             const R *px, const R *py, const R *pz,
+                                             const R *pnx, const R *pny, const R *pnz,
+                                             const R *sf, const R *sh, R inv_ebar, R *M) {
+    __shared__ R Wv[2][16][65];
+    __shared__ int kslot[2][16];
     const int box = leaf_ids[blockIdx.x];
     const int lev = T.level[box];
     if (lev < 2) return;
-    const int lane = threadIdx.x, K = B.K;
+    const int lane = threadIdx.x & 63;
+    const int kern = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int K = B.K;
+    R *Mb = M + ((long long)box * 2 + kern) * K;
     const R cx = R(T.center[3 * box]), cy = R(T.center[3 * box + 1]), cz = R(T.center[3 * box + 2]);
     const int b = T.ptb[box], e = T.pte[box];
     for (int c0 = b; c0 < e; c0 += 64) {
-        int i = c0 + lane;
-        bool ok = i < e;
-        R vx = ok ? px[i] - cx : R(0), vy = ok ? py[i] - cy : R(0), vz = ok ? pz[i] - cz : R(0);
-        R nx = ok ? pnx[i] : R(0), ny = ok ? pny[i] : R(0), nz = ok ? pnz[i] : R(0);
-        R q = ok ? sh[i] : R(0);
-        R dmag = ok ? -sf[i] : R(0);
-        for (int kern = 0; kern < 2; ++kern) {
-            R dip = (kern == 0) ? dmag * inv_ebar : dmag;
-            R *Mb = M + ((long long)box * 2 + kern) * K;
-            regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, nx), Dual<R>(vy, ny),
-                                      Dual<R>(vz, nz), [&](int k, Dual<R> r) {
-                                          R tot = wave_sum(q * r.v + dip * r.d);
-                                          if (lane == 0) Mb[k] = (c0 == b) ? tot : Mb[k] + tot;
-                                      });
-        }
+        const int i = c0 + lane;
+        const bool ok = i < e;
+        const R vx = ok ? px[i] - cx : R(0), vy = ok ? py[i] - cy : R(0), vz = ok ? pz[i] - cz : R(0);
+        const R nx = ok ? pnx[i] : R(0), ny = ok ? pny[i] : R(0), nz = ok ? pnz[i] : R(0);
+        const R q = ok ? sh[i] : R(0);
+        const R dmag = ok ? -sf[i] : R(0);
+        const R dip = (kern == 0) ? dmag * inv_ebar : dmag;
+        int cnt = 0;                       // coefficients emitted so far (uniform)
+        auto flush = [&](int nslot) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int slot = lane >> 2, qu = lane & 3;
+            R acc = R(0);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc += Wv[kern][slot][qu * 16 + j];
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            if (qu == 0 && slot < nslot) {
+                const int k = kslot[kern][slot];
+                Mb[k] = (c0 == b) ? acc : Mb[k] + acc;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, nx), Dual<R>(vy, ny), Dual<R>(vz, nz),
+                                  [&](int k, Dual<R> r) {
+                                      const int sl = cnt & 15;
+                                      Wv[kern][sl][lane] = q * r.v + dip * r.d;
+                                      if (lane == 0) kslot[kern][sl] = k;
+                                      ++cnt;
+                                      if ((cnt & 15) == 0) flush(16);
+                                  });
+        if (cnt & 15) flush(cnt & 15);
     }
 }
 
@@ -482,32 +512,33 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(int K, long long nbox, const
         L[box * W + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
+// L2P: one block per leaf, wave w evaluates the local expansion of kernel w
+// (potential and normal derivative) at one target point per lane.
 template <typename R>
-__global__ void k_l2p(BasisDev B, TreeDev T, const int *leaf_ids, const R *px, const R *py,
-                      const R *pz, const R *pnx, const R *pny, const R *pnz, const R *L,
-                      long long n, R *phi) {
+__global__ void __launch_bounds__(128) k_l2p(BasisDev B, TreeDev T, const int *leaf_ids,
+                                             const R *px, const R *py, const R *pz,
+                                             const R *pnx, const R *pny, const R *pnz,
+                                             const R *L, long long n, R *phi) {
     const int box = leaf_ids[blockIdx.x];
     const int lev = T.level[box];
     const int K = B.K;
+    const int lane = threadIdx.x & 63;
+    const int kern = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const R cx = R(T.center[3 * box]), cy = R(T.center[3 * box + 1]), cz = R(T.center[3 * box + 2]);
-    for (int i = T.ptb[box] + threadIdx.x; i < T.pte[box]; i += blockDim.x) {
-        R out[4] = {R(0), R(0), R(0), R(0)};
+    const R *Lb = L + ((long long)box * 2 + kern) * K;
+    for (int i = T.ptb[box] + lane; i < T.pte[box]; i += 64) {
+        R p = R(0), dp = R(0);
         if (lev >= 2) {
-            R vx = px[i] - cx, vy = py[i] - cy, vz = pz[i] - cz;
-            for (int kern = 0; kern < 2; ++kern) {
-                const R *Lb = L + ((long long)box * 2 + kern) * K;
-                R p = R(0), dp = R(0);
-                regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, pnx[i]), Dual<R>(vy, pny[i]),
-                                          Dual<R>(vz, pnz[i]), [&](int k, Dual<R> r) {
-                                              R l = Lb[k];
-                                              p += l * r.v;
-                                              dp += l * r.d;
-                                          });
-                out[2 * kern] = p;
-                out[2 * kern + 1] = dp;
-            }
+            const R vx = px[i] - cx, vy = py[i] - cy, vz = pz[i] - cz;
+            regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, pnx[i]), Dual<R>(vy, pny[i]),
+                                      Dual<R>(vz, pnz[i]), [&](int k, Dual<R> r) {
+                                          const R l = Lb[k];
+                                          p += l * r.v;
+                                          dp += l * r.d;
+                                      });
         }
-        for (int c = 0; c < 4; ++c) phi[c * n + i] = out[c];
+        phi[(2 * kern) * n + i] = p;
+        phi[(2 * kern + 1) * n + i] = dp;
     }
 }
 
@@ -535,6 +566,19 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, Fm
         }
     double df = 1.0;
     for (int n = 0; n <= P + 1; ++n) { df *= (2.0 * n + 1.0); idf[n] = 1.0 / df; }
+    // recurrence coefficients of the solid harmonics and g_n series ratios
+    std::vector<double> rec((size_t)2 * (P + 1) * (P + 1), 0.0), gser(2 * GSER, 0.0);
+    for (int n = 0; n <= P; ++n)
+        for (int m = 0; m < n; ++m) {
+            rec[2 * (n * (P + 1) + m)] = (2.0 * n - 1.0) / (n - m);
+            rec[2 * (n * (P + 1) + m) + 1] = (n + m - 1.0) / (n - m);
+        }
+    for (int row = 0; row < 2; ++row) {
+        const int n = P - row;
+        for (int k = 1; k < GSER; ++k) gser[row * GSER + k] = 0.5 / ((double)k * (2.0 * n + 2.0 * k + 1.0));
+    }
+    F.rec.alloc(rec.size()); F.rec.upload(rec.data(), rec.size(), s);
+    F.gser.alloc(gser.size()); F.gser.upload(gser.data(), gser.size(), s);
     F.norm.alloc(K); F.norm.upload(norm.data(), K, s);
     F.inv_dfact.alloc(P + 2); F.inv_dfact.upload(idf.data(), P + 2, s);
     F.side.alloc(nlev); F.side.upload(t.side.data(), nlev, s);
@@ -666,7 +710,7 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "p2m", s);
-        k_p2m<R><<<(unsigned)L.n_leaves, 64, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
+        k_p2m<R><<<(unsigned)L.n_leaves, 128, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
                                                      sf, sh, R(inv_ebar), w.M);
         KCHK();
     }
@@ -715,7 +759,7 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "l2p", s);
-        k_l2p<R><<<(unsigned)L.n_leaves, 64, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
+        k_l2p<R><<<(unsigned)L.n_leaves, 128, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
                                                      w.Lc, n, w.phi);
         KCHK();
     }

@@ -25,6 +25,7 @@ struct MatvecPlan {
     R *sf = nullptr, *sh = nullptr;
     double *pf = nullptr, *ph = nullptr;   // P2P sums (double in both precisions)
     double *part = nullptr;                // P2P chunk partial sums [chunks][2][64]
+    const R *delta = nullptr;              // near corrections [nnz][4], working precision
     FarWork<R> far{};
 };
 

@@ -183,27 +183,41 @@ __global__ void k_gather_sources(const double *__restrict__ x, const double *__r
     sh[i] = R(area[i] * x[n + i]);
 }
 
-// One group of 8 lanes per row for the near correction; the row's result is
-// combined with every other part of the matvec.
+// One group of 8 lanes per row for the near correction (two entries in
+// flight per lane); the row's result is combined with every other part of
+// the matvec.  Lane partial sums are added by a fixed butterfly.
 template <typename R>
 __global__ void k_combine(long long n, const double *__restrict__ x, const double *__restrict__ pf,
                           const double *__restrict__ ph, const R *__restrict__ phi,
                           const long long *__restrict__ nptr, const int *__restrict__ ncol,
-                          const double *__restrict__ nd, double alpha, double inv_ebar,
+                          const R *__restrict__ nd, double alpha, double inv_ebar,
                           double *__restrict__ y) {
     long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long p = gid >> 3;
     int sub = (int)(gid & 7);
-    double cf = 0.0, ch = 0.0;
+    double cf = 0.0, ch = 0.0, cf2 = 0.0, ch2 = 0.0;
     if (p < n) {
-        for (long long e = nptr[p] + sub; e < nptr[p + 1]; e += 8) {
-            int t = ncol[e];
-            double f = x[t], h = x[n + t];
-            const double *d = nd + 4 * e;
-            cf += d[1] * f - d[0] * h;
-            ch += d[3] * f - d[2] * h;
+        const long long e1 = nptr[p + 1];
+        long long e = nptr[p] + sub;
+        for (; e + 8 < e1; e += 16) {
+            const int t = ncol[e], t2 = ncol[e + 8];
+            const double f = x[t], h = x[n + t], f2 = x[t2], h2 = x[n + t2];
+            const R *d = nd + 4 * e, *d2 = nd + 4 * (e + 8);
+            cf += (double)d[1] * f - (double)d[0] * h;
+            ch += (double)d[3] * f - (double)d[2] * h;
+            cf2 += (double)d2[1] * f2 - (double)d2[0] * h2;
+            ch2 += (double)d2[3] * f2 - (double)d2[2] * h2;
+        }
+        if (e < e1) {
+            const int t = ncol[e];
+            const double f = x[t], h = x[n + t];
+            const R *d = nd + 4 * e;
+            cf += (double)d[1] * f - (double)d[0] * h;
+            ch += (double)d[3] * f - (double)d[2] * h;
         }
     }
+    cf += cf2;
+    ch += ch2;
 #pragma unroll
     for (int o = 4; o > 0; o >>= 1) {
         cf += __shfl_xor(cf, o, 8);
@@ -272,7 +286,7 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
         ProfScope ps(prof, "near_combine", s);
         k_combine<R><<<grid_for(8 * n, 256), 256, 0, s>>>(n, x, mp.pf, mp.ph, mp.far.phi,
                                                           mp.near->ptr.p, mp.near->col.p,
-                                                          mp.near->delta.p, mp.alpha,
+                                                          mp.delta, mp.alpha,
                                                           mp.inv_ebar, y);
         KCHK();
     }

@@ -8,6 +8,7 @@ struct NearSet {
     DBuf<long long> ptr;     // [n+1]
     DBuf<int> col;           // [nnz] ascending per row, Morton positions
     DBuf<double> delta;      // [nnz][4] corrections of {A, B, C, D}
+    DBuf<float> delta32;     // the same, rounded to FP32 (mixed-precision matvec)
     long long nnz = 0;
 };
 

@@ -287,6 +287,11 @@ __global__ void k_near_coeffs(Ctx C, long long n, long long nnz, const long long
     }
 }
 
+__global__ void k_round_f32(const double *a, float *b, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
 }  // namespace
 
 // Gauss-Legendre nodes and weights on [0,1] (Newton iteration on P_n).
@@ -386,6 +391,9 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
     out.delta.alloc(4 * out.nnz);
     k_near_coeffs<<<grid_for(out.nnz, 64), 64, 0, s>>>(C, n, out.nnz, out.ptr.p, out.col.p,
                                                          out.delta.p);
+    KCHK();
+    out.delta32.alloc(4 * out.nnz);
+    k_round_f32<<<grid_for(4 * out.nnz, 256), 256, 0, s>>>(out.delta.p, out.delta32.p, 4 * out.nnz);
     KCHK();
     HIPCHK(hipStreamSynchronize(s));
 }
