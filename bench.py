@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the plain FP64 comparison run")
+    ap.add_argument("--no-solve", action="store_true", help="skip the full solve")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the run, one device-to-device copy of this many MiB "
+                         "(reference kernel for HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -81,7 +85,7 @@ def cpu_baseline(mol, target_s, x, y_gpu):
             {"matvec_rel_l2_vs_oracle": acc, "rows": int(len(rows))})
 
 
-def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host):
+def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host, do_solve=True):
     """Setup, warm-up, K timed matvecs (device-resident vectors), one solve."""
     n = mol.n_nodes
     stream = torch.cuda.current_stream()
@@ -110,10 +114,13 @@ def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host):
     ms = (t1 - t0) * 1e3 / steps
     y_host = s.matvec(x_host)
     torch.cuda.synchronize()
-    f, h, E, sinfo, _ = s.solve(allow_not_converged=True)
-    solve = {"energy_kcal_mol": E, "iterations": sinfo.iterations,
-             "converged": bool(sinfo.converged), "true_rel_residual": sinfo.true_rel_residual,
-             "ms_gmres": sinfo.ms_gmres, "ms_total": sinfo.ms_total}
+    solve = None
+    if do_solve:
+        f, h, E, sinfo, _ = s.solve(allow_not_converged=True)
+        solve = {"energy_kcal_mol": E, "iterations": sinfo.iterations,
+                 "converged": bool(sinfo.converged),
+                 "true_rel_residual": sinfo.true_rel_residual,
+                 "ms_gmres": sinfo.ms_gmres, "ms_total": sinfo.ms_total}
     s.close()
     return {"ms": ms, "value": 2 * n / (ms * 1e-3) / 1e6, "prof": prof, "info": info,
             "setup_ms": setup_ms, "solve": solve, "y_host": y_host}
@@ -160,7 +167,8 @@ def main():
     mol = W.globular()
     n = mol.n_nodes
     x_host = np.random.default_rng(99).normal(size=2 * n)
-    r = run_config(A, torch, mol, a.precision, a.order, a.leaf, a.steps, a.warmup, x_host)
+    r = run_config(A, torch, mol, a.precision, a.order, a.leaf, a.steps, a.warmup, x_host,
+                   not a.no_solve)
     roof, roofs, dom = roofline(r, a.order, a.precision)
     info = r["info"]
     line = {
@@ -185,7 +193,8 @@ def main():
     y_gpu = {f"{a.precision}_p{a.order}": r["y_host"]}
     if a.precision != "fp64" and not a.no_fp64:
         # the plain FP64 path on the same workload, for comparison
-        r64 = run_config(A, torch, mol, "fp64", a.order, a.leaf, a.steps, a.warmup, x_host)
+        r64 = run_config(A, torch, mol, "fp64", a.order, a.leaf, a.steps, a.warmup, x_host,
+                         not a.no_solve)
         line["fp64_plain"] = {"value": r64["value"], "ms_per_step": r64["ms"],
                               "kernels_ms_per_step": {k: v[0] / a.steps
                                                       for k, v in r64["prof"].items()},
@@ -194,6 +203,12 @@ def main():
         y_gpu[f"fp64_p{a.order}"] = r64["y_host"]
     if not a.no_cpu_baseline:
         line["cpu_baseline"], line["accuracy"] = cpu_baseline(mol, a.cpu_seconds, x_host, y_gpu)
+    if a.calib_copy_mb > 0:
+        src = torch.ones(a.calib_copy_mb << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calib_copy_bytes"] = a.calib_copy_mb << 20
     print(json.dumps(line), flush=True)
 
 

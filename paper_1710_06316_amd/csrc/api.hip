@@ -60,18 +60,21 @@ Prof::~Prof() {
     for (auto e : pool) (void)hipEventDestroy(e);
 }
 
-ProfScope::ProfScope(Prof *p, const char *name, hipStream_t st) : prof(p), id(-1), s(st) {
+ProfScope::ProfScope(Prof *p, const char *name, hipStream_t st)
+    : prof(p), id(-1), s(st), slot(0) {
     if (!prof || !prof->on) { prof = nullptr; return; }
     id = prof->id_of(name);
     hipEvent_t a = prof->take(), b = prof->take();
     HIPCHK(hipEventRecord(a, s));
+    slot = prof->pending.size();
     prof->pending.emplace_back(id, a, b);
+    ++prof->open;
 }
 
 ProfScope::~ProfScope() {
     if (!prof) return;
-    (void)hipEventRecord(std::get<2>(prof->pending.back()), s);
-    if (prof->pending.size() > 4096) {
+    (void)hipEventRecord(std::get<2>(prof->pending[slot]), s);
+    if (--prof->open == 0 && prof->pending.size() > 4096) {
         try { prof->flush(); } catch (...) {}
     }
 }
@@ -150,6 +153,10 @@ using namespace afmpb;
 struct afmpb_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // second stream for the near field, forked from and joined to `stream`
+    // inside every matvec (default priority)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::string err;
     bool loaded = false;
     afmpb_params prm{};
@@ -281,6 +288,9 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.lists = &c->lists;
     mp.fmm = &c->fmm;
     mp.near = &c->near;
+    mp.side = c->side;
+    mp.fork = c->ev_fork;
+    mp.join = c->ev_join;
     if constexpr (sizeof(R) == sizeof(double)) mp.delta = c->near.delta.p;
     else mp.delta = c->near.delta32.p;
     mp.nd64 = c->nodes();
@@ -623,6 +633,15 @@ afmpb_status afmpb_create(int device, void *hip_stream, afmpb_ctx **out) {
     if (!c) return AFMPB_E_OOM;
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+        if (c->side) (void)hipStreamDestroy(c->side);
+        delete c;
+        return AFMPB_E_DEVICE;
+    }
     *out = c;
     return AFMPB_OK;
 }
@@ -631,6 +650,10 @@ afmpb_status afmpb_destroy(afmpb_ctx *ctx) {
     if (!ctx) return AFMPB_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipEventDestroy(ctx->ev_fork);
+    (void)hipEventDestroy(ctx->ev_join);
+    (void)hipStreamDestroy(ctx->side);
     delete ctx;
     return AFMPB_OK;
 }

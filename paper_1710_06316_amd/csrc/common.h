@@ -117,7 +117,7 @@ void sort_rows_i32(const int *ptr, int *idx, long long nrows, hipStream_t s);
 
 struct Prof;
 struct ProfScope {
-    Prof *prof; int id; hipStream_t s;
+    Prof *prof; int id; hipStream_t s; size_t slot;
     ProfScope(Prof *p, const char *name, hipStream_t st);
     ~ProfScope();
 };

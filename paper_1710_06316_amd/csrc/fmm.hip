@@ -321,36 +321,158 @@ struct TransArgs {
     // M2M / L2L
     long long lb, le;            // boxes of the parent level
     long long ncap;              // mode 1: capacity (boxes) of one octant slice of the scratch
+    int n_items;                 // mode 0: number of work items
     const int *cb, *nc;          // child begin / count
     const unsigned long long *prefix;
 };
 
+// Row stride (elements) of the gathered expansions in LDS, chosen so that
+// the operand reads of one k-step (16 columns x 4 consecutive k) fall in
+// distinct banks.
+__host__ __device__ inline int lds_stride(int kk, int elem_bytes) {
+    return elem_bytes == 4 ? kk + ((2 - kk) % 32 + 32) % 32 : (kk | 1);
+}
+
+// Result of one 16 x 16 output tile: destination offset of column col, or
+// -1 when the column is absent.
 template <typename R, int CC, int MODE>
+__device__ inline long long trans_dst(const TransArgs &a, const int *colbox,
+                                      const int (*child)[CC], int col, int o, int kern) {
+    const int K = a.K;
+    if (MODE == 0) {
+        // slot of the V entry (target-major list order)
+        return ((long long)colbox[col] * 2 + kern) * K;
+    } else if (MODE == 1) {
+        // per-octant product of parent column col (summed by k_m2m_sum)
+        return (((long long)o * a.ncap + (colbox[col] - a.lb)) * 2 + kern) * K;
+    } else {
+        const int ch = child[o][col];
+        return ch < 0 ? -1 : ((long long)ch * 2 + kern) * K;
+    }
+}
+
+template <typename R, int CC, int MODE, int NA>
+__device__ inline void trans_store(const TransArgs &a, typename Acc4<R>::T (&acc)[NA],
+                                   R *__restrict__ out, const int *colbox,
+                                   const int (*child)[CC], int ncols, int o, int kern, int lane,
+                                   int rt) {
+#pragma unroll
+    for (int ct = 0; ct < NA; ++ct) {
+        const int col = ct * 16 + (lane & 15);
+        if (col >= ncols) continue;
+        const long long dst = trans_dst<R, CC, MODE>(a, colbox, child, col, o, kern);
+        if (dst < 0) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rr = rt * 16 + drow<R>(lane, r);
+            if (rr < a.K) {
+                if (MODE == 2) out[dst + rr] += acc[ct][r];
+                else out[dst + rr] = acc[ct][r];
+            }
+        }
+    }
+}
+
+// Streaming form (any order): waves take row tiles in turn; operator
+// fragments are loaded four k-steps ahead and each feeds NA products.
+template <typename R, int CC, int MODE, int NA>
+__device__ inline void trans_rows(const TransArgs &a, const R *__restrict__ op0, const R *Ms,
+                                  int KKp, R *__restrict__ out, const int *colbox,
+                                  const int (*child)[CC], int ncols, int o, int kern, int lane,
+                                  int wave) {
+    typedef typename Acc4<R>::T V4;
+    const int K = a.K, KK = a.KK, KS = KK / 4;
+    const int NRT = (K + 15) / 16;
+    const R *Bp = Ms + (lane & 15) * KKp + (lane >> 4);
+    const int nwave = (int)(blockDim.x >> 6);
+    for (int rt = wave; rt < NRT; rt += nwave) {
+        const R *A = op0 + (long long)rt * KS * 64 + lane;
+        V4 acc[NA];
+#pragma unroll
+        for (int ct = 0; ct < NA; ++ct) acc[ct] = V4{0, 0, 0, 0};
+        R pre[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pre[j] = A[j * 64];
+        for (int ks = 0; ks < KS; ks += 4) {
+            R cur[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                cur[j] = pre[j];
+                pre[j] = A[(ks + 4 + j) * 64];   // in bounds: operators carry a tail pad
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (ks + j < KS) {
+#pragma unroll
+                    for (int ct = 0; ct < NA; ++ct)
+                        acc[ct] = mfma16(cur[j], Bp[ct * 16 * KKp + (ks + j) * 4], acc[ct]);
+                }
+            }
+        }
+        trans_store<R, CC, MODE, NA>(a, acc, out, colbox, child, ncols, o, kern, lane, rt);
+    }
+}
+
+// Register-resident form (one row tile per wave, at most KSR k-steps): the
+// wave's operator rows were loaded into areg before the operand gather; the
+// product runs KSR k-steps from registers and LDS only (operand rows past K
+// are zero in LDS, so the operator values there do not matter).
+template <typename R, int CC, int MODE, int NA, int KSR>
+__device__ inline void trans_rows_res(const TransArgs &a, const R (&areg)[KSR], const R *Ms,
+                                      int KKp, R *__restrict__ out, const int *colbox,
+                                      const int (*child)[CC], int ncols, int o, int kern,
+                                      int lane, int rt) {
+    typedef typename Acc4<R>::T V4;
+    const R *Bp = Ms + (lane & 15) * KKp + (lane >> 4);
+    V4 acc[NA];
+#pragma unroll
+    for (int ct = 0; ct < NA; ++ct) acc[ct] = V4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KSR; ++ks) {
+#pragma unroll
+        for (int ct = 0; ct < NA; ++ct)
+            acc[ct] = mfma16(areg[ks], Bp[ct * 16 * KKp + ks * 4], acc[ct]);
+    }
+    trans_store<R, CC, MODE, NA>(a, acc, out, colbox, child, ncols, o, kern, lane, rt);
+}
+
+template <typename R, int CC, int MODE, int KSR>
 __global__ void __launch_bounds__(512) k_trans(TransArgs a, const R *__restrict__ ops,
                                                const R *__restrict__ in, R *__restrict__ out,
                                                int lev) {
     extern __shared__ unsigned char smem_raw[];
-    R *Ms = reinterpret_cast<R *>(smem_raw);         // [CC][KK|1]
-    __shared__ int colbox[CC];                         // column -> bucket position / box
+    R *Ms = reinterpret_cast<R *>(smem_raw);         // [CC][KKp]
+    __shared__ int colbox[CC];                         // mode 0: V entry; 1, 2: parent box
+    __shared__ int srcbox[CC];                         // box whose expansion is column c
     __shared__ int child[8][CC];                       // modes 1, 2: child of octant o
-    typedef typename Acc4<R>::T V4;
-    constexpr int NCT = CC / 16;
-    const int K = a.K, KK = a.KK, KS = KK / 4, KKp = KK | 1;
+    const int K = a.K, KK = a.KK, KS = KK / 4;
+    // operand rows held in LDS: KK, or all KSR k-steps of the resident form
+    const int KR = KSR > 0 ? 4 * KSR : KK;
+    const int KKp = lds_stride(KR, (int)sizeof(R));
     const int kern = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int NRT = (K + 15) / 16;
     const int o = (MODE == 0) ? 0 : (int)blockIdx.z;  // child octant (modes 1, 2)
     int ncols;
     const R *op0;
     if (MODE == 0) {
-        // work item blockIdx.x, columns [blockIdx.z * CC, +CC) of its <= 64 entries
-        const int w = blockIdx.x;
+        // Work item w, columns [blockIdx.z * CC, +CC) of its <= 64 entries.
+        // Blocks are dealt to the 8 XCDs in turn (block b runs on XCD b % 8);
+        // XCD x takes the contiguous item range [x per, (x+1) per), so the
+        // items of one (level, class) bucket share their operator in one L2.
+        // gridDim.x = 8 per, so b -> w is a bijection onto [0, 8 per).
+        const int per = (int)(gridDim.x >> 3);
+        const int w = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+        if (w >= a.n_items) return;                      // uniform for the block
         const int off = blockIdx.z * CC;
         ncols = min(CC, a.item_count[w] - off);
         if (ncols <= 0) return;                          // uniform for the block
         const int beg = a.item_begin[w] + off;
-        if (tid < CC) colbox[tid] = tid < ncols ? beg + tid : -1;
+        if (tid < CC) {
+            const int q = tid < ncols ? a.pairs[beg + tid] : -1;
+            colbox[tid] = q;
+            srcbox[tid] = q >= 0 ? a.vidx[q] : -1;
+        }
         op0 = ops + ((long long)kern * a.nkey + a.item_key[w]) * a.PM;
     } else {
         const long long c0 = a.lb + (long long)blockIdx.x * CC;
@@ -366,74 +488,77 @@ __global__ void __launch_bounds__(512) k_trans(TransArgs a, const R *__restrict_
         }
         op0 = ops + ((((long long)kern * a.nlev + lev) * 8) + o) * a.PM;
     }
-    __syncthreads();
-    // gather the B operand column-major (consecutive threads read consecutive
-    // coefficients of one expansion); missing columns are zero
-    for (int idx = tid; idx < KK * CC; idx += (int)blockDim.x) {
-        const int c = idx / KK, k = idx % KK;
-        R v = R(0);
-        if (k < K && c < ncols) {
-            const int src = (MODE == 0) ? a.vidx[a.pairs[colbox[c]]]
-                          : (MODE == 1) ? child[o][c] : colbox[c];
-            if (src >= 0) v = in[((long long)src * 2 + kern) * K + k];
-        }
-        Ms[c * KKp + k] = v;
+    // resident form: this wave's operator rows (row tile = wave), issued now
+    // so that their latency overlaps the operand gather
+    R areg[KSR > 0 ? KSR : 1];
+    if constexpr (KSR > 0) {
+        const R *A = op0 + (long long)wave * KS * 64 + lane;
+#pragma unroll
+        for (int j = 0; j < KSR; ++j) areg[j] = A[j * 64];   // in bounds: tail pad
     }
     __syncthreads();
-    // waves take row tiles in turn; one row tile per pass over all column
-    // tiles, so each operator fragment is
-    // loaded once (four k-steps ahead) and used NCT times
-    const R *Bp = Ms + (lane & 15) * KKp + (lane >> 4);
-    const int nwave = (int)(blockDim.x >> 6);
-    for (int rt = wave; rt < NRT; rt += nwave) {
-        const R *A = op0 + (long long)rt * KS * 64 + lane;
-        V4 acc[NCT];
+    if (MODE != 0 && tid < CC) srcbox[tid] = (MODE == 1) ? child[o][tid] : colbox[tid];
+    __syncthreads();
+    // gather the B operand column by column (consecutive lanes read
+    // consecutive coefficients of one expansion); a wave issues the loads of
+    // four columns before it stores any, so their latencies overlap.  Rows
+    // past K and missing columns are zero.
+    const int nact = (ncols + 15) / 16;                  // active column tiles
+    {
+        const int nwave = (int)(blockDim.x >> 6);
+        const int ncs = nact * 16;
+        for (int c0 = wave; c0 < ncs; c0 += 4 * nwave) {
+            R v[4][4];
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[ct] = V4{0, 0, 0, 0};
-        R pre[4];
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * nwave;
+                const int src = (c < ncols) ? srcbox[c] : -1;
+                const R *col = in + ((long long)(src < 0 ? 0 : src) * 2 + kern) * K;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) pre[j] = A[j * 64];
-        for (int ks = 0; ks < KS; ks += 4) {
-            R cur[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                cur[j] = pre[j];
-                pre[j] = A[(ks + 4 + j) * 64];   // in bounds: operators carry a tail pad
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (ks + j < KS) {
-#pragma unroll
-                    for (int ct = 0; ct < NCT; ++ct)
-                        acc[ct] = mfma16(cur[j], Bp[ct * 16 * KKp + (ks + j) * 4], acc[ct]);
+                for (int j = 0; j < 4; ++j) {
+                    const int k = lane + 64 * j;
+                    v[u][j] = (src >= 0 && k < K) ? col[k] : R(0);
                 }
             }
-        }
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-            const int col = ct * 16 + (lane & 15);
-            if (col >= ncols) continue;
-            long long dst;
-            if (MODE == 0) {
-                // slot of the V entry (target-major list order)
-                dst = ((long long)a.pairs[colbox[col]] * 2 + kern) * K;
-            } else if (MODE == 1) {
-                // per-octant product of parent column col (summed by k_m2m_sum)
-                dst = (((long long)o * a.ncap + (colbox[col] - a.lb)) * 2 + kern) * K;
-            } else {
-                const int ch = child[o][col];
-                if (ch < 0) continue;
-                dst = ((long long)ch * 2 + kern) * K;
-            }
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * nwave;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int rr = rt * 16 + drow<R>(lane, r);
-                if (rr < K) {
-                    if (MODE == 2) out[dst + rr] += acc[ct][r];
-                    else out[dst + rr] = acc[ct][r];
+                for (int j = 0; j < 4; ++j) {
+                    const int k = lane + 64 * j;
+                    if (c < ncs && k < KR) Ms[c * KKp + k] = v[u][j];
                 }
             }
+            // rows past 256 (expansion order above 14)
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * nwave;
+                if (c >= ncs) break;
+                const int src = (c < ncols) ? srcbox[c] : -1;
+                const R *col = in + ((long long)(src < 0 ? 0 : src) * 2 + kern) * K;
+                for (int k = lane + 256; k < KR; k += 64)
+                    Ms[c * KKp + k] = (src >= 0 && k < K) ? col[k] : R(0);
+            }
         }
+    }
+    __syncthreads();
+    if constexpr (KSR > 0) {
+        if constexpr (CC >= 64) {
+            if (nact == 4) { trans_rows_res<R, CC, MODE, 4, KSR>(a, areg, Ms, KKp, out, colbox, child, ncols, o, kern, lane, wave); return; }
+            if (nact == 3) { trans_rows_res<R, CC, MODE, 3, KSR>(a, areg, Ms, KKp, out, colbox, child, ncols, o, kern, lane, wave); return; }
+        }
+        if constexpr (CC >= 32) {
+            if (nact == 2) { trans_rows_res<R, CC, MODE, 2, KSR>(a, areg, Ms, KKp, out, colbox, child, ncols, o, kern, lane, wave); return; }
+        }
+        trans_rows_res<R, CC, MODE, 1, KSR>(a, areg, Ms, KKp, out, colbox, child, ncols, o, kern, lane, wave);
+    } else {
+        if constexpr (CC >= 64) {
+            if (nact == 4) { trans_rows<R, CC, MODE, 4>(a, op0, Ms, KKp, out, colbox, child, ncols, o, kern, lane, wave); return; }
+            if (nact == 3) { trans_rows<R, CC, MODE, 3>(a, op0, Ms, KKp, out, colbox, child, ncols, o, kern, lane, wave); return; }
+        }
+        if constexpr (CC >= 32) {
+            if (nact == 2) { trans_rows<R, CC, MODE, 2>(a, op0, Ms, KKp, out, colbox, child, ncols, o, kern, lane, wave); return; }
+        }
+        trans_rows<R, CC, MODE, 1>(a, op0, Ms, KKp, out, colbox, child, ncols, o, kern, lane, wave);
     }
 }
 
@@ -452,34 +577,51 @@ __global__ void k_m2m_sum(int K, long long lb, long long le, long long ncap,
     }
 }
 
-template <typename R, int MODE>
-void launch_trans(const TransArgs &ta, dim3 grid_items, const R *ops, const R *in, R *out,
-                  int lev, hipStream_t s) {
+template <typename R, int MODE, int KSR>
+void launch_trans_k(const TransArgs &ta, dim3 g, unsigned nthr, const R *ops, const R *in,
+                    R *out, int lev, hipStream_t s) {
     const size_t lim = 60 * 1024;
-    // one wave per 16-row tile of the operator, at most 8 waves (balanced passes)
-    const int nrt = (ta.K + 15) / 16, passes = (nrt + 7) / 8;
-    const unsigned nthr = 64u * (unsigned)((nrt + passes - 1) / passes);
-    auto shmem = [&](int cc) { return (size_t)(ta.KK | 1) * cc * sizeof(R); };
+    const int KR = KSR > 0 ? 4 * KSR : ta.KK;
+    auto shmem = [&](int cc) { return (size_t)lds_stride(KR, (int)sizeof(R)) * cc * sizeof(R); };
     if (MODE == 0) {
-        dim3 g = grid_items;
         if (shmem(64) <= lim) {
             g.z = 1;
-            k_trans<R, 64, 0><<<g, nthr, shmem(64), s>>>(ta, ops, in, out, lev);
+            k_trans<R, 64, 0, KSR><<<g, nthr, shmem(64), s>>>(ta, ops, in, out, lev);
         } else if (shmem(32) <= lim) {
             g.z = 2;
-            k_trans<R, 32, 0><<<g, nthr, shmem(32), s>>>(ta, ops, in, out, lev);
+            k_trans<R, 32, 0, KSR><<<g, nthr, shmem(32), s>>>(ta, ops, in, out, lev);
         } else if (shmem(16) <= lim) {
             g.z = 4;
-            k_trans<R, 16, 0><<<g, nthr, shmem(16), s>>>(ta, ops, in, out, lev);
+            k_trans<R, 16, 0, KSR><<<g, nthr, shmem(16), s>>>(ta, ops, in, out, lev);
         } else {
             throw Error(ST_INVALID, "expansion order too large for the translation kernels");
         }
     } else {
         require(shmem(16) <= lim, ST_INVALID, "expansion order too large for the translation kernels");
-        dim3 g((unsigned)((ta.le - ta.lb + 15) / 16), 2, 8);
-        k_trans<R, 16, MODE><<<g, nthr, shmem(16), s>>>(ta, ops, in, out, lev);
+        g = dim3((unsigned)((ta.le - ta.lb + 15) / 16), 2, 8);
+        k_trans<R, 16, MODE, KSR><<<g, nthr, shmem(16), s>>>(ta, ops, in, out, lev);
     }
     KCHK();
+}
+
+// M2M / L2L with up to 8 row tiles and 32 k-steps (p <= 10): one wave per
+// row tile with its operator rows in registers; otherwise (and for M2L) the
+// streaming form with at most 8 waves in balanced passes.
+template <typename R, int MODE>
+void launch_trans(const TransArgs &ta, dim3 grid_items, const R *ops, const R *in, R *out,
+                  int lev, hipStream_t s) {
+    const int nrt = (ta.K + 15) / 16, ks = ta.KK / 4;
+    // (M2L streams its operators: measured faster there than the resident form)
+    if (MODE != 0 && nrt <= 8 && ks <= 32) {
+        const unsigned nthr = 64u * (unsigned)nrt;
+        if (ks <= 16) launch_trans_k<R, MODE, 16>(ta, grid_items, nthr, ops, in, out, lev, s);
+        else if (ks <= 24) launch_trans_k<R, MODE, 24>(ta, grid_items, nthr, ops, in, out, lev, s);
+        else launch_trans_k<R, MODE, 32>(ta, grid_items, nthr, ops, in, out, lev, s);
+    } else {
+        const int passes = (nrt + 7) / 8;
+        const unsigned nthr = 64u * (unsigned)((nrt + passes - 1) / passes);
+        launch_trans_k<R, MODE, 0>(ta, grid_items, nthr, ops, in, out, lev, s);
+    }
 }
 
 // L[B] = sum over V(B) in list order of the M2L products (every box written).
@@ -498,7 +640,15 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(int K, long long nbox, const
     R acc[14];
 #pragma unroll
     for (int j = 0; j < 14; ++j) acc[j] = R(0);
-    for (long long q = q0 + wave; q < q1; q += 4) {
+    long long q = q0 + wave;
+    // two rows per step: their loads are independent and overlap
+    for (; q + 4 < q1; q += 8) {
+        const R *z = Z + q * W, *z2 = z + 4 * (long long)W;
+#pragma unroll
+        for (int j = 0; j < 14; ++j)
+            if (j < NJ && lane + 64 * j < W) acc[j] += z[lane + 64 * j] + z2[lane + 64 * j];
+    }
+    if (q < q1) {
         const R *z = Z + q * W;
 #pragma unroll
         for (int j = 0; j < 14; ++j)
@@ -663,12 +813,13 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, Fm
     F.PM = (long long)NRT * 16 * F.KK;
     auto pack = [&](const DBuf<double> &src, long long nmat, int transpose, DBuf<double> &d,
                     DBuf<float> &d32) {
-        // tail pad: the translation kernels prefetch up to 8 fragments past a
-        // matrix (values unused)
-        d.alloc((size_t)nmat * F.PM + 512);
-        d32.alloc((size_t)nmat * F.PM + 512);
-        HIPCHK(hipMemsetAsync(d.p, 0, ((size_t)nmat * F.PM + 512) * sizeof(double), s));
-        HIPCHK(hipMemsetAsync(d32.p, 0, ((size_t)nmat * F.PM + 512) * sizeof(float), s));
+        // tail pad: the translation kernels read up to 32 fragments of 64
+        // past the start of a matrix's last row tile (values unused)
+        const size_t pad = 32 * 64;
+        d.alloc((size_t)nmat * F.PM + pad);
+        d32.alloc((size_t)nmat * F.PM + pad);
+        HIPCHK(hipMemsetAsync(d.p, 0, ((size_t)nmat * F.PM + pad) * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(d32.p, 0, ((size_t)nmat * F.PM + pad) * sizeof(float), s));
         k_pack<<<grid_for(nmat * F.PM, 256), 256, 0, s>>>(src.p, nmat, K, F.KK, NRT, transpose,
                                                           d.p, d32.p);
         KCHK();
@@ -742,7 +893,10 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     if (L.n_m2l_items > 0) {
         ProfScope ps(prof, "m2l", s);
-        launch_trans<R, 0>(ta, dim3((unsigned)L.n_m2l_items, 2), Ops<R>::T(F), w.M, w.Z, 0, s);
+        ta.n_items = (int)L.n_m2l_items;
+        // grid padded to a multiple of 8 for the XCD-contiguous item mapping
+        const unsigned gx = (unsigned)((L.n_m2l_items + 7) / 8 * 8);
+        launch_trans<R, 0>(ta, dim3(gx, 2), Ops<R>::T(F), w.M, w.Z, 0, s);
     }
     {
         ProfScope ps(prof, "m2l_reduce", s);

@@ -26,6 +26,8 @@ struct MatvecPlan {
     double *pf = nullptr, *ph = nullptr;   // P2P sums (double in both precisions)
     double *part = nullptr;                // P2P chunk partial sums [chunks][2][64]
     const R *delta = nullptr;              // near corrections [nnz][4], working precision
+    hipStream_t side = nullptr;            // near field runs here, between fork and join
+    hipEvent_t fork = nullptr, join = nullptr;
     FarWork<R> far{};
 };
 

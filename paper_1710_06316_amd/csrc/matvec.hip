@@ -183,15 +183,14 @@ __global__ void k_gather_sources(const double *__restrict__ x, const double *__r
     sh[i] = R(area[i] * x[n + i]);
 }
 
-// One group of 8 lanes per row for the near correction (two entries in
-// flight per lane); the row's result is combined with every other part of
-// the matvec.  Lane partial sums are added by a fixed butterfly.
+// Near correction: one group of 8 lanes per row (two entries in flight per
+// lane), lane partial sums added by a fixed butterfly; the row's sums are
+// added to the P2P sums.
 template <typename R>
-__global__ void k_combine(long long n, const double *__restrict__ x, const double *__restrict__ pf,
-                          const double *__restrict__ ph, const R *__restrict__ phi,
-                          const long long *__restrict__ nptr, const int *__restrict__ ncol,
-                          const R *__restrict__ nd, double alpha, double inv_ebar,
-                          double *__restrict__ y) {
+__global__ void k_near_apply(long long n, const double *__restrict__ x,
+                             const long long *__restrict__ nptr, const int *__restrict__ ncol,
+                             const R *__restrict__ nd, double *__restrict__ pf,
+                             double *__restrict__ ph) {
     long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long p = gid >> 3;
     int sub = (int)(gid & 7);
@@ -224,11 +223,22 @@ __global__ void k_combine(long long n, const double *__restrict__ x, const doubl
         ch += __shfl_xor(ch, o, 8);
     }
     if (p < n && sub == 0) {
-        double far_f = -(double)phi[p] + (double)phi[2 * n + p];
-        double far_h = -(double)phi[n + p] + inv_ebar * (double)phi[3 * n + p];
-        y[p] = alpha * x[p] + pf[p] + far_f + cf;
-        y[n + p] = alpha * x[n + p] + ph[p] + far_h + ch;
+        pf[p] += cf;
+        ph[p] += ch;
     }
+}
+
+// y = alpha x + (P2P + near) - far field of Eq. (5).
+template <typename R>
+__global__ void k_combine(long long n, const double *__restrict__ x, const double *__restrict__ pf,
+                          const double *__restrict__ ph, const R *__restrict__ phi, double alpha,
+                          double inv_ebar, double *__restrict__ y) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double far_f = -(double)phi[p] + (double)phi[2 * n + p];
+    const double far_h = -(double)phi[n + p] + inv_ebar * (double)phi[3 * n + p];
+    y[p] = alpha * x[p] + pf[p] + far_f;
+    y[n + p] = alpha * x[n + p] + ph[p] + far_h;
 }
 
 __global__ void k_to_morton(const double *__restrict__ in, const int *__restrict__ perm,
@@ -269,25 +279,35 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
         k_gather_sources<R><<<grid_for(n, 256), 256, 0, s>>>(x, mp.area, n, mp.sf, mp.sh);
         KCHK();
     }
-    far_field<R>(*mp.fmm, *mp.tree, *mp.lists, mp.nd64, mp.nd.x, mp.nd.y, mp.nd.z, mp.nd.nx,
-                 mp.nd.ny, mp.nd.nz, mp.sf, mp.sh, mp.inv_ebar, n, mp.far, prof, s);
+    // fork: the near field (P2P and patch corrections) depends only on the
+    // gathered sources and x, and runs beside the far-field chain
+    HIPCHK(hipEventRecord(mp.fork, s));
+    HIPCHK(hipStreamWaitEvent(mp.side, mp.fork, 0));
     {
-        ProfScope ps(prof, "p2p", s);
+        ProfScope ps(prof, "p2p", mp.side);
         const Lists &L = *mp.lists;
-        k_p2p<R><<<(unsigned)L.n_chunks, 64, 0, s>>>(
+        k_p2p<R><<<(unsigned)L.n_chunks, 64, 0, mp.side>>>(
             L.ch_lo.p, L.ch_hi.p, L.ch_grp.p, L.grp_tbeg.p, L.grp_tend.p, L.rng_b.p, L.rng_e.p,
             mp.nd, mp.sf, mp.sh, R(mp.kappa), R(mp.inv_ebar), mp.part);
         KCHK();
-        k_p2p_reduce<<<(unsigned)L.n_groups, 64, 0, s>>>(L.grp_ptr.p, L.grp_tbeg.p, L.grp_tend.p,
-                                                          mp.part, mp.pf, mp.ph);
+        k_p2p_reduce<<<(unsigned)L.n_groups, 64, 0, mp.side>>>(L.grp_ptr.p, L.grp_tbeg.p,
+                                                                L.grp_tend.p, mp.part, mp.pf, mp.ph);
         KCHK();
     }
     {
-        ProfScope ps(prof, "near_combine", s);
-        k_combine<R><<<grid_for(8 * n, 256), 256, 0, s>>>(n, x, mp.pf, mp.ph, mp.far.phi,
-                                                          mp.near->ptr.p, mp.near->col.p,
-                                                          mp.delta, mp.alpha,
-                                                          mp.inv_ebar, y);
+        ProfScope ps(prof, "near", mp.side);
+        k_near_apply<R><<<grid_for(8 * n, 256), 256, 0, mp.side>>>(
+            n, x, mp.near->ptr.p, mp.near->col.p, mp.delta, mp.pf, mp.ph);
+        KCHK();
+    }
+    HIPCHK(hipEventRecord(mp.join, mp.side));
+    far_field<R>(*mp.fmm, *mp.tree, *mp.lists, mp.nd64, mp.nd.x, mp.nd.y, mp.nd.z, mp.nd.nx,
+                 mp.nd.ny, mp.nd.nz, mp.sf, mp.sh, mp.inv_ebar, n, mp.far, prof, s);
+    HIPCHK(hipStreamWaitEvent(s, mp.join, 0));
+    {
+        ProfScope ps(prof, "combine", s);
+        k_combine<R><<<grid_for(n, 256), 256, 0, s>>>(n, x, mp.pf, mp.ph, mp.far.phi, mp.alpha,
+                                                      mp.inv_ebar, y);
         KCHK();
     }
 }

@@ -1,4 +1,4 @@
-// Per-phase timing with HIP events on the context stream.
+// Per-phase timing with HIP events on the stream each phase runs on.
 #pragma once
 #include <map>
 #include <string>
@@ -20,6 +20,7 @@ struct Prof {
     // (entry, start, stop) events awaiting readout
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
     std::vector<hipEvent_t> pool;
+    int open = 0;   // scopes not yet closed (pending is only flushed at zero)
     int id_of(const char *name);
     hipEvent_t take();
     void flush();   // synchronises on pending events and accumulates
