@@ -54,7 +54,9 @@ typedef enum {
     AFMPB_E_NOT_CONVERGED = -4,  /* solve: outputs hold the last iterate, info filled */
     AFMPB_E_NUMERIC = -5,        /* NaN/Inf met in an iterate or input vector          */
     AFMPB_E_DEVICE = -6,         /* HIP runtime error; the context must be destroyed   */
-    AFMPB_E_STATE = -7           /* call out of order (e.g. matvec before a molecule)  */
+    AFMPB_E_STATE = -7,          /* call out of order (e.g. matvec before a molecule)  */
+    AFMPB_E_PENDING = -8,        /* server: request not finished yet                   */
+    AFMPB_E_CANCELLED = -9       /* server: request cancelled                          */
 } afmpb_status;
 
 typedef enum {
@@ -203,6 +205,95 @@ afmpb_status afmpb_debug_tree(afmpb_ctx *ctx, const afmpb_tree_view *out);
 afmpb_status afmpb_profile_enable(afmpb_ctx *ctx, int enable);
 afmpb_status afmpb_profile_read(afmpb_ctx *ctx, int idx, const char **name,
                                 double *total_ms, long long *launches);
+
+/* ------------------------------------------------------------------------
+ * Solve server: continuous batching of independent solves on one device.
+ *
+ * Requests are admitted in arrival order while the device bytes of the
+ * admitted molecules stay within hbm_budget_bytes (a single request larger
+ * than the budget runs alone) and fewer than max_active are in flight.  Each
+ * admitted molecule gets its own context and stream; its matvec is captured
+ * once into HIP graphs, and one host thread advances all admitted solves by
+ * one asynchronous GMRES chunk (one Arnoldi step) at a time, so their work
+ * overlaps on the device and late arrivals join while others run.  Every
+ * solve follows the same algorithm, kernels and order as afmpb_solve on the
+ * same molecule and parameters, so its result does not depend on what else
+ * is in flight.  All server functions are thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct afmpb_server afmpb_server;
+
+/* One request: host arrays as for afmpb_set_molecule (copied on submit). */
+typedef struct {
+    long long n_nodes;
+    const double *xyz;            /* [n_nodes][3]                           */
+    long long n_tri;
+    const int *tri;               /* [n_tri][3], outward (solvent) orientation */
+    long long n_atoms;
+    const double *atom_xyz;       /* [n_atoms][3]                           */
+    const double *charge;         /* [n_atoms]                              */
+} afmpb_molecule;
+
+/* Per-size choice of leaf capacity and expansion order, used for requests
+ * when the server's parameters have leaf_cap == 0 or order_p == 0: the first
+ * entry with n_nodes <= max_nodes applies (entries ascending in max_nodes;
+ * beyond the last entry: leaf 64, p 8). */
+typedef struct {
+    long long max_nodes;
+    int leaf_cap;
+    int order_p;
+} afmpb_tuning_entry;
+
+typedef struct {
+    int status;                   /* AFMPB_OK, AFMPB_E_PENDING, or the error     */
+    long long n_nodes;
+    double energy;                /* polar energy, kcal/mol                      */
+    afmpb_solve_info info;        /* ms_total = submit -> completion             */
+    long long device_bytes;       /* device memory the request held              */
+    double ms_admit;              /* submit -> admitted (setup starts)           */
+    double ms_ready;              /* submit -> set up (first GMRES chunk issued) */
+    double ms_done;               /* submit -> finished                          */
+    char message[128];            /* error text ("" on success)                  */
+} afmpb_result;
+
+typedef struct {
+    long long queued, active, completed, failed;
+    long long device_bytes, device_bytes_peak;
+} afmpb_server_counts;
+
+/* Starts a server on `device` (its setup and stepping threads).  params as
+ * for afmpb_set_molecule, except that order_p == 0 / leaf_cap == 0 select
+ * per request from the tuning table.  Errors: AFMPB_E_INVALID. */
+afmpb_status afmpb_server_create(const afmpb_params *params,
+                                 long long hbm_budget_bytes, int max_active,
+                                 int device, afmpb_server **out);
+
+/* Replaces the tuning table (n entries, copied). */
+afmpb_status afmpb_server_set_tuning(afmpb_server *s, int n,
+                                     const afmpb_tuning_entry *table);
+
+/* Queues a request (inputs copied) and returns its ticket.  Mesh errors are
+ * reported on the request's result. */
+afmpb_status afmpb_server_submit(afmpb_server *s, const afmpb_molecule *m,
+                                 unsigned long long *ticket);
+
+/* Result of a request.  wait != 0 blocks until it has finished.  Returns
+ * AFMPB_E_PENDING (and fills status/timings so far) while it runs; once
+ * finished returns AFMPB_OK, fills *out (out->status holds the request's own
+ * outcome) and copies f, h [n_nodes] (physical units, caller order; either
+ * may be NULL), and releases the ticket.  Unknown ticket: AFMPB_E_INVALID. */
+afmpb_status afmpb_server_poll(afmpb_server *s, unsigned long long ticket,
+                               int wait, afmpb_result *out, double *f,
+                               double *h);
+
+/* Cancels a request: a queued one finishes at once, a running one at its
+ * next GMRES chunk, with status AFMPB_E_CANCELLED. */
+afmpb_status afmpb_server_cancel(afmpb_server *s, unsigned long long ticket);
+
+afmpb_status afmpb_server_stats(afmpb_server *s, afmpb_server_counts *out);
+
+/* Stops the threads, cancels queued requests and frees everything.  Results
+ * not yet polled are discarded.  NULL is accepted. */
+afmpb_status afmpb_server_destroy(afmpb_server *s);
 
 #ifdef __cplusplus
 }

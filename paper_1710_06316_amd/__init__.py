@@ -28,17 +28,22 @@ AFMPB_E_NOT_CONVERGED = -4
 AFMPB_E_NUMERIC = -5
 AFMPB_E_DEVICE = -6
 AFMPB_E_STATE = -7
+AFMPB_E_PENDING = -8
+AFMPB_E_CANCELLED = -9
 AFMPB_FP64 = 0
 AFMPB_FP32_REFINED = 1
 
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_MESH", -3: "E_OOM",
-                -4: "E_NOT_CONVERGED", -5: "E_NUMERIC", -6: "E_DEVICE", -7: "E_STATE"}
+                -4: "E_NOT_CONVERGED", -5: "E_NUMERIC", -6: "E_DEVICE", -7: "E_STATE",
+                -8: "E_PENDING", -9: "E_CANCELLED"}
 
 ABI_FUNCTIONS = (
     "afmpb_default_params", "afmpb_create", "afmpb_destroy", "afmpb_last_error",
     "afmpb_set_molecule", "afmpb_matvec", "afmpb_matvec_dev", "afmpb_solve",
     "afmpb_rhs", "afmpb_energy", "afmpb_tree_info", "afmpb_debug_tree",
     "afmpb_profile_enable", "afmpb_profile_read",
+    "afmpb_server_create", "afmpb_server_set_tuning", "afmpb_server_submit",
+    "afmpb_server_poll", "afmpb_server_cancel", "afmpb_server_stats", "afmpb_server_destroy",
 )
 
 
@@ -84,6 +89,35 @@ class afmpb_tree_view(ctypes.Structure):
     _fields_ = [(k, _P) for k in _TREE_FIELDS]
 
 
+class afmpb_molecule(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_longlong), ("xyz", ctypes.POINTER(ctypes.c_double)),
+                ("n_tri", ctypes.c_longlong), ("tri", ctypes.POINTER(ctypes.c_int)),
+                ("n_atoms", ctypes.c_longlong), ("atom_xyz", ctypes.POINTER(ctypes.c_double)),
+                ("charge", ctypes.POINTER(ctypes.c_double))]
+
+
+class afmpb_tuning_entry(ctypes.Structure):
+    _fields_ = [("max_nodes", ctypes.c_longlong), ("leaf_cap", ctypes.c_int),
+                ("order_p", ctypes.c_int)]
+
+
+class afmpb_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("n_nodes", ctypes.c_longlong),
+                ("energy", ctypes.c_double), ("info", afmpb_solve_info),
+                ("device_bytes", ctypes.c_longlong), ("ms_admit", ctypes.c_double),
+                ("ms_ready", ctypes.c_double), ("ms_done", ctypes.c_double),
+                ("message", ctypes.c_char * 128)]
+
+
+class afmpb_server_counts(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_longlong) for k in
+                ("queued", "active", "completed", "failed", "device_bytes",
+                 "device_bytes_peak")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -115,6 +149,17 @@ def lib():
         L.afmpb_profile_enable.argtypes = [vp, ctypes.c_int]
         L.afmpb_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                          dp, ctypes.POINTER(ll)]
+        L.afmpb_server_create.argtypes = [ctypes.POINTER(afmpb_params), ll, ctypes.c_int,
+                                          ctypes.c_int, ctypes.POINTER(vp)]
+        L.afmpb_server_set_tuning.argtypes = [vp, ctypes.c_int,
+                                              ctypes.POINTER(afmpb_tuning_entry)]
+        L.afmpb_server_submit.argtypes = [vp, ctypes.POINTER(afmpb_molecule),
+                                          ctypes.POINTER(ctypes.c_ulonglong)]
+        L.afmpb_server_poll.argtypes = [vp, ctypes.c_ulonglong, ctypes.c_int,
+                                        ctypes.POINTER(afmpb_result), dp, dp]
+        L.afmpb_server_cancel.argtypes = [vp, ctypes.c_ulonglong]
+        L.afmpb_server_stats.argtypes = [vp, ctypes.POINTER(afmpb_server_counts)]
+        L.afmpb_server_destroy.argtypes = [vp]
         for name in ABI_FUNCTIONS:
             if name != "afmpb_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -328,3 +373,113 @@ class Solver:
 
     def profile_read(self):
         return afmpb_profile_read(self.ctx)
+
+
+# --- solve server ---------------------------------------------------------------
+
+def afmpb_server_create(params: afmpb_params, hbm_budget_bytes: int, max_active: int,
+                        device: int = 0):
+    h = ctypes.c_void_p()
+    st = lib().afmpb_server_create(ctypes.byref(params), int(hbm_budget_bytes), int(max_active),
+                                   int(device), ctypes.byref(h))
+    if st != AFMPB_OK:
+        raise AfmpbError(st, "afmpb_server_create failed")
+    return h
+
+
+def afmpb_server_set_tuning(srv, table):
+    """table: sequence of (max_nodes, leaf_cap, order_p), ascending max_nodes."""
+    arr = (afmpb_tuning_entry * max(len(table), 1))()
+    for i, (mx, leaf, p) in enumerate(table):
+        arr[i] = afmpb_tuning_entry(int(mx), int(leaf), int(p))
+    st = lib().afmpb_server_set_tuning(srv, len(table), arr)
+    if st != AFMPB_OK:
+        raise AfmpbError(st, "bad tuning table")
+
+
+def afmpb_server_submit(srv, xyz, tri, atom_xyz, charge) -> int:
+    xyz = _f64(xyz).reshape(-1, 3)
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    ax = _f64(atom_xyz).reshape(-1, 3)
+    q = _f64(charge).reshape(-1)
+    m = afmpb_molecule(len(xyz), _dp(xyz), len(tri), _ip(tri), len(q), _dp(ax), _dp(q))
+    t = ctypes.c_ulonglong()
+    st = lib().afmpb_server_submit(srv, ctypes.byref(m), ctypes.byref(t))
+    if st != AFMPB_OK:
+        raise AfmpbError(st, "afmpb_server_submit failed")
+    return t.value
+
+
+def afmpb_server_poll(srv, ticket: int, n_nodes: int, wait: bool = False):
+    """(status, result, f, h); status AFMPB_E_PENDING while the request runs."""
+    res = afmpb_result()
+    f = np.empty(n_nodes)
+    h = np.empty(n_nodes)
+    st = lib().afmpb_server_poll(srv, ctypes.c_ulonglong(ticket), 1 if wait else 0,
+                                 ctypes.byref(res), _dp(f), _dp(h))
+    if st not in (AFMPB_OK, AFMPB_E_PENDING):
+        raise AfmpbError(st, "afmpb_server_poll failed")
+    return st, res, f, h
+
+
+def afmpb_server_cancel(srv, ticket: int):
+    st = lib().afmpb_server_cancel(srv, ctypes.c_ulonglong(ticket))
+    if st != AFMPB_OK:
+        raise AfmpbError(st, "afmpb_server_cancel failed")
+
+
+def afmpb_server_stats(srv) -> dict:
+    c = afmpb_server_counts()
+    st = lib().afmpb_server_stats(srv, ctypes.byref(c))
+    if st != AFMPB_OK:
+        raise AfmpbError(st, "afmpb_server_stats failed")
+    return c.as_dict()
+
+
+def afmpb_server_destroy(srv):
+    return lib().afmpb_server_destroy(srv)
+
+
+class Server:
+    """Continuous-batching solve server (one device)."""
+
+    def __init__(self, hbm_budget_bytes: int = 32 << 30, max_active: int = 64, device: int = 0,
+                 tuning=None, **params):
+        p = afmpb_default_params()
+        for k, v in params.items():
+            setattr(p, k, v)
+        self.srv = afmpb_server_create(p, hbm_budget_bytes, max_active, device)
+        self.n_of = {}
+        if tuning:
+            afmpb_server_set_tuning(self.srv, tuning)
+
+    def submit(self, mol) -> int:
+        t = afmpb_server_submit(self.srv, mol.xyz, mol.tri, mol.atom_xyz, mol.charge)
+        self.n_of[t] = int(np.asarray(mol.xyz).reshape(-1, 3).shape[0])
+        return t
+
+    def poll(self, ticket: int, wait: bool = False):
+        st, res, f, h = afmpb_server_poll(self.srv, ticket, self.n_of[ticket], wait)
+        if st == AFMPB_OK:
+            del self.n_of[ticket]
+        return st, res, f, h
+
+    def wait(self, ticket: int):
+        return self.poll(ticket, wait=True)[1:]
+
+    def cancel(self, ticket: int):
+        afmpb_server_cancel(self.srv, ticket)
+
+    def stats(self) -> dict:
+        return afmpb_server_stats(self.srv)
+
+    def close(self):
+        if self.srv is not None:
+            afmpb_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,10 +7,7 @@
 #include <cstdlib>
 #include <numeric>
 
-#include "../../include/afmpb.h"
-#include "krylov.h"
-#include "matvec.h"
-#include "prof.h"
+#include "ctx.h"
 
 namespace afmpb {
 
@@ -150,52 +147,8 @@ void validate_mesh(long long n, const double *V, long long m, const int *T) {
 
 using namespace afmpb;
 
-struct afmpb_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    // second stream for the near field, forked from and joined to `stream`
-    // inside every matvec (default priority)
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    std::string err;
-    bool loaded = false;
-    afmpb_params prm{};
-    long long n = 0, m = 0, na = 0;
-    double ebar = 1, alpha = 1, inv_ebar = 1;
-    double ms_setup = 0;
-    DBuf<double> V, ax, aq, tri_area, tri_n, area_c, nrm_c, rho2_c;
-    DBuf<int> T, inc_ptr, inc_tri, perm;
-    DBuf<unsigned long long> keys;
-    DBuf<double> node64;      // 8n: x y z nx ny nz area rho2
-    DBuf<float> node32;       // 6n
-    double lo[3] = {0, 0, 0}, scale = 1;
-    Tree tree;
-    Lists lists;
-    NearSet near;
-    Fmm fmm;
-    DBuf<double> w64, far64, p2p64, p2p_part;
-    DBuf<float> w32, far32;
-    MatvecPlan<double> mp64;
-    MatvecPlan<float> mp32;
-    // vectors in Morton order
-    DBuf<double> xa, ya, bvec, xsol, tmp, hbuf, dscratch, phi_at, dotv;
-    DBuf<double> krylov;
-    int krylov_m = 0;
-    Prof prof;
 
-    NodeSoA nodes() const {
-        double *b = node64.p;
-        long long N = n;
-        return NodeSoA{b, b + N, b + 2 * N, b + 3 * N, b + 4 * N, b + 5 * N, b + 6 * N, b + 7 * N};
-    }
-    void sync() { HIPCHK(hipStreamSynchronize(stream)); }
-    void matvec_m(const double *x, double *y, bool fp64) {
-        if (fp64 || prm.precision == AFMPB_FP64) apply_operator<double>(mp64, x, y, &prof, stream);
-        else apply_operator<float>(mp32, x, y, &prof, stream);
-    }
-};
-
-namespace {
+namespace afmpb {
 
 int fail(afmpb_ctx *ctx, const Error &e) {
     if (ctx) ctx->err = e.what();
@@ -612,7 +565,20 @@ Gmres gmres(afmpb_ctx *c, const double *b, double *x, bool x_zero, double rel_to
     return g;
 }
 
-}  // namespace
+double energy_of(afmpb_ctx *ctx, const double *x_morton) {
+    if (ctx->na == 0) return 0.0;
+    reaction_potential(ctx->nodes(), ctx->n, x_morton, ctx->ax.p, ctx->na, ctx->ebar,
+                       ctx->phi_at.p, ctx->stream);
+    std::vector<double> phi(ctx->na), q(ctx->na);
+    ctx->phi_at.download(phi.data(), ctx->na, ctx->stream);
+    ctx->aq.download(q.data(), ctx->na, ctx->stream);
+    ctx->sync();
+    double sum = 0.0;
+    for (long long k = 0; k < ctx->na; ++k) sum += q[k] * phi[k];
+    return 0.5 * sum * unit_scale();
+}
+
+}  // namespace afmpb
 
 extern "C" {
 
@@ -723,18 +689,6 @@ afmpb_status afmpb_rhs(afmpb_ctx *ctx, double *b) {
     });
 }
 
-static double energy_of(afmpb_ctx *ctx, const double *x_morton) {
-    if (ctx->na == 0) return 0.0;
-    reaction_potential(ctx->nodes(), ctx->n, x_morton, ctx->ax.p, ctx->na, ctx->ebar,
-                       ctx->phi_at.p, ctx->stream);
-    std::vector<double> phi(ctx->na), q(ctx->na);
-    ctx->phi_at.download(phi.data(), ctx->na, ctx->stream);
-    ctx->aq.download(q.data(), ctx->na, ctx->stream);
-    ctx->sync();
-    double sum = 0.0;
-    for (long long k = 0; k < ctx->na; ++k) sum += q[k] * phi[k];
-    return 0.5 * sum * unit_scale();
-}
 
 afmpb_status afmpb_energy(afmpb_ctx *ctx, const double *x, double *energy) {
     if (!ctx) return AFMPB_E_INVALID;

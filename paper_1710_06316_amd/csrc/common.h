@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -46,17 +47,27 @@ inline void require(bool ok, int code, const std::string &msg) {
 // Device buffer (owning, move-only)
 // ---------------------------------------------------------------------------
 
+// Device bytes held by DBufs are added to the counter that is current on the
+// allocating thread (if any) and taken off it again on release; the solve
+// server uses this for its memory budget.
+inline thread_local std::atomic<long long> *g_dev_bytes = nullptr;
+
 template <typename T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
+    std::atomic<long long> *acct = nullptr;
     DBuf() = default;
     explicit DBuf(size_t count) { alloc(count); }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), acct(o.acct) { o.p = nullptr; o.n = 0; o.acct = nullptr; }
     DBuf &operator=(DBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; acct = o.acct;
+            o.p = nullptr; o.n = 0; o.acct = nullptr;
+        }
         return *this;
     }
     ~DBuf() { release(); }
@@ -65,9 +76,15 @@ struct DBuf {
         if (count == 0) count = 1;  // keep a valid pointer for empty arrays
         HIPCHK(hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)));
         n = count;
+        acct = g_dev_bytes;
+        if (acct) *acct += (long long)(n * sizeof(T));
     }
     void release() {
-        if (p) { (void)hipFree(p); p = nullptr; n = 0; }
+        if (p) {
+            (void)hipFree(p);
+            if (acct) *acct -= (long long)(n * sizeof(T));
+            p = nullptr; n = 0; acct = nullptr;
+        }
     }
     T *get() const { return p; }
     void upload(const T *h, size_t count, hipStream_t s) {

@@ -692,6 +692,12 @@ __global__ void __launch_bounds__(128) k_l2p(BasisDev B, TreeDev T, const int *l
     }
 }
 
+template <typename R>
+__global__ void k_fill_zero(R *a, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = R(0);
+}
+
 }  // namespace
 
 void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, Fmm &F,
@@ -855,8 +861,10 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
               t.prefix.p, t.center.p};
     const int K = F.K;
     if (L.n_v == 0) {
-        // no box has a far field: every pair is in a U/W/X list
-        HIPCHK(hipMemsetAsync(w.phi, 0, sizeof(R) * 4 * n, s));
+        // no box has a far field: every pair is in a U/W/X list (a fill
+        // kernel, not a memset, so that the matvec can be graph-captured)
+        k_fill_zero<R><<<grid_for(4 * n, 256), 256, 0, s>>>(w.phi, 4 * n);
+        KCHK();
         return;
     }
     {

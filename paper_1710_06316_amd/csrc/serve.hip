@@ -1,0 +1,812 @@
+// Solve server: continuous batching of independent PB solves on one GPU.
+//
+// Requests (a surface mesh and its charges) are queued on submit.  A setup
+// thread admits them in arrival order while the device bytes of the admitted
+// molecules stay within the budget and a slot is free, builds each one's
+// context (geometry, tree, lists, near set, operators; Section 3) on a stream
+// of its own and captures its matvec (Eq. 5, far field and near field) into
+// HIP graphs.  A stepping thread advances every admitted solve through its
+// restarted GMRES (Section 2, Algorithm of the Krylov solver, stopping rule
+// Eq. 7) as a resumable state machine: each call issues one asynchronous
+// chunk of device work (one Arnoldi step = one graph launch plus the block
+// Gram-Schmidt kernels and one small device-to-host copy) and returns; the
+// next chunk is issued once its completion event has fired.  Work of all
+// active solves therefore overlaps on the device, and requests that arrive
+// while others run join as memory and slots free up.  Results (potential,
+// normal derivative, polar energy) are kept until the caller polls them.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "ctx.h"
+
+namespace afmpb {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+// Page-locked host staging (asynchronous copies need it).
+struct Pinned {
+    double *p = nullptr;
+    size_t n = 0;
+    void alloc(size_t count) {
+        release();
+        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&p), std::max<size_t>(count, 1) * sizeof(double),
+                             hipHostMallocDefault));
+        n = count;
+    }
+    void release() {
+        if (p) { (void)hipHostFree(p); p = nullptr; n = 0; }
+    }
+    ~Pinned() { release(); }
+};
+
+// The matvec of one context captured once (input ctx->xa, output ctx->ya).
+struct MatvecGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void capture(afmpb_ctx *c, bool fp64) {
+        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        try {
+            c->matvec_m(c->xa.p, c->ya.p, fp64);
+        } catch (...) {
+            hipGraph_t tmp = nullptr;
+            (void)hipStreamEndCapture(c->stream, &tmp);
+            if (tmp) (void)hipGraphDestroy(tmp);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(c->stream, &g));
+        HIPCHK(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    }
+    void launch(hipStream_t s) const { HIPCHK(hipGraphLaunch(exec, s)); }
+    ~MatvecGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+struct Request {
+    unsigned long long ticket = 0;
+    // copied inputs
+    std::vector<double> xyz, axyz, q;
+    std::vector<int> tri;
+    long long n = 0, m = 0, na = 0;
+    afmpb_params prm{};
+    // outcome
+    int status = AFMPB_E_PENDING;
+    std::string message;
+    double energy = 0;
+    afmpb_solve_info info{};
+    std::vector<double> f, h;
+    std::atomic<bool> cancelled{false};
+    long long dev_bytes = 0;
+    Clock::time_point t_submit, t_admit, t_ready, t_done;
+};
+
+// Restarted GMRES as a state machine over asynchronous chunks.  One run
+// solves M x = b for the current (b, x) with the FP64 or FP32 operator graph;
+// the plain form wraps one run, the refined form (FP32 operator inside, FP64
+// residual outside) wraps several.
+struct SolveJob {
+    std::atomic<long long> bytes{0};        // first: outlives every buffer below
+    Request *req = nullptr;
+    std::unique_ptr<afmpb_ctx> c;
+    MatvecGraph g64, g32;
+    bool refine = false;
+    hipEvent_t ev = nullptr;
+    bool pending = false;                   // a chunk is in flight
+
+    enum Phase {
+        RHS_NORM,       // ||b|| on the host
+        RUN_CYCLE,      // residual of a cycle start on the host
+        RUN_STEP,       // one Arnoldi column on the host
+        OUTER_RES,      // refined form: FP64 residual norm
+        TRUE_RES,       // plain form: FP64 residual norm
+        FINISH,         // energy and result download
+        DONE
+    } ph = RHS_NORM;
+
+    long long n = 0, len = 0;
+    int m = 80, max_restarts = 5;
+    double nb = 0, tol = 0;
+    // current GMRES run
+    const double *rb = nullptr;             // right-hand side of the run
+    double *rx = nullptr;                   // iterate of the run
+    bool run_fp64 = true, run_zero = true, run_first = true;
+    double run_tol = 0;
+    int cycle = 0, j = 0, k = 0;
+    double beta = 0, hn = 0;
+    bool scale_pending = false;             // V[j] = w / hn before the next step
+    double scale_by = 1;
+    std::vector<double> H, cs, sn, gv;
+    // refined form
+    DBuf<double> r, d;
+    int outer_it = 0;
+    double rn = 0;
+    // statistics
+    int iterations = 0, restarts = 0, refinement = 0;
+    long long inner = 0;
+    double est = 0, true_rel = 0;
+    bool converged = false;
+    // staging: [0, m+2) h1, [m+2, 2m+4) h2, [2m+4] scalar, [2m+8, 3m+8) y
+    Pinned hp, xout, phi;
+
+    double *V() const { return c->krylov.p; }
+    double *col(int i) const { return c->krylov.p + (size_t)i * len; }
+    hipStream_t s() const { return c->stream; }
+
+    void record() {
+        HIPCHK(hipEventRecord(ev, s()));
+        pending = true;
+    }
+
+    // ---- run control --------------------------------------------------
+    void issue_dot_to_host(const double *a, long long L, int slot) {
+        dots(a, 0, 1, a, L, c->hbuf.p + slot, c->dscratch, s());
+        HIPCHK(hipMemcpyAsync(hp.p + slot, c->hbuf.p + slot, sizeof(double),
+                              hipMemcpyDeviceToHost, s()));
+    }
+    const MatvecGraph &graph(bool fp64) const { return fp64 ? g64 : g32; }
+
+    // r0 = b - M x (or b when x = 0 on the first cycle) into V[0], and its norm
+    void issue_cycle_start() {
+        if (run_first && run_zero) {
+            HIPCHK(hipMemcpyAsync(col(0), rb, len * sizeof(double), hipMemcpyDeviceToDevice, s()));
+        } else {
+            HIPCHK(hipMemcpyAsync(c->xa.p, rx, len * sizeof(double), hipMemcpyDeviceToDevice, s()));
+            graph(run_fp64).launch(s());
+            axpby(1.0, rb, -1.0, c->ya.p, len, col(0), s());
+        }
+        run_first = false;
+        issue_dot_to_host(col(0), len, 2 * m + 4);
+        record();
+        ph = RUN_CYCLE;
+    }
+
+    void start_run(const double *b, double *x, bool x_zero, double rel, double abs_t, bool fp64) {
+        rb = b;
+        rx = x;
+        run_zero = x_zero;
+        run_first = true;
+        run_fp64 = fp64;
+        run_tol = rel;       // relative to ||b|| of this run; set after its norm
+        cycle = 0;
+        if (x_zero) {
+            // zero fill by kernel (x may be V memory of a later capture)
+            axpby(0.0, b, 0.0, b, len, x, s());
+        }
+        // ||b|| of the run first: reuse the cycle-start residual when x = 0
+        (void)abs_t;
+        issue_cycle_start();
+    }
+
+    void issue_step() {
+        if (scale_pending) {
+            scale(c->ya.p, scale_by, len, col(j), s());
+            scale_pending = false;
+        }
+        HIPCHK(hipMemcpyAsync(c->xa.p, col(j), len * sizeof(double), hipMemcpyDeviceToDevice, s()));
+        graph(run_fp64).launch(s());
+        double *w = c->ya.p;
+        dots(V(), len, j + 1, w, len, c->hbuf.p, c->dscratch, s());
+        gemv(V(), len, j + 1, c->hbuf.p, -1.0, len, w, s());
+        dots(V(), len, j + 1, w, len, c->hbuf.p + (m + 2), c->dscratch, s());
+        gemv(V(), len, j + 1, c->hbuf.p + (m + 2), -1.0, len, w, s());
+        dots(w, 0, 1, w, len, c->hbuf.p + 2 * m + 4, c->dscratch, s());
+        HIPCHK(hipMemcpyAsync(hp.p, c->hbuf.p, (2 * m + 5) * sizeof(double),
+                              hipMemcpyDeviceToHost, s()));
+        record();
+        ph = RUN_STEP;
+    }
+
+    // x += V y for the k columns of the finished cycle
+    void issue_cycle_end() {
+        std::vector<double> y(k);
+        for (int i = k - 1; i >= 0; --i) {
+            double acc = gv[i];
+            for (int l = i + 1; l < k; ++l) acc -= H[(size_t)i * m + l] * y[l];
+            y[i] = acc / H[(size_t)i * m + i];
+        }
+        std::memcpy(hp.p + 2 * m + 8, y.data(), k * sizeof(double));
+        HIPCHK(hipMemcpyAsync(c->hbuf.p + 2 * m + 8, hp.p + 2 * m + 8, k * sizeof(double),
+                              hipMemcpyHostToDevice, s()));
+        gemv(V(), len, k, c->hbuf.p + 2 * m + 8, 1.0, len, rx, s());
+    }
+
+    // returns true when the run has finished (converged or out of restarts)
+    bool consume_cycle() {
+        beta = std::sqrt(hp.p[2 * m + 4]);
+        inner += 1;
+        require(std::isfinite(beta), ST_NUMERIC, "non-finite residual");
+        if (cycle == 0) {
+            // the first residual of a run fixes its tolerance (Eq. 7)
+            run_tol = run_tol * beta_ref() + abs_run();
+        }
+        est = beta;
+        if (beta <= run_tol) { run_converged = true; return true; }
+        if (cycle > 0) restarts += 1;
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        j = 0;
+        k = 0;
+        scale_pending = false;
+        scale(col(0), 1.0 / beta, len, col(0), s());
+        issue_step();
+        return false;
+    }
+
+    bool run_converged = false;
+    double run_bnorm = 0, run_abs = 0;
+    double beta_ref() const { return run_bnorm; }
+    double abs_run() const { return run_abs; }
+
+    // returns true when the run has finished
+    bool consume_step() {
+        iterations += 1;
+        const double *h1 = hp.p, *h2 = hp.p + (m + 2);
+        hn = std::sqrt(hp.p[2 * m + 4]);
+        inner += 2 * (j + 1) + 1;
+        require(std::isfinite(hn), ST_NUMERIC, "non-finite value in the Arnoldi process");
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h1[i] + h2[i];
+        H[(size_t)(j + 1) * m + j] = hn;
+        for (int i = 0; i < j; ++i) {
+            double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+            H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+            H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+        }
+        double den = std::hypot(H[(size_t)j * m + j], hn);
+        cs[j] = H[(size_t)j * m + j] / den;
+        sn[j] = hn / den;
+        H[(size_t)j * m + j] = den;
+        H[(size_t)(j + 1) * m + j] = 0.0;
+        gv[j + 1] = -sn[j] * gv[j];
+        gv[j] = cs[j] * gv[j];
+        k = j + 1;
+        est = std::fabs(gv[j + 1]);
+        const bool done = est <= run_tol || hn == 0.0;
+        if (done || j + 1 == m) {
+            issue_cycle_end();
+            if (done) { run_converged = true; return true; }
+            if (cycle >= max_restarts) return true;
+            ++cycle;
+            issue_cycle_start();
+            return false;
+        }
+        scale_pending = true;
+        scale_by = 1.0 / hn;
+        ++j;
+        issue_step();
+        return false;
+    }
+
+    // ---- solve control ------------------------------------------------
+    void begin() {
+        n = c->n;
+        len = 2 * n;
+        const afmpb_params &p = c->prm;
+        m = p.restart;
+        max_restarts = p.max_restarts;
+        refine = p.precision != AFMPB_FP64;
+        H.assign((size_t)(m + 1) * m, 0.0);
+        cs.assign(m, 0.0);
+        sn.assign(m, 0.0);
+        gv.assign(m + 1, 0.0);
+        hp.alloc(3 * m + 16);
+        xout.alloc(len);
+        phi.alloc(std::max(c->na, 1ll));
+        if (c->krylov_m < m) {
+            c->krylov.alloc((size_t)(m + 1) * len);
+            c->krylov_m = m;
+        }
+        if (c->hbuf.n < (size_t)(3 * m + 16)) c->hbuf.alloc(3 * m + 16);
+        if (refine) {
+            r.alloc(len);
+            d.alloc(len);
+        }
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        rhs(c->nodes(), n, c->ax.p, c->aq.p, c->na, p.eps_s, c->bvec.p, s());
+        issue_dot_to_host(c->bvec.p, len, 2 * m + 4);
+        record();
+        ph = RHS_NORM;
+    }
+
+    void start_plain() {
+        run_bnorm = nb;
+        run_abs = c->prm.abs_tol;
+        run_converged = false;
+        start_run(c->bvec.p, c->xsol.p, true, c->prm.rel_tol, c->prm.abs_tol, true);
+    }
+
+    void start_inner() {
+        // inner FP32 run on the current residual r (norm rn), d = 0
+        run_bnorm = rn;
+        run_abs = 0.0;
+        run_converged = false;
+        start_run(r.p, d.p, true, std::max(tol / rn, 1e-6), 0.0, false);
+    }
+
+    void issue_residual(Phase next, double *rout) {
+        HIPCHK(hipMemcpyAsync(c->xa.p, c->xsol.p, len * sizeof(double), hipMemcpyDeviceToDevice, s()));
+        g64.launch(s());
+        axpby(1.0, c->bvec.p, -1.0, c->ya.p, len, rout, s());
+        issue_dot_to_host(rout, len, 2 * m + 4);
+        record();
+        ph = next;
+    }
+
+    void issue_finish() {
+        if (c->na > 0) {
+            reaction_potential(c->nodes(), n, c->xsol.p, c->ax.p, c->na, c->ebar, c->phi_at.p, s());
+            HIPCHK(hipMemcpyAsync(phi.p, c->phi_at.p, c->na * sizeof(double),
+                                  hipMemcpyDeviceToHost, s()));
+        }
+        from_morton(c->xsol.p, c->perm.p, n, c->tmp.p, s());
+        HIPCHK(hipMemcpyAsync(xout.p, c->tmp.p, len * sizeof(double), hipMemcpyDeviceToHost, s()));
+        record();
+        ph = FINISH;
+    }
+
+    void run_finished() {
+        if (!refine) {
+            converged = run_converged;
+            // true residual with the FP64 operator
+            issue_residual(TRUE_RES, c->tmp.p);
+            return;
+        }
+        // refined: x += d, then the FP64 residual
+        axpby(1.0, c->xsol.p, 1.0, d.p, len, c->xsol.p, s());
+        ++refinement;
+        issue_residual(OUTER_RES, r.p);
+    }
+
+    // Called when the chunk in flight has completed.
+    void advance() {
+        pending = false;
+        switch (ph) {
+        case RHS_NORM: {
+            nb = std::sqrt(hp.p[2 * m + 4]);
+            inner += 1;
+            tol = c->prm.rel_tol * nb + c->prm.abs_tol;
+            if (!refine) {
+                start_plain();
+            } else {
+                axpby(0.0, c->bvec.p, 0.0, c->bvec.p, len, c->xsol.p, s());   // x = 0
+                HIPCHK(hipMemcpyAsync(r.p, c->bvec.p, len * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s()));
+                rn = nb;
+                if (rn <= tol) {
+                    converged = true;
+                    true_rel = 0.0;
+                    issue_finish();
+                } else {
+                    start_inner();
+                }
+            }
+            break;
+        }
+        case RUN_CYCLE:
+            if (consume_cycle()) run_finished();
+            break;
+        case RUN_STEP:
+            if (consume_step()) run_finished();
+            break;
+        case OUTER_RES: {
+            rn = std::sqrt(hp.p[2 * m + 4]);
+            require(std::isfinite(rn), ST_NUMERIC, "non-finite residual");
+            est = rn;
+            if (rn <= tol || ++outer_it >= 8) {
+                converged = rn <= tol;
+                true_rel = nb > 0 ? rn / nb : rn;
+                issue_finish();
+            } else {
+                start_inner();
+            }
+            break;
+        }
+        case TRUE_RES: {
+            const double rr = std::sqrt(hp.p[2 * m + 4]);
+            true_rel = nb > 0 ? rr / nb : rr;
+            issue_finish();
+            break;
+        }
+        case FINISH:
+        case DONE:
+            ph = DONE;
+            break;
+        }
+    }
+
+    // polar energy and outputs in physical units (after FINISH completed)
+    void collect(Request &q) {
+        const double us = unit_scale();
+        double sum = 0.0;
+        for (long long kk = 0; kk < c->na; ++kk) sum += q.q[kk] * phi.p[kk];
+        q.energy = 0.5 * sum * us;
+        q.f.resize(n);
+        q.h.resize(n);
+        for (long long i = 0; i < n; ++i) {
+            q.f[i] = xout.p[i] * us;
+            q.h[i] = xout.p[n + i] * us;
+        }
+        afmpb_solve_info &inf = q.info;
+        std::memset(&inf, 0, sizeof(inf));
+        inf.iterations = iterations;
+        inf.restarts = restarts;
+        inf.inner_products = inner;
+        inf.rel_residual_estimate = nb > 0 ? est / nb : est;
+        inf.true_rel_residual = true_rel;
+        inf.converged = converged ? 1 : 0;
+        inf.refinement_steps = refinement;
+        inf.ms_setup = c->ms_setup;
+    }
+
+    ~SolveJob() {
+        if (ev) (void)hipEventDestroy(ev);
+        if (!c) return;
+        hipStream_t st = c->stream, sd = c->side;
+        hipEvent_t e1 = c->ev_fork, e2 = c->ev_join;
+        if (st) (void)hipStreamSynchronize(st);
+        if (sd) (void)hipStreamSynchronize(sd);
+        r.release();
+        d.release();
+        c.reset();                              // device buffers of the context
+        if (e1) (void)hipEventDestroy(e1);
+        if (e2) (void)hipEventDestroy(e2);
+        if (sd) (void)hipStreamDestroy(sd);
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+
+}  // namespace
+}  // namespace afmpb
+
+using namespace afmpb;
+
+struct afmpb_server {
+    afmpb_params prm{};
+    long long budget = 0;
+    int max_active = 0;
+    int device = 0;
+    std::vector<afmpb_tuning_entry> tuning;
+    std::mutex mu;
+    std::condition_variable cv_setup, cv_step, cv_done;
+    std::deque<Request *> queue;                       // submitted, not admitted
+    std::map<unsigned long long, std::unique_ptr<Request>> reqs;
+    std::vector<std::unique_ptr<SolveJob>> ready;      // set up, not yet stepping
+    std::atomic<long long> bytes_in_use{0}, bytes_peak{0};
+    long long bytes_reserved = 0;                      // estimates of jobs in setup
+    int n_active = 0;                                  // admitted, not finished
+    long long completed = 0, failed = 0;
+    unsigned long long next_ticket = 1;
+    bool stop = false;
+    std::thread setup_thr, step_thr;
+    std::string err;
+
+    static long long estimate_bytes(long long n, int p) {
+        // near set (~120 entries/node x 52 B), Krylov basis, M2L slots and
+        // expansions (~30 KB/node at p = 8) plus the dense translation
+        // operators (316 classes per level); a deliberately generous bound
+        const long long K = (long long)(p + 1) * (p + 1);
+        return n * (8000 + 160 * K) + 6 * 316 * 2 * K * K * 12 + (64ll << 20);
+    }
+
+    afmpb_params params_for(const Request &q) const {
+        afmpb_params p = prm;
+        if (prm.leaf_cap == 0 || prm.order_p == 0) {
+            int leaf = 64, order = 8;
+            for (const auto &t : tuning) {
+                if (q.n <= t.max_nodes) { leaf = t.leaf_cap; order = t.order_p; break; }
+            }
+            if (prm.leaf_cap == 0) p.leaf_cap = leaf;
+            if (prm.order_p == 0) p.order_p = order;
+        }
+        return normalise(p);
+    }
+
+    void setup_loop();
+    void step_loop();
+};
+
+void afmpb_server::setup_loop() {
+    (void)hipSetDevice(device);
+    for (;;) {
+        Request *q = nullptr;
+        long long est = 0;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_setup.wait(lk, [&] {
+                if (stop) return true;
+                if (queue.empty() || n_active >= max_active) return false;
+                const Request *h = queue.front();
+                const long long e = estimate_bytes(h->n, params_for(*h).order_p);
+                // admit when it fits, or when nothing else is running (a single
+                // request larger than the budget still gets its turn alone)
+                return bytes_in_use.load() + bytes_reserved + e <= budget || n_active == 0;
+            });
+            if (stop) return;
+            q = queue.front();
+            queue.pop_front();
+            est = estimate_bytes(q->n, params_for(*q).order_p);
+            bytes_reserved += est;
+            ++n_active;
+        }
+        q->t_admit = Clock::now();
+        auto job = std::make_unique<SolveJob>();
+        job->req = q;
+        try {
+            if (q->cancelled) throw Error(AFMPB_E_CANCELLED, "cancelled");
+            g_dev_bytes = &job->bytes;
+            job->c = std::make_unique<afmpb_ctx>();
+            afmpb_ctx *c = job->c.get();
+            c->device = device;
+            HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+            load_molecule(c, q->n, q->xyz.data(), q->m, q->tri.data(), q->na, q->axyz.data(),
+                          q->q.data(), params_for(*q));
+            job->g64.capture(c, true);
+            if (c->prm.precision != AFMPB_FP64) job->g32.capture(c, false);
+            job->begin();
+            g_dev_bytes = nullptr;
+            q->t_ready = Clock::now();
+            std::lock_guard<std::mutex> lk(mu);
+            bytes_reserved -= est;
+            bytes_in_use += job->bytes.load();
+            q->dev_bytes = job->bytes.load();
+            long long cur = bytes_in_use.load();
+            if (cur > bytes_peak.load()) bytes_peak = cur;
+            ready.push_back(std::move(job));
+            cv_step.notify_one();
+        } catch (const std::exception &e) {
+            g_dev_bytes = nullptr;
+            const Error *ae = dynamic_cast<const Error *>(&e);
+            job.reset();
+            std::lock_guard<std::mutex> lk(mu);
+            bytes_reserved -= est;
+            --n_active;
+            ++failed;
+            q->status = ae ? ae->code : AFMPB_E_DEVICE;
+            q->message = e.what();
+            q->t_done = Clock::now();
+            cv_done.notify_all();
+            cv_setup.notify_one();
+        }
+    }
+}
+
+void afmpb_server::step_loop() {
+    (void)hipSetDevice(device);
+    std::vector<std::unique_ptr<SolveJob>> active;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (active.empty())
+                cv_step.wait(lk, [&] { return stop || !ready.empty(); });
+            if (stop) break;
+            for (auto &j : ready) active.push_back(std::move(j));
+            ready.clear();
+        }
+        bool progressed = false;
+        for (size_t i = 0; i < active.size();) {
+            SolveJob &jb = *active[i];
+            Request &q = *jb.req;
+            bool finished = false;
+            try {
+                if (q.cancelled) throw Error(AFMPB_E_CANCELLED, "cancelled");
+                if (jb.pending) {
+                    hipError_t e = hipEventQuery(jb.ev);
+                    if (e == hipSuccess) {
+                        jb.advance();
+                        progressed = true;
+                    } else if (e != hipErrorNotReady) {
+                        HIPCHK(e);
+                    }
+                }
+                if (jb.ph == SolveJob::DONE) {
+                    jb.collect(q);
+                    q.status = (jb.converged ? AFMPB_OK : AFMPB_E_NOT_CONVERGED);
+                    if (!jb.converged) q.message = "GMRES did not reach the tolerance";
+                    finished = true;
+                }
+            } catch (const std::exception &e) {
+                const Error *ae = dynamic_cast<const Error *>(&e);
+                q.status = ae ? ae->code : AFMPB_E_DEVICE;
+                q.message = e.what();
+                finished = true;
+            }
+            if (finished) {
+                const long long b = q.dev_bytes;
+                q.t_done = Clock::now();
+                q.info.ms_total = ms_between(q.t_submit, q.t_done);
+                active[i].reset();                      // frees the context
+                active.erase(active.begin() + (long)i);
+                std::lock_guard<std::mutex> lk(mu);
+                bytes_in_use -= b;
+                --n_active;
+                if (q.status == AFMPB_OK) ++completed; else ++failed;
+                cv_done.notify_all();
+                cv_setup.notify_one();
+                progressed = true;
+                continue;
+            }
+            ++i;
+        }
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    active.clear();
+}
+
+extern "C" {
+
+afmpb_status afmpb_server_create(const afmpb_params *params, long long hbm_budget_bytes,
+                                 int max_active, int device, afmpb_server **out) {
+    if (!out || !params) return AFMPB_E_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return AFMPB_E_INVALID;
+    if (hbm_budget_bytes <= 0 || max_active < 1 || max_active > 4096) return AFMPB_E_INVALID;
+    afmpb_params p = *params;
+    try {
+        // order_p / leaf_cap 0 mean "tuned per request"; check the rest now
+        afmpb_params chk = p;
+        if (chk.order_p == 0) chk.order_p = 8;
+        if (chk.leaf_cap == 0) chk.leaf_cap = 64;
+        (void)normalise(chk);
+    } catch (const Error &) {
+        return AFMPB_E_INVALID;
+    }
+    auto *s = new (std::nothrow) afmpb_server();
+    if (!s) return AFMPB_E_OOM;
+    s->prm = p;
+    s->budget = hbm_budget_bytes;
+    s->max_active = max_active;
+    s->device = device;
+    s->setup_thr = std::thread([s] { s->setup_loop(); });
+    s->step_thr = std::thread([s] { s->step_loop(); });
+    *out = s;
+    return AFMPB_OK;
+}
+
+afmpb_status afmpb_server_set_tuning(afmpb_server *s, int n, const afmpb_tuning_entry *table) {
+    if (!s || n < 0 || (n > 0 && !table)) return AFMPB_E_INVALID;
+    for (int i = 0; i < n; ++i) {
+        if (table[i].leaf_cap < 1 || table[i].order_p < 2 || table[i].order_p > MAXP ||
+            (i > 0 && table[i].max_nodes <= table[i - 1].max_nodes))
+            return AFMPB_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->tuning.assign(table, table + n);
+    return AFMPB_OK;
+}
+
+afmpb_status afmpb_server_submit(afmpb_server *s, const afmpb_molecule *mol,
+                                 unsigned long long *ticket) {
+    if (!s || !mol || !ticket) return AFMPB_E_INVALID;
+    if (!mol->xyz || !mol->tri || mol->n_nodes < 4 || mol->n_tri < 4 || mol->n_atoms < 0 ||
+        (mol->n_atoms > 0 && (!mol->atom_xyz || !mol->charge)))
+        return AFMPB_E_INVALID;
+    auto q = std::make_unique<Request>();
+    try {
+        q->n = mol->n_nodes;
+        q->m = mol->n_tri;
+        q->na = mol->n_atoms;
+        q->xyz.assign(mol->xyz, mol->xyz + 3 * mol->n_nodes);
+        q->tri.assign(mol->tri, mol->tri + 3 * mol->n_tri);
+        if (q->na > 0) {
+            q->axyz.assign(mol->atom_xyz, mol->atom_xyz + 3 * q->na);
+            q->q.assign(mol->charge, mol->charge + q->na);
+        }
+    } catch (const std::bad_alloc &) {
+        return AFMPB_E_OOM;
+    }
+    q->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return AFMPB_E_STATE;
+    q->ticket = s->next_ticket++;
+    *ticket = q->ticket;
+    s->queue.push_back(q.get());
+    s->reqs[q->ticket] = std::move(q);
+    s->cv_setup.notify_one();
+    return AFMPB_OK;
+}
+
+static void fill_result(const Request &q, afmpb_result *out) {
+    std::memset(out, 0, sizeof(*out));
+    out->status = q.status;
+    out->n_nodes = q.n;
+    out->energy = q.energy;
+    out->info = q.info;
+    out->device_bytes = q.dev_bytes;
+    const auto z = q.t_submit;
+    auto rel = [&](Clock::time_point t) {
+        return t.time_since_epoch().count() == 0 ? 0.0 : ms_between(z, t);
+    };
+    out->ms_admit = rel(q.t_admit);
+    out->ms_ready = rel(q.t_ready);
+    out->ms_done = rel(q.t_done);
+    std::strncpy(out->message, q.message.c_str(), sizeof(out->message) - 1);
+}
+
+afmpb_status afmpb_server_poll(afmpb_server *s, unsigned long long ticket, int wait,
+                               afmpb_result *out, double *f, double *h) {
+    if (!s || !out) return AFMPB_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return AFMPB_E_INVALID;
+    Request &q = *it->second;
+    if (wait) s->cv_done.wait(lk, [&] { return q.status != AFMPB_E_PENDING; });
+    fill_result(q, out);
+    if (q.status == AFMPB_E_PENDING) return AFMPB_E_PENDING;
+    if (f && !q.f.empty()) std::memcpy(f, q.f.data(), q.n * sizeof(double));
+    if (h && !q.h.empty()) std::memcpy(h, q.h.data(), q.n * sizeof(double));
+    s->reqs.erase(it);                       // results are handed over once
+    return AFMPB_OK;
+}
+
+afmpb_status afmpb_server_cancel(afmpb_server *s, unsigned long long ticket) {
+    if (!s) return AFMPB_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return AFMPB_E_INVALID;
+    Request &q = *it->second;
+    if (q.status != AFMPB_E_PENDING) return AFMPB_OK;       // already finished
+    q.cancelled = true;
+    for (auto qi = s->queue.begin(); qi != s->queue.end(); ++qi) {
+        if (*qi == &q) {
+            s->queue.erase(qi);
+            q.status = AFMPB_E_CANCELLED;
+            q.message = "cancelled";
+            q.t_done = Clock::now();
+            s->cv_done.notify_all();
+            break;
+        }
+    }
+    return AFMPB_OK;
+}
+
+afmpb_status afmpb_server_stats(afmpb_server *s, afmpb_server_counts *out) {
+    if (!s || !out) return AFMPB_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    out->queued = (long long)s->queue.size();
+    out->active = s->n_active;
+    out->completed = s->completed;
+    out->failed = s->failed;
+    out->device_bytes = s->bytes_in_use.load();
+    out->device_bytes_peak = s->bytes_peak.load();
+    return AFMPB_OK;
+}
+
+afmpb_status afmpb_server_destroy(afmpb_server *s) {
+    if (!s) return AFMPB_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (Request *q : s->queue) {
+            q->status = AFMPB_E_CANCELLED;
+            q->message = "server destroyed";
+        }
+        s->queue.clear();
+    }
+    s->cv_setup.notify_all();
+    s->cv_step.notify_all();
+    if (s->setup_thr.joinable()) s->setup_thr.join();
+    if (s->step_thr.joinable()) s->step_thr.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->ready.clear();
+    }
+    delete s;
+    return AFMPB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+"""GPU tests of the solve server (continuous batching) through the C ABI.
+
+Every served solve runs the same algorithm, kernels and order as afmpb_solve
+on its own, so each result must be the same whether the request ran alone,
+in a mix with others, or through afmpb_solve directly (compared here to
+1e-12 relative; the stated tolerance is 1e-4 on the energy).  Small requests
+are also checked against the FP64 CPU oracle (1e-4 relative energy)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _server(**kw):
+    import paper_1710_06316_amd as A
+    _say(f"server {kw}")
+    return A.Server(**kw)
+
+
+def _solo(mol, **params):
+    import paper_1710_06316_amd as A
+    s = A.Solver(0)
+    s.load(mol, **params)
+    f, h, E, info, _ = s.solve()
+    s.close()
+    return f, h, E, info
+
+
+def _mix(levels):
+    return [W.star_request(100 + i, level=L) for i, L in enumerate(levels)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_server_matches_direct_solve(precision):
+    mols = _mix([3, 4, 3])
+    srv = _server(max_active=8, precision=precision, order_p=8, leaf_cap=64)
+    tickets = [srv.submit(m) for m in mols]
+    for m, t in zip(mols, tickets):
+        st, res, f, h = srv.poll(t, wait=True)
+        assert res.status == 0, res.message
+        f0, h0, E0, info0 = _solo(m, precision=precision, order_p=8, leaf_cap=64)
+        _say(f"{m.name} n={m.n_nodes} E_server={res.energy:.10f} E_direct={E0:.10f} "
+             f"iters {res.info.iterations}/{info0.iterations}")
+        assert res.info.iterations == info0.iterations
+        assert abs(res.energy - E0) <= 1e-12 * abs(E0)
+        assert np.allclose(f, f0, rtol=1e-12, atol=0) and np.allclose(h, h0, rtol=1e-12, atol=0)
+    srv.close()
+
+
+def test_alone_equals_in_mix_and_oracle():
+    mols = _mix([3, 5, 4, 3, 6, 4, 3, 5])
+    # alone: one request in flight at a time
+    srv = _server(max_active=1, order_p=8, leaf_cap=64)
+    alone = {}
+    for m in mols:
+        t = srv.submit(m)
+        _, res, f, h = srv.poll(t, wait=True)
+        assert res.status == 0, res.message
+        alone[m.name] = (res.energy, f, h)
+    srv.close()
+    # the same requests submitted together, several in flight
+    srv = _server(max_active=6, order_p=8, leaf_cap=64)
+    t0 = time.perf_counter()
+    tickets = [srv.submit(m) for m in mols]
+    peak_active = 0
+    while srv.stats()["completed"] + srv.stats()["failed"] < len(mols):
+        peak_active = max(peak_active, srv.stats()["active"])
+        time.sleep(0.002)
+    dt = time.perf_counter() - t0
+    for m, t in zip(mols, tickets):
+        _, res, f, h = srv.poll(t, wait=True)
+        assert res.status == 0, res.message
+        Ea, fa, ha = alone[m.name]
+        assert abs(res.energy - Ea) <= 1e-12 * abs(Ea)
+        assert np.array_equal(f, fa) and np.array_equal(h, ha)
+    _say(f"mix of {len(mols)} in {dt:.3f} s, peak active {peak_active}, stats {srv.stats()}")
+    assert peak_active >= 2
+    srv.close()
+    # the small ones against the oracle
+    for m in mols:
+        if m.n_nodes <= 642:
+            ref = O.solve(m)
+            Ea = alone[m.name][0]
+            _say(f"{m.name} oracle {ref.energy:.6f} server {Ea:.6f}")
+            assert abs(Ea - ref.energy) <= 1e-4 * abs(ref.energy)
+
+
+def test_budget_admission_and_errors():
+    import paper_1710_06316_amd as A
+    mols = _mix([3, 3, 4])
+    # a budget below one request: they run one after another, all complete
+    srv = _server(hbm_budget_bytes=1, max_active=8, order_p=8)
+    tickets = [srv.submit(m) for m in mols]
+    seen = 0
+    while srv.stats()["completed"] + srv.stats()["failed"] < len(mols):
+        seen = max(seen, srv.stats()["active"])
+        time.sleep(0.001)
+    assert seen <= 1
+    for t in tickets:
+        _, res, _, _ = srv.poll(t, wait=True)
+        assert res.status == 0, res.message
+        assert res.device_bytes > 0
+    # a bad mesh fails alone, with its own status
+    bad = _mix([3])[0]
+    tb = A.afmpb_server_submit(srv.srv, bad.xyz, bad.tri[:, [0, 2, 1]], bad.atom_xyz, bad.charge)
+    srv.n_of[tb] = bad.n_nodes
+    good = srv.submit(_mix([4])[0])
+    _, rb, _, _ = srv.poll(tb, wait=True)
+    _, rg, _, _ = srv.poll(good, wait=True)
+    assert rb.status == A.AFMPB_E_MESH and rg.status == 0
+    assert srv.stats()["device_bytes"] == 0
+    srv.close()
+
+
+def test_cancel_queued():
+    import paper_1710_06316_amd as A
+    mols = _mix([5, 5, 3])
+    srv = _server(max_active=1, order_p=8)
+    ts = [srv.submit(m) for m in mols]
+    srv.cancel(ts[2])
+    _, r2, _, _ = srv.poll(ts[2], wait=True)
+    assert r2.status == A.AFMPB_E_CANCELLED
+    for t in ts[:2]:
+        _, r, _, _ = srv.poll(t, wait=True)
+        assert r.status == 0, r.message
+    srv.close()
