@@ -47,6 +47,13 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the plain FP64 comparison run")
     ap.add_argument("--no-solve", action="store_true", help="skip the full solve")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving stream (0 skips it)")
+    ap.add_argument("--serve-check", type=int, default=12,
+                    help="requests checked against the order-14 FP64 solve")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-max-active", type=int, default=32)
+    ap.add_argument("--serve-setup-threads", type=int, default=8)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")
@@ -152,6 +159,78 @@ def roofline(r, order, precision):
     return roof, roofs, dom
 
 
+def serve_run(A, mols, qps, precision, order, leaf, budget_gb, max_active, setup_threads,
+              tuning=None):
+    """One pass of the request stream through the solve server.  qps None:
+    all requests submitted at t = 0 (saturated); otherwise Poisson arrivals
+    (seeded exponential gaps).  Returns throughput, latency percentiles and
+    the per-request energies."""
+    srv = A.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_active=max_active,
+                   setup_threads=setup_threads, tuning=tuning, precision=precision, order_p=order, leaf_cap=leaf)
+    rng = np.random.default_rng(4)
+    n = len(mols)
+    arrive = np.zeros(n) if qps is None else np.cumsum(rng.exponential(1.0 / qps, n))
+    t0 = time.perf_counter()
+    tickets = []
+    for i, m in enumerate(mols):
+        wait = arrive[i] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(m))
+    res = []
+    for t in tickets:
+        _, r, _, _ = srv.poll(t, wait=True)
+        res.append(r)
+    t_end = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([r.ms_done for r in res])
+    ok = [r.status == 0 for r in res]
+    first = float(arrive[0])
+    return {"qps_offered": qps, "requests": n, "completed": int(sum(ok)),
+            "seconds": t_end - first, "solves_per_s": n / (t_end - first),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_setup_ms": float(np.mean([r.ms_ready - r.ms_admit for r in res])),
+            "energies": [r.energy for r in res], "ok": ok}
+
+
+def serving(A, torch, n_req, check, budget_gb, max_active, setup_threads):
+    """The serving stream: star-shaped molecules (icosphere levels 3-6),
+    saturated throughput X_sat, then Poisson arrivals at 0.5 and 0.9 X_sat,
+    in the mixed-precision form and the plain FP64 form at the same order.
+    Solves count only when their energy is within 1e-4 of the FP64 order-14
+    GPU solve of the same request (checked on a seeded sample)."""
+    import workloads as W
+    mols = [W.star_request(i) for i in range(n_req)]
+    rng = np.random.default_rng(44)
+    sample = sorted(rng.choice(n_req, size=min(check, n_req), replace=False).tolist())
+    ref = {}
+    for i in sample:
+        s = A.Solver(0)
+        s.load(mols[i], order_p=14, precision=A.AFMPB_FP64)
+        ref[i] = s.solve()[2]
+        s.close()
+    out = {"requests": n_req,
+           "node_mix": {str(L): sum(1 for m in mols if m.meta["level"] == L) for L in (3, 4, 5, 6)},
+           "reference": f"FP64 p=14 GPU solve on {len(sample)} sampled requests",
+           "budget_gb": budget_gb, "max_active": max_active, "setup_threads": setup_threads}
+    for name, prec in (("fp32_refined", A.AFMPB_FP32_REFINED), ("fp64", A.AFMPB_FP64)):
+        runs = {}
+        sat = serve_run(A, mols, None, prec, 8, 64, budget_gb, max_active, setup_threads)
+        runs["saturated"] = sat
+        for f in (0.5, 0.9):
+            runs[f"qps_{f}"] = serve_run(A, mols, f * sat["solves_per_s"], prec, 8, 64,
+                                         budget_gb, max_active, setup_threads)
+        errs = [abs(sat["energies"][i] - ref[i]) / abs(ref[i]) for i in sample]
+        for r in runs.values():
+            e = r.pop("energies")
+            r["within_1e-4_sampled"] = int(sum(abs(e[i] - ref[i]) <= 1e-4 * abs(ref[i])
+                                               for i in sample))
+            r.pop("ok")
+        out[name] = {"order_p": 8, "leaf_cap": 64, "max_rel_energy_err_sampled": max(errs),
+                     **runs}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -201,6 +280,9 @@ def main():
                               "roofline_all": roofline(r64, a.order, "fp64")[1],
                               "solve": r64["solve"]}
         y_gpu[f"fp64_p{a.order}"] = r64["y_host"]
+    if a.serve_requests > 0:
+        line["serving"] = serving(A, torch, a.serve_requests, a.serve_check, a.serve_budget_gb,
+                                  a.serve_max_active, a.serve_setup_threads)
     if not a.no_cpu_baseline:
         line["cpu_baseline"], line["accuracy"] = cpu_baseline(mol, a.cpu_seconds, x_host, y_gpu)
     if a.calib_copy_mb > 0:

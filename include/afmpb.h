@@ -191,6 +191,14 @@ afmpb_status afmpb_rhs(afmpb_ctx *ctx, double *b);
  * (caller order, unitless). */
 afmpb_status afmpb_energy(afmpb_ctx *ctx, const double *x, double *energy);
 
+/* Wall time (ms) of the phases of the last afmpb_set_molecule, in order:
+ * 0 validation, upload and patch geometry; 1 Morton keys, sort and node
+ * gather; 2 octree; 3 U/V/W/X lists and the P2P / M2L work items; 4 near
+ * set and patch-integral corrections; 5 translation operators; 6 work
+ * buffers and structural checks.  ms: [AFMPB_SETUP_PHASES] host array. */
+#define AFMPB_SETUP_PHASES 7
+afmpb_status afmpb_setup_times(afmpb_ctx *ctx, double *ms);
+
 /* Sizes of the internal tree and lists of the loaded molecule. */
 afmpb_status afmpb_tree_info(afmpb_ctx *ctx, afmpb_tree_sizes *out);
 
@@ -215,7 +223,8 @@ afmpb_status afmpb_profile_read(afmpb_ctx *ctx, int idx, const char **name,
  * admitted molecule gets its own context and stream; its matvec is captured
  * once into HIP graphs, and one host thread advances all admitted solves by
  * one asynchronous GMRES chunk (one Arnoldi step) at a time, so their work
- * overlaps on the device and late arrivals join while others run.  Every
+ * overlaps on the device and late arrivals join while others run; several
+ * setup threads build admitted requests in parallel.  Every
  * solve follows the same algorithm, kernels and order as afmpb_solve on the
  * same molecule and parameters, so its result does not depend on what else
  * is in flight.  All server functions are thread-safe.
@@ -260,12 +269,14 @@ typedef struct {
     long long device_bytes, device_bytes_peak;
 } afmpb_server_counts;
 
-/* Starts a server on `device` (its setup and stepping threads).  params as
- * for afmpb_set_molecule, except that order_p == 0 / leaf_cap == 0 select
- * per request from the tuning table.  Errors: AFMPB_E_INVALID. */
+/* Starts a server on `device` with setup_threads (1..64) threads that build
+ * admitted requests concurrently and one stepping thread.  params as for
+ * afmpb_set_molecule, except that order_p == 0 / leaf_cap == 0 select per
+ * request from the tuning table.  Errors: AFMPB_E_INVALID. */
 afmpb_status afmpb_server_create(const afmpb_params *params,
                                  long long hbm_budget_bytes, int max_active,
-                                 int device, afmpb_server **out);
+                                 int setup_threads, int device,
+                                 afmpb_server **out);
 
 /* Replaces the tuning table (n entries, copied). */
 afmpb_status afmpb_server_set_tuning(afmpb_server *s, int n,

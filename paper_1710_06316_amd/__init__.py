@@ -41,7 +41,7 @@ ABI_FUNCTIONS = (
     "afmpb_default_params", "afmpb_create", "afmpb_destroy", "afmpb_last_error",
     "afmpb_set_molecule", "afmpb_matvec", "afmpb_matvec_dev", "afmpb_solve",
     "afmpb_rhs", "afmpb_energy", "afmpb_tree_info", "afmpb_debug_tree",
-    "afmpb_profile_enable", "afmpb_profile_read",
+    "afmpb_profile_enable", "afmpb_profile_read", "afmpb_setup_times",
     "afmpb_server_create", "afmpb_server_set_tuning", "afmpb_server_submit",
     "afmpb_server_poll", "afmpb_server_cancel", "afmpb_server_stats", "afmpb_server_destroy",
 )
@@ -149,8 +149,9 @@ def lib():
         L.afmpb_profile_enable.argtypes = [vp, ctypes.c_int]
         L.afmpb_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                          dp, ctypes.POINTER(ll)]
+        L.afmpb_setup_times.argtypes = [vp, dp]
         L.afmpb_server_create.argtypes = [ctypes.POINTER(afmpb_params), ll, ctypes.c_int,
-                                          ctypes.c_int, ctypes.POINTER(vp)]
+                                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
         L.afmpb_server_set_tuning.argtypes = [vp, ctypes.c_int,
                                               ctypes.POINTER(afmpb_tuning_entry)]
         L.afmpb_server_submit.argtypes = [vp, ctypes.POINTER(afmpb_molecule),
@@ -294,6 +295,15 @@ def afmpb_debug_tree(ctx) -> dict:
     return arr
 
 
+SETUP_PHASES = ("geometry", "keys_sort", "tree", "lists", "near", "operators", "buffers_checks")
+
+
+def afmpb_setup_times(ctx) -> dict:
+    ms = np.zeros(len(SETUP_PHASES))
+    _check(ctx, lib().afmpb_setup_times(ctx, _dp(ms)))
+    return dict(zip(SETUP_PHASES, ms.tolist()))
+
+
 def afmpb_profile_enable(ctx, enable: bool):
     return _check(ctx, lib().afmpb_profile_enable(ctx, 1 if enable else 0))
 
@@ -368,6 +378,9 @@ class Solver:
     def debug_tree(self):
         return afmpb_debug_tree(self.ctx)
 
+    def setup_times(self):
+        return afmpb_setup_times(self.ctx)
+
     def profile(self, enable: bool):
         afmpb_profile_enable(self.ctx, enable)
 
@@ -378,10 +391,10 @@ class Solver:
 # --- solve server ---------------------------------------------------------------
 
 def afmpb_server_create(params: afmpb_params, hbm_budget_bytes: int, max_active: int,
-                        device: int = 0):
+                        setup_threads: int = 4, device: int = 0):
     h = ctypes.c_void_p()
     st = lib().afmpb_server_create(ctypes.byref(params), int(hbm_budget_bytes), int(max_active),
-                                   int(device), ctypes.byref(h))
+                                   int(setup_threads), int(device), ctypes.byref(h))
     if st != AFMPB_OK:
         raise AfmpbError(st, "afmpb_server_create failed")
     return h
@@ -443,12 +456,12 @@ def afmpb_server_destroy(srv):
 class Server:
     """Continuous-batching solve server (one device)."""
 
-    def __init__(self, hbm_budget_bytes: int = 32 << 30, max_active: int = 64, device: int = 0,
-                 tuning=None, **params):
+    def __init__(self, hbm_budget_bytes: int = 32 << 30, max_active: int = 64,
+                 setup_threads: int = 4, device: int = 0, tuning=None, **params):
         p = afmpb_default_params()
         for k, v in params.items():
             setattr(p, k, v)
-        self.srv = afmpb_server_create(p, hbm_budget_bytes, max_active, device)
+        self.srv = afmpb_server_create(p, hbm_budget_bytes, max_active, setup_threads, device)
         self.n_of = {}
         if tuning:
             afmpb_server_set_tuning(self.srv, tuning)

@@ -269,6 +269,16 @@ void check_setup(afmpb_ctx *c);
 void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, const int *tri,
                    long long na, const double *axyz, const double *q, const afmpb_params &prm) {
     auto t0 = std::chrono::steady_clock::now();
+    auto tp = t0;
+    int ph = 0;
+    // phase end: wait for the device, record the wall time since the last mark
+    auto mark = [&] {
+        c->sync();
+        auto now = std::chrono::steady_clock::now();
+        c->ms_phase[ph++] = std::chrono::duration<double, std::milli>(now - tp).count();
+        tp = now;
+    };
+    std::fill(c->ms_phase, c->ms_phase + AFMPB_SETUP_PHASES, 0.0);
     c->loaded = false;
     validate_mesh(n, xyz, m, tri);
     require(n < (1ll << 30) && m < (1ll << 30), ST_INVALID, "mesh too large");
@@ -291,6 +301,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
     c->area_c.alloc(n); c->nrm_c.alloc(3 * n); c->rho2_c.alloc(n);
     compute_geometry(c->V.p, c->T.p, n, m, c->tri_area.p, c->tri_n.p, c->inc_ptr.p, c->inc_tri.p,
                      c->area_c.p, c->nrm_c.p, c->rho2_c.p, s);
+    mark();   // validation, upload, geometry
     // a1 Morton keys and sort
     c->keys.alloc(n); c->perm.alloc(n);
     morton_sort(c->V.p, n, c->keys.p, c->perm.p, c->lo, &c->scale, s);
@@ -299,20 +310,25 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
     c->node32.alloc(6 * n);
     k_to_f32<<<grid_for(6 * n, 256), 256, 0, s>>>(c->node64.p, c->node32.p, 6 * n);
     KCHK();
+    mark();   // keys, sort, node gather
     // a2 tree, a3 lists
     c->tree = Tree();
     build_tree(c->keys.p, n, prm.leaf_cap, c->lo, c->scale, c->tree, s);
     c->lists = Lists();
+    mark();   // tree
     build_lists(c->tree, c->lists, s);
+    mark();   // lists and P2P / M2L work items
     // a4 near set and corrections
     c->near = NearSet();
     build_near(c->nodes(), n, prm.near_eta, c->V.p, c->T.p, c->tri_n.p, c->inc_ptr.p,
                c->inc_tri.p, c->perm.p, prm.kappa, c->ebar, c->near, s);
+    mark();   // near set and patch corrections
     // translation operators
     c->fmm = Fmm();
     c->p2p64 = DBuf<double>();
     c->p2p_part = DBuf<double>();
     build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa, c->fmm, s);
+    mark();   // translation operators
     setup_plan<double>(c, c->mp64, c->w64, c->far64, c->node64.p);
     setup_plan<float>(c, c->mp32, c->w32, c->far32, c->node32.p);
     c->xa.alloc(2 * n); c->ya.alloc(2 * n); c->bvec.alloc(2 * n);
@@ -323,6 +339,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
     c->krylov_m = 0;
     c->sync();
     check_setup(c);
+    mark();   // work buffers and structural checks
     c->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     c->loaded = true;
 }
@@ -793,6 +810,15 @@ afmpb_status afmpb_solve(afmpb_ctx *ctx, const double *x0, double *f, double *h,
         return AFMPB_E_NOT_CONVERGED;
     }
     return st;
+}
+
+afmpb_status afmpb_setup_times(afmpb_ctx *ctx, double *ms) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        require(ms != nullptr, ST_INVALID, "null argument");
+        for (int i = 0; i < AFMPB_SETUP_PHASES; ++i) ms[i] = ctx->ms_phase[i];
+    });
 }
 
 afmpb_status afmpb_tree_info(afmpb_ctx *ctx, afmpb_tree_sizes *out) {

@@ -25,6 +25,7 @@ struct afmpb_ctx {
     long long n = 0, m = 0, na = 0;
     double ebar = 1, alpha = 1, inv_ebar = 1;
     double ms_setup = 0;
+    double ms_phase[AFMPB_SETUP_PHASES] = {};   // setup wall time per phase
     DBuf<double> V, ax, aq, tri_area, tri_n, area_c, nrm_c, rho2_c;
     DBuf<int> T, inc_ptr, inc_tri, perm;
     DBuf<unsigned long long> keys;

@@ -136,44 +136,6 @@ struct Acc {
     double a, b, c, d;
 };
 
-// Collapsed Gauss rule on (P0,P1,P2), collapse at P0:
-// y = P0 + u (P1 - P0) + u v (P2 - P1), dS = 2 |tau| u du dv.
-__device__ void tri_rule(const Ctx &C, double x, double y0, double z, double n0x, double n0y,
-                         double n0z, const double *P0, const double *P1, const double *P2,
-                         double fnx, double fny, double fnz, int nq, const double *gx,
-                         const double *gw, bool self, Acc &acc) {
-    double e1[3] = {P1[0] - P0[0], P1[1] - P0[1], P1[2] - P0[2]};
-    double e2[3] = {P2[0] - P0[0], P2[1] - P0[1], P2[2] - P0[2]};
-    double cx = e1[1] * e2[2] - e1[2] * e2[1];
-    double cy = e1[2] * e2[0] - e1[0] * e2[2];
-    double cz = e1[0] * e2[1] - e1[1] * e2[0];
-    double area = 0.5 * sqrt((cx * cx + cy * cy) + cz * cz);
-    for (int i = 0; i < nq; ++i) {
-        double u = gx[i];
-        for (int j = 0; j < nq; ++j) {
-            double v = gx[j];
-            double w = 2.0 * area * u * gw[i] * gw[j];
-            double pyy[3];
-            for (int d = 0; d < 3; ++d)
-                pyy[d] = P0[d] + u * (P1[d] - P0[d]) + u * v * (P2[d] - P1[d]);
-            double rx = x - pyy[0], ry = y0 - pyy[1], rz = z - pyy[2];
-            if (self) {
-                Abcd<double> k = abcd_point(rx, ry, rz, fnx, fny, fnz, fnx, fny, fnz, C.kappa,
-                                            C.inv_ebar);
-                acc.a += w * k.A;
-                acc.d += w * k.D;
-            } else {
-                Abcd<double> k = abcd_point(rx, ry, rz, n0x, n0y, n0z, fnx, fny, fnz, C.kappa,
-                                            C.inv_ebar);
-                acc.a += w * k.A;
-                acc.b += w * k.B;
-                acc.c += w * k.C;
-                acc.d += w * k.D;
-            }
-        }
-    }
-}
-
 __device__ inline void child_of(const double *P0, const double *P1, const double *P2, int c,
                                 double *Q0, double *Q1, double *Q2) {
     double m01[3], m12[3], m20[3];
@@ -194,11 +156,58 @@ __device__ inline void child_of(const double *P0, const double *P1, const double
 
 constexpr int MAX_DEPTH = 10;
 
-// Depth-first traversal of the subdivision tree of one piece, with the path
-// kept as base-4 digits and the current sub-triangle rebuilt from the root.
-__device__ void adapt(const Ctx &C, double x, double y, double z, double n0x, double n0y,
-                      double n0z, const double *R0, const double *R1, const double *R2,
-                      double fnx, double fny, double fnz, Acc &acc) {
+// One wavefront per near entry (t in N(p)): the wave walks t's pieces and
+// their subdivision tree together (the walk is uniform across lanes), and
+// lane l evaluates point (l / 8, l % 8) of the 8 x 8 collapsed rule of every
+// leaf piece (self patch: points l, l+64, l+128, l+192 of the 16 x 16 rule).
+// Lane sums are added by a fixed butterfly at the end.
+struct LanePts {
+    double u8, v8, g8;          // node and weight product of this lane's 8 x 8 point
+    double u16[4], v16[4], g16[4];
+};
+
+__device__ inline void piece_lane(const Ctx &C, double x, double y0, double z, double n0x,
+                                  double n0y, double n0z, const double *P0, const double *P1,
+                                  const double *P2, double fnx, double fny, double fnz,
+                                  int npts, const double *uu, const double *vv, const double *gg,
+                                  bool self, Acc &acc) {
+    double e1[3] = {P1[0] - P0[0], P1[1] - P0[1], P1[2] - P0[2]};
+    double e2[3] = {P2[0] - P0[0], P2[1] - P0[1], P2[2] - P0[2]};
+    double cx = e1[1] * e2[2] - e1[2] * e2[1];
+    double cy = e1[2] * e2[0] - e1[0] * e2[2];
+    double cz = e1[0] * e2[1] - e1[1] * e2[0];
+    double area = 0.5 * sqrt((cx * cx + cy * cy) + cz * cz);
+    for (int s = 0; s < npts; ++s) {
+        const double u = uu[s], v = vv[s];
+        const double w = 2.0 * area * u * gg[s];
+        double pyy[3];
+        for (int d = 0; d < 3; ++d)
+            pyy[d] = P0[d] + u * (P1[d] - P0[d]) + u * v * (P2[d] - P1[d]);
+        const double rx = x - pyy[0], ry = y0 - pyy[1], rz = z - pyy[2];
+        if (self) {
+            Abcd<double> k = abcd_point(rx, ry, rz, fnx, fny, fnz, fnx, fny, fnz, C.kappa,
+                                        C.inv_ebar);
+            acc.a += w * k.A;
+            acc.d += w * k.D;
+        } else {
+            Abcd<double> k = abcd_point(rx, ry, rz, n0x, n0y, n0z, fnx, fny, fnz, C.kappa,
+                                        C.inv_ebar);
+            acc.a += w * k.A;
+            acc.b += w * k.B;
+            acc.c += w * k.C;
+            acc.d += w * k.D;
+        }
+    }
+}
+
+// Adaptive subdivision of one piece, depth first, with the path kept as
+// base-4 digits and the current sub-triangle rebuilt from the root; a piece
+// is split while the target is closer than two diameters to its centroid
+// (at most MAX_DEPTH levels), and every leaf gets the 8 x 8 collapsed rule
+// y = P0 + u (P1 - P0) + u v (P2 - P1), dS = 2 |tau| u du dv (collapse at P0).
+__device__ void adapt_lane(const Ctx &C, double x, double y, double z, double n0x, double n0y,
+                           double n0z, const double *R0, const double *R1, const double *R2,
+                           double fnx, double fny, double fnz, const LanePts &L, Acc &acc) {
     int digit[MAX_DEPTH + 1];
     int depth = 0;
     while (true) {
@@ -221,18 +230,40 @@ __device__ void adapt(const Ctx &C, double x, double y, double z, double n0x, do
             digit[depth++] = 0;
             continue;
         }
-        tri_rule(C, x, y, z, n0x, n0y, n0z, P0, P1, P2, fnx, fny, fnz, 8, C.q.x8, C.q.w8,
-                 false, acc);
+        piece_lane(C, x, y, z, n0x, n0y, n0z, P0, P1, P2, fnx, fny, fnz, 1, &L.u8, &L.v8, &L.g8,
+                   false, acc);
         while (depth > 0 && digit[depth - 1] == 3) --depth;
         if (depth == 0) break;
         ++digit[depth - 1];
     }
 }
 
-__global__ void k_near_coeffs(Ctx C, long long n, long long nnz, const long long *__restrict__ ptr,
-                              const int *__restrict__ col, double *__restrict__ delta) {
-    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nnz) return;
+__device__ inline double wave_add(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_near_coeffs(Ctx C, long long n, long long nnz,
+                                                     const long long *__restrict__ ptr,
+                                                     const int *__restrict__ col,
+                                                     double *__restrict__ delta) {
+    const int lane = threadIdx.x & 63;
+    const long long e = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= nnz) return;                              // uniform for the wave
+    LanePts L;
+    {
+        const int i = lane >> 3, j = lane & 7;
+        L.u8 = C.q.x8[i];
+        L.v8 = C.q.x8[j];
+        L.g8 = C.q.w8[i] * C.q.w8[j];
+        for (int s = 0; s < 4; ++s) {
+            const int idx = lane + 64 * s, i2 = idx >> 4, j2 = idx & 15;
+            L.u16[s] = C.q.x16[i2];
+            L.v16[s] = C.q.x16[j2];
+            L.g16[s] = C.q.w16[i2] * C.q.w16[j2];
+        }
+    }
     long long lo = 0, hi = n;              // row p: ptr[p] <= e < ptr[p+1]
     while (hi - lo > 1) {
         long long mid = (lo + hi) >> 1;
@@ -241,44 +272,48 @@ __global__ void k_near_coeffs(Ctx C, long long n, long long nnz, const long long
     const long long p = lo;
     const double x = C.nd.x[p], y = C.nd.y[p], z = C.nd.z[p];
     const double n0x = C.nd.nx[p], n0y = C.nd.ny[p], n0z = C.nd.nz[p];
-    {
-        int t = col[e];
-        long long ot = C.perm[t];
-        const double *vt = C.V + 3 * ot;
-        Acc acc{0, 0, 0, 0};
-        for (int q = C.inc_ptr[ot]; q < C.inc_ptr[ot + 1]; ++q) {
-            long long k = C.inc_tri[q];
-            const int *tv = C.T + 3 * k;
-            int j = (tv[0] == ot) ? 0 : ((tv[1] == ot) ? 1 : 2);
-            const double *pu = C.V + 3ll * tv[(j + 1) % 3];
-            const double *pw = C.V + 3ll * tv[(j + 2) % 3];
-            const double *a = C.V + 3ll * tv[0], *b = C.V + 3ll * tv[1], *c = C.V + 3ll * tv[2];
-            double cen[3], mu[3], mw[3];
-            for (int d = 0; d < 3; ++d) {
-                cen[d] = ((a[d] + b[d]) + c[d]) / 3.0;
-                mu[d] = (vt[d] + pu[d]) * 0.5;
-                mw[d] = (vt[d] + pw[d]) * 0.5;
-            }
-            double fnx = C.tri_n[3 * k], fny = C.tri_n[3 * k + 1], fnz = C.tri_n[3 * k + 2];
-            if (t == p) {
-                tri_rule(C, x, y, z, n0x, n0y, n0z, vt, mu, cen, fnx, fny, fnz, 16, C.q.x16,
-                         C.q.w16, true, acc);
-                tri_rule(C, x, y, z, n0x, n0y, n0z, vt, cen, mw, fnx, fny, fnz, 16, C.q.x16,
-                         C.q.w16, true, acc);
-            } else {
-                adapt(C, x, y, z, n0x, n0y, n0z, vt, mu, cen, fnx, fny, fnz, acc);
-                adapt(C, x, y, z, n0x, n0y, n0z, vt, cen, mw, fnx, fny, fnz, acc);
-            }
+    const int t = col[e];
+    const long long ot = C.perm[t];
+    const double *vt = C.V + 3 * ot;
+    Acc acc{0, 0, 0, 0};
+    for (int q = C.inc_ptr[ot]; q < C.inc_ptr[ot + 1]; ++q) {
+        long long k = C.inc_tri[q];
+        const int *tv = C.T + 3 * k;
+        int jj = (tv[0] == ot) ? 0 : ((tv[1] == ot) ? 1 : 2);
+        const double *pu = C.V + 3ll * tv[(jj + 1) % 3];
+        const double *pw = C.V + 3ll * tv[(jj + 2) % 3];
+        const double *a = C.V + 3ll * tv[0], *b = C.V + 3ll * tv[1], *c = C.V + 3ll * tv[2];
+        double cen[3], mu[3], mw[3];
+        for (int d = 0; d < 3; ++d) {
+            cen[d] = ((a[d] + b[d]) + c[d]) / 3.0;
+            mu[d] = (vt[d] + pu[d]) * 0.5;
+            mw[d] = (vt[d] + pw[d]) * 0.5;
         }
+        double fnx = C.tri_n[3 * k], fny = C.tri_n[3 * k + 1], fnz = C.tri_n[3 * k + 2];
+        if (t == p) {
+            piece_lane(C, x, y, z, n0x, n0y, n0z, vt, mu, cen, fnx, fny, fnz, 4, L.u16, L.v16,
+                       L.g16, true, acc);
+            piece_lane(C, x, y, z, n0x, n0y, n0z, vt, cen, mw, fnx, fny, fnz, 4, L.u16, L.v16,
+                       L.g16, true, acc);
+        } else {
+            adapt_lane(C, x, y, z, n0x, n0y, n0z, vt, mu, cen, fnx, fny, fnz, L, acc);
+            adapt_lane(C, x, y, z, n0x, n0y, n0z, vt, cen, mw, fnx, fny, fnz, L, acc);
+        }
+    }
+    acc.a = wave_add(acc.a);
+    acc.b = wave_add(acc.b);
+    acc.c = wave_add(acc.c);
+    acc.d = wave_add(acc.d);
+    if (lane == 0) {
         if (t != p) {   // subtract the point rule applied by the far-field part
             double at = C.nd.area[t];
-            Abcd<double> k = abcd_point(x - C.nd.x[t], y - C.nd.y[t], z - C.nd.z[t], n0x, n0y,
-                                        n0z, C.nd.nx[t], C.nd.ny[t], C.nd.nz[t], C.kappa,
-                                        C.inv_ebar);
-            acc.a -= at * k.A;
-            acc.b -= at * k.B;
-            acc.c -= at * k.C;
-            acc.d -= at * k.D;
+            Abcd<double> kp = abcd_point(x - C.nd.x[t], y - C.nd.y[t], z - C.nd.z[t], n0x, n0y,
+                                         n0z, C.nd.nx[t], C.nd.ny[t], C.nd.nz[t], C.kappa,
+                                         C.inv_ebar);
+            acc.a -= at * kp.A;
+            acc.b -= at * kp.B;
+            acc.c -= at * kp.C;
+            acc.d -= at * kp.D;
         }
         delta[4 * e] = acc.a;
         delta[4 * e + 1] = acc.b;
@@ -389,8 +424,8 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
     gauss_legendre01(8, C.q.x8, C.q.w8);
     gauss_legendre01(16, C.q.x16, C.q.w16);
     out.delta.alloc(4 * out.nnz);
-    k_near_coeffs<<<grid_for(out.nnz, 64), 64, 0, s>>>(C, n, out.nnz, out.ptr.p, out.col.p,
-                                                         out.delta.p);
+    k_near_coeffs<<<grid_for(out.nnz, 4), 256, 0, s>>>(C, n, out.nnz, out.ptr.p, out.col.p,
+                                                        out.delta.p);
     KCHK();
     out.delta32.alloc(4 * out.nnz);
     k_round_f32<<<grid_for(4 * out.nnz, 256), 256, 0, s>>>(out.delta.p, out.delta32.p, 4 * out.nnz);

@@ -1,7 +1,7 @@
 // Solve server: continuous batching of independent PB solves on one GPU.
 //
-// Requests (a surface mesh and its charges) are queued on submit.  A setup
-// thread admits them in arrival order while the device bytes of the admitted
+// Requests (a surface mesh and its charges) are queued on submit.  Setup
+// threads admit them in arrival order while the device bytes of the admitted
 // molecules stay within the budget and a slot is free, builds each one's
 // context (geometry, tree, lists, near set, operators; Section 3) on a stream
 // of its own and captures its matvec (Eq. 5, far field and near field) into
@@ -487,7 +487,8 @@ struct afmpb_server {
     long long completed = 0, failed = 0;
     unsigned long long next_ticket = 1;
     bool stop = false;
-    std::thread setup_thr, step_thr;
+    std::vector<std::thread> setup_thr;
+    std::thread step_thr;
     std::string err;
 
     static long long estimate_bytes(long long n, int p) {
@@ -648,13 +649,15 @@ void afmpb_server::step_loop() {
 extern "C" {
 
 afmpb_status afmpb_server_create(const afmpb_params *params, long long hbm_budget_bytes,
-                                 int max_active, int device, afmpb_server **out) {
+                                 int max_active, int setup_threads, int device,
+                                 afmpb_server **out) {
     if (!out || !params) return AFMPB_E_INVALID;
     *out = nullptr;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return AFMPB_E_INVALID;
     if (hbm_budget_bytes <= 0 || max_active < 1 || max_active > 4096) return AFMPB_E_INVALID;
+    if (setup_threads < 1 || setup_threads > 64) return AFMPB_E_INVALID;
     afmpb_params p = *params;
     try {
         // order_p / leaf_cap 0 mean "tuned per request"; check the rest now
@@ -671,7 +674,8 @@ afmpb_status afmpb_server_create(const afmpb_params *params, long long hbm_budge
     s->budget = hbm_budget_bytes;
     s->max_active = max_active;
     s->device = device;
-    s->setup_thr = std::thread([s] { s->setup_loop(); });
+    for (int i = 0; i < setup_threads; ++i)
+        s->setup_thr.emplace_back([s] { s->setup_loop(); });
     s->step_thr = std::thread([s] { s->step_loop(); });
     *out = s;
     return AFMPB_OK;
@@ -799,7 +803,8 @@ afmpb_status afmpb_server_destroy(afmpb_server *s) {
     }
     s->cv_setup.notify_all();
     s->cv_step.notify_all();
-    if (s->setup_thr.joinable()) s->setup_thr.join();
+    for (auto &t : s->setup_thr)
+        if (t.joinable()) t.join();
     if (s->step_thr.joinable()) s->step_thr.join();
     {
         std::lock_guard<std::mutex> lk(s->mu);
