@@ -53,7 +53,7 @@ def parse():
                     help="requests checked against the order-14 FP64 solve")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-max-active", type=int, default=32)
-    ap.add_argument("--serve-setup-threads", type=int, default=8)
+    ap.add_argument("--serve-setup-threads", type=int, default=1)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")

@@ -223,8 +223,7 @@ afmpb_status afmpb_profile_read(afmpb_ctx *ctx, int idx, const char **name,
  * admitted molecule gets its own context and stream; its matvec is captured
  * once into HIP graphs, and one host thread advances all admitted solves by
  * one asynchronous GMRES chunk (one Arnoldi step) at a time, so their work
- * overlaps on the device and late arrivals join while others run; several
- * setup threads build admitted requests in parallel.  Every
+ * overlaps on the device and late arrivals join while others run.  Every
  * solve follows the same algorithm, kernels and order as afmpb_solve on the
  * same molecule and parameters, so its result does not depend on what else
  * is in flight.  All server functions are thread-safe.
@@ -269,8 +268,10 @@ typedef struct {
     long long device_bytes, device_bytes_peak;
 } afmpb_server_counts;
 
-/* Starts a server on `device` with setup_threads (1..64) threads that build
- * admitted requests concurrently and one stepping thread.  params as for
+/* Starts a server on `device` with setup_threads threads that build admitted
+ * requests and one stepping thread.  setup_threads must be 1 in this build:
+ * parallel setup is switched off until a host crash seen with several setup
+ * threads is understood (AFMPB_E_INVALID otherwise).  params as for
  * afmpb_set_molecule, except that order_p == 0 / leaf_cap == 0 select per
  * request from the tuning table.  Errors: AFMPB_E_INVALID. */
 afmpb_status afmpb_server_create(const afmpb_params *params,

@@ -391,7 +391,7 @@ class Solver:
 # --- solve server ---------------------------------------------------------------
 
 def afmpb_server_create(params: afmpb_params, hbm_budget_bytes: int, max_active: int,
-                        setup_threads: int = 4, device: int = 0):
+                        setup_threads: int = 1, device: int = 0):
     h = ctypes.c_void_p()
     st = lib().afmpb_server_create(ctypes.byref(params), int(hbm_budget_bytes), int(max_active),
                                    int(setup_threads), int(device), ctypes.byref(h))
@@ -457,7 +457,7 @@ class Server:
     """Continuous-batching solve server (one device)."""
 
     def __init__(self, hbm_budget_bytes: int = 32 << 30, max_active: int = 64,
-                 setup_threads: int = 4, device: int = 0, tuning=None, **params):
+                 setup_threads: int = 1, device: int = 0, tuning=None, **params):
         p = afmpb_default_params()
         for k, v in params.items():
             setattr(p, k, v)

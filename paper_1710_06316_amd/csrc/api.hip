@@ -501,6 +501,7 @@ Gmres gmres(afmpb_ctx *c, const double *b, double *x, bool x_zero, double rel_to
         c->krylov_m = m;
     }
     if (c->hbuf.n < (size_t)(2 * (m + 2))) c->hbuf.alloc(2 * (m + 2));
+    if (c->dscratch.n < (size_t)dots_scratch(len, m + 1)) c->dscratch.alloc(dots_scratch(len, m + 1));
     double *Vk = c->krylov.p;
     Gmres g;
     const double nb = std::sqrt(host_dot(c, b, b, len));

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
+#include <shared_mutex>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -52,6 +54,11 @@ inline void require(bool ok, int code, const std::string &msg) {
 // server uses this for its memory budget.
 inline thread_local std::atomic<long long> *g_dev_bytes = nullptr;
 
+// Device frees (which may synchronise the device) never overlap a graph
+// capture in another thread: frees hold this lock shared, captures hold it
+// exclusively.
+inline std::shared_mutex g_capture_mu;
+
 template <typename T>
 struct DBuf {
     T *p = nullptr;
@@ -81,7 +88,10 @@ struct DBuf {
     }
     void release() {
         if (p) {
-            (void)hipFree(p);
+            {
+                std::shared_lock<std::shared_mutex> lk(g_capture_mu);
+                (void)hipFree(p);
+            }
             if (acct) *acct -= (long long)(n * sizeof(T));
             p = nullptr; n = 0; acct = nullptr;
         }

@@ -4,6 +4,9 @@
 
 namespace afmpb {
 
+// Scratch elements dots() needs for nvec vectors of length len (size the
+// scratch once for the largest nvec: dots() grows it otherwise).
+long long dots_scratch(long long len, int nvec);
 // out[j] = <V[j], w> for j < nvec (V rows of length len, stride ld).
 void dots(const double *V, long long ld, int nvec, const double *w, long long len, double *out,
           DBuf<double> &scratch, hipStream_t s);

@@ -142,6 +142,10 @@ __global__ void k_reaction(NodeSoA nd, long long n, const double *__restrict__ x
 
 }  // namespace
 
+long long dots_scratch(long long len, int nvec) {
+    return ((len + DOT_CHUNK - 1) / DOT_CHUNK) * (long long)nvec;
+}
+
 void dots(const double *V, long long ld, int nvec, const double *w, long long len, double *out,
           DBuf<double> &scratch, hipStream_t s) {
     int nblk = (int)((len + DOT_CHUNK - 1) / DOT_CHUNK);

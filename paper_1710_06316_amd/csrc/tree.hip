@@ -376,16 +376,17 @@ void build_tree(const unsigned long long *keys, long long n, int cap, const doub
     t.n_child.alloc(capb); t.pt_begin.alloc(capb); t.pt_end.alloc(capb);
     t.prefix.alloc(capb);
     {
-        // synchronous copies: the host values live on this stack frame only
+        // copies on this context's stream, waited for before the host values
+        // (on this stack frame) go out of scope; no legacy-stream operation,
+        // so other threads may capture graphs meanwhile
         const int root_i[6] = {0, -1, -1, 0, 0, (int)n};  // level parent cb nc ptb pte
         const unsigned long long z = 0;
-        HIPCHK(hipMemcpy(t.level.p, &root_i[0], sizeof(int), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(t.parent.p, &root_i[1], sizeof(int), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(t.child_begin.p, &root_i[2], sizeof(int), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(t.n_child.p, &root_i[3], sizeof(int), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(t.pt_begin.p, &root_i[4], sizeof(int), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(t.pt_end.p, &root_i[5], sizeof(int), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(t.prefix.p, &z, sizeof(z), hipMemcpyHostToDevice));
+        int *dst[6] = {t.level.p, t.parent.p, t.child_begin.p, t.n_child.p, t.pt_begin.p,
+                       t.pt_end.p};
+        for (int i = 0; i < 6; ++i)
+            HIPCHK(hipMemcpyAsync(dst[i], &root_i[i], sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(t.prefix.p, &z, sizeof(z), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
     }
     DBuf<int> box_of(n), flag(n + 1), pos(n + 1), gerr(1);
     box_of.zero(n, s);
