@@ -136,6 +136,24 @@ def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host, do_
             "setup_ms": setup_ms, "solve": solve, "y_host": y_host}
 
 
+def measured_traffic(kernel, order, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    the same workload and configuration, or None (other configuration, or the
+    kernel source changed since the counters were taken)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "m2l_globular_5000_fp32_p10_hbm_traffic.md")
+    if kernel != "m2l" or order != 10 or precision != "fp32" or not os.path.exists(path):
+        return None
+    for ln in open(path):
+        if ln.startswith("traffic-json:"):
+            rec = json.loads(ln.split(":", 1)[1])
+            src = os.path.join(ROOT, rec["source"])
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+                return None
+            return rec["bytes_per_launch"]
+    return None
+
+
 def roofline(r, order, precision):
     """Roofline entries for P2P (vector ALU) and M2L (matrix cores); the
     dominant kernel of the step (largest total time) is the headline one."""
@@ -155,7 +173,8 @@ def roofline(r, order, precision):
         avg_s = tot_ms / cnt * 1e-3
         achieved = flops / avg_s / 1e12
         roofs[name] = {"kernel": name, "bound": bound, "achieved": achieved, "peak": pk,
-                       "unit": "TFLOP/s", "frac": achieved / pk, "traffic": None,
+                       "unit": "TFLOP/s", "frac": achieved / pk,
+                       "traffic": measured_traffic(name, order, precision),
                        "flops_per_launch": flops, "avg_ms": avg_s * 1e3}
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
     roof = roofs.get(dom) or max(roofs.values(), key=lambda q: q["avg_ms"])
