@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
     ap.add_argument("--order", type=int, default=10)
     ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--workload", choices=["globular", "complex_100k"], default="globular",
+                    help="globular (headline) or the 100k-atom complex (~1M nodes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the plain FP64 comparison run")
@@ -136,13 +138,14 @@ def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host, do_
             "setup_ms": setup_ms, "solve": solve, "y_host": y_host}
 
 
-def measured_traffic(kernel, order, precision):
+def measured_traffic(kernel, order, precision, workload="globular"):
     """HBM bytes per launch of `kernel` from the committed counter summary of
     the same workload and configuration, or None (other configuration, or the
     kernel source changed since the counters were taken)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "m2l_globular_5000_fp32_p10_hbm_traffic.md")
-    if kernel != "m2l" or order != 10 or precision != "fp32" or not os.path.exists(path):
+    if (kernel != "m2l" or order != 10 or precision != "fp32" or workload != "globular"
+            or not os.path.exists(path)):
         return None
     for ln in open(path):
         if ln.startswith("traffic-json:"):
@@ -154,7 +157,7 @@ def measured_traffic(kernel, order, precision):
     return None
 
 
-def roofline(r, order, precision):
+def roofline(r, order, precision, workload="globular"):
     """Roofline entries for P2P (vector ALU) and M2L (matrix cores); the
     dominant kernel of the step (largest total time) is the headline one."""
     info, prof = r["info"], r["prof"]
@@ -174,7 +177,7 @@ def roofline(r, order, precision):
         achieved = flops / avg_s / 1e12
         roofs[name] = {"kernel": name, "bound": bound, "achieved": achieved, "peak": pk,
                        "unit": "TFLOP/s", "frac": achieved / pk,
-                       "traffic": measured_traffic(name, order, precision),
+                       "traffic": measured_traffic(name, order, precision, workload),
                        "flops_per_launch": flops, "avg_ms": avg_s * 1e3}
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
     roof = roofs.get(dom) or max(roofs.values(), key=lambda q: q["avg_ms"])
@@ -293,12 +296,12 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    mol = W.globular()
+    mol = W.globular() if a.workload == "globular" else W.complex_100k()
     n = mol.n_nodes
     x_host = np.random.default_rng(99).normal(size=2 * n)
     r = run_config(A, torch, mol, a.precision, a.order, a.leaf, a.steps, a.warmup, x_host,
                    not a.no_solve)
-    roof, roofs, dom = roofline(r, a.order, a.precision)
+    roof, roofs, dom = roofline(r, a.order, a.precision, a.workload)
     info = r["info"]
     line = {
         "metric": "FMM matvec Munknowns/s", "value": r["value"], "unit": "Munknowns/s",
@@ -306,8 +309,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "globular_5000: SAW atoms in 25 A, Gaussian isosurface, "
-                               f"{n} nodes / {len(mol.tri)} triangles",
+        "config": {"workload": (("globular_5000: SAW atoms in 25 A" if a.workload == "globular"
+                                 else "complex_100k: SAW atoms in 90 A")
+                                + f", Gaussian isosurface, {n} nodes / {len(mol.tri)} triangles"),
                    "unknowns": 2 * n, "order_p": a.order, "leaf_cap": a.leaf,
                    "precision": a.precision, "n_boxes": info["n_boxes"],
                    "n_p2p_pairs": info["n_p2p_pairs"], "n_m2l_pairs": info["n_m2l_pairs"],
@@ -327,7 +331,7 @@ def main():
         line["fp64_plain"] = {"value": r64["value"], "ms_per_step": r64["ms"],
                               "kernels_ms_per_step": {k: v[0] / a.steps
                                                       for k, v in r64["prof"].items()},
-                              "roofline_all": roofline(r64, a.order, "fp64")[1],
+                              "roofline_all": roofline(r64, a.order, "fp64", a.workload)[1],
                               "solve": r64["solve"]}
         y_gpu[f"fp64_p{a.order}"] = r64["y_host"]
     if a.serve_requests > 0:

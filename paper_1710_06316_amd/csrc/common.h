@@ -114,9 +114,18 @@ __host__ __device__ inline int p2p_replicas(int ntarget) {
     return ntarget <= 8 ? 8 : ntarget <= 16 ? 4 : ntarget <= 32 ? 2 : 1;
 }
 
+// Blocks for n threads.  A dispatch's grid size per dimension is a 32-bit
+// count of work-items, so a launch of 2^32 or more threads would silently
+// drop work: refuse it (large loops use a capped grid and a stride).
+inline unsigned blocks_ok(long long blocks, long long block) {
+    require(blocks >= 1 && blocks * block < (1ll << 32), -1, "launch larger than 2^32 work-items");
+    return (unsigned)blocks;
+}
 inline unsigned grid_for(long long n, int block) {
     long long g = (n + block - 1) / block;
-    return (unsigned)(g < 1 ? 1 : g);
+    if (g < 1) g = 1;
+    require(g * (long long)block < (1ll << 32), -1, "launch larger than 2^32 work-items");
+    return (unsigned)g;
 }
 
 // ---------------------------------------------------------------------------

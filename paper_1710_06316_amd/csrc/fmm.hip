@@ -581,6 +581,7 @@ template <typename R, int MODE, int KSR>
 void launch_trans_k(const TransArgs &ta, dim3 g, unsigned nthr, const R *ops, const R *in,
                     R *out, int lev, hipStream_t s) {
     const size_t lim = 60 * 1024;
+    (void)blocks_ok(g.x, nthr);   // per grid dimension
     const int KR = KSR > 0 ? 4 * KSR : ta.KK;
     auto shmem = [&](int cc) { return (size_t)lds_stride(KR, (int)sizeof(R)) * cc * sizeof(R); };
     if (MODE == 0) {
@@ -869,7 +870,7 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "p2m", s);
-        k_p2m<R><<<(unsigned)L.n_leaves, 128, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
+        k_p2m<R><<<blocks_ok(L.n_leaves, 128), 128, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
                                                      sf, sh, R(inv_ebar), w.M);
         KCHK();
     }
@@ -908,7 +909,7 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "m2l_reduce", s);
-        k_m2l_reduce<R><<<(unsigned)t.nbox, 256, 0, s>>>(K, t.nbox, L.v_ptr.p, w.Z, w.Lc);
+        k_m2l_reduce<R><<<blocks_ok(t.nbox, 256), 256, 0, s>>>(K, t.nbox, L.v_ptr.p, w.Z, w.Lc);
         KCHK();
     }
     {
@@ -921,7 +922,7 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "l2p", s);
-        k_l2p<R><<<(unsigned)L.n_leaves, 128, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
+        k_l2p<R><<<blocks_ok(L.n_leaves, 128), 128, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
                                                      w.Lc, n, w.phi);
         KCHK();
     }

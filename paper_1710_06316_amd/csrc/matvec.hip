@@ -286,11 +286,11 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
     {
         ProfScope ps(prof, "p2p", mp.side);
         const Lists &L = *mp.lists;
-        k_p2p<R><<<(unsigned)L.n_chunks, 64, 0, mp.side>>>(
+        k_p2p<R><<<blocks_ok(L.n_chunks, 64), 64, 0, mp.side>>>(
             L.ch_lo.p, L.ch_hi.p, L.ch_grp.p, L.grp_tbeg.p, L.grp_tend.p, L.rng_b.p, L.rng_e.p,
             mp.nd, mp.sf, mp.sh, R(mp.kappa), R(mp.inv_ebar), mp.part);
         KCHK();
-        k_p2p_reduce<<<(unsigned)L.n_groups, 64, 0, mp.side>>>(L.grp_ptr.p, L.grp_tbeg.p,
+        k_p2p_reduce<<<blocks_ok(L.n_groups, 64), 64, 0, mp.side>>>(L.grp_ptr.p, L.grp_tbeg.p,
                                                                 L.grp_tend.p, mp.part, mp.pf, mp.ph);
         KCHK();
     }

@@ -249,8 +249,6 @@ __global__ void __launch_bounds__(256) k_near_coeffs(Ctx C, long long n, long lo
                                                      const int *__restrict__ col,
                                                      double *__restrict__ delta) {
     const int lane = threadIdx.x & 63;
-    const long long e = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (e >= nnz) return;                              // uniform for the wave
     LanePts L;
     {
         const int i = lane >> 3, j = lane & 7;
@@ -264,6 +262,10 @@ __global__ void __launch_bounds__(256) k_near_coeffs(Ctx C, long long n, long lo
             L.g16[s] = C.q.w16[i2] * C.q.w16[j2];
         }
     }
+    // grid-stride over the entries (wave-uniform), so that the launch stays
+    // far below the 2^32 work-item limit of one dispatch
+    for (long long e = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); e < nnz;
+         e += (long long)gridDim.x * 4) {
     long long lo = 0, hi = n;              // row p: ptr[p] <= e < ptr[p+1]
     while (hi - lo > 1) {
         long long mid = (lo + hi) >> 1;
@@ -319,6 +321,7 @@ __global__ void __launch_bounds__(256) k_near_coeffs(Ctx C, long long n, long lo
         delta[4 * e + 1] = acc.b;
         delta[4 * e + 2] = acc.c;
         delta[4 * e + 3] = acc.d;
+    }
     }
 }
 
@@ -424,8 +427,10 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
     gauss_legendre01(8, C.q.x8, C.q.w8);
     gauss_legendre01(16, C.q.x16, C.q.w16);
     out.delta.alloc(4 * out.nnz);
-    k_near_coeffs<<<grid_for(out.nnz, 4), 256, 0, s>>>(C, n, out.nnz, out.ptr.p, out.col.p,
-                                                        out.delta.p);
+    // one wave per entry, at most 2^22 blocks of 4 waves (the kernel strides)
+    const long long nblk = std::min<long long>((out.nnz + 3) / 4, 1ll << 22);
+    k_near_coeffs<<<(unsigned)std::max(nblk, 1ll), 256, 0, s>>>(C, n, out.nnz, out.ptr.p,
+                                                               out.col.p, out.delta.p);
     KCHK();
     out.delta32.alloc(4 * out.nnz);
     k_round_f32<<<grid_for(4 * out.nnz, 256), 256, 0, s>>>(out.delta.p, out.delta32.p, 4 * out.nnz);

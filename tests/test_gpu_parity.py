@@ -251,3 +251,57 @@ def test_error_contract():
     f, h, E, info, st = s.solve(allow_not_converged=True)
     assert st == A.AFMPB_E_NOT_CONVERGED and info.iterations == 1 and np.isfinite(E)
     s.close()
+
+
+# ------------------------- 100k-atom complex (~1M nodes) --------------------
+
+_COMPLEX = {}
+
+
+def _complex():
+    if "mol" not in _COMPLEX:
+        _say("generating complex_100k")
+        mol = W.complex_100k()
+        rng = np.random.default_rng(31)
+        rows = np.sort(rng.choice(mol.n_nodes, size=96, replace=False))
+        _say(f"complex_100k n={mol.n_nodes}: oracle rows")
+        op = O.operator(mol.xyz, mol.tri, mol.eps_p, mol.eps_s, mol.kappa, rows=rows,
+                        validate=False)
+        x = rng.normal(size=2 * mol.n_nodes)
+        yf, yh = op.apply_rows(x)
+        _COMPLEX.update(mol=mol, rows=rows, x=x, ref=np.r_[yf, yh])
+    return _COMPLEX
+
+
+@pytest.mark.parametrize("p,precision,tol", [(6, 0, 2e-4), (10, 0, 1e-5), (14, 0, 2e-6),
+                                             (10, 1, 1e-5)])
+def test_complex_sampled_rows(p, precision, tol):
+    """~1M-node matvec on 96 oracle rows at expansion orders 6 / 10 / 14
+    (errors fall with p; the 1e-5 tolerance is met from p = 10)."""
+    c = _complex()
+    mol, rows, x, ref = c["mol"], c["rows"], c["x"], c["ref"]
+    n = mol.n_nodes
+    s = _solver(mol, order_p=p, precision=precision)
+    y = s.matvec(x)
+    info = s.tree_info()
+    s.close()
+    err = np.linalg.norm(np.r_[y[rows], y[n + rows]] - ref) / np.linalg.norm(ref)
+    _say(f"complex p={p} precision={precision} rows err {err:.3e} boxes {info['n_boxes']} "
+         f"V {info['n_m2l_pairs']} near {info['n_near']}")
+    assert err < tol
+
+
+def test_complex_energy_mixed_vs_fp64():
+    """~1M-node solve: the mixed-precision form at p = 10 against the FP64
+    form at p = 14 (parity unpinned: no oracle solve at this size)."""
+    mol = _complex()["mol"]
+    out = {}
+    for p, prec in ((10, 1), (14, 0)):
+        s = _solver(mol, order_p=p, precision=prec)
+        f, h, E, info, _ = s.solve()
+        s.close()
+        _say(f"complex solve p={p} precision={prec} E={E:.6f} iters={info.iterations} "
+             f"res={info.true_rel_residual:.2e}")
+        assert info.converged
+        out[p] = E
+    assert abs(out[10] - out[14]) <= 1e-4 * abs(out[14])

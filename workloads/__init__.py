@@ -285,52 +285,63 @@ def gaussian_surface(atoms, radii, h_grid: float, beta: float = 2.0,
     keep = (nin > 0) & (nin < 4)
     gid, val, ins, nin = gid[keep], val[keep], ins[keep], nin[keep]
 
-    edge_key_to_vid: dict[int, int] = {}
-    vert_list: list = []
     npts = nx * ny * nz
-
-    def vid(a, b, fa, fb):
-        # a inside, b outside
-        lo_, hi_ = (a, b) if a < b else (b, a)
-        k = lo_ * npts + hi_
-        v = edge_key_to_vid.get(k)
-        if v is None:
-            t = fa / (fa - fb)
-            t = min(1.0 - clamp, max(clamp, t))
-            pa = np.array(np.unravel_index(a, shape), dtype=np.float64)
-            pb = np.array(np.unravel_index(b, shape), dtype=np.float64)
-            p = lo + h_grid * (pa + t * (pb - pa))
-            v = len(vert_list)
-            vert_list.append(p)
-            edge_key_to_vid[k] = v
-        return v
-
-    tris = []
-    for g, f, s in zip(gid.tolist(), val.tolist(), ins.tolist()):
-        I = [i for i in range(4) if s[i]]
-        O = [i for i in range(4) if not s[i]]
-        if len(I) == 1 or len(O) == 1:
-            if len(I) == 1:
-                a = I[0]
-                vs = [vid(g[a], g[o], f[a], f[o]) for o in O]
-            else:
-                o = O[0]
-                vs = [vid(g[i], g[o], f[i], f[o]) for i in I]
-            tris.append((vs, g, s))
-        else:
-            i0, i1 = I
-            o0, o1 = O
-            q0 = vid(g[i0], g[o0], f[i0], f[o0])
-            q1 = vid(g[i0], g[o1], f[i0], f[o1])
-            q2 = vid(g[i1], g[o1], f[i1], f[o1])
-            q3 = vid(g[i1], g[o0], f[i1], f[o0])
-            tris.append(([q0, q1, q2], g, s))
-            tris.append(([q0, q2, q3], g, s))
-    V = np.array(vert_list, dtype=np.float64)
-    T = np.array([t[0] for t in tris], dtype=np.int64)
+    nt = len(gid)
+    # crossing edges of every tetrahedron, in a fixed per-tet order: one
+    # corner inside (its 3 edges to the outside corners in index order), three
+    # inside (the inside corners' edges to the outside corner), or two inside
+    # (i0-o0, i0-o1, i1-o1, i1-o0); a vertex is numbered at the first tet
+    # (in tet order) that uses its edge
+    order = np.argsort(~ins, axis=1, kind="stable")          # inside corners first
+    srt_in = np.take_along_axis(ins, order, 1)
+    assert np.array_equal(srt_in.sum(1), nin)
+    ea = np.zeros((nt, 4), np.int64)
+    eb = np.zeros((nt, 4), np.int64)
+    nslot = np.where(nin == 2, 4, 3)
+    one = nin == 1
+    three = nin == 3
+    two = nin == 2
+    # one inside: corner order[0] with order[1..3]
+    ea[one, :3] = order[one, 0:1]
+    eb[one, :3] = order[one, 1:4]
+    # three inside: order[0..2] with order[3]
+    ea[three, :3] = order[three, 0:3]
+    eb[three, :3] = order[three, 3:4]
+    # two inside: i0=order[0], i1=order[1], o0=order[2], o1=order[3]
+    o2 = order[two]
+    ea[two] = np.stack([o2[:, 0], o2[:, 0], o2[:, 1], o2[:, 1]], 1)
+    eb[two] = np.stack([o2[:, 2], o2[:, 3], o2[:, 3], o2[:, 2]], 1)
+    valid = np.arange(4)[None, :] < nslot[:, None]
+    ga = np.take_along_axis(gid, ea, 1)                      # inside grid point
+    gb = np.take_along_axis(gid, eb, 1)                      # outside grid point
+    fa = np.take_along_axis(val, ea, 1)
+    fb = np.take_along_axis(val, eb, 1)
+    key = np.minimum(ga, gb) * npts + np.maximum(ga, gb)
+    kv, av, bv, fav, fbv = key[valid], ga[valid], gb[valid], fa[valid], fb[valid]
+    uk, first, inv = np.unique(kv, return_index=True, return_inverse=True)
+    rank = np.empty(len(uk), np.int64)                       # first appearance order
+    rank[np.argsort(first, kind="stable")] = np.arange(len(uk))
+    slot_vid = np.full((nt, 4), -1, np.int64)
+    slot_vid[valid] = rank[inv]
+    src = first[np.argsort(first, kind="stable")]            # defining slot per vertex
+    t = fav[src] / (fav[src] - fbv[src])
+    t = np.minimum(1.0 - clamp, np.maximum(clamp, t))
+    pa = np.stack(np.unravel_index(av[src], shape), -1).astype(np.float64)
+    pb = np.stack(np.unravel_index(bv[src], shape), -1).astype(np.float64)
+    V = lo + h_grid * (pa + t[:, None] * (pb - pa))
+    # triangles in tet order (two per two-inside tet: q0 q1 q2, q0 q2 q3)
+    tri = np.full((nt, 2, 3), -1, np.int64)
+    tri[:, 0, :] = slot_vid[:, :3]
+    tri[two, 0, :] = slot_vid[two][:, [0, 1, 2]]
+    tri[two, 1, :] = slot_vid[two][:, [0, 2, 3]]
+    tmask = np.zeros((nt, 2), bool)
+    tmask[:, 0] = True
+    tmask[two, 1] = True
+    T = tri[tmask]
+    owner = np.repeat(np.arange(nt), tmask.sum(1))
     # orientation: normal must point from inside corners to outside corners
-    gpos = np.stack(np.unravel_index(np.array([t[1] for t in tris]), shape), -1)
-    sg = np.array([t[2] for t in tris])
+    gpos = np.stack(np.unravel_index(gid[owner], shape), -1)
+    sg = ins[owner]
     cin = (gpos * sg[..., None]).sum(1) / sg.sum(1, keepdims=True)
     cout = (gpos * (~sg)[..., None]).sum(1) / (~sg).sum(1, keepdims=True)
     nrm = np.cross(V[T[:, 1]] - V[T[:, 0]], V[T[:, 2]] - V[T[:, 0]])
@@ -397,8 +408,10 @@ def globular(seed: int = 2, n_atoms: int = 5000, r_max: float = 25.0,
 
 
 def complex_100k(seed: int = 3, n_atoms: int = 100000, r_max: float = 90.0,
-                 h_grid: float = 0.7):
-    """Config 'synthetic large protein complex' (100,000 atoms, ~1M nodes)."""
+                 h_grid: float = 1.5):
+    """Config 'synthetic large protein complex' (100,000 atoms): the grid
+    spacing 1.5 A puts the isosurface near the configuration's ~2M triangles
+    (~1M nodes)."""
     pos, rad, q = saw_atoms(n_atoms, r_max, seed)
     V, T, meta = gaussian_surface(pos, rad, h_grid)
     return Molecule(name=f"complex_{n_atoms}", xyz=V, tri=T, atom_xyz=pos,
