@@ -438,6 +438,32 @@ void check_setup(afmpb_ctx *c) {
             if (gb[g] < 0 || ge[g] > n || gb[g] >= ge[g] || ge[g] - gb[g] > 64) bad("P2P group targets");
         }
     }
+    {
+        // P2M / L2P items: every leaf once, <= 4 leaves and <= 64 points per
+        // item unless the item is a single leaf
+        const long long nl = L.n_leaves;
+        auto pl = host_copy(L.pm_leaf, nl, s);
+        auto pf = host_copy(L.pm_first, L.n_pm, s);
+        auto pc = host_copy(L.pm_count, L.n_pm, s);
+        auto lb = host_copy(c->tree.pt_begin, c->tree.nbox, s);
+        auto le = host_copy(c->tree.pt_end, c->tree.nbox, s);
+        auto nch = host_copy(c->tree.n_child, c->tree.nbox, s);
+        c->sync();
+        std::vector<char> seen(c->tree.nbox, 0);
+        for (long long i = 0; i < nl; ++i) {
+            if (pl[i] < 0 || pl[i] >= c->tree.nbox || nch[pl[i]] != 0 || seen[pl[i]]) bad("P2M leaf list");
+            seen[pl[i]] = 1;
+        }
+        long long covered = 0;
+        for (long long w = 0; w < L.n_pm; ++w) {
+            if (pc[w] < 1 || pc[w] > 4 || pf[w] != covered || pf[w] + pc[w] > nl) bad("P2M item");
+            long long pts = 0;
+            for (int g = 0; g < pc[w]; ++g) pts += le[pl[pf[w] + g]] - lb[pl[pf[w] + g]];
+            if (pc[w] > 1 && pts > 64) bad("P2M item points");
+            covered += pc[w];
+        }
+        if (covered != nl) bad("P2M items do not cover the leaves");
+    }
     if (L.n_m2l_items > 0) {
         auto ik = host_copy(L.m2l_item_key, L.n_m2l_items, s);
         auto ibg = host_copy(L.m2l_item_begin, L.n_m2l_items, s);

@@ -220,32 +220,57 @@ struct TreeDev {
     const double *center;
 };
 
-// P2M: one block per leaf, wave w computes the expansion of kernel w.  Each
-// lane evaluates the regular basis at one source point; the coefficients are
-// emitted 16 at a time into LDS and summed over the points by 16 groups of 4
-// lanes (fixed order, so the result is deterministic).
+// P2M / L2P work item: up to 4 leaves (consecutive in point order) with at
+// most 64 points together share one wave, point q of the item on lane q; a
+// leaf of more than 64 points is an item of its own, taken 64 points at a time.
+struct PmItem {
+    int first, cnt, tot;
+    int offs[5];                 // point offset of each leaf in the item
+    __device__ PmItem(const int *pm_leaf, const int *pm_first, const int *pm_count,
+                      const TreeDev &T, int w) {
+        first = pm_first[w];
+        cnt = pm_count[w];
+        offs[0] = 0;
+        for (int g = 0; g < 4; ++g) {
+            const int L = g < cnt ? pm_leaf[first + g] : -1;
+            offs[g + 1] = offs[g] + (L >= 0 ? T.pte[L] - T.ptb[L] : 0);
+        }
+        tot = offs[cnt];
+    }
+    __device__ int leaf_of(int q) const {     // item point q -> leaf slot g
+        return (q >= offs[1] && cnt > 1) + (q >= offs[2] && cnt > 2) + (q >= offs[3] && cnt > 3);
+    }
+};
+
+// P2M: one block per item, wave w computes the expansions of kernel w.  Each
+// lane evaluates the regular basis at one source point (about its own
+// leaf's centre); the coefficients are emitted 16 at a time into LDS, and
+// lane (slot, g) sums slot's coefficient over the points of leaf g in point
+// order (deterministic).
 template <typename R>
-__global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *leaf_ids,
+__global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *pm_leaf,
+                                             const int *pm_first, const int *pm_count,
                                              const R *px, const R *py, const R *pz,
                                              const R *pnx, const R *pny, const R *pnz,
                                              const R *sf, const R *sh, R inv_ebar, R *M) {
     __shared__ R Wv[2][16][65];
     __shared__ int kslot[2][16];
-    const int box = leaf_ids[blockIdx.x];
-    const int lev = T.level[box];
-    if (lev < 2) return;
+    const PmItem it(pm_leaf, pm_first, pm_count, T, blockIdx.x);
     const int lane = threadIdx.x & 63;
     const int kern = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int K = B.K;
-    R *Mb = M + ((long long)box * 2 + kern) * K;
-    const R cx = R(T.center[3 * box]), cy = R(T.center[3 * box + 1]), cz = R(T.center[3 * box + 2]);
-    const int b = T.ptb[box], e = T.pte[box];
-    for (int c0 = b; c0 < e; c0 += 64) {
-        const int i = c0 + lane;
-        const bool ok = i < e;
+    for (int c0 = 0; c0 < it.tot; c0 += 64) {
+        const int q = c0 + lane;
+        const bool ok = q < it.tot;
+        const int g = it.leaf_of(ok ? q : 0);
+        const int leaf = pm_leaf[it.first + g];
+        const int lev = T.level[leaf];
+        const int i = T.ptb[leaf] + (ok ? q - it.offs[g] : 0);
+        const R cx = R(T.center[3 * leaf]), cy = R(T.center[3 * leaf + 1]);
+        const R cz = R(T.center[3 * leaf + 2]);
         const R vx = ok ? px[i] - cx : R(0), vy = ok ? py[i] - cy : R(0), vz = ok ? pz[i] - cz : R(0);
         const R nx = ok ? pnx[i] : R(0), ny = ok ? pny[i] : R(0), nz = ok ? pnz[i] : R(0);
-        const R q = ok ? sh[i] : R(0);
+        const R qv = ok ? sh[i] : R(0);
         const R dmag = ok ? -sf[i] : R(0);
         const R dip = (kern == 0) ? dmag * inv_ebar : dmag;
         int cnt = 0;                       // coefficients emitted so far (uniform)
@@ -253,15 +278,17 @@ __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *l
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int slot = lane >> 2, qu = lane & 3;
-            R acc = R(0);
-#pragma unroll
-            for (int j = 0; j < 16; ++j) acc += Wv[kern][slot][qu * 16 + j];
-            acc += __shfl_xor(acc, 1, 64);
-            acc += __shfl_xor(acc, 2, 64);
-            if (qu == 0 && slot < nslot) {
-                const int k = kslot[kern][slot];
-                Mb[k] = (c0 == b) ? acc : Mb[k] + acc;
+            const int slot = lane >> 2, gg = lane & 3;
+            if (slot < nslot && gg < it.cnt) {
+                const int b0 = max(it.offs[gg] - c0, 0), b1 = min(it.offs[gg + 1] - c0, 64);
+                R acc = R(0);
+                for (int j = b0; j < b1; ++j) acc += Wv[kern][slot][j];
+                const int lg = pm_leaf[it.first + gg];
+                if (b0 < b1 && T.level[lg] >= 2) {
+                    R *Mb = M + ((long long)lg * 2 + kern) * K;
+                    const int k = kslot[kern][slot];
+                    Mb[k] = (c0 == 0) ? acc : Mb[k] + acc;
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -270,7 +297,7 @@ __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *l
         regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, nx), Dual<R>(vy, ny), Dual<R>(vz, nz),
                                   [&](int k, Dual<R> r) {
                                       const int sl = cnt & 15;
-                                      Wv[kern][sl][lane] = q * r.v + dip * r.d;
+                                      Wv[kern][sl][lane] = qv * r.v + dip * r.d;
                                       if (lane == 0) kslot[kern][sl] = k;
                                       ++cnt;
                                       if ((cnt & 15) == 0) flush(16);
@@ -663,33 +690,41 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(int K, long long nbox, const
         L[box * W + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
-// L2P: one block per leaf, wave w evaluates the local expansion of kernel w
-// (potential and normal derivative) at one target point per lane.
+// L2P: one block per item, wave w evaluates the local expansion of kernel w
+// (potential and normal derivative) at one target point per lane, with the
+// coefficients of that point's leaf.
 template <typename R>
-__global__ void __launch_bounds__(128) k_l2p(BasisDev B, TreeDev T, const int *leaf_ids,
+__global__ void __launch_bounds__(128) k_l2p(BasisDev B, TreeDev T, const int *pm_leaf,
+                                             const int *pm_first, const int *pm_count,
                                              const R *px, const R *py, const R *pz,
                                              const R *pnx, const R *pny, const R *pnz,
                                              const R *L, long long n, R *phi) {
-    const int box = leaf_ids[blockIdx.x];
-    const int lev = T.level[box];
+    const PmItem it(pm_leaf, pm_first, pm_count, T, blockIdx.x);
     const int K = B.K;
     const int lane = threadIdx.x & 63;
     const int kern = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const R cx = R(T.center[3 * box]), cy = R(T.center[3 * box + 1]), cz = R(T.center[3 * box + 2]);
-    const R *Lb = L + ((long long)box * 2 + kern) * K;
-    for (int i = T.ptb[box] + lane; i < T.pte[box]; i += 64) {
+    for (int c0 = 0; c0 < it.tot; c0 += 64) {
+        const int q = c0 + lane;
+        const bool ok = q < it.tot;
+        const int g = it.leaf_of(ok ? q : 0);
+        const int leaf = pm_leaf[it.first + g];
+        const int lev = T.level[leaf];
+        const int i = T.ptb[leaf] + (ok ? q - it.offs[g] : 0);
+        const R cx = R(T.center[3 * leaf]), cy = R(T.center[3 * leaf + 1]);
+        const R cz = R(T.center[3 * leaf + 2]);
+        const R *Lb = L + ((long long)leaf * 2 + kern) * K;
         R p = R(0), dp = R(0);
-        if (lev >= 2) {
-            const R vx = px[i] - cx, vy = py[i] - cy, vz = pz[i] - cz;
-            regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, pnx[i]), Dual<R>(vy, pny[i]),
-                                      Dual<R>(vz, pnz[i]), [&](int k, Dual<R> r) {
-                                          const R l = Lb[k];
-                                          p += l * r.v;
-                                          dp += l * r.d;
-                                      });
+        const R vx = px[i] - cx, vy = py[i] - cy, vz = pz[i] - cz;
+        regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, pnx[i]), Dual<R>(vy, pny[i]),
+                                  Dual<R>(vz, pnz[i]), [&](int k, Dual<R> r) {
+                                      const R l = Lb[k];
+                                      p += l * r.v;
+                                      dp += l * r.d;
+                                  });
+        if (ok) {
+            phi[(2 * kern) * n + i] = lev >= 2 ? p : R(0);
+            phi[(2 * kern + 1) * n + i] = lev >= 2 ? dp : R(0);
         }
-        phi[(2 * kern) * n + i] = p;
-        phi[(2 * kern + 1) * n + i] = dp;
     }
 }
 
@@ -870,8 +905,9 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "p2m", s);
-        k_p2m<R><<<blocks_ok(L.n_leaves, 128), 128, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
-                                                     sf, sh, R(inv_ebar), w.M);
+        k_p2m<R><<<blocks_ok(L.n_pm, 128), 128, 0, s>>>(B, T, L.pm_leaf.p, L.pm_first.p,
+                                                        L.pm_count.p, px, py, pz, pnx, pny, pnz,
+                                                        sf, sh, R(inv_ebar), w.M);
         KCHK();
     }
     TransArgs ta{};
@@ -922,8 +958,9 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "l2p", s);
-        k_l2p<R><<<blocks_ok(L.n_leaves, 128), 128, 0, s>>>(B, T, L.leaf_ids.p, px, py, pz, pnx, pny, pnz,
-                                                     w.Lc, n, w.phi);
+        k_l2p<R><<<blocks_ok(L.n_pm, 128), 128, 0, s>>>(B, T, L.pm_leaf.p, L.pm_first.p,
+                                                        L.pm_count.p, px, py, pz, pnx, pny, pnz,
+                                                        w.Lc, n, w.phi);
         KCHK();
     }
 }

@@ -53,6 +53,10 @@ struct Lists {
     DBuf<int> grp_ptr, grp_tbeg, grp_tend;  // [n_groups+1], [n_groups], [n_groups]
     DBuf<int> ch_grp;                    // [n_chunks] owning group
     long long n_chunks = 0, n_groups = 0, n_rng = 0;
+    // P2M / L2P work: leaves in point order, packed into items of <= 4
+    // consecutive leaves with <= 64 points together (a larger leaf alone)
+    DBuf<int> pm_leaf, pm_first, pm_count;
+    long long n_pm = 0;
     // M2L: V entries grouped by (level, offset class) into chunks of <= 64.
     DBuf<int> v_tgt;                   // [n_v] target box of each V entry
     DBuf<int> m2l_pairs;               // [n_v] V-entry indices grouped by bucket

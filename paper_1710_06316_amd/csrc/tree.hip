@@ -583,6 +583,26 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
         L.ch_grp.upload(cgrp.data(), cgrp.size(), s);
         L.grp_ptr.upload(gptr.data(), gptr.size(), s);
         L.grp_tbeg.upload(gtb.data(), gtb.size(), s); L.grp_tend.upload(gte.data(), gte.size(), s);
+        // P2M / L2P items: leaves sorted by first point, packed
+        std::vector<int> pml(leaf.begin(), leaf.end()), pmf, pmc;
+        std::sort(pml.begin(), pml.end(), [&](int a, int b) { return ptb_h[a] < ptb_h[b]; });
+        for (long long i = 0; i < nl;) {
+            int cnt = 1, pts = pte_h[pml[i]] - ptb_h[pml[i]];
+            if (pts <= 64)
+                while (i + cnt < nl && cnt < 4 &&
+                       pts + (pte_h[pml[i + cnt]] - ptb_h[pml[i + cnt]]) <= 64) {
+                    pts += pte_h[pml[i + cnt]] - ptb_h[pml[i + cnt]];
+                    ++cnt;
+                }
+            pmf.push_back((int)i);
+            pmc.push_back(cnt);
+            i += cnt;
+        }
+        L.n_pm = (long long)pmf.size();
+        L.pm_leaf.alloc(nl); L.pm_first.alloc(L.n_pm); L.pm_count.alloc(L.n_pm);
+        L.pm_leaf.upload(pml.data(), pml.size(), s);
+        L.pm_first.upload(pmf.data(), pmf.size(), s);
+        L.pm_count.upload(pmc.data(), pmc.size(), s);
         HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
     }
     // M2L buckets by (level, class), chunks of <= 64 entries
