@@ -32,6 +32,7 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0     # dense bf16 matrix rate
 PEAK_HBM_GBS = 8000.0
 
 
@@ -40,7 +41,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp32",
+                    help="fp64; fp32 (FP32 FMM, FP64 refinement); bf16 (as fp32 with "
+                         "bf16-split M2L)")
     ap.add_argument("--order", type=int, default=10)
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--workload", choices=["globular", "complex_100k"], default="globular",
@@ -101,7 +104,8 @@ def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host, do_
     """Setup, warm-up, K timed matvecs (device-resident vectors), one solve."""
     n = mol.n_nodes
     stream = torch.cuda.current_stream()
-    prec = A.AFMPB_FP64 if precision == "fp64" else A.AFMPB_FP32_REFINED
+    prec = {"fp64": A.AFMPB_FP64, "fp32": A.AFMPB_FP32_REFINED,
+            "bf16": A.AFMPB_FP32_BF16M2L_REFINED}[precision]
     s = A.Solver(0, stream.cuda_stream)
     t0 = time.perf_counter()
     s.load(mol, order_p=order, leaf_cap=leaf, precision=prec)
@@ -163,7 +167,9 @@ def roofline(r, order, precision, workload="globular"):
     info, prof = r["info"], r["prof"]
     K = (order + 1) ** 2
     peak = PEAK_FP64_VECTOR_TFLOPS if precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
-    peak_mfma = PEAK_FP64_MFMA_TFLOPS if precision == "fp64" else PEAK_FP32_MFMA_TFLOPS
+    # bf16-split M2L counts the same algorithmic flops, against the bf16 peak
+    peak_mfma = {"fp64": PEAK_FP64_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS,
+                 "bf16": PEAK_BF16_MFMA_TFLOPS}[precision]
     work = {
         "p2p": ("alu", info["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR, peak),
         "m2l": ("mfma", info["n_m2l_pairs"] * 4 * K * K, peak_mfma),
@@ -307,7 +313,7 @@ def main():
         "metric": "FMM matvec Munknowns/s", "value": r["value"], "unit": "Munknowns/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16x3+f32+f64"}[a.precision],
         "data": "synthetic",
         "config": {"workload": (("globular_5000: SAW atoms in 25 A" if a.workload == "globular"
                                  else "complex_100k: SAW atoms in 90 A")

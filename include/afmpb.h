@@ -61,9 +61,14 @@ typedef enum {
 
 typedef enum {
     AFMPB_FP64 = 0,              /* every kernel in double precision                   */
-    AFMPB_FP32_REFINED = 1       /* FMM/P2P in single precision with compensated sums,
+    AFMPB_FP32_REFINED = 1,      /* FMM/P2P in single precision with compensated sums,
                                     near correction, Arnoldi, residuals and energy in
                                     double; iterative refinement restores the residual */
+    AFMPB_FP32_BF16M2L_REFINED = 2 /* as AFMPB_FP32_REFINED, with the M2L products taken
+                                    as three bf16 products of split operands (hi*hi +
+                                    hi*lo + lo*hi, FP32 accumulation) on the bf16
+                                    matrix instruction; about 2^-16 relative error per
+                                    product, which the refinement loop absorbs      */
 } afmpb_precision;
 
 /* Problem and solver parameters (the problem statement of Section 2 and the

@@ -32,6 +32,7 @@ AFMPB_E_PENDING = -8
 AFMPB_E_CANCELLED = -9
 AFMPB_FP64 = 0
 AFMPB_FP32_REFINED = 1
+AFMPB_FP32_BF16M2L_REFINED = 2
 
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_MESH", -3: "E_OOM",
                 -4: "E_NOT_CONVERGED", -5: "E_NUMERIC", -6: "E_DEVICE", -7: "E_STATE",

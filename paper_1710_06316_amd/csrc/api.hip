@@ -196,7 +196,8 @@ afmpb_params normalise(const afmpb_params &in) {
     require(p.order_p >= 2 && p.order_p <= MAXP, ST_INVALID, "order_p must be in [2, 20]");
     if (p.leaf_cap == 0) p.leaf_cap = 64;
     require(p.leaf_cap >= 1, ST_INVALID, "leaf_cap must be >= 1");
-    require(p.precision == AFMPB_FP64 || p.precision == AFMPB_FP32_REFINED, ST_INVALID,
+    require(p.precision == AFMPB_FP64 || p.precision == AFMPB_FP32_REFINED ||
+                p.precision == AFMPB_FP32_BF16M2L_REFINED, ST_INVALID,
             "unknown precision");
     require(fin(p.rel_tol) && p.rel_tol >= 0 && fin(p.abs_tol) && p.abs_tol >= 0, ST_INVALID,
             "tolerances must be finite and >= 0");
@@ -262,6 +263,8 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.far.Z = f + 4 * nb * K;
     mp.far.phi = f + 4 * nb * K + std::max(nv, 1ll) * 2 * K;
     mp.far.Mt = mp.far.phi + 4 * n;
+    mp.far.bf16_m2l = (sizeof(R) == sizeof(float) &&
+                       c->prm.precision == AFMPB_FP32_BF16M2L_REFINED) ? 1 : 0;
 }
 
 void check_setup(afmpb_ctx *c);
@@ -327,7 +330,8 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
     c->fmm = Fmm();
     c->p2p64 = DBuf<double>();
     c->p2p_part = DBuf<double>();
-    build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa, c->fmm, s);
+    build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa,
+                        prm.precision == AFMPB_FP32_BF16M2L_REFINED, c->fmm, s);
     mark();   // translation operators
     setup_plan<double>(c, c->mp64, c->w64, c->far64, c->node64.p);
     setup_plan<float>(c, c->mp32, c->w32, c->far32, c->node32.p);

@@ -35,13 +35,20 @@ struct Fmm {
     int KK = 0;
     DBuf<double> Tp, Up, Lp;             // M2L, M2M (A = U), L2L (A = U^T)
     DBuf<float> Tp32, Up32, Lp32;
+    // M2L operators split into bf16 high and low parts, in the operand order
+    // of the 16x16x32 bf16 matrix instruction: per matrix [K/16 row tiles]
+    // [KC = ceil(K/32) k-chunks][64 lanes][8], lane l holding
+    // A[16 rt + l%16][32 kc + 8 (l/16) + e] (zero padded); PMB per matrix
+    int KC = 0;
+    long long PMB = 0;
+    DBuf<unsigned short> Tbh, Tbl;
     BasisDev dev() const {
         return BasisDev{P, K, screened, kappa, norm.p, inv_dfact.p, ginv.p, side.p, rec.p, gser.p};
     }
 };
 
-void build_fmm_operators(const Tree &t, const Lists &L, int P, double kappa, Fmm &F,
-                         hipStream_t s);
+void build_fmm_operators(const Tree &t, const Lists &L, int P, double kappa, bool bf16_m2l,
+                         Fmm &F, hipStream_t s);
 
 // Far-field evaluation for one matvec.  sf = a*f, sh = a*h per node (Morton
 // order).  Writes phi[4][n] = {Phi_L, dPhi_L/dn, Phi_Y, dPhi_Y/dn} at every
@@ -50,6 +57,7 @@ template <typename R>
 struct FarWork {
     R *M, *Lc, *Z, *phi;       // [nbox][2][K], [nbox][2][K], [n_v][2][K], [4][n]
     R *Mt;                     // [8][widest level][2][K] per-octant M2M products
+    int bf16_m2l = 0;          // FP32 path: M2L as three bf16 products (split operands)
 };
 
 template <typename R>

@@ -349,6 +349,8 @@ struct TransArgs {
     long long lb, le;            // boxes of the parent level
     long long ncap;              // mode 1: capacity (boxes) of one octant slice of the scratch
     int n_items;                 // mode 0: number of work items
+    int KC;                      // bf16 M2L: 32-deep k-chunks
+    long long PMB;               // bf16 M2L: elements per packed matrix (each part)
     const int *cb, *nc;          // child begin / count
     const unsigned long long *prefix;
 };
@@ -589,6 +591,178 @@ __global__ void __launch_bounds__(512) k_trans(TransArgs a, const R *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// M2L with bf16-split operands on the 16x16x32 bf16 matrix instruction: each
+// FP32 value v = hi + lo with hi = bf16(v), lo = bf16(v - hi); the product
+// T m is taken as hi(T) hi(m) + hi(T) lo(m) + lo(T) hi(m) (the lo*lo term,
+// about 2^-16 of the product, is dropped), accumulated in FP32.  Operand
+// layout (measured on gfx950): lane l, element e holds A[l%16][8 (l/16) + e]
+// and B[8 (l/16) + e][l%16] of each 32-deep chunk; results as the FP32
+// 16x16x4 instruction.  Same work items, XCD mapping and outputs as the
+// FP32 M2L.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ inline unsigned short bf16_bits(float v) {
+    return __builtin_bit_cast(unsigned short, (__bf16)v);
+}
+__device__ inline float bf16_value(unsigned short b) {
+    return (float)__builtin_bit_cast(__bf16, b);
+}
+__device__ inline f4v mfma_bf16(u16x8_t a, u16x8_t b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                   __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+}
+
+// Row stride (elements) of the bf16 operand rows in LDS: a multiple of 8 (16 B
+// reads) with an odd number of 16-byte units, so that 16 columns read at one
+// k offset hit 16 different 16-byte bank groups.
+__host__ __device__ inline int bf16_stride(int kr) {
+    int u = (kr + 7) / 8;
+    if ((u & 1) == 0) ++u;
+    return 8 * u;
+}
+
+template <int NA>
+__device__ inline void m2l_bf16_rows(const TransArgs &a, const u16x8_t *__restrict__ Ah0,
+                                     const u16x8_t *__restrict__ Al0, const unsigned short *Mh,
+                                     const unsigned short *Ml, int KKp, float *__restrict__ out,
+                                     const int *colbox, int ncols, int kern, int lane, int wave) {
+    const int K = a.K, KC = a.KC, NRT = (K + 15) / 16;
+    const int nwave = (int)(blockDim.x >> 6);
+    const int boff = (lane & 15) * KKp + 8 * (lane >> 4);
+    for (int rt = wave; rt < NRT; rt += nwave) {
+        const u16x8_t *Ah = Ah0 + (long long)rt * KC * 64 + lane;
+        const u16x8_t *Al = Al0 + (long long)rt * KC * 64 + lane;
+        f4v acc[NA];
+#pragma unroll
+        for (int ct = 0; ct < NA; ++ct) acc[ct] = f4v{0, 0, 0, 0};
+        u16x8_t ph = Ah[0], pl = Al[0];
+        for (int kc = 0; kc < KC; ++kc) {
+            const u16x8_t ah = ph, al = pl;
+            ph = Ah[(kc + 1) * 64];        // in bounds: operators carry a tail pad
+            pl = Al[(kc + 1) * 64];
+#pragma unroll
+            for (int ct = 0; ct < NA; ++ct) {
+                const int o = ct * 16 * KKp + boff + 32 * kc;
+                const u16x8_t bh = *reinterpret_cast<const u16x8_t *>(Mh + o);
+                const u16x8_t bl = *reinterpret_cast<const u16x8_t *>(Ml + o);
+                acc[ct] = mfma_bf16(ah, bh, acc[ct]);
+                acc[ct] = mfma_bf16(ah, bl, acc[ct]);
+                acc[ct] = mfma_bf16(al, bh, acc[ct]);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < NA; ++ct) {
+            const int col = ct * 16 + (lane & 15);
+            if (col >= ncols) continue;
+            const long long dst = ((long long)colbox[col] * 2 + kern) * K;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = rt * 16 + drow<float>(lane, r);
+                if (rr < K) out[dst + rr] = acc[ct][r];
+            }
+        }
+    }
+}
+
+// One block per work item (as the FP32 M2L, XCD-contiguous); waves take the
+// operator's row tiles in turn, fragments loaded one chunk ahead.
+template <int CC>
+__global__ void __launch_bounds__(512) k_m2l_bf16(TransArgs a, const u16x8_t *__restrict__ opsh,
+                                                  const u16x8_t *__restrict__ opsl,
+                                                  const float *__restrict__ in,
+                                                  float *__restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem_bf[];
+    __shared__ int colbox[CC];
+    __shared__ int srcbox[CC];
+    const int K = a.K, KR = 32 * a.KC, KKp = bf16_stride(KR);
+    unsigned short *Mh = reinterpret_cast<unsigned short *>(smem_bf);    // [CC][KKp]
+    unsigned short *Ml = Mh + CC * KKp;
+    const int kern = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int per = (int)(gridDim.x >> 3);
+    const int w = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+    if (w >= a.n_items) return;
+    const int off = blockIdx.z * CC;
+    const int ncols = min(CC, a.item_count[w] - off);
+    if (ncols <= 0) return;
+    const int beg = a.item_begin[w] + off;
+    if (tid < CC) {
+        const int q = tid < ncols ? a.pairs[beg + tid] : -1;
+        colbox[tid] = q;
+        srcbox[tid] = q >= 0 ? a.vidx[q] : -1;
+    }
+    __syncthreads();
+    const int nact = (ncols + 15) / 16;
+    {
+        const int nwave = (int)(blockDim.x >> 6);
+        for (int c = wave; c < nact * 16; c += nwave) {
+            const int src = c < ncols ? srcbox[c] : -1;
+            const float *col = in + ((long long)(src < 0 ? 0 : src) * 2 + kern) * K;
+            for (int k = lane; k < KR; k += 64) {
+                const float v = (src >= 0 && k < K) ? col[k] : 0.0f;
+                const unsigned short h = bf16_bits(v);
+                Mh[c * KKp + k] = h;
+                Ml[c * KKp + k] = bf16_bits(v - bf16_value(h));
+            }
+        }
+    }
+    __syncthreads();
+    const long long mat = (long long)kern * a.nkey + a.item_key[w];
+    const u16x8_t *Ah = opsh + mat * (a.PMB / 8), *Al = opsl + mat * (a.PMB / 8);
+    if constexpr (CC >= 64) {
+        if (nact == 4) { m2l_bf16_rows<4>(a, Ah, Al, Mh, Ml, KKp, out, colbox, ncols, kern, lane, wave); return; }
+        if (nact == 3) { m2l_bf16_rows<3>(a, Ah, Al, Mh, Ml, KKp, out, colbox, ncols, kern, lane, wave); return; }
+    }
+    if constexpr (CC >= 32) {
+        if (nact == 2) { m2l_bf16_rows<2>(a, Ah, Al, Mh, Ml, KKp, out, colbox, ncols, kern, lane, wave); return; }
+    }
+    m2l_bf16_rows<1>(a, Ah, Al, Mh, Ml, KKp, out, colbox, ncols, kern, lane, wave);
+}
+
+void launch_m2l_bf16(const TransArgs &ta, unsigned gx, const u16x8_t *opsh, const u16x8_t *opsl,
+                     const float *in, float *out, hipStream_t s) {
+    const int nrt = (ta.K + 15) / 16, passes = (nrt + 7) / 8;
+    const unsigned nthr = 64u * (unsigned)((nrt + passes - 1) / passes);
+    (void)blocks_ok(gx, nthr);
+    const size_t kkp = (size_t)bf16_stride(32 * ta.KC);
+    auto shmem = [&](int cc) { return 2 * kkp * cc * sizeof(unsigned short); };
+    const size_t lim = 60 * 1024;
+    if (shmem(64) <= lim) {
+        k_m2l_bf16<64><<<dim3(gx, 2, 1), nthr, shmem(64), s>>>(ta, opsh, opsl, in, out);
+    } else if (shmem(32) <= lim) {
+        k_m2l_bf16<32><<<dim3(gx, 2, 2), nthr, shmem(32), s>>>(ta, opsh, opsl, in, out);
+    } else {
+        require(shmem(16) <= lim, ST_INVALID, "expansion order too large for the bf16 M2L");
+        k_m2l_bf16<16><<<dim3(gx, 2, 4), nthr, shmem(16), s>>>(ta, opsh, opsl, in, out);
+    }
+    KCHK();
+}
+
+// packed bf16 parts of the M2L operators (from the FP64 operators)
+__global__ void k_pack_bf16(const double *__restrict__ src, long long nmat, int K, int KC,
+                            int NRT, unsigned short *__restrict__ hi,
+                            unsigned short *__restrict__ lo) {
+    const long long PMB = (long long)NRT * KC * 64 * 8;
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nmat * PMB) return;
+    const long long m = id / PMB;
+    long long r = id % PMB;
+    const int e = (int)(r % 8);
+    r /= 8;
+    const int l = (int)(r % 64);
+    r /= 64;
+    const int kc = (int)(r % KC), rt = (int)(r / KC);
+    const int row = rt * 16 + (l & 15), k = kc * 32 + 8 * (l >> 4) + e;
+    const double v = (row < K && k < K) ? src[m * K * K + (long long)row * K + k] : 0.0;
+    const unsigned short h = bf16_bits((float)v);
+    hi[id] = h;
+    lo[id] = bf16_bits((float)(v - (double)bf16_value(h)));
+}
+
 // M of the non-leaf boxes of one level = sum over the 8 octant products.
 template <typename R>
 __global__ void k_m2m_sum(int K, long long lb, long long le, long long ncap,
@@ -736,8 +910,8 @@ __global__ void k_fill_zero(R *a, long long n) {
 
 }  // namespace
 
-void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, Fmm &F,
-                         hipStream_t s) {
+void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, bool bf16_m2l,
+                         Fmm &F, hipStream_t s) {
     require(P >= 2 && P <= MAXP, ST_INVALID, "expansion order must be in [2, 20]");
     require(t.nlev <= 64, ST_INVALID, "too many tree levels");
     F.P = P;
@@ -869,6 +1043,19 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, Fm
     pack(F.T, 2 * std::max(F.nkey, 1ll), 0, F.Tp, F.Tp32);
     pack(F.Ut, 2ll * nlev * 8, 1, F.Up, F.Up32);
     pack(F.Ut, 2ll * nlev * 8, 0, F.Lp, F.Lp32);
+    if (bf16_m2l) {
+        F.KC = (K + 31) / 32;
+        F.PMB = (long long)NRT * F.KC * 64 * 8;
+        const long long nmat = 2 * std::max(F.nkey, 1ll);
+        const size_t padb = 64 * 8;   // one prefetched chunk past the last matrix
+        F.Tbh.alloc((size_t)nmat * F.PMB + padb);
+        F.Tbl.alloc((size_t)nmat * F.PMB + padb);
+        HIPCHK(hipMemsetAsync(F.Tbh.p, 0, ((size_t)nmat * F.PMB + padb) * 2, s));
+        HIPCHK(hipMemsetAsync(F.Tbl.p, 0, ((size_t)nmat * F.PMB + padb) * 2, s));
+        k_pack_bf16<<<grid_for(nmat * F.PMB, 256), 256, 0, s>>>(F.T.p, nmat, K, F.KC, NRT,
+                                                               F.Tbh.p, F.Tbl.p);
+        KCHK();
+    }
     HIPCHK(hipStreamSynchronize(s));
     F.T.release();
     F.Ut.release();
@@ -941,7 +1128,18 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
         ta.n_items = (int)L.n_m2l_items;
         // grid padded to a multiple of 8 for the XCD-contiguous item mapping
         const unsigned gx = (unsigned)((L.n_m2l_items + 7) / 8 * 8);
-        launch_trans<R, 0>(ta, dim3(gx, 2), Ops<R>::T(F), w.M, w.Z, 0, s);
+        if constexpr (sizeof(R) == sizeof(float)) {
+            if (w.bf16_m2l) {
+                ta.KC = F.KC;
+                ta.PMB = F.PMB;
+                launch_m2l_bf16(ta, gx, reinterpret_cast<const u16x8_t *>(F.Tbh.p),
+                                reinterpret_cast<const u16x8_t *>(F.Tbl.p), w.M, w.Z, s);
+            } else {
+                launch_trans<R, 0>(ta, dim3(gx, 2), Ops<R>::T(F), w.M, w.Z, 0, s);
+            }
+        } else {
+            launch_trans<R, 0>(ta, dim3(gx, 2), Ops<R>::T(F), w.M, w.Z, 0, s);
+        }
     }
     {
         ProfScope ps(prof, "m2l_reduce", s);

@@ -640,7 +640,7 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
         L.m2l_item_key.upload(ik.data(), ik.size(), s);
         L.m2l_item_begin.upload(ib.data(), ib.size(), s);
         L.m2l_item_count.upload(ic.data(), ic.size(), s);
-        HIPCHK(hipStreamSynchronize(s));   // ik/ib/ic must outlive the copies
+        HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
     }
     HIPCHK(hipStreamSynchronize(s));
 }

@@ -305,3 +305,41 @@ def test_complex_energy_mixed_vs_fp64():
         assert info.converged
         out[p] = E
     assert abs(out[10] - out[14]) <= 1e-4 * abs(out[14])
+
+
+# ------------------------- bf16-split M2L -----------------------------------
+
+def test_bf16_m2l_matvec_and_solve():
+    """Mixed precision with bf16-split M2L: the matvec stays within the FMM
+    error plus ~2^-16 of the far field, and the refined solve reaches the
+    oracle energy (1e-4)."""
+    import paper_1710_06316_amd as A
+    mol = MOLS["born4"]()
+    ref = O.solve(mol)
+    x = np.random.default_rng(3).normal(size=2 * mol.n_nodes)
+    y_ref = ref.op.matvec(x)
+    errs = {}
+    for prec in (A.AFMPB_FP32_REFINED, A.AFMPB_FP32_BF16M2L_REFINED):
+        s = _solver(mol, order_p=10, precision=prec)
+        errs[prec] = _rel(s.matvec(x), y_ref)
+        f, h, E, info, _ = s.solve()
+        s.close()
+        _say(f"born4 precision={prec} matvec err {errs[prec]:.3e} E={E:.6f} oracle={ref.energy:.6f} "
+             f"iters={info.iterations} refine={info.refinement_steps}")
+        assert info.converged
+        assert abs(E - ref.energy) <= 1e-4 * abs(ref.energy)
+    assert errs[A.AFMPB_FP32_BF16M2L_REFINED] < 5e-5
+
+
+def test_bf16_m2l_complex_rows():
+    """~1M nodes, p = 14: bf16-split M2L on 96 oracle rows."""
+    import paper_1710_06316_amd as A
+    c = _complex()
+    mol, rows, x, ref = c["mol"], c["rows"], c["x"], c["ref"]
+    n = mol.n_nodes
+    s = _solver(mol, order_p=14, precision=A.AFMPB_FP32_BF16M2L_REFINED)
+    y = s.matvec(x)
+    s.close()
+    err = np.linalg.norm(np.r_[y[rows], y[n + rows]] - ref) / np.linalg.norm(ref)
+    _say(f"complex p=14 bf16 rows err {err:.3e}")
+    assert err < 5e-5
