@@ -217,7 +217,9 @@ def serve_run(A, mols, qps, precision, order, leaf, budget_gb, max_active, setup
     lat = np.array([r.ms_done for r in res])
     ok = [r.status == 0 for r in res]
     first = float(arrive[0])
-    return {"qps_offered": qps, "requests": n, "completed": int(sum(ok)),
+    fails = [{"request": i, "status": r.status, "message": r.message.decode(errors="replace")}
+             for i, r in enumerate(res) if r.status != 0]
+    return {"qps_offered": qps, "requests": n, "completed": int(sum(ok)), "failures": fails[:5],
             "seconds": t_end - first, "solves_per_s": n / (t_end - first),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_setup_ms": float(np.mean([r.ms_ready - r.ms_admit for r in res])),
@@ -244,21 +246,32 @@ def serving(A, torch, n_req, check, budget_gb, max_active, setup_threads):
            "node_mix": {str(L): sum(1 for m in mols if m.meta["level"] == L) for L in (3, 4, 5, 6)},
            "reference": f"FP64 p=14 GPU solve on {len(sample)} sampled requests",
            "budget_gb": budget_gb, "max_active": max_active, "setup_threads": setup_threads}
-    for name, prec in (("fp32_refined", A.AFMPB_FP32_REFINED), ("fp64", A.AFMPB_FP64)):
+    from paper_1710_06316_amd import autotune
+    table = autotune.load_table()
+    forms = [("fp32_refined", A.AFMPB_FP32_REFINED, 8, 64, None),
+             ("fp64", A.AFMPB_FP64, 8, 64, None)]
+    if table:
+        # the same stream with leaf capacity and order from the tuning table
+        forms.append(("fp32_refined_tuned", A.AFMPB_FP32_REFINED, 0, 0, table))
+    for name, prec, order, leaf, tun in forms:
         runs = {}
-        sat = serve_run(A, mols, None, prec, 8, 64, budget_gb, max_active, setup_threads)
+        sat = serve_run(A, mols, None, prec, order, leaf, budget_gb, max_active, setup_threads,
+                        tun)
         runs["saturated"] = sat
         for f in (0.5, 0.9):
-            runs[f"qps_{f}"] = serve_run(A, mols, f * sat["solves_per_s"], prec, 8, 64,
-                                         budget_gb, max_active, setup_threads)
+            runs[f"qps_{f}"] = serve_run(A, mols, f * sat["solves_per_s"], prec, order, leaf,
+                                         budget_gb, max_active, setup_threads, tun)
         errs = [abs(sat["energies"][i] - ref[i]) / abs(ref[i]) for i in sample]
         for r in runs.values():
             e = r.pop("energies")
             r["within_1e-4_sampled"] = int(sum(abs(e[i] - ref[i]) <= 1e-4 * abs(ref[i])
                                                for i in sample))
             r.pop("ok")
-        out[name] = {"order_p": 8, "leaf_cap": 64, "max_rel_energy_err_sampled": max(errs),
-                     **runs}
+        out[name] = {"order_p": order if order else "tuned",
+                     "leaf_cap": leaf if leaf else "tuned",
+                     "max_rel_energy_err_sampled": max(errs), **runs}
+        if tun:
+            out[name]["tuning_table"] = [list(t) for t in tun]
     return out
 
 
@@ -285,11 +298,8 @@ def serving_child(a):
 def main():
     a = parse()
     if a.serve_only:
-        import torch
-
         import paper_1710_06316_amd as A
-        torch.cuda.set_device(0)
-        print(json.dumps(serving(A, torch, a.serve_requests, a.serve_check, a.serve_budget_gb,
+        print(json.dumps(serving(A, None, a.serve_requests, a.serve_check, a.serve_budget_gb,
                                  a.serve_max_active, a.serve_setup_threads)), flush=True)
         return
     if a.gpus != 1:

@@ -635,6 +635,8 @@ void afmpb_server::step_loop() {
             std::string msg;
             try {
                 if (q.cancelled) throw Error(AFMPB_E_CANCELLED, "cancelled");
+                // no HIP call of this thread overlaps an open graph capture
+                std::shared_lock<std::shared_mutex> cap(g_capture_mu);
                 if (jb.pending) {
                     hipError_t e = hipEventQuery(jb.ev);
                     if (e == hipSuccess) {
