@@ -92,38 +92,49 @@ void validate_mesh(long long n, const double *V, long long m, const int *T) {
     require(n >= 4 && m >= 4, ST_MESH, "mesh needs at least 4 nodes and 4 triangles");
     for (long long i = 0; i < 3 * n; ++i)
         require(std::isfinite(V[i]), ST_INVALID, "non-finite node coordinate");
-    std::vector<char> used(n, 0);
+    std::vector<int> deg(n + 1, 0);
     for (long long i = 0; i < 3 * m; ++i) {
         require(T[i] >= 0 && T[i] < n, ST_MESH, "triangle index out of range");
-        used[T[i]] = 1;
+        ++deg[T[i]];
     }
-    for (long long i = 0; i < n; ++i) require(used[i], ST_MESH, "node not used by any triangle");
-    std::vector<long long> ord(n);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::sort(ord.begin(), ord.end(), [&](long long a, long long b) {
-        for (int d = 0; d < 3; ++d)
-            if (V[3 * a + d] != V[3 * b + d]) return V[3 * a + d] < V[3 * b + d];
-        return a < b;
+    for (long long i = 0; i < n; ++i) require(deg[i] > 0, ST_MESH, "node not used by any triangle");
+    // duplicate vertices: sort (x, y, z, index) records
+    struct Pt { double x, y, z; long long i; };
+    std::vector<Pt> pts(n);
+    for (long long i = 0; i < n; ++i) pts[i] = Pt{V[3 * i], V[3 * i + 1], V[3 * i + 2], i};
+    std::sort(pts.begin(), pts.end(), [](const Pt &a, const Pt &b) {
+        if (a.x != b.x) return a.x < b.x;
+        if (a.y != b.y) return a.y < b.y;
+        if (a.z != b.z) return a.z < b.z;
+        return a.i < b.i;
     });
-    for (long long i = 1; i < n; ++i) {
-        const double *a = V + 3 * ord[i - 1], *b = V + 3 * ord[i];
-        require(!(a[0] == b[0] && a[1] == b[1] && a[2] == b[2]), ST_MESH, "duplicate vertex");
-    }
-    std::vector<unsigned long long> e(3 * m);
+    for (long long i = 1; i < n; ++i)
+        require(!(pts[i].x == pts[i - 1].x && pts[i].y == pts[i - 1].y && pts[i].z == pts[i - 1].z),
+                ST_MESH, "duplicate vertex");
+    // directed edges a -> b of every triangle as rows per start node; each
+    // directed edge must appear once, and its reverse once (closed, manifold,
+    // consistently oriented)
+    std::vector<long long> ptr(n + 1, 0);
+    for (long long v = 0; v < n; ++v) ptr[v + 1] = ptr[v] + deg[v];
+    std::vector<int> nxt(3 * m);
+    std::vector<long long> fill(ptr.begin(), ptr.end() - 1);
     for (long long k = 0; k < m; ++k)
         for (int j = 0; j < 3; ++j) {
-            unsigned long long a = (unsigned)T[3 * k + j], b = (unsigned)T[3 * k + (j + 1) % 3];
+            const int a = T[3 * k + j], b = T[3 * k + (j + 1) % 3];
             require(a != b, ST_MESH, "degenerate triangle (repeated node)");
-            e[3 * k + j] = a * (unsigned long long)n + b;
+            nxt[fill[a]++] = b;
         }
-    std::sort(e.begin(), e.end());
-    for (size_t i = 1; i < e.size(); ++i)
-        require(e[i] != e[i - 1], ST_MESH, "edge used twice in one direction (non-manifold)");
-    for (auto x : e) {
-        unsigned long long a = x / n, b = x % n;
-        require(std::binary_search(e.begin(), e.end(), b * (unsigned long long)n + a), ST_MESH,
-                "open surface or inconsistent orientation");
+    for (long long v = 0; v < n; ++v) {
+        std::sort(nxt.begin() + ptr[v], nxt.begin() + ptr[v + 1]);
+        for (long long e = ptr[v] + 1; e < ptr[v + 1]; ++e)
+            require(nxt[e] != nxt[e - 1], ST_MESH, "edge used twice in one direction (non-manifold)");
     }
+    for (long long v = 0; v < n; ++v)
+        for (long long e = ptr[v]; e < ptr[v + 1]; ++e) {
+            const int b = nxt[e];
+            require(std::binary_search(nxt.begin() + ptr[b], nxt.begin() + ptr[b + 1], (int)v),
+                    ST_MESH, "open surface or inconsistent orientation");
+        }
     double asum = 0.0, vol = 0.0;
     std::vector<double> ar(m);
     for (long long k = 0; k < m; ++k) {
