@@ -117,10 +117,6 @@ __global__ void k_count_to_i64(const int *c, long long *o, long long n) {
 
 // ----------------------------- quadrature ----------------------------------
 
-struct QuadRules {
-    double x8[8], w8[8], x16[16], w16[16];
-};
-
 struct Ctx {
     const double *V;           // caller-order coordinates [n][3]
     const int *T;              // [m][3]
@@ -129,112 +125,49 @@ struct Ctx {
     const int *perm;           // Morton position -> caller index
     NodeSoA nd;                // Morton order
     double kappa, inv_ebar;
-    QuadRules q;
+    // (u, v, weight product) of the collapsed Gauss rules: 64 points of the
+    // 8 x 8 rule, then 256 points of the 16 x 16 rule
+    const double *rule;
 };
-
-struct Acc {
-    double a, b, c, d;
-};
-
-__device__ inline void child_of(const double *P0, const double *P1, const double *P2, int c,
-                                double *Q0, double *Q1, double *Q2) {
-    double m01[3], m12[3], m20[3];
-    for (int d = 0; d < 3; ++d) {
-        m01[d] = (P0[d] + P1[d]) * 0.5;
-        m12[d] = (P1[d] + P2[d]) * 0.5;
-        m20[d] = (P2[d] + P0[d]) * 0.5;
-    }
-    const double *a, *b, *cc;
-    switch (c) {
-        case 0: a = P0; b = m01; cc = m20; break;
-        case 1: a = m01; b = P1; cc = m12; break;
-        case 2: a = m20; b = m12; cc = P2; break;
-        default: a = m12; b = m20; cc = m01; break;
-    }
-    for (int d = 0; d < 3; ++d) { Q0[d] = a[d]; Q1[d] = b[d]; Q2[d] = cc[d]; }
-}
 
 constexpr int MAX_DEPTH = 10;
 
-// One wavefront per near entry (t in N(p)): the wave walks t's pieces and
-// their subdivision tree together (the walk is uniform across lanes), and
-// lane l evaluates point (l / 8, l % 8) of the 8 x 8 collapsed rule of every
-// leaf piece (self patch: points l, l+64, l+128, l+192 of the 16 x 16 rule).
-// Lane sums are added by a fixed butterfly at the end.
-struct LanePts {
-    double u8, v8, g8;          // node and weight product of this lane's 8 x 8 point
-    double u16[4], v16[4], g16[4];
-};
-
-__device__ inline void piece_lane(const Ctx &C, double x, double y0, double z, double n0x,
-                                  double n0y, double n0z, const double *P0, const double *P1,
-                                  const double *P2, double fnx, double fny, double fnz,
-                                  int npts, const double *uu, const double *vv, const double *gg,
-                                  bool self, Acc &acc) {
-    double e1[3] = {P1[0] - P0[0], P1[1] - P0[1], P1[2] - P0[2]};
-    double e2[3] = {P2[0] - P0[0], P2[1] - P0[1], P2[2] - P0[2]};
-    double cx = e1[1] * e2[2] - e1[2] * e2[1];
-    double cy = e1[2] * e2[0] - e1[0] * e2[2];
-    double cz = e1[0] * e2[1] - e1[1] * e2[0];
-    double area = 0.5 * sqrt((cx * cx + cy * cy) + cz * cz);
-    for (int s = 0; s < npts; ++s) {
-        const double u = uu[s], v = vv[s];
-        const double w = 2.0 * area * u * gg[s];
-        double pyy[3];
-        for (int d = 0; d < 3; ++d)
-            pyy[d] = P0[d] + u * (P1[d] - P0[d]) + u * v * (P2[d] - P1[d]);
-        const double rx = x - pyy[0], ry = y0 - pyy[1], rz = z - pyy[2];
-        if (self) {
-            Abcd<double> k = abcd_point(rx, ry, rz, fnx, fny, fnz, fnx, fny, fnz, C.kappa,
-                                        C.inv_ebar);
-            acc.a += w * k.A;
-            acc.d += w * k.D;
-        } else {
-            Abcd<double> k = abcd_point(rx, ry, rz, n0x, n0y, n0z, fnx, fny, fnz, C.kappa,
-                                        C.inv_ebar);
-            acc.a += w * k.A;
-            acc.b += w * k.B;
-            acc.c += w * k.C;
-            acc.d += w * k.D;
-        }
+// Vertices of piece `half` of incident triangle k of node ot: (t, m_tu, c_T)
+// or (t, c_T, m_tw), and the facet normal.
+__device__ inline void piece_root(const Ctx &C, long long ot, long long k, int half, double *R0,
+                                  double *R1, double *R2, double &fnx, double &fny, double &fnz) {
+    const int *tv = C.T + 3 * k;
+    const int i0 = tv[0], i1 = tv[1], i2 = tv[2];
+    const int jj = (i0 == ot) ? 0 : ((i1 == ot) ? 1 : 2);
+    const int iu = jj == 0 ? i1 : (jj == 1 ? i2 : i0);
+    const int iw = jj == 0 ? i2 : (jj == 1 ? i0 : i1);
+    const double *vt = C.V + 3 * ot, *pu = C.V + 3ll * iu, *pw = C.V + 3ll * iw;
+    const double *a = C.V + 3ll * i0, *b = C.V + 3ll * i1, *c = C.V + 3ll * i2;
+    for (int d = 0; d < 3; ++d) {
+        const double cen = ((a[d] + b[d]) + c[d]) / 3.0;
+        R0[d] = vt[d];
+        R1[d] = half ? cen : (vt[d] + pu[d]) * 0.5;
+        R2[d] = half ? (vt[d] + pw[d]) * 0.5 : cen;
     }
+    fnx = C.tri_n[3 * k];
+    fny = C.tri_n[3 * k + 1];
+    fnz = C.tri_n[3 * k + 2];
 }
 
-// Adaptive subdivision of one piece, depth first, with the path kept as
-// base-4 digits and the current sub-triangle rebuilt from the root; a piece
-// is split while the target is closer than two diameters to its centroid
-// (at most MAX_DEPTH levels), and every leaf gets the 8 x 8 collapsed rule
-// y = P0 + u (P1 - P0) + u v (P2 - P1), dS = 2 |tau| u du dv (collapse at P0).
-__device__ void adapt_lane(const Ctx &C, double x, double y, double z, double n0x, double n0y,
-                           double n0z, const double *R0, const double *R1, const double *R2,
-                           double fnx, double fny, double fnz, const LanePts &L, Acc &acc) {
-    int digit[MAX_DEPTH + 1];
-    int depth = 0;
-    while (true) {
-        double P0[3], P1[3], P2[3];
-        for (int d = 0; d < 3; ++d) { P0[d] = R0[d]; P1[d] = R1[d]; P2[d] = R2[d]; }
-        for (int k = 0; k < depth; ++k) {
-            double Q0[3], Q1[3], Q2[3];
-            child_of(P0, P1, P2, digit[k], Q0, Q1, Q2);
-            for (int d = 0; d < 3; ++d) { P0[d] = Q0[d]; P1[d] = Q1[d]; P2[d] = Q2[d]; }
+// Sub-triangle c of (P0, P1, P2) under midpoint subdivision, in place.
+__device__ inline void to_child(double *P0, double *P1, double *P2, int c) {
+    for (int d = 0; d < 3; ++d) {
+        const double m01 = (P0[d] + P1[d]) * 0.5;
+        const double m12 = (P1[d] + P2[d]) * 0.5;
+        const double m20 = (P2[d] + P0[d]) * 0.5;
+        double a, b, cc;
+        switch (c) {
+            case 0: a = P0[d]; b = m01; cc = m20; break;
+            case 1: a = m01; b = P1[d]; cc = m12; break;
+            case 2: a = m20; b = m12; cc = P2[d]; break;
+            default: a = m12; b = m20; cc = m01; break;
         }
-        double cx = ((P0[0] + P1[0]) + P2[0]) / 3.0;
-        double cy = ((P0[1] + P1[1]) + P2[1]) / 3.0;
-        double cz = ((P0[2] + P1[2]) + P2[2]) / 3.0;
-        double dm = dist2(P0[0], P0[1], P0[2], P1[0], P1[1], P1[2]);
-        double d12 = dist2(P1[0], P1[1], P1[2], P2[0], P2[1], P2[2]);
-        double d20 = dist2(P2[0], P2[1], P2[2], P0[0], P0[1], P0[2]);
-        if (d12 > dm) dm = d12;
-        if (d20 > dm) dm = d20;
-        if (depth < MAX_DEPTH && dist2(x, y, z, cx, cy, cz) < 4.0 * dm) {
-            digit[depth++] = 0;
-            continue;
-        }
-        piece_lane(C, x, y, z, n0x, n0y, n0z, P0, P1, P2, fnx, fny, fnz, 1, &L.u8, &L.v8, &L.g8,
-                   false, acc);
-        while (depth > 0 && digit[depth - 1] == 3) --depth;
-        if (depth == 0) break;
-        ++digit[depth - 1];
+        P0[d] = a; P1[d] = b; P2[d] = cc;
     }
 }
 
@@ -244,84 +177,133 @@ __device__ inline double wave_add(double v) {
     return v;
 }
 
-__global__ void __launch_bounds__(256) k_near_coeffs(Ctx C, long long n, long long nnz,
-                                                     const long long *__restrict__ ptr,
-                                                     const int *__restrict__ col,
-                                                     double *__restrict__ delta) {
+// One wavefront per near entry (t in N(p)).  The wave walks t's pieces and
+// their subdivision trees in a fixed order (the walk is uniform across
+// lanes); every step of the loop evaluates one quadrature point per lane, so
+// the point kernel is inlined once.  A piece is split while the target is
+// closer than two diameters to its centroid (at most MAX_DEPTH levels; the
+// path is kept as base-4 digits in one integer and the piece rebuilt from
+// its root); every leaf piece gets the 8 x 8 collapsed rule
+// y = P0 + u (P1 - P0) + u v (P2 - P1), dS = 2 |tau| u du dv (lane l: point
+// l).  The self patch takes the 16 x 16 rule unsplit, lane l evaluating
+// points l, l + 64, l + 128, l + 192 in four steps.  Lane sums are added by a
+// fixed butterfly at the end.
+// Register budget: 4 waves per SIMD (a few spills of loop-invariant values
+// cost less than the latency hiding they buy for the FP64 point kernel).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_near_coeffs(Ctx C, long long n, long long nnz, const long long *__restrict__ ptr,
+              const int *__restrict__ col, double *__restrict__ delta) {
     const int lane = threadIdx.x & 63;
-    LanePts L;
-    {
-        const int i = lane >> 3, j = lane & 7;
-        L.u8 = C.q.x8[i];
-        L.v8 = C.q.x8[j];
-        L.g8 = C.q.w8[i] * C.q.w8[j];
-        for (int s = 0; s < 4; ++s) {
-            const int idx = lane + 64 * s, i2 = idx >> 4, j2 = idx & 15;
-            L.u16[s] = C.q.x16[i2];
-            L.v16[s] = C.q.x16[j2];
-            L.g16[s] = C.q.w16[i2] * C.q.w16[j2];
-        }
-    }
-    // grid-stride over the entries (wave-uniform), so that the launch stays
-    // far below the 2^32 work-item limit of one dispatch
-    for (long long e = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); e < nnz;
+    const double u8 = C.rule[3 * lane], v8 = C.rule[3 * lane + 1], g8 = C.rule[3 * lane + 2];
+    // grid-stride over the entries, so that the launch stays far below the
+    // 2^32 work-item limit of one dispatch; the entry index is made visibly
+    // wave-uniform so that the walk's addresses and loads stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (long long e = (long long)blockIdx.x * 4 + wave; e < nnz;
          e += (long long)gridDim.x * 4) {
-    long long lo = 0, hi = n;              // row p: ptr[p] <= e < ptr[p+1]
-    while (hi - lo > 1) {
-        long long mid = (lo + hi) >> 1;
-        if (ptr[mid] <= e) lo = mid; else hi = mid;
-    }
-    const long long p = lo;
-    const double x = C.nd.x[p], y = C.nd.y[p], z = C.nd.z[p];
-    const double n0x = C.nd.nx[p], n0y = C.nd.ny[p], n0z = C.nd.nz[p];
-    const int t = col[e];
-    const long long ot = C.perm[t];
-    const double *vt = C.V + 3 * ot;
-    Acc acc{0, 0, 0, 0};
-    for (int q = C.inc_ptr[ot]; q < C.inc_ptr[ot + 1]; ++q) {
-        long long k = C.inc_tri[q];
-        const int *tv = C.T + 3 * k;
-        int jj = (tv[0] == ot) ? 0 : ((tv[1] == ot) ? 1 : 2);
-        const double *pu = C.V + 3ll * tv[(jj + 1) % 3];
-        const double *pw = C.V + 3ll * tv[(jj + 2) % 3];
-        const double *a = C.V + 3ll * tv[0], *b = C.V + 3ll * tv[1], *c = C.V + 3ll * tv[2];
-        double cen[3], mu[3], mw[3];
-        for (int d = 0; d < 3; ++d) {
-            cen[d] = ((a[d] + b[d]) + c[d]) / 3.0;
-            mu[d] = (vt[d] + pu[d]) * 0.5;
-            mw[d] = (vt[d] + pw[d]) * 0.5;
+        long long lo = 0, hi = n;              // row p: ptr[p] <= e < ptr[p+1]
+        while (hi - lo > 1) {
+            long long mid = (lo + hi) >> 1;
+            if (ptr[mid] <= e) lo = mid; else hi = mid;
         }
-        double fnx = C.tri_n[3 * k], fny = C.tri_n[3 * k + 1], fnz = C.tri_n[3 * k + 2];
-        if (t == p) {
-            piece_lane(C, x, y, z, n0x, n0y, n0z, vt, mu, cen, fnx, fny, fnz, 4, L.u16, L.v16,
-                       L.g16, true, acc);
-            piece_lane(C, x, y, z, n0x, n0y, n0z, vt, cen, mw, fnx, fny, fnz, 4, L.u16, L.v16,
-                       L.g16, true, acc);
-        } else {
-            adapt_lane(C, x, y, z, n0x, n0y, n0z, vt, mu, cen, fnx, fny, fnz, L, acc);
-            adapt_lane(C, x, y, z, n0x, n0y, n0z, vt, cen, mw, fnx, fny, fnz, L, acc);
+        const long long p = lo;
+        const double x = C.nd.x[p], y = C.nd.y[p], z = C.nd.z[p];
+        const int t = col[e];
+        const bool self = t == p;
+        double n0x = C.nd.nx[p], n0y = C.nd.ny[p], n0z = C.nd.nz[p];
+        const long long ot = C.perm[t];
+        double acc_a = 0, acc_b = 0, acc_c = 0, acc_d = 0;
+        const int q_end = C.inc_ptr[ot + 1];
+        int q = C.inc_ptr[ot], half = 0;
+        double R0[3], R1[3], R2[3], fnx = 0, fny = 0, fnz = 0;
+        if (q < q_end) piece_root(C, ot, C.inc_tri[q], 0, R0, R1, R2, fnx, fny, fnz);
+        unsigned path = 0;                     // digit k in bits 2k, 2k+1
+        int depth = 0, sub = 0;                // sub: self-rule step 0..3
+        while (q < q_end) {
+            double P0[3], P1[3], P2[3];
+            for (int d = 0; d < 3; ++d) { P0[d] = R0[d]; P1[d] = R1[d]; P2[d] = R2[d]; }
+            for (int k = 0; k < depth; ++k) to_child(P0, P1, P2, (path >> (2 * k)) & 3);
+            if (!self) {
+                while (depth < MAX_DEPTH) {    // descend through child 0 while too close
+                    const double cx = ((P0[0] + P1[0]) + P2[0]) / 3.0;
+                    const double cy = ((P0[1] + P1[1]) + P2[1]) / 3.0;
+                    const double cz = ((P0[2] + P1[2]) + P2[2]) / 3.0;
+                    double dm = dist2(P0[0], P0[1], P0[2], P1[0], P1[1], P1[2]);
+                    const double d12 = dist2(P1[0], P1[1], P1[2], P2[0], P2[1], P2[2]);
+                    const double d20 = dist2(P2[0], P2[1], P2[2], P0[0], P0[1], P0[2]);
+                    if (d12 > dm) dm = d12;
+                    if (d20 > dm) dm = d20;
+                    if (!(dist2(x, y, z, cx, cy, cz) < 4.0 * dm)) break;
+                    to_child(P0, P1, P2, 0);   // digit 0 adds no bits to the path
+                    ++depth;
+                }
+            }
+            double u = u8, v = v8, g = g8;
+            if (self) {
+                const double *r = C.rule + 3 * (64 + lane + 64 * sub);
+                u = r[0]; v = r[1]; g = r[2];
+                n0x = fnx; n0y = fny; n0z = fnz;
+            }
+            {
+                const double e1x = P1[0] - P0[0], e1y = P1[1] - P0[1], e1z = P1[2] - P0[2];
+                const double e2x = P2[0] - P0[0], e2y = P2[1] - P0[1], e2z = P2[2] - P0[2];
+                const double cx = e1y * e2z - e1z * e2y;
+                const double cy = e1z * e2x - e1x * e2z;
+                const double cz = e1x * e2y - e1y * e2x;
+                const double area = 0.5 * sqrt((cx * cx + cy * cy) + cz * cz);
+                const double w = 2.0 * area * u * g;
+                const double yx = P0[0] + u * (P1[0] - P0[0]) + u * v * (P2[0] - P1[0]);
+                const double yy = P0[1] + u * (P1[1] - P0[1]) + u * v * (P2[1] - P1[1]);
+                const double yz = P0[2] + u * (P1[2] - P0[2]) + u * v * (P2[2] - P1[2]);
+                Abcd<double> kk = abcd_point(x - yx, y - yy, z - yz, n0x, n0y, n0z, fnx, fny,
+                                             fnz, C.kappa, C.inv_ebar);
+                acc_a += w * kk.A;
+                acc_b += w * kk.B;
+                acc_c += w * kk.C;
+                acc_d += w * kk.D;
+            }
+            // advance: next self-rule step, next leaf of the walk, next piece
+            bool next_piece;
+            if (self) {
+                next_piece = ++sub == 4;
+                if (next_piece) sub = 0;
+            } else {
+                while (depth > 0 && ((path >> (2 * (depth - 1))) & 3) == 3) {
+                    path &= ~(3u << (2 * (depth - 1)));
+                    --depth;
+                }
+                next_piece = depth == 0;
+                if (!next_piece) path += 1u << (2 * (depth - 1));
+            }
+            if (next_piece) {
+                half ^= 1;
+                if (half == 0) ++q;
+                if (q < q_end) piece_root(C, ot, C.inc_tri[q], half, R0, R1, R2, fnx, fny, fnz);
+            }
         }
-    }
-    acc.a = wave_add(acc.a);
-    acc.b = wave_add(acc.b);
-    acc.c = wave_add(acc.c);
-    acc.d = wave_add(acc.d);
-    if (lane == 0) {
-        if (t != p) {   // subtract the point rule applied by the far-field part
-            double at = C.nd.area[t];
-            Abcd<double> kp = abcd_point(x - C.nd.x[t], y - C.nd.y[t], z - C.nd.z[t], n0x, n0y,
-                                         n0z, C.nd.nx[t], C.nd.ny[t], C.nd.nz[t], C.kappa,
-                                         C.inv_ebar);
-            acc.a -= at * kp.A;
-            acc.b -= at * kp.B;
-            acc.c -= at * kp.C;
-            acc.d -= at * kp.D;
+        acc_a = wave_add(acc_a);
+        acc_b = wave_add(acc_b);
+        acc_c = wave_add(acc_c);
+        acc_d = wave_add(acc_d);
+        if (lane == 0) {
+            if (!self) {   // subtract the point rule applied by the far-field part
+                const double at = C.nd.area[t];
+                Abcd<double> kp = abcd_point(x - C.nd.x[t], y - C.nd.y[t], z - C.nd.z[t], n0x,
+                                             n0y, n0z, C.nd.nx[t], C.nd.ny[t], C.nd.nz[t],
+                                             C.kappa, C.inv_ebar);
+                acc_a -= at * kp.A;
+                acc_b -= at * kp.B;
+                acc_c -= at * kp.C;
+                acc_d -= at * kp.D;
+            } else {       // flat facet: the B and C integrands vanish
+                acc_b = 0;
+                acc_c = 0;
+            }
+            delta[4 * e] = acc_a;
+            delta[4 * e + 1] = acc_b;
+            delta[4 * e + 2] = acc_c;
+            delta[4 * e + 3] = acc_d;
         }
-        delta[4 * e] = acc.a;
-        delta[4 * e + 1] = acc.b;
-        delta[4 * e + 2] = acc.c;
-        delta[4 * e + 3] = acc.d;
-    }
     }
 }
 
@@ -424,8 +406,25 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
     Ctx C;
     C.V = V; C.T = T; C.tri_n = tri_n; C.inc_ptr = inc_ptr; C.inc_tri = inc_tri; C.perm = perm;
     C.nd = nd; C.kappa = kappa; C.inv_ebar = 1.0 / ebar;
-    gauss_legendre01(8, C.q.x8, C.q.w8);
-    gauss_legendre01(16, C.q.x16, C.q.w16);
+    double x8[8], w8[8], x16[16], w16[16];
+    gauss_legendre01(8, x8, w8);
+    gauss_legendre01(16, x16, w16);
+    std::vector<double> rule(3 * (64 + 256));
+    for (int l = 0; l < 64; ++l) {
+        rule[3 * l] = x8[l >> 3];
+        rule[3 * l + 1] = x8[l & 7];
+        rule[3 * l + 2] = w8[l >> 3] * w8[l & 7];
+    }
+    for (int l = 0; l < 256; ++l) {
+        double *r = &rule[3 * (64 + l)];
+        r[0] = x16[l >> 4];
+        r[1] = x16[l & 15];
+        r[2] = w16[l >> 4] * w16[l & 15];
+    }
+    DBuf<double> rule_d(rule.size());
+    HIPCHK(hipMemcpyAsync(rule_d.p, rule.data(), rule.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+    C.rule = rule_d.p;
     out.delta.alloc(4 * out.nnz);
     // one wave per entry, at most 2^22 blocks of 4 waves (the kernel strides)
     const long long nblk = std::min<long long>((out.nnz + 3) / 4, 1ll << 22);
