@@ -246,7 +246,8 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     long long widest = 1;
     for (int l = 0; l < c->tree.nlev; ++l)
         widest = std::max(widest, c->tree.level_start[l + 1] - c->tree.level_start[l]);
-    far.alloc((size_t)(2 * nb * K) * 2 + (size_t)std::max(nv, 1ll) * 2 * K + 4 * n +
+    const long long KZ = c->fmm.KZ;
+    far.alloc((size_t)(2 * nb * K) * 2 + (size_t)std::max(nv, 1ll) * 2 * KZ + 4 * n +
               (size_t)8 * widest * 2 * K);
     mp.n = n;
     mp.tree = &c->tree;
@@ -271,8 +272,8 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     R *f = far.p;
     mp.far.M = f;
     mp.far.Lc = f + 2 * nb * K;
-    mp.far.Z = f + 4 * nb * K;
-    mp.far.phi = f + 4 * nb * K + std::max(nv, 1ll) * 2 * K;
+    mp.far.Z = f + 4 * nb * K;         // 16-byte aligned: 4 nb K elements precede it
+    mp.far.phi = f + 4 * nb * K + std::max(nv, 1ll) * 2 * KZ;
     mp.far.Mt = mp.far.phi + 4 * n;
     mp.far.bf16_m2l = (sizeof(R) == sizeof(float) &&
                        c->prm.precision == AFMPB_FP32_BF16M2L_REFINED) ? 1 : 0;

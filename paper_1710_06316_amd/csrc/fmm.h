@@ -33,6 +33,7 @@ struct Fmm {
     // (zero padded); PM elements per matrix.
     long long PM = 0;
     int KK = 0;
+    int KZ = 0;                          // M2L result slot length: K rounded up to 16
     DBuf<double> Tp, Up, Lp;             // M2L, M2M (A = U), L2L (A = U^T)
     DBuf<float> Tp32, Up32, Lp32;
     // M2L operators split into bf16 high and low parts, in the operand order
@@ -55,7 +56,7 @@ void build_fmm_operators(const Tree &t, const Lists &L, int P, double kappa, boo
 // node (zero where no local expansion exists).
 template <typename R>
 struct FarWork {
-    R *M, *Lc, *Z, *phi;       // [nbox][2][K], [nbox][2][K], [n_v][2][K], [4][n]
+    R *M, *Lc, *Z, *phi;       // [nbox][2][K], [nbox][2][K], [n_v][2][KZ], [4][n]
     R *Mt;                     // [8][widest level][2][K] per-octant M2M products
     int bf16_m2l = 0;          // FP32 path: M2L as three bf16 products (split operands)
 };

@@ -342,6 +342,7 @@ template <> __device__ inline int drow<float>(int lane, int r) { return 4 * (lan
 
 struct TransArgs {
     int K, KK, nlev;
+    int KZ;                      // M2L: slot length of one result (K rounded up to 16)
     long long nkey, PM;
     // M2L
     const int *item_key, *item_begin, *item_count, *pairs, *vidx;
@@ -370,7 +371,8 @@ __device__ inline long long trans_dst(const TransArgs &a, const int *colbox,
     const int K = a.K;
     if (MODE == 0) {
         // slot of the V entry (target-major list order)
-        return ((long long)colbox[col] * 2 + kern) * K;
+        (void)K;
+        return ((long long)colbox[col] * 2 + kern) * a.KZ;
     } else if (MODE == 1) {
         // per-octant product of parent column col (summed by k_m2m_sum)
         return (((long long)o * a.ncap + (colbox[col] - a.lb)) * 2 + kern) * K;
@@ -391,10 +393,16 @@ __device__ inline void trans_store(const TransArgs &a, typename Acc4<R>::T (&acc
         if (col >= ncols) continue;
         const long long dst = trans_dst<R, CC, MODE>(a, colbox, child, col, o, kern);
         if (dst < 0) continue;
+        if constexpr (MODE == 0 && sizeof(R) == sizeof(float)) {
+            // M2L slots hold whole row tiles (KZ >= 16 NRT, 64-byte aligned):
+            // the four consecutive rows of a lane go out as one 16-byte store
+            *reinterpret_cast<typename Acc4<R>::T *>(out + dst + rt * 16 + 4 * (lane >> 4)) = acc[ct];
+            continue;
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int rr = rt * 16 + drow<R>(lane, r);
-            if (rr < a.K) {
+            if (MODE == 0 || rr < a.K) {     // M2L: rows past K are the slot's zero pad
                 if (MODE == 2) out[dst + rr] += acc[ct][r];
                 else out[dst + rr] = acc[ct][r];
             }
@@ -657,12 +665,8 @@ __device__ inline void m2l_bf16_rows(const TransArgs &a, const u16x8_t *__restri
         for (int ct = 0; ct < NA; ++ct) {
             const int col = ct * 16 + (lane & 15);
             if (col >= ncols) continue;
-            const long long dst = ((long long)colbox[col] * 2 + kern) * K;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int rr = rt * 16 + drow<float>(lane, r);
-                if (rr < K) out[dst + rr] = acc[ct][r];
-            }
+            const long long dst = ((long long)colbox[col] * 2 + kern) * a.KZ;
+            *reinterpret_cast<f4v *>(out + dst + rt * 16 + 4 * (lane >> 4)) = acc[ct];
         }
     }
 }
@@ -826,24 +830,24 @@ void launch_trans(const TransArgs &ta, dim3 grid_items, const R *ops, const R *i
     }
 }
 
-// L[B] = sum over V(B) in list order of the M2L products (every box written).
 // L[B] = sum of the M2L products of the entries of V(B), stored in list
-// order as rows [v_ptr[B], v_ptr[B+1]) of Z (2K values each).  Four waves
-// take every fourth row; their partial sums are added in wave order.
+// order as slots [v_ptr[B], v_ptr[B+1]) of Z (2 KZ values each: kernel 0,
+// then kernel 1, each K values and a zero pad).  Four waves take every
+// fourth slot; their partial sums are added in wave order.
 template <typename R>
-__global__ void __launch_bounds__(256) k_m2l_reduce(int K, long long nbox, const int *vptr,
+__global__ void __launch_bounds__(256) k_m2l_reduce(int K, int KZ, long long nbox, const int *vptr,
                                                     const R *__restrict__ Z, R *__restrict__ L) {
-    __shared__ R red[4][2 * (MAXP + 1) * (MAXP + 1)];
+    __shared__ R red[4][2 * ((MAXP + 1) * (MAXP + 1) + 15) / 16 * 16];
     const long long box = blockIdx.x;
     if (box >= nbox) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int W = 2 * K, NJ = (W + 63) / 64;
+    const int W = 2 * KZ, NJ = (W + 63) / 64;
     const long long q0 = vptr[box], q1 = vptr[box + 1];
     R acc[14];
 #pragma unroll
     for (int j = 0; j < 14; ++j) acc[j] = R(0);
     long long q = q0 + wave;
-    // two rows per step: their loads are independent and overlap
+    // two slots per step: their loads are independent and overlap
     for (; q + 4 < q1; q += 8) {
         const R *z = Z + q * W, *z2 = z + 4 * (long long)W;
 #pragma unroll
@@ -860,8 +864,11 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(int K, long long nbox, const
     for (int j = 0; j < 14; ++j)
         if (j < NJ && lane + 64 * j < W) red[wave][lane + 64 * j] = acc[j];
     __syncthreads();
-    for (int i = threadIdx.x; i < W; i += 256)
-        L[box * W + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+    for (int i = threadIdx.x; i < W; i += 256) {
+        const int kern = i >= KZ, k = i - kern * KZ;
+        if (k < K)
+            L[box * 2 * K + kern * K + k] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+    }
 }
 
 // L2P: one block per item, wave w evaluates the local expansion of kernel w
@@ -1026,6 +1033,7 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, bo
     // operand-order packing (FP64 and FP32), then drop the plain copies
     F.KK = (K + 3) / 4 * 4;
     const int NRT = (K + 15) / 16;
+    F.KZ = NRT * 16;
     F.PM = (long long)NRT * 16 * F.KK;
     auto pack = [&](const DBuf<double> &src, long long nmat, int transpose, DBuf<double> &d,
                     DBuf<float> &d32) {
@@ -1100,6 +1108,7 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     TransArgs ta{};
     ta.K = K;
     ta.KK = F.KK;
+    ta.KZ = F.KZ;
     ta.PM = F.PM;
     ta.nlev = F.nlev;
     ta.nkey = F.nkey;
@@ -1143,7 +1152,8 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "m2l_reduce", s);
-        k_m2l_reduce<R><<<blocks_ok(t.nbox, 256), 256, 0, s>>>(K, t.nbox, L.v_ptr.p, w.Z, w.Lc);
+        k_m2l_reduce<R><<<blocks_ok(t.nbox, 256), 256, 0, s>>>(K, F.KZ, t.nbox, L.v_ptr.p, w.Z,
+                                                                w.Lc);
         KCHK();
     }
     {
