@@ -139,6 +139,7 @@ def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host, do_
                  "ms_gmres": sinfo.ms_gmres, "ms_total": sinfo.ms_total}
     s.close()
     return {"ms": ms, "value": 2 * n / (ms * 1e-3) / 1e6, "prof": prof, "info": info,
+            "steps": steps,
             "setup_ms": setup_ms, "solve": solve, "y_host": y_host}
 
 
@@ -178,13 +179,17 @@ def roofline(r, order, precision, workload="globular"):
     for name, (bound, flops, pk) in work.items():
         if name not in prof:
             continue
+        # M2L runs as one launch per tree level: the step's flops are spread
+        # over its launches, and the average launch is timed
         tot_ms, cnt = prof[name]
+        per_step = cnt / r["steps"]
         avg_s = tot_ms / cnt * 1e-3
-        achieved = flops / avg_s / 1e12
+        achieved = flops / per_step / avg_s / 1e12
         roofs[name] = {"kernel": name, "bound": bound, "achieved": achieved, "peak": pk,
                        "unit": "TFLOP/s", "frac": achieved / pk,
                        "traffic": measured_traffic(name, order, precision, workload),
-                       "flops_per_launch": flops, "avg_ms": avg_s * 1e3}
+                       "flops_per_launch": flops / per_step, "launches_per_step": per_step,
+                       "avg_ms": avg_s * 1e3}
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
     roof = roofs.get(dom) or max(roofs.values(), key=lambda q: q["avg_ms"])
     return roof, roofs, dom

@@ -833,36 +833,48 @@ void launch_trans(const TransArgs &ta, dim3 grid_items, const R *ops, const R *i
 // L[B] = sum of the M2L products of the entries of V(B), stored in list
 // order as slots [v_ptr[B], v_ptr[B+1]) of Z (2 KZ values each: kernel 0,
 // then kernel 1, each K values and a zero pad).  Four waves take every
-// fourth slot; their partial sums are added in wave order.
+// fourth slot, reading 16 bytes per lane and four slots per step; their
+// partial sums are added in wave order.
 template <typename R>
 __global__ void __launch_bounds__(256) k_m2l_reduce(int K, int KZ, long long nbox, const int *vptr,
                                                     const R *__restrict__ Z, R *__restrict__ L) {
-    __shared__ R red[4][2 * ((MAXP + 1) * (MAXP + 1) + 15) / 16 * 16];
+    constexpr int VB = 16 / (int)sizeof(R);            // elements per 16-byte vector
+    typedef R V __attribute__((ext_vector_type(VB)));
+    constexpr int KZMAX = ((MAXP + 1) * (MAXP + 1) + 15) / 16 * 16;
+    constexpr int NT = (2 * KZMAX / VB + 63) / 64;     // vectors per lane, at most
+    __shared__ R red[4][2 * KZMAX];
     const long long box = blockIdx.x;
     if (box >= nbox) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int W = 2 * KZ, NJ = (W + 63) / 64;
+    const int W = 2 * KZ, NV = W / VB;                 // KZ is a multiple of 16
     const long long q0 = vptr[box], q1 = vptr[box + 1];
-    R acc[14];
+    V acc[NT];
 #pragma unroll
-    for (int j = 0; j < 14; ++j) acc[j] = R(0);
+    for (int t = 0; t < NT; ++t) acc[t] = V{};
     long long q = q0 + wave;
-    // two slots per step: their loads are independent and overlap
-    for (; q + 4 < q1; q += 8) {
-        const R *z = Z + q * W, *z2 = z + 4 * (long long)W;
+    for (; q + 12 < q1; q += 16) {
+        const V *z0 = reinterpret_cast<const V *>(Z + q * W);
+        const V *z1 = z0 + 4 * (long long)NV, *z2 = z0 + 8 * (long long)NV;
+        const V *z3 = z0 + 12 * (long long)NV;
 #pragma unroll
-        for (int j = 0; j < 14; ++j)
-            if (j < NJ && lane + 64 * j < W) acc[j] += z[lane + 64 * j] + z2[lane + 64 * j];
+        for (int t = 0; t < NT; ++t) {
+            const int v = lane + 64 * t;
+            if (v < NV) acc[t] += (z0[v] + z1[v]) + (z2[v] + z3[v]);
+        }
     }
-    if (q < q1) {
-        const R *z = Z + q * W;
+    for (; q < q1; q += 4) {
+        const V *z0 = reinterpret_cast<const V *>(Z + q * W);
 #pragma unroll
-        for (int j = 0; j < 14; ++j)
-            if (j < NJ && lane + 64 * j < W) acc[j] += z[lane + 64 * j];
+        for (int t = 0; t < NT; ++t) {
+            const int v = lane + 64 * t;
+            if (v < NV) acc[t] += z0[v];
+        }
     }
 #pragma unroll
-    for (int j = 0; j < 14; ++j)
-        if (j < NJ && lane + 64 * j < W) red[wave][lane + 64 * j] = acc[j];
+    for (int t = 0; t < NT; ++t) {
+        const int v = lane + 64 * t;
+        if (v < NV) *reinterpret_cast<V *>(&red[wave][v * VB]) = acc[t];
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < W; i += 256) {
         const int kern = i >= KZ, k = i - kern * KZ;
