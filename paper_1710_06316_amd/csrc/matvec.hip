@@ -77,68 +77,91 @@ __global__ void __launch_bounds__(64) k_p2p(
     const R x = nd.x[ii], y = nd.y[ii], z = nd.z[ii];
     const R n0x = nd.nx[ii], n0y = nd.ny[ii], n0z = nd.nz[ii];
     double af = 0.0, ah = 0.0;
-    const int rhi = ch_hi[c];
-    for (int r = ch_lo[c]; r < rhi; ++r) {
-        const int cb = rng_b[r], ce = rng_e[r];
-        for (int s0 = cb; s0 < ce; s0 += 64) {
-            const int j = s0 + lane;
-            __builtin_amdgcn_wave_barrier();
-            const bool in = j < ce;
-            T[lane][0] = in ? nd.x[j] : R(0); T[lane][1] = in ? nd.y[j] : R(0);
-            T[lane][2] = in ? nd.z[j] : R(0); T[lane][3] = in ? nd.nx[j] : R(0);
-            T[lane][4] = in ? nd.ny[j] : R(0); T[lane][5] = in ? nd.nz[j] : R(0);
-            T[lane][6] = in ? sf[j] : R(0);   T[lane][7] = in ? sh[j] : R(0);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int cnt = min(64, ce - s0);
-            R bf = R(0), bh = R(0);
-            // jb + rep <= 63: jb is a multiple of f below cnt <= 64 and f | 64
-            for (int jb = 0; jb < cnt; jb += f) {
-                const int jj = jb + rep;
-                const R rx = x - T[jj][0], ry = y - T[jj][1], rz = z - T[jj][2];
-                const R snx = T[jj][3], sny = T[jj][4], snz = T[jj][5];
-                const R sfv = T[jj][6], shv = T[jj][7];
-                const bool ok = act && jj < cnt && s0 + jj != i;
-                R r2 = (rx * rx + ry * ry) + rz * rz;
-                r2 = ok ? r2 : R(1);
-                const R ir = Fast<R>::rsq(r2);
-                const R rr = r2 * ir;
-                const R s = kappa * rr;
-                const R e = Fast<R>::ex(-s);
-                R om, fa, fb;
-                if (s < R(0.1)) {
-                    constexpr int N = Fast<R>::NSER;
-                    R po = R(S.om[N]), pa = R(S.a[N]), pb = R(S.b[N]);
+    // one source pair (T row jj) against this lane's target
+    auto pair = [&](int jj, bool ok, R &bf, R &bh) {
+        const R rx = x - T[jj][0], ry = y - T[jj][1], rz = z - T[jj][2];
+        const R snx = T[jj][3], sny = T[jj][4], snz = T[jj][5];
+        const R sfv = T[jj][6], shv = T[jj][7];
+        R r2 = (rx * rx + ry * ry) + rz * rz;
+        r2 = ok ? r2 : R(1);
+        const R ir = Fast<R>::rsq(r2);
+        const R rr = r2 * ir;
+        const R s = kappa * rr;
+        const R e = Fast<R>::ex(-s);
+        R om, fa, fb;
+        if (s < R(0.1)) {
+            constexpr int N = Fast<R>::NSER;
+            R po = R(S.om[N]), pa = R(S.a[N]), pb = R(S.b[N]);
 #pragma unroll
-                    for (int k = N - 1; k >= 2; --k) {
-                        po = po * s + R(S.om[k]);
-                        pa = pa * s + R(S.a[k]);
-                        pb = pb * s + R(S.b[k]);
-                    }
-                    om = (po * s + R(1)) * s;
-                    fa = pa * s * s;
-                    fb = pb * s * s;
-                } else {
-                    om = R(1) - e;
-                    fa = om - s * e;
-                    fb = R(3) * om - e * s * (R(3) + s);
-                }
-                const R Rn = (rx * snx + ry * sny) + rz * snz;
-                const R Rn0 = (rx * n0x + ry * n0y) + rz * n0z;
-                const R n0n = (n0x * snx + n0y * sny) + n0z * snz;
-                const R ir3 = ir * ir * ir;
-                const R e1 = e * (R(1) + s);
-                const R A = om * ir;
-                const R B = Rn * ir3 * (inv_ebar - e1);
-                const R Cc = Rn0 * ir3 * (e1 * inv_ebar - R(1));
-                const R D = inv_ebar * ir3 * (n0n * fa - Rn0 * Rn * fb * ir * ir);
-                bf += ok ? (B * sfv - A * shv) : R(0);
-                bh += ok ? (D * sfv - Cc * shv) : R(0);
+            for (int k = N - 1; k >= 2; --k) {
+                po = po * s + R(S.om[k]);
+                pa = pa * s + R(S.a[k]);
+                pb = pb * s + R(S.b[k]);
             }
-            af += (double)bf;
-            ah += (double)bh;
+            om = (po * s + R(1)) * s;
+            fa = pa * s * s;
+            fb = pb * s * s;
+        } else {
+            om = R(1) - e;
+            fa = om - s * e;
+            fb = R(3) * om - e * s * (R(3) + s);
         }
+        const R Rn = (rx * snx + ry * sny) + rz * snz;
+        const R Rn0 = (rx * n0x + ry * n0y) + rz * n0z;
+        const R n0n = (n0x * snx + n0y * sny) + n0z * snz;
+        const R ir3 = ir * ir * ir;
+        const R e1 = e * (R(1) + s);
+        const R A = om * ir;
+        const R B = Rn * ir3 * (inv_ebar - e1);
+        const R Cc = Rn0 * ir3 * (e1 * inv_ebar - R(1));
+        const R D = inv_ebar * ir3 * (n0n * fa - Rn0 * Rn * fb * ir * ir);
+        bf += ok ? (B * sfv - A * shv) : R(0);
+        bh += ok ? (D * sfv - Cc * shv) : R(0);
+    };
+    // Source tiles of 64 points, walked over the chunk's ranges; the next
+    // tile is loaded into registers while the current one is evaluated.
+    int r = ch_lo[c];
+    const int rhi = ch_hi[c];
+    int cb = 0, ce = 0, s0 = 0;
+    if (r < rhi) { cb = rng_b[r]; ce = rng_e[r]; s0 = cb; }
+    R v[8];
+    auto fetch = [&](int s0n, int cen) {
+        const int j = s0n + lane;
+        const bool in = j < cen;
+        v[0] = in ? nd.x[j] : R(0);  v[1] = in ? nd.y[j] : R(0);
+        v[2] = in ? nd.z[j] : R(0);  v[3] = in ? nd.nx[j] : R(0);
+        v[4] = in ? nd.ny[j] : R(0); v[5] = in ? nd.nz[j] : R(0);
+        v[6] = in ? sf[j] : R(0);    v[7] = in ? sh[j] : R(0);
+    };
+    if (r < rhi) fetch(s0, ce);
+    while (r < rhi) {
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) T[lane][q] = v[q];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int cnt = min(64, ce - s0), s0c = s0;
+        // next tile (uniform): the rest of this range, else the next range
+        s0 += 64;
+        if (s0 >= ce) {
+            ++r;
+            if (r < rhi) { cb = rng_b[r]; ce = rng_e[r]; s0 = cb; }
+        }
+        if (r < rhi) fetch(s0, ce);
+        R bf = R(0), bh = R(0);
+        // two sources per trip, added in source order; jb + rep <= 63 (jb is a
+        // multiple of f below cnt <= 64 and f | 64); the second row index is
+        // clamped into the tile when it is past cnt (then masked)
+        for (int jb = 0; jb < cnt; jb += 2 * f) {
+            const int ja = jb + rep, jc = jb + f + rep;
+            const bool oka = act && ja < cnt && s0c + ja != i;
+            const bool okc = act && jc < cnt && s0c + jc != i;
+            pair(ja, oka, bf, bh);
+            pair(min(jc, 63), okc, bf, bh);
+        }
+        af += (double)bf;
+        ah += (double)bh;
     }
     red[0][lane] = af;
     red[1][lane] = ah;
