@@ -7,6 +7,8 @@
 #include <cstdlib>
 #include <numeric>
 
+#include <cstring>
+
 #include "ctx.h"
 
 namespace afmpb {
@@ -98,19 +100,33 @@ void validate_mesh(long long n, const double *V, long long m, const int *T) {
         ++deg[T[i]];
     }
     for (long long i = 0; i < n; ++i) require(deg[i] > 0, ST_MESH, "node not used by any triangle");
-    // duplicate vertices: sort (x, y, z, index) records
-    struct Pt { double x, y, z; long long i; };
-    std::vector<Pt> pts(n);
-    for (long long i = 0; i < n; ++i) pts[i] = Pt{V[3 * i], V[3 * i + 1], V[3 * i + 2], i};
-    std::sort(pts.begin(), pts.end(), [](const Pt &a, const Pt &b) {
-        if (a.x != b.x) return a.x < b.x;
-        if (a.y != b.y) return a.y < b.y;
-        if (a.z != b.z) return a.z < b.z;
-        return a.i < b.i;
-    });
-    for (long long i = 1; i < n; ++i)
-        require(!(pts[i].x == pts[i - 1].x && pts[i].y == pts[i - 1].y && pts[i].z == pts[i - 1].z),
-                ST_MESH, "duplicate vertex");
+    // duplicate vertices: open-addressing hash of the exact coordinates
+    // (-0.0 taken as +0.0, so that equal values hash alike)
+    {
+        size_t cap = 16;
+        while (cap < 2 * (size_t)n) cap <<= 1;
+        std::vector<int> slot(cap, -1);
+        auto bits = [](double v) {
+            if (v == 0.0) v = 0.0;
+            unsigned long long u;
+            std::memcpy(&u, &v, sizeof u);
+            return u;
+        };
+        for (long long i = 0; i < n; ++i) {
+            const double *p = V + 3 * i;
+            unsigned long long h = bits(p[0]) * 0x9E3779B97F4A7C15ull;
+            h = (h ^ (h >> 29) ^ bits(p[1])) * 0xBF58476D1CE4E5B9ull;
+            h = (h ^ (h >> 31) ^ bits(p[2])) * 0x94D049BB133111EBull;
+            size_t q = (size_t)(h ^ (h >> 32)) & (cap - 1);
+            while (slot[q] >= 0) {
+                const double *o = V + 3ll * slot[q];
+                require(!(o[0] == p[0] && o[1] == p[1] && o[2] == p[2]), ST_MESH,
+                        "duplicate vertex");
+                q = (q + 1) & (cap - 1);
+            }
+            slot[q] = (int)i;
+        }
+    }
     // directed edges a -> b of every triangle as rows per start node; each
     // directed edge must appear once, and its reverse once (closed, manifold,
     // consistently oriented)
@@ -125,9 +141,20 @@ void validate_mesh(long long n, const double *V, long long m, const int *T) {
             nxt[fill[a]++] = b;
         }
     for (long long v = 0; v < n; ++v) {
-        std::sort(nxt.begin() + ptr[v], nxt.begin() + ptr[v + 1]);
-        for (long long e = ptr[v] + 1; e < ptr[v + 1]; ++e)
-            require(nxt[e] != nxt[e - 1], ST_MESH, "edge used twice in one direction (non-manifold)");
+        int *r = nxt.data() + ptr[v];
+        const long long d = ptr[v + 1] - ptr[v];
+        if (d <= 32) {                       // rows are short: insertion sort
+            for (long long a = 1; a < d; ++a) {
+                const int key = r[a];
+                long long b = a - 1;
+                while (b >= 0 && r[b] > key) { r[b + 1] = r[b]; --b; }
+                r[b + 1] = key;
+            }
+        } else {
+            std::sort(r, r + d);
+        }
+        for (long long e = 1; e < d; ++e)
+            require(r[e] != r[e - 1], ST_MESH, "edge used twice in one direction (non-manifold)");
     }
     for (long long v = 0; v < n; ++v)
         for (long long e = ptr[v]; e < ptr[v + 1]; ++e) {
