@@ -88,8 +88,8 @@ __device__ inline void for_each_regular(S x, S y, S z, int P, const NT *norm, co
 // consecutive series terms over t (row 0: n = P, row 1: n = P-1).
 constexpr int GSER = 200;
 
-template <typename R, typename S>
-__device__ inline S g_series(int n, S t, const R *inv_dfact, const double *ser) {
+template <typename R, typename S, typename ST>
+__device__ inline S g_series(int n, S t, const R *inv_dfact, const ST *ser) {
     S sum(R(1)), term(R(1));
     for (int k = 1; k < GSER; ++k) {
         term = term * t * R(ser[k]);
@@ -100,8 +100,8 @@ __device__ inline S g_series(int n, S t, const R *inv_dfact, const double *ser) 
     return sum * inv_dfact[n];
 }
 
-template <typename R, typename S>
-__device__ inline void g_all(int P, S t, const R *inv_dfact, const double *ser, S *g) {
+template <typename R, typename S, typename ST>
+__device__ inline void g_all(int P, S t, const R *inv_dfact, const ST *ser, S *g) {
     g[P] = g_series<R, S>(P, t, inv_dfact, ser);
     if (P >= 1) g[P - 1] = g_series<R, S>(P - 1, t, inv_dfact, ser + GSER);
     for (int n = P - 1; n >= 1; --n) g[n - 1] = t * g[n + 1] + R(2 * n + 1) * g[n];

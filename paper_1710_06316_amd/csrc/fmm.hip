@@ -55,6 +55,57 @@ __device__ inline void regular_basis(const BasisDev &B, int kern, int lev, S vx,
     }
 }
 
+// Recurrence tables of the expansion bases in the working precision, staged
+// in LDS by the point kernels (P2M, L2P), so that each use is an LDS read
+// rather than a memory load on the recurrence's critical path.  Values are
+// those of the tables in memory, rounded to R once.
+template <typename R>
+struct BasisTab {
+    const R *rec, *norm, *ginv, *idf, *ser;
+};
+
+// LDS bytes of the staged tables for order P and nlev tree levels.
+__host__ __device__ inline size_t basis_tab_bytes(int P, int nlev, size_t elem) {
+    const size_t K = (size_t)(P + 1) * (P + 1);
+    return (3 * K + (size_t)nlev * (P + 1) + (P + 2) + 2 * GSER) * elem;
+}
+
+// Block-cooperative copy of the tables into dynamic LDS at `raw`; ends with a
+// block barrier.
+template <typename R>
+__device__ inline BasisTab<R> stage_basis(const BasisDev &B, int nlev, unsigned char *raw) {
+    const int P = B.P, K = B.K;
+    R *rec = reinterpret_cast<R *>(raw);
+    R *norm = rec + 2 * K, *ginv = norm + K, *idf = ginv + nlev * (P + 1), *ser = idf + P + 2;
+    for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) rec[i] = R(B.rec[i]);
+    for (int i = threadIdx.x; i < K; i += blockDim.x) norm[i] = R(B.norm[i]);
+    for (int i = threadIdx.x; i < nlev * (P + 1); i += blockDim.x) ginv[i] = R(B.ginv[i]);
+    for (int i = threadIdx.x; i < P + 2; i += blockDim.x) idf[i] = R(B.inv_dfact[i]);
+    if (B.screened)
+        for (int i = threadIdx.x; i < 2 * GSER; i += blockDim.x) ser[i] = R(B.gser[i]);
+    __syncthreads();
+    return BasisTab<R>{rec, norm, ginv, idf, ser};
+}
+
+// regular_basis with the staged tables (same values, same order of operations).
+template <typename R, typename S, typename F>
+__device__ inline void regular_basis_tab(const BasisDev &B, const BasisTab<R> &T, int kern,
+                                         int lev, S vx, S vy, S vz, F &&emit) {
+    const R is = R(1.0 / B.side[lev]);
+    S ux = vx * is, uy = vy * is, uz = vz * is;
+    if (kern == 0 || !B.screened) {
+        for_each_regular<R>(ux, uy, uz, B.P, T.norm, T.rec, [&](int k, int, S r) { emit(k, r); });
+    } else {
+        R ks = R(B.kappa * B.side[lev]);
+        S t = (ks * ks) * ((ux * ux + uy * uy) + uz * uz);
+        S g[MAXP + 1];
+        g_all<R, S>(B.P, t, T.idf, T.ser, g);
+        const R *gi = T.ginv + lev * (B.P + 1);
+        for_each_regular<R>(ux, uy, uz, B.P, T.norm, T.rec,
+                            [&](int k, int n, S r) { emit(k, r * (g[n] * gi[n])); });
+    }
+}
+
 // ------------------------- operator construction ---------------------------
 
 struct MatDesc {
@@ -252,9 +303,12 @@ __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *p
                                              const int *pm_first, const int *pm_count,
                                              const R *px, const R *py, const R *pz,
                                              const R *pnx, const R *pny, const R *pnz,
-                                             const R *sf, const R *sh, R inv_ebar, R *M) {
+                                             const R *sf, const R *sh, R inv_ebar, R *M,
+                                             int nlev) {
     __shared__ R Wv[2][16][65];
     __shared__ int kslot[2][16];
+    extern __shared__ __align__(16) unsigned char tab_raw[];
+    const BasisTab<R> tab = stage_basis<R>(B, nlev, tab_raw);
     const PmItem it(pm_leaf, pm_first, pm_count, T, blockIdx.x);
     const int lane = threadIdx.x & 63;
     const int kern = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -294,8 +348,8 @@ __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *p
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         };
-        regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, nx), Dual<R>(vy, ny), Dual<R>(vz, nz),
-                                  [&](int k, Dual<R> r) {
+        regular_basis_tab<R, Dual<R>>(B, tab, kern, lev, Dual<R>(vx, nx), Dual<R>(vy, ny),
+                                      Dual<R>(vz, nz), [&](int k, Dual<R> r) {
                                       const int sl = cnt & 15;
                                       Wv[kern][sl][lane] = qv * r.v + dip * r.d;
                                       if (lane == 0) kslot[kern][sl] = k;
@@ -891,9 +945,15 @@ __global__ void __launch_bounds__(128) k_l2p(BasisDev B, TreeDev T, const int *p
                                              const int *pm_first, const int *pm_count,
                                              const R *px, const R *py, const R *pz,
                                              const R *pnx, const R *pny, const R *pnz,
-                                             const R *L, long long n, R *phi) {
+                                             const R *L, long long n, R *phi, int nlev) {
+    extern __shared__ __align__(16) unsigned char tab_raw[];
     const PmItem it(pm_leaf, pm_first, pm_count, T, blockIdx.x);
     const int K = B.K;
+    // the item's local expansions (<= 4 leaves, both kernels) after the tables
+    R *Ls = reinterpret_cast<R *>(tab_raw + basis_tab_bytes(B.P, nlev, sizeof(R)));
+    for (int idx = threadIdx.x; idx < it.cnt * 2 * K; idx += blockDim.x)
+        Ls[idx] = L[(long long)pm_leaf[it.first + idx / (2 * K)] * 2 * K + idx % (2 * K)];
+    const BasisTab<R> tab = stage_basis<R>(B, nlev, tab_raw);   // (ends with a barrier)
     const int lane = threadIdx.x & 63;
     const int kern = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int c0 = 0; c0 < it.tot; c0 += 64) {
@@ -905,11 +965,12 @@ __global__ void __launch_bounds__(128) k_l2p(BasisDev B, TreeDev T, const int *p
         const int i = T.ptb[leaf] + (ok ? q - it.offs[g] : 0);
         const R cx = R(T.center[3 * leaf]), cy = R(T.center[3 * leaf + 1]);
         const R cz = R(T.center[3 * leaf + 2]);
-        const R *Lb = L + ((long long)leaf * 2 + kern) * K;
+        const R *Lb = Ls + (g * 2 + kern) * K;
         R p = R(0), dp = R(0);
         const R vx = px[i] - cx, vy = py[i] - cy, vz = pz[i] - cz;
-        regular_basis<R, Dual<R>>(B, kern, lev, Dual<R>(vx, pnx[i]), Dual<R>(vy, pny[i]),
-                                  Dual<R>(vz, pnz[i]), [&](int k, Dual<R> r) {
+        regular_basis_tab<R, Dual<R>>(B, tab, kern, lev, Dual<R>(vx, pnx[i]),
+                                      Dual<R>(vy, pny[i]), Dual<R>(vz, pnz[i]),
+                                      [&](int k, Dual<R> r) {
                                       const R l = Lb[k];
                                       p += l * r.v;
                                       dp += l * r.d;
@@ -1112,9 +1173,9 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "p2m", s);
-        k_p2m<R><<<blocks_ok(L.n_pm, 128), 128, 0, s>>>(B, T, L.pm_leaf.p, L.pm_first.p,
-                                                        L.pm_count.p, px, py, pz, pnx, pny, pnz,
-                                                        sf, sh, R(inv_ebar), w.M);
+        k_p2m<R><<<blocks_ok(L.n_pm, 128), 128, basis_tab_bytes(F.P, F.nlev, sizeof(R)), s>>>(
+            B, T, L.pm_leaf.p, L.pm_first.p, L.pm_count.p, px, py, pz, pnx, pny, pnz, sf, sh,
+            R(inv_ebar), w.M, F.nlev);
         KCHK();
     }
     TransArgs ta{};
@@ -1178,9 +1239,10 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "l2p", s);
-        k_l2p<R><<<blocks_ok(L.n_pm, 128), 128, 0, s>>>(B, T, L.pm_leaf.p, L.pm_first.p,
-                                                        L.pm_count.p, px, py, pz, pnx, pny, pnz,
-                                                        w.Lc, n, w.phi);
+        const size_t l2p_lds = basis_tab_bytes(F.P, F.nlev, sizeof(R)) + 4 * 2 * K * sizeof(R);
+        k_l2p<R><<<blocks_ok(L.n_pm, 128), 128, l2p_lds, s>>>(
+            B, T, L.pm_leaf.p, L.pm_first.p, L.pm_count.p, px, py, pz, pnx, pny, pnz, w.Lc, n,
+            w.phi, F.nlev);
         KCHK();
     }
 }
