@@ -159,7 +159,9 @@ __global__ void k_sphere_table(BasisDev B, int Q, const double *dir, const doubl
 // B[m][q][j]: basis values of matrix m at quadrature point q, and row scales.
 __global__ void k_basis_samples(BasisDev B, const MatDesc *desc, int nmat, int Q,
                                 const double *dir, const double *kinv, const double *W,
-                                double *out, double *rowscale) {
+                                double *out, double *rowscale, int nlev) {
+    extern __shared__ __align__(16) unsigned char tab_raw[];
+    const BasisTab<double> tab = stage_basis<double>(B, nlev, tab_raw);
     long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (long long)nmat * Q) return;
     int m = (int)(id / Q), q = (int)(id % Q);
@@ -170,8 +172,8 @@ __global__ void k_basis_samples(BasisDev B, const MatDesc *desc, int nmat, int Q
            vz = d.dz + d.rq * dir[3 * q + 2];
     double *o = out + id * K;
     if (d.kind == 1) {
-        regular_basis<double, double>(B, d.kern, d.lev, vx, vy, vz,
-                                      [&](int k, double r) { o[k] = r; });
+        regular_basis_tab<double, double>(B, tab, d.kern, d.lev, vx, vy, vz,
+                                          [&](int k, double r) { o[k] = r; });
     } else {
         double ux = vx / s, uy = vy / s, uz = vz / s;
         double ru = sqrt((ux * ux + uy * uy) + uz * uz);
@@ -194,7 +196,7 @@ __global__ void k_basis_samples(BasisDev B, const MatDesc *desc, int nmat, int Q
                 f *= ir;
             }
         }
-        for_each_regular<double>(ux, uy, uz, P, B.norm, B.rec,
+        for_each_regular<double>(ux, uy, uz, P, tab.norm, tab.rec,
                                  [&](int k, int n, double r) { o[k] = r * rad[n]; });
     }
     if (q == 0) {
@@ -213,28 +215,57 @@ __global__ void k_basis_samples(BasisDev B, const MatDesc *desc, int nmat, int Q
     }
 }
 
-// C[m][i][j] = rs[m][i] * sum_q A[q][i] Bm[m][q][j]  (16 x 16 LDS tiles).
-__global__ void k_project_gemm(const double *A, const double *Bm, const double *rs,
-                               const MatDesc *desc, int K, int Q, double *Tbase,
-                               double *Ubase) {
-    __shared__ double As[16][17], Bs[16][17];
-    int m = blockIdx.z;
-    int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
-    int ty = threadIdx.y, tx = threadIdx.x;
+// C[m][i][j] = rs[m][i] * sum_q A[q][i] Bm[m][q][j]: 64 x 64 output tiles, 16 x 16
+// threads with 4 x 4 outputs each (rows ty + 16 a, columns tx + 16 b), q in
+// chunks of 16 through LDS (each output summed in q order).
+__global__ void __launch_bounds__(256) k_project_gemm(const double *A, const double *Bm,
+                                                      const double *rs, const MatDesc *desc,
+                                                      int K, int Q, double *Tbase,
+                                                      double *Ubase) {
+    __shared__ double As[16][64], Bs[16][64];
+    const int m = blockIdx.z;
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 16 + tx;
     const double *B = Bm + (long long)m * Q * K;
-    double acc = 0.0;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
     for (int q0 = 0; q0 < Q; q0 += 16) {
-        int q = q0 + ty;
-        As[ty][tx] = (q < Q && i0 + tx < K) ? A[(long long)q * K + i0 + tx] : 0.0;
-        Bs[ty][tx] = (q < Q && j0 + tx < K) ? B[(long long)q * K + j0 + tx] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = tid + 256 * r, qq = e >> 6, ii = e & 63, q = q0 + qq;
+            As[qq][ii] = (q < Q && i0 + ii < K) ? A[(long long)q * K + i0 + ii] : 0.0;
+            Bs[qq][ii] = (q < Q && j0 + ii < K) ? B[(long long)q * K + j0 + ii] : 0.0;
+        }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) acc += As[kk][ty] * Bs[kk][tx];
+        for (int kk = 0; kk < 16; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tx + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
         __syncthreads();
     }
-    int i = i0 + ty, j = j0 + tx;
     double *C = desc[m].kind == 0 ? Tbase : Ubase;
-    if (i < K && j < K) C[desc[m].dst + (long long)i * K + j] = rs[(long long)m * K + i] * acc;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = i0 + ty + 16 * a;
+        if (i >= K) continue;
+        const double sc = rs[(long long)m * K + i];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int j = j0 + tx + 16 * b;
+            if (j < K) C[desc[m].dst + (long long)i * K + j] = sc * acc[a][b];
+        }
+    }
 }
 
 // packed[m][rt][ks][l] = A_m[16 rt + l % 16][4 ks + l / 16], A_m = op_m or its
@@ -255,6 +286,12 @@ __global__ void k_pack(const double *__restrict__ src, long long nmat, int K, in
         v = transpose ? src[m * K * K + (long long)k * K + row] : src[m * K * K + (long long)row * K + k];
     dst[id] = v;
     dst32[id] = (float)v;
+}
+
+__global__ void k_scale_copy(const double *__restrict__ a, double f, long long n,
+                             double *__restrict__ b) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i] * f;
 }
 
 __global__ void k_to_float(const double *a, float *b, long long n) {
@@ -1066,8 +1103,15 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, bo
                 if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) > 1) {
                     offs.push_back(dx); offs.push_back(dy); offs.push_back(dz);
                 }
+    // The Laplace operators are projected at one level only: in the level-scaled
+    // bases every M2L input scales with the box side by an exact power of two
+    // (offsets, sphere radius, the 1/((2n+1) s) weights), so the level-l
+    // operator is the reference one times side[ref]/side[l], bit for bit; the
+    // Laplace M2M / L2L operators are the same at every level.
+    const int ref_lev = Ls.levels_with_v.empty() ? 2 : Ls.levels_with_v.front();
     for (int kern = 0; kern < 2; ++kern) {
         for (int lev : Ls.levels_with_v) {
+            if (kern == 0 && lev != ref_lev) continue;
             double sl = t.side[lev];
             for (int c = 0; c < 316; ++c) {
                 // target centre minus source centre = -offset * side
@@ -1079,6 +1123,7 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, bo
             }
         }
         for (int lev = 2; lev + 1 < nlev; ++lev) {
+            if (kern == 0 && lev != 2) continue;
             double sc = t.side[lev + 1];
             for (int o = 0; o < 8; ++o) {
                 double d[3];
@@ -1095,13 +1140,31 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, bo
     ddesc.upload(desc.data(), desc.size(), s);
     for (size_t m0 = 0; m0 < desc.size(); m0 += batch) {
         int nb = (int)std::min<size_t>(batch, desc.size() - m0);
-        k_basis_samples<<<grid_for((long long)nb * Q, 128), 128, 0, s>>>(
-            B, ddesc.p + m0, nb, Q, ddir.p, F.kinv.p, F.weight.p, samples.p, rs.p);
+        k_basis_samples<<<grid_for((long long)nb * Q, 128), 128,
+                          basis_tab_bytes(P, nlev, sizeof(double)), s>>>(
+            B, ddesc.p + m0, nb, Q, ddir.p, F.kinv.p, F.weight.p, samples.p, rs.p, nlev);
         KCHK();
-        dim3 grid((K + 15) / 16, (K + 15) / 16, nb);
+        dim3 grid((K + 63) / 64, (K + 63) / 64, nb);
         k_project_gemm<<<grid, dim3(16, 16), 0, s>>>(Yw.p, samples.p, rs.p, ddesc.p + m0, K, Q,
                                                      F.T.p, F.Ut.p);
         KCHK();
+    }
+    // the other levels' Laplace operators from the reference ones
+    {
+        const long long KK2 = (long long)K * K;
+        for (int lev : Ls.levels_with_v) {
+            if (lev == ref_lev) continue;
+            const double f = t.side[ref_lev] / t.side[lev];   // a power of two
+            k_scale_copy<<<grid_for(316 * KK2, 256), 256, 0, s>>>(
+                F.T.p + (long long)(ref_lev - 2) * 316 * KK2, f, 316 * KK2,
+                F.T.p + (long long)(lev - 2) * 316 * KK2);
+            KCHK();
+        }
+        for (int lev = 3; lev + 1 < nlev; ++lev) {
+            k_scale_copy<<<grid_for(8 * KK2, 256), 256, 0, s>>>(
+                F.Ut.p + (long long)2 * 8 * KK2, 1.0, 8 * KK2, F.Ut.p + (long long)lev * 8 * KK2);
+            KCHK();
+        }
     }
     // operand-order packing (FP64 and FP32), then drop the plain copies
     F.KK = (K + 3) / 4 * 4;
