@@ -218,6 +218,11 @@ afmpb_status afmpb_debug_tree(afmpb_ctx *ctx, const afmpb_tree_view *out);
 afmpb_status afmpb_profile_enable(afmpb_ctx *ctx, int enable);
 afmpb_status afmpb_profile_read(afmpb_ctx *ctx, int idx, const char **name,
                                 double *total_ms, long long *launches);
+/* Restricts the timing to the scopes named `scope` (a name afmpb_profile_read
+ * reports, e.g. "m2l"); NULL or "" times every scope again.  Each timed scope
+ * costs two event records on its stream, so timing one kernel perturbs the
+ * matvec far less than timing all of them.  The string is copied. */
+afmpb_status afmpb_profile_only(afmpb_ctx *ctx, const char *scope);
 
 /* ------------------------------------------------------------------------
  * Solve server: continuous batching of independent solves on one device.

@@ -42,7 +42,7 @@ ABI_FUNCTIONS = (
     "afmpb_default_params", "afmpb_create", "afmpb_destroy", "afmpb_last_error",
     "afmpb_set_molecule", "afmpb_matvec", "afmpb_matvec_dev", "afmpb_solve",
     "afmpb_rhs", "afmpb_energy", "afmpb_tree_info", "afmpb_debug_tree",
-    "afmpb_profile_enable", "afmpb_profile_read", "afmpb_setup_times",
+    "afmpb_profile_enable", "afmpb_profile_read", "afmpb_profile_only", "afmpb_setup_times",
     "afmpb_server_create", "afmpb_server_set_tuning", "afmpb_server_submit",
     "afmpb_server_poll", "afmpb_server_cancel", "afmpb_server_stats", "afmpb_server_destroy",
 )
@@ -148,6 +148,7 @@ def lib():
         L.afmpb_tree_info.argtypes = [vp, ctypes.POINTER(afmpb_tree_sizes)]
         L.afmpb_debug_tree.argtypes = [vp, ctypes.POINTER(afmpb_tree_view)]
         L.afmpb_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.afmpb_profile_only.argtypes = [vp, ctypes.c_char_p]
         L.afmpb_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                          dp, ctypes.POINTER(ll)]
         L.afmpb_setup_times.argtypes = [vp, dp]
@@ -309,6 +310,10 @@ def afmpb_profile_enable(ctx, enable: bool):
     return _check(ctx, lib().afmpb_profile_enable(ctx, 1 if enable else 0))
 
 
+def afmpb_profile_only(ctx, scope=None):
+    return _check(ctx, lib().afmpb_profile_only(ctx, scope.encode() if scope else None))
+
+
 def afmpb_profile_read(ctx) -> dict:
     out = {}
     i = 0
@@ -387,6 +392,9 @@ class Solver:
 
     def profile_read(self):
         return afmpb_profile_read(self.ctx)
+
+    def profile_only(self, scope=None):
+        afmpb_profile_only(self.ctx, scope)
 
 
 # --- solve server ---------------------------------------------------------------

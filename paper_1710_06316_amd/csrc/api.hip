@@ -61,7 +61,10 @@ Prof::~Prof() {
 
 ProfScope::ProfScope(Prof *p, const char *name, hipStream_t st)
     : prof(p), id(-1), s(st), slot(0) {
-    if (!prof || !prof->on) { prof = nullptr; return; }
+    if (!prof || !prof->on || (!prof->only.empty() && prof->only != name)) {
+        prof = nullptr;
+        return;
+    }
     id = prof->id_of(name);
     hipEvent_t a = prof->take(), b = prof->take();
     HIPCHK(hipEventRecord(a, s));
@@ -953,6 +956,14 @@ afmpb_status afmpb_profile_enable(afmpb_ctx *ctx, int enable) {
             for (auto &e : ctx->prof.entries) { e.ms = 0; e.count = 0; }
         }
         ctx->prof.on = enable != 0;
+    });
+}
+
+afmpb_status afmpb_profile_only(afmpb_ctx *ctx, const char *scope) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ctx->prof.flush();
+        ctx->prof.only = scope ? scope : "";
     });
 }
 

@@ -10,6 +10,7 @@ namespace afmpb {
 
 struct Prof {
     bool on = false;
+    std::string only;   // non-empty: time only the scopes of this name
     struct Entry {
         std::string name;
         double ms = 0;

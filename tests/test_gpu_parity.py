@@ -253,6 +253,33 @@ def test_error_contract():
     s.close()
 
 
+def test_profile_scopes_and_filter():
+    """Per-kernel timing: every scope when unrestricted; only the named one
+    (with one launch per matvec for M2L here) after afmpb_profile_only; the
+    result of the matvec is the same with and without timing."""
+    mol = MOLS["born4"]()
+    s = _solver(mol, order_p=8, precision=1, leaf_cap=16)
+    assert s.tree_info()["n_m2l_pairs"] > 0
+    x = np.random.default_rng(11).normal(size=2 * mol.n_nodes)
+    y0 = s.matvec(x)
+    s.profile(True)
+    s.matvec(x)
+    allp = s.profile_read()
+    s.profile(False)
+    for k in ("p2m", "m2l", "m2l_reduce", "l2p", "p2p", "near", "combine"):
+        assert allp[k][1] >= 1 and allp[k][0] > 0, (k, allp.get(k))
+    s.profile_only("m2l")
+    s.profile(True)
+    y1 = s.matvec(x)
+    only = s.profile_read()
+    s.profile(False)
+    s.profile_only(None)
+    assert only["m2l"][1] == allp["m2l"][1] and only["m2l"][0] > 0
+    assert all(v[1] == 0 for k, v in only.items() if k != "m2l"), only
+    assert np.array_equal(y0, y1)
+    s.close()
+
+
 # ------------------------- 100k-atom complex (~1M nodes) --------------------
 
 _COMPLEX = {}
