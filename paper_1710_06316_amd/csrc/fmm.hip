@@ -544,7 +544,8 @@ __device__ inline void trans_rows(const TransArgs &a, const R *__restrict__ op0,
 // Register-resident form (one row tile per wave, at most KSR k-steps): the
 // wave's operator rows were loaded into areg before the operand gather; the
 // product runs KSR k-steps from registers and LDS only (operand rows past K
-// are zero in LDS, so the operator values there do not matter).
+// are zero in LDS, and so are the operator fragments past the operator's own
+// k-steps: a non-finite value there would survive the multiplication by zero).
 template <typename R, int CC, int MODE, int NA, int KSR>
 __device__ inline void trans_rows_res(const TransArgs &a, const R (&areg)[KSR], const R *Ms,
                                       int KKp, R *__restrict__ out, const int *colbox,
@@ -622,7 +623,10 @@ __global__ void __launch_bounds__(512) k_trans(TransArgs a, const R *__restrict_
     if constexpr (KSR > 0) {
         const R *A = op0 + (long long)wave * KS * 64 + lane;
 #pragma unroll
-        for (int j = 0; j < KSR; ++j) areg[j] = A[j * 64];   // in bounds: tail pad
+        // k-steps past the operator's KS are zero in registers: the values
+        // beyond belong to the next matrix (or are unwritten), and although
+        // the matching operand rows in LDS are zero, NaN * 0 would be NaN
+        for (int j = 0; j < KSR; ++j) areg[j] = j < KS ? A[j * 64] : R(0);
     }
     __syncthreads();
     if (MODE != 0 && tid < CC) srcbox[tid] = (MODE == 1) ? child[o][tid] : colbox[tid];
@@ -1096,6 +1100,9 @@ void build_fmm_operators(const Tree &t, const Lists &Ls, int P, double kappa, bo
     F.nkey = nlev > 2 ? (long long)(nlev - 2) * 316 : 0;
     F.T.alloc((size_t)2 * std::max(F.nkey, 1ll) * K * K);
     F.Ut.alloc((size_t)2 * nlev * 8 * K * K);
+    // levels without operators stay zero in the packed copies too
+    F.T.zero((size_t)2 * std::max(F.nkey, 1ll) * K * K, s);
+    F.Ut.zero((size_t)2 * nlev * 8 * K * K, s);
     std::vector<int> offs;  // offset class -> (dx,dy,dz)
     for (int dx = -3; dx <= 3; ++dx)
         for (int dy = -3; dy <= 3; ++dy)
