@@ -8,6 +8,8 @@
 #include <numeric>
 
 #include <cstring>
+#include <future>
+#include <system_error>
 
 #include "ctx.h"
 
@@ -93,16 +95,27 @@ double unit_scale() {
     return 4.0 * M_PI * ce;
 }
 
-void validate_mesh(long long n, const double *V, long long m, const int *T) {
+// What the device setup relies on for memory safety: sizes, finite
+// coordinates, triangle indices in range, every node used.
+void validate_mesh_indices(long long n, const double *V, long long m, const int *T) {
     require(n >= 4 && m >= 4, ST_MESH, "mesh needs at least 4 nodes and 4 triangles");
+    require(n < (1ll << 30) && m < (1ll << 30), ST_INVALID, "mesh too large");
     for (long long i = 0; i < 3 * n; ++i)
         require(std::isfinite(V[i]), ST_INVALID, "non-finite node coordinate");
-    std::vector<int> deg(n + 1, 0);
+    std::vector<char> used(n, 0);
     for (long long i = 0; i < 3 * m; ++i) {
         require(T[i] >= 0 && T[i] < n, ST_MESH, "triangle index out of range");
-        ++deg[T[i]];
+        used[T[i]] = 1;
     }
-    for (long long i = 0; i < n; ++i) require(deg[i] > 0, ST_MESH, "node not used by any triangle");
+    for (long long i = 0; i < n; ++i) require(used[i], ST_MESH, "node not used by any triangle");
+}
+
+// The rest of the surface conditions (closed, manifold, consistently and
+// outward oriented, no duplicate vertex, no zero-area triangle); the indices
+// must have passed validate_mesh_indices.
+void validate_mesh_topology(long long n, const double *V, long long m, const int *T) {
+    std::vector<int> deg(n + 1, 0);
+    for (long long i = 0; i < 3 * m; ++i) ++deg[T[i]];
     // duplicate vertices: open-addressing hash of the exact coordinates
     // (-0.0 taken as +0.0, so that equal values hash alike)
     {
@@ -325,67 +338,82 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
     };
     std::fill(c->ms_phase, c->ms_phase + AFMPB_SETUP_PHASES, 0.0);
     c->loaded = false;
-    validate_mesh(n, xyz, m, tri);
-    require(n < (1ll << 30) && m < (1ll << 30), ST_INVALID, "mesh too large");
-    for (long long i = 0; i < 3 * na; ++i)
-        require(std::isfinite(axyz[i]), ST_INVALID, "non-finite atom coordinate");
-    for (long long i = 0; i < na; ++i) require(std::isfinite(q[i]), ST_INVALID, "non-finite charge");
-    hipStream_t s = c->stream;
-    c->prm = prm;
-    c->n = n; c->m = m; c->na = na;
-    c->ebar = prm.eps_s / prm.eps_p;
-    c->inv_ebar = 1.0 / c->ebar;
-    c->alpha = 0.5 / c->ebar + 0.5;
-    c->V.alloc(3 * n); c->V.upload(xyz, 3 * n, s);
-    c->T.alloc(3 * m); c->T.upload(tri, 3 * m, s);
-    c->ax.alloc(3 * std::max(na, 1ll)); c->ax.upload(axyz, 3 * na, s);
-    c->aq.alloc(std::max(na, 1ll)); c->aq.upload(q, na, s);
-    // a0 geometry (caller order)
-    c->tri_area.alloc(m); c->tri_n.alloc(3 * m);
-    c->inc_ptr.alloc(n + 1); c->inc_tri.alloc(3 * m);
-    c->area_c.alloc(n); c->nrm_c.alloc(3 * n); c->rho2_c.alloc(n);
-    compute_geometry(c->V.p, c->T.p, n, m, c->tri_area.p, c->tri_n.p, c->inc_ptr.p, c->inc_tri.p,
-                     c->area_c.p, c->nrm_c.p, c->rho2_c.p, s);
-    mark();   // validation, upload, geometry
-    // a1 Morton keys and sort
-    c->keys.alloc(n); c->perm.alloc(n);
-    morton_sort(c->V.p, n, c->keys.p, c->perm.p, c->lo, &c->scale, s);
-    c->node64.alloc(8 * n);
-    gather_nodes(c->V.p, c->nrm_c.p, c->area_c.p, c->rho2_c.p, c->perm.p, n, c->nodes(), s);
-    c->node32.alloc(6 * n);
-    k_to_f32<<<grid_for(6 * n, 256), 256, 0, s>>>(c->node64.p, c->node32.p, 6 * n);
-    KCHK();
-    mark();   // keys, sort, node gather
-    // a2 tree, a3 lists
-    c->tree = Tree();
-    build_tree(c->keys.p, n, prm.leaf_cap, c->lo, c->scale, c->tree, s);
-    c->lists = Lists();
-    mark();   // tree
-    build_lists(c->tree, c->lists, s);
-    mark();   // lists and P2P / M2L work items
-    // a4 near set and corrections
-    c->near = NearSet();
-    build_near(c->nodes(), n, prm.near_eta, c->V.p, c->T.p, c->tri_n.p, c->inc_ptr.p,
-               c->inc_tri.p, c->perm.p, prm.kappa, c->ebar, c->near, s);
-    mark();   // near set and patch corrections
-    // translation operators
-    c->fmm = Fmm();
-    c->p2p64 = DBuf<double>();
-    c->p2p_part = DBuf<double>();
-    build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa,
-                        prm.precision == AFMPB_FP32_BF16M2L_REFINED, c->fmm, s);
-    mark();   // translation operators
-    setup_plan<double>(c, c->mp64, c->w64, c->far64, c->node64.p);
-    setup_plan<float>(c, c->mp32, c->w32, c->far32, c->node32.p);
-    c->xa.alloc(2 * n); c->ya.alloc(2 * n); c->bvec.alloc(2 * n);
-    c->xsol.alloc(2 * n); c->tmp.alloc(2 * n);
-    c->hbuf.alloc(2 * 1024 + 8);
-    c->phi_at.alloc(std::max(na, 1ll));
-    c->krylov = DBuf<double>();
-    c->krylov_m = 0;
-    c->sync();
-    check_setup(c);
-    mark();   // work buffers and structural checks
+    validate_mesh_indices(n, xyz, m, tri);
+    // the remaining mesh checks run on the host beside the device setup
+    // (which needs only valid indices); a failure is raised before the
+    // context is marked loaded
+    std::future<void> topo;
+    try {
+        topo = std::async(std::launch::async, validate_mesh_topology, n, xyz, m, tri);
+    } catch (const std::system_error &) {
+        validate_mesh_topology(n, xyz, m, tri);   // no thread available: in line
+    }
+    try {
+        for (long long i = 0; i < 3 * na; ++i)
+            require(std::isfinite(axyz[i]), ST_INVALID, "non-finite atom coordinate");
+        for (long long i = 0; i < na; ++i) require(std::isfinite(q[i]), ST_INVALID, "non-finite charge");
+        hipStream_t s = c->stream;
+        c->prm = prm;
+        c->n = n; c->m = m; c->na = na;
+        c->ebar = prm.eps_s / prm.eps_p;
+        c->inv_ebar = 1.0 / c->ebar;
+        c->alpha = 0.5 / c->ebar + 0.5;
+        c->V.alloc(3 * n); c->V.upload(xyz, 3 * n, s);
+        c->T.alloc(3 * m); c->T.upload(tri, 3 * m, s);
+        c->ax.alloc(3 * std::max(na, 1ll)); c->ax.upload(axyz, 3 * na, s);
+        c->aq.alloc(std::max(na, 1ll)); c->aq.upload(q, na, s);
+        // a0 geometry (caller order)
+        c->tri_area.alloc(m); c->tri_n.alloc(3 * m);
+        c->inc_ptr.alloc(n + 1); c->inc_tri.alloc(3 * m);
+        c->area_c.alloc(n); c->nrm_c.alloc(3 * n); c->rho2_c.alloc(n);
+        compute_geometry(c->V.p, c->T.p, n, m, c->tri_area.p, c->tri_n.p, c->inc_ptr.p, c->inc_tri.p,
+                         c->area_c.p, c->nrm_c.p, c->rho2_c.p, s);
+        mark();   // validation, upload, geometry
+        // a1 Morton keys and sort
+        c->keys.alloc(n); c->perm.alloc(n);
+        morton_sort(c->V.p, n, c->keys.p, c->perm.p, c->lo, &c->scale, s);
+        c->node64.alloc(8 * n);
+        gather_nodes(c->V.p, c->nrm_c.p, c->area_c.p, c->rho2_c.p, c->perm.p, n, c->nodes(), s);
+        c->node32.alloc(6 * n);
+        k_to_f32<<<grid_for(6 * n, 256), 256, 0, s>>>(c->node64.p, c->node32.p, 6 * n);
+        KCHK();
+        mark();   // keys, sort, node gather
+        // a2 tree, a3 lists
+        c->tree = Tree();
+        build_tree(c->keys.p, n, prm.leaf_cap, c->lo, c->scale, c->tree, s);
+        c->lists = Lists();
+        mark();   // tree
+        build_lists(c->tree, c->lists, s);
+        mark();   // lists and P2P / M2L work items
+        // a4 near set and corrections
+        c->near = NearSet();
+        build_near(c->nodes(), n, prm.near_eta, c->V.p, c->T.p, c->tri_n.p, c->inc_ptr.p,
+                   c->inc_tri.p, c->perm.p, prm.kappa, c->ebar, c->near, s);
+        mark();   // near set and patch corrections
+        // translation operators
+        c->fmm = Fmm();
+        c->p2p64 = DBuf<double>();
+        c->p2p_part = DBuf<double>();
+        build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa,
+                            prm.precision == AFMPB_FP32_BF16M2L_REFINED, c->fmm, s);
+        mark();   // translation operators
+        setup_plan<double>(c, c->mp64, c->w64, c->far64, c->node64.p);
+        setup_plan<float>(c, c->mp32, c->w32, c->far32, c->node32.p);
+        c->xa.alloc(2 * n); c->ya.alloc(2 * n); c->bvec.alloc(2 * n);
+        c->xsol.alloc(2 * n); c->tmp.alloc(2 * n);
+        c->hbuf.alloc(2 * 1024 + 8);
+        c->phi_at.alloc(std::max(na, 1ll));
+        c->krylov = DBuf<double>();
+        c->krylov_m = 0;
+        c->sync();
+        check_setup(c);
+        if (topo.valid()) topo.get();   // rethrows a mesh error
+        mark();   // work buffers, structural checks, mesh checks
+    } catch (...) {
+        // a mesh error found meanwhile explains a failure of the device setup
+        if (topo.valid()) topo.get();
+        throw;
+    }
     c->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     c->loaded = true;
 }
