@@ -182,3 +182,26 @@ def test_parallel_setup_rejected():
     with pytest.raises(A.AfmpbError) as e:
         A.Server(setup_threads=2)
     assert e.value.status == A.AFMPB_E_INVALID
+
+
+def test_tuned_stream_all_finite():
+    """The benchmark's request stream (48 star requests, tuned leaf/order per
+    size) served twice at saturation: every request converges with a finite
+    energy (regression: M2M/L2L operator fragments past the operator's last
+    k-step, read from the next matrix or from unwritten levels, turned some
+    requests' far field into NaN although their operand rows were zero)."""
+    import paper_1710_06316_amd as A
+    from paper_1710_06316_amd import autotune
+    table = autotune.load_table()
+    mols = [W.star_request(i) for i in range(48)]
+    for rep in range(2):
+        srv = _server(hbm_budget_bytes=64 << 30, max_active=32, tuning=table,
+                      precision=A.AFMPB_FP32_REFINED, order_p=0, leaf_cap=0)
+        tickets = [srv.submit(m) for m in mols]
+        res = [srv.poll(t, wait=True)[1] for t in tickets]
+        srv.close()
+        bad = [(i, r.status, r.message) for i, r in enumerate(res) if r.status != 0]
+        _say(f"tuned stream pass {rep}: failures {bad}")
+        assert not bad
+        assert all(np.isfinite(r.energy) for r in res)
+
