@@ -82,6 +82,42 @@ __device__ inline void for_each_regular(S x, S y, S z, int P, const NT *norm, co
     }
 }
 
+// for_each_regular for a compile-time order P: the loops unroll completely,
+// the recurrence coefficients become constants (the same double values the
+// table holds, rounded to R) and every index is static.
+template <int P, typename R, typename S, typename F, typename NT>
+__device__ inline void for_each_regular_p(S x, S y, S z, const NT *norm, F &&emit) {
+    S r2 = (x * x + y * y) + z * z;
+    S cm(R(1)), sm(R(0));
+    R dfact = R(1);
+#pragma unroll
+    for (int m = 0; m <= P; ++m) {
+        S pc = cm * dfact, ps = sm * dfact;
+        S qc(R(0)), qs(R(0));
+#pragma unroll
+        for (int n = m; n <= P; ++n) {
+            if (n > m) {
+                const R a = R((2.0 * n - 1.0) / (n - m)), b = R((n + m - 1.0) / (n - m));
+                S nc = a * (z * pc) - b * (r2 * qc);
+                S ns = a * (z * ps) - b * (r2 * qs);
+                qc = pc; qs = ps;
+                pc = nc; ps = ns;
+            }
+            const int k0 = n * n + n;
+            if (m == 0) {
+                emit(k0, n, R(norm[k0]) * pc);
+            } else {
+                emit(k0 + m, n, R(norm[k0 + m]) * pc);
+                emit(k0 - m, n, R(norm[k0 - m]) * ps);
+            }
+        }
+        S c2 = cm * x - sm * y;
+        sm = cm * y + sm * x;
+        cm = c2;
+        dfact *= R(2 * m + 1);
+    }
+}
+
 // g_n(x) = i_n(x) / x^n for n = 0..P as functions of t = x^2: series for
 // n = P and P-1, then the downward recurrence g_{n-1} = t g_{n+1} + (2n+1) g_n.
 // inv_dfact[n] = 1/(2n+1)!!; ser[k] = 1/(2 k (2n+2k+1)) is the ratio of
@@ -104,6 +140,15 @@ template <typename R, typename S, typename ST>
 __device__ inline void g_all(int P, S t, const R *inv_dfact, const ST *ser, S *g) {
     g[P] = g_series<R, S>(P, t, inv_dfact, ser);
     if (P >= 1) g[P - 1] = g_series<R, S>(P - 1, t, inv_dfact, ser + GSER);
+    for (int n = P - 1; n >= 1; --n) g[n - 1] = t * g[n + 1] + R(2 * n + 1) * g[n];
+}
+
+// g_all for a compile-time order (static indices: g stays in registers).
+template <int P, typename R, typename S, typename ST>
+__device__ inline void g_all_p(S t, const R *inv_dfact, const ST *ser, S *g) {
+    g[P] = g_series<R, S>(P, t, inv_dfact, ser);
+    if (P >= 1) g[P - 1] = g_series<R, S>(P - 1, t, inv_dfact, ser + GSER);
+#pragma unroll
     for (int n = P - 1; n >= 1; --n) g[n - 1] = t * g[n + 1] + R(2 * n + 1) * g[n];
 }
 

@@ -106,6 +106,29 @@ __device__ inline void regular_basis_tab(const BasisDev &B, const BasisTab<R> &T
     }
 }
 
+// The same for a compile-time order PC (PC = 0: B.P at run time).
+template <int PC, typename R, typename S, typename F>
+__device__ inline void regular_basis_o(const BasisDev &B, const BasisTab<R> &T, int kern,
+                                       int lev, S vx, S vy, S vz, F &&emit) {
+    if constexpr (PC == 0) {
+        regular_basis_tab<R, S>(B, T, kern, lev, vx, vy, vz, emit);
+    } else {
+        const R is = R(1.0 / B.side[lev]);
+        S ux = vx * is, uy = vy * is, uz = vz * is;
+        if (kern == 0 || !B.screened) {
+            for_each_regular_p<PC, R>(ux, uy, uz, T.norm, [&](int k, int, S r) { emit(k, r); });
+        } else {
+            R ks = R(B.kappa * B.side[lev]);
+            S t = (ks * ks) * ((ux * ux + uy * uy) + uz * uz);
+            S g[PC + 1];
+            g_all_p<PC, R, S>(t, T.idf, T.ser, g);
+            const R *gi = T.ginv + lev * (PC + 1);
+            for_each_regular_p<PC, R>(ux, uy, uz, T.norm,
+                                      [&](int k, int n, S r) { emit(k, r * (g[n] * gi[n])); });
+        }
+    }
+}
+
 // ------------------------- operator construction ---------------------------
 
 struct MatDesc {
@@ -981,7 +1004,7 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(int K, int KZ, long long nbo
 // L2P: one block per item, wave w evaluates the local expansion of kernel w
 // (potential and normal derivative) at one target point per lane, with the
 // coefficients of that point's leaf.
-template <typename R>
+template <typename R, int PC>
 __global__ void __launch_bounds__(128) k_l2p(BasisDev B, TreeDev T, const int *pm_leaf,
                                              const int *pm_first, const int *pm_count,
                                              const R *px, const R *py, const R *pz,
@@ -1009,9 +1032,9 @@ __global__ void __launch_bounds__(128) k_l2p(BasisDev B, TreeDev T, const int *p
         const R *Lb = Ls + (g * 2 + kern) * K;
         R p = R(0), dp = R(0);
         const R vx = px[i] - cx, vy = py[i] - cy, vz = pz[i] - cz;
-        regular_basis_tab<R, Dual<R>>(B, tab, kern, lev, Dual<R>(vx, pnx[i]),
-                                      Dual<R>(vy, pny[i]), Dual<R>(vz, pnz[i]),
-                                      [&](int k, Dual<R> r) {
+        regular_basis_o<PC, R, Dual<R>>(B, tab, kern, lev, Dual<R>(vx, pnx[i]),
+                                        Dual<R>(vy, pny[i]), Dual<R>(vz, pnz[i]),
+                                        [&](int k, Dual<R> r) {
                                       const R l = Lb[k];
                                       p += l * r.v;
                                       dp += l * r.d;
@@ -1243,6 +1266,8 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
     {
         ProfScope ps(prof, "p2m", s);
+        // P2M keeps the generic table recurrence: the unrolled orders need
+        // up to 185 VGPRs here (two waves per SIMD) and run slower
         k_p2m<R><<<blocks_ok(L.n_pm, 128), 128, basis_tab_bytes(F.P, F.nlev, sizeof(R)), s>>>(
             B, T, L.pm_leaf.p, L.pm_first.p, L.pm_count.p, px, py, pz, pnx, pny, pnz, sf, sh,
             R(inv_ebar), w.M, F.nlev);
@@ -1310,9 +1335,20 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     {
         ProfScope ps(prof, "l2p", s);
         const size_t l2p_lds = basis_tab_bytes(F.P, F.nlev, sizeof(R)) + 4 * 2 * K * sizeof(R);
-        k_l2p<R><<<blocks_ok(L.n_pm, 128), 128, l2p_lds, s>>>(
-            B, T, L.pm_leaf.p, L.pm_first.p, L.pm_count.p, px, py, pz, pnx, pny, pnz, w.Lc, n,
-            w.phi, F.nlev);
+        // common orders run with a compile-time recurrence (static indices,
+        // constant coefficients), others with the generic table recurrence
+        auto go = [&](auto kfn) {
+            kfn<<<blocks_ok(L.n_pm, 128), 128, l2p_lds, s>>>(
+                B, T, L.pm_leaf.p, L.pm_first.p, L.pm_count.p, px, py, pz, pnx, pny, pnz, w.Lc,
+                n, w.phi, F.nlev);
+        };
+        switch (F.P) {
+            case 6: go(k_l2p<R, 6>); break;
+            case 8: go(k_l2p<R, 8>); break;
+            case 10: go(k_l2p<R, 10>); break;
+            case 14: go(k_l2p<R, 14>); break;
+            default: go(k_l2p<R, 0>); break;
+        }
         KCHK();
     }
 }
