@@ -334,6 +334,26 @@ struct TreeDev {
 // P2M / L2P work item: up to 4 leaves (consecutive in point order) with at
 // most 64 points together share one wave, point q of the item on lane q; a
 // leaf of more than 64 points is an item of its own, taken 64 points at a time.
+// 16x16x4 matrix instructions (FP32 and FP64 accumulate in four result
+// registers per lane; the operand layout is described with the batched
+// translations below).
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <typename R> struct Acc4;
+template <> struct Acc4<double> { typedef d4v T; };
+template <> struct Acc4<float> { typedef f4v T; };
+
+__device__ inline d4v mfma16(double a, double b, d4v c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4v mfma16(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// output row (within the 16-row tile) of result register r
+template <typename R> __device__ inline int drow(int lane, int r);
+template <> __device__ inline int drow<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+template <> __device__ inline int drow<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+
 struct PmItem {
     int first, cnt, tot;
     int offs[5];                 // point offset of each leaf in the item
@@ -355,9 +375,11 @@ struct PmItem {
 
 // P2M: one block per item, wave w computes the expansions of kernel w.  Each
 // lane evaluates the regular basis at one source point (about its own
-// leaf's centre); the coefficients are emitted 16 at a time into LDS, and
-// lane (slot, g) sums slot's coefficient over the points of leaf g in point
-// order (deterministic).
+// leaf's centre); the coefficients are emitted 16 at a time into LDS
+// (W[slot][point]), and the per-leaf sums over points are one product on the
+// matrix cores: W (16 x 64) times the 0/1 indicator of point-in-leaf
+// (64 x 4, padded to 16 columns), 16 k-steps of four points.  The products
+// by 1 and 0 are exact and the accumulation order is fixed (deterministic).
 template <typename R>
 __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *pm_leaf,
                                              const int *pm_first, const int *pm_count,
@@ -392,16 +414,30 @@ __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *p
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int slot = lane >> 2, gg = lane & 3;
-            if (slot < nslot && gg < it.cnt) {
-                const int b0 = max(it.offs[gg] - c0, 0), b1 = min(it.offs[gg + 1] - c0, 64);
-                R acc = R(0);
-                for (int j = b0; j < b1; ++j) acc += Wv[kern][slot][j];
-                const int lg = pm_leaf[it.first + gg];
-                if (b0 < b1 && T.level[lg] >= 2) {
+            // A[i][k] = W[i][4 ks + k] (i = lane % 16, k = lane / 16);
+            // B[k][j] = 1 when point 4 ks + k of the chunk is in leaf j
+            const int j = lane & 15, kq = lane >> 4;
+            const int lo = j < it.cnt ? it.offs[j] - c0 : 0;
+            const int hi = j < it.cnt ? it.offs[j + 1] - c0 : 0;
+            typename Acc4<R>::T acc{0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) {
+                const int pt = 4 * ks + kq;
+                acc = mfma16(Wv[kern][j][pt], (pt >= lo && pt < hi) ? R(1) : R(0), acc);
+            }
+            // D[i][j]: the sum of slot i over the points of leaf j
+            if (j < it.cnt && max(lo, 0) < min(hi, 64)) {
+                const int lg = pm_leaf[it.first + j];
+                if (T.level[lg] >= 2) {
                     R *Mb = M + ((long long)lg * 2 + kern) * K;
-                    const int k = kslot[kern][slot];
-                    Mb[k] = (c0 == 0) ? acc : Mb[k] + acc;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int slot = drow<R>(lane, r);
+                        if (slot < nslot) {
+                            const int k = kslot[kern][slot];
+                            Mb[k] = (c0 == 0) ? acc[r] : Mb[k] + acc[r];
+                        }
+                    }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -437,23 +473,6 @@ __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *p
 //   D[i][j]: j = l % 16 and, for result register r = 0..3,
 //            f32: i = 4 (l / 16) + r        f64: i = (l / 16) + 4 r.
 // ---------------------------------------------------------------------------
-typedef double d4v __attribute__((ext_vector_type(4)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-template <typename R> struct Acc4;
-template <> struct Acc4<double> { typedef d4v T; };
-template <> struct Acc4<float> { typedef f4v T; };
-
-__device__ inline d4v mfma16(double a, double b, d4v c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ inline f4v mfma16(float a, float b, f4v c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-// output row (within the 16-row tile) of result register r
-template <typename R> __device__ inline int drow(int lane, int r);
-template <> __device__ inline int drow<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
-template <> __device__ inline int drow<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
-
 struct TransArgs {
     int K, KK, nlev;
     int KZ;                      // M2L: slot length of one result (K rounded up to 16)
