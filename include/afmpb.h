@@ -86,6 +86,14 @@ typedef struct {
     int restart;         /* Krylov vectors per GMRES cycle (>= 1); 0 selects 80     */
     int max_restarts;    /* restarts after the first cycle (>= 0)                   */
     double near_eta;     /* near-set radius factor eta (> 0); 0 selects 4           */
+    int m2l_layout;      /* M2L work layout: 0 automatic; 1 one result slot per
+                            V-list entry, items of one (level, offset class);
+                            2 one slot per (target, colleague of its parent),
+                            all children of the colleague accumulated in
+                            registers.  Automatic takes 2 from 2^21 V-list
+                            entries on (large trees, where the result traffic
+                            of 1 dominates).  Every layout computes the same
+                            sums (rounding order aside)                         */
 } afmpb_params;
 
 typedef struct {
@@ -109,6 +117,9 @@ typedef struct {
     long long n_p2p_pairs;           /* point pairs evaluated by P2P per matvec  */
     long long n_m2l_pairs;           /* V-list box pairs per matvec              */
     int order_p, leaf_cap;
+    long long n_m2l_slots;           /* M2L result slots per kernel and matvec
+                                        (= n_m2l_pairs in the per-entry layout)  */
+    int m2l_layout;                  /* layout in use: 1 per entry, 2 grouped    */
 } afmpb_tree_sizes;
 
 /* Caller-allocated host buffers for afmpb_debug_tree (sizes from

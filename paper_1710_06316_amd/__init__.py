@@ -54,7 +54,7 @@ class afmpb_params(ctypes.Structure):
                 ("leaf_cap", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rel_tol", ctypes.c_double), ("abs_tol", ctypes.c_double),
                 ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
-                ("near_eta", ctypes.c_double)]
+                ("near_eta", ctypes.c_double), ("m2l_layout", ctypes.c_int)]
 
 
 class afmpb_solve_info(ctypes.Structure):
@@ -74,7 +74,9 @@ class afmpb_tree_sizes(ctypes.Structure):
     _fields_ = [(k, ctypes.c_longlong) for k in
                 ("n_nodes", "n_boxes", "n_levels", "n_u", "n_v", "n_w", "n_x", "n_near",
                  "n_p2p_pairs", "n_m2l_pairs")] + [("order_p", ctypes.c_int),
-                                                   ("leaf_cap", ctypes.c_int)]
+                                                   ("leaf_cap", ctypes.c_int),
+                                                   ("n_m2l_slots", ctypes.c_longlong),
+                                                   ("m2l_layout", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -238,6 +238,7 @@ void fill_defaults(afmpb_params &p) {
     p.restart = 80;
     p.max_restarts = 5;
     p.near_eta = 4.0;
+    p.m2l_layout = 0;
 }
 
 afmpb_params normalise(const afmpb_params &in) {
@@ -258,6 +259,7 @@ afmpb_params normalise(const afmpb_params &in) {
     if (p.restart == 0) p.restart = 80;
     require(p.restart >= 1 && p.restart <= 1000, ST_INVALID, "restart must be in [1, 1000]");
     require(p.max_restarts >= 0, ST_INVALID, "max_restarts must be >= 0");
+    require(p.m2l_layout >= 0 && p.m2l_layout <= 2, ST_INVALID, "m2l_layout must be 0, 1 or 2");
     if (p.near_eta == 0) p.near_eta = 4.0;
     require(fin(p.near_eta) && p.near_eta > 0, ST_INVALID, "near_eta must be > 0");
     return p;
@@ -280,7 +282,8 @@ __global__ void k_finite(const double *a, long long n, int *bad) {
 
 template <typename R>
 void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const R *ndR) {
-    const long long n = c->n, K = c->fmm.K, nb = c->tree.nbox, nv = c->lists.n_v;
+    const long long n = c->n, K = c->fmm.K, nb = c->tree.nbox;
+    const long long ng = c->lists.n_vg * c->lists.m2l_split;   // result slots
     w.alloc((size_t)2 * n);
     if (c->p2p64.n < (size_t)2 * n) c->p2p64.alloc((size_t)2 * n);
     if (c->p2p_part.n < (size_t)c->lists.n_chunks * 128)
@@ -290,7 +293,7 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     for (int l = 0; l < c->tree.nlev; ++l)
         widest = std::max(widest, c->tree.level_start[l + 1] - c->tree.level_start[l]);
     const long long KZ = c->fmm.KZ;
-    far.alloc((size_t)(2 * nb * K) * 2 + (size_t)std::max(nv, 1ll) * 2 * KZ + 4 * n +
+    far.alloc((size_t)(2 * nb * K) * 2 + (size_t)std::max(ng, 1ll) * 2 * KZ + 4 * n +
               (size_t)8 * widest * 2 * K);
     mp.n = n;
     mp.tree = &c->tree;
@@ -316,7 +319,7 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.far.M = f;
     mp.far.Lc = f + 2 * nb * K;
     mp.far.Z = f + 4 * nb * K;         // 16-byte aligned: 4 nb K elements precede it
-    mp.far.phi = f + 4 * nb * K + std::max(nv, 1ll) * 2 * KZ;
+    mp.far.phi = f + 4 * nb * K + std::max(ng, 1ll) * 2 * KZ;
     mp.far.Mt = mp.far.phi + 4 * n;
     mp.far.bf16_m2l = (sizeof(R) == sizeof(float) &&
                        c->prm.precision == AFMPB_FP32_BF16M2L_REFINED) ? 1 : 0;
@@ -383,7 +386,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
         build_tree(c->keys.p, n, prm.leaf_cap, c->lo, c->scale, c->tree, s);
         c->lists = Lists();
         mark();   // tree
-        build_lists(c->tree, c->lists, s);
+        build_lists(c->tree, c->lists, prm.m2l_layout, s);
         mark();   // lists and P2P / M2L work items
         // a4 near set and corrections
         c->near = NearSet();
@@ -539,22 +542,56 @@ void check_setup(afmpb_ctx *c) {
         if (covered != nl) bad("P2M items do not cover the leaves");
     }
     if (L.n_m2l_items > 0) {
-        auto ik = host_copy(L.m2l_item_key, L.n_m2l_items, s);
+        auto iops = host_copy(L.m2l_item_ops, 8 * L.n_m2l_items, s);
         auto ibg = host_copy(L.m2l_item_begin, L.n_m2l_items, s);
         auto icn = host_copy(L.m2l_item_count, L.n_m2l_items, s);
-        auto pairs = host_copy(L.m2l_pairs, L.n_v, s);
+        auto cols = host_copy(L.m2l_cols, L.n_vg, s);
+        auto vp = host_copy(L.v_ptr, nb + 1, s);
+        auto vcls = host_copy(L.v_cls, L.n_v, s), vtgt = host_copy(L.v_tgt, L.n_v, s);
+        std::vector<int> vgp, vgs;
+        if (L.m2l_grouped) {
+            vgp = host_copy(L.vg_ptr, nb + 1, s);
+            vgs = host_copy(L.vg_src, 8 * L.n_vg, s);
+        }
         c->sync();
+        if (!L.m2l_grouped && L.n_vg != L.n_v) bad("M2L entries");
         long long covered = 0;
         for (long long w = 0; w < L.n_m2l_items; ++w) {
-            if (ik[w] < 0 || ik[w] >= c->fmm.nkey) bad("M2L item key");
-            if (icn[w] < 1 || icn[w] > 64 || ibg[w] < 0 || ibg[w] + icn[w] > L.n_v) bad("M2L item range");
+            for (int o = 0; o < 8; ++o)
+                if (iops[8 * w + o] < -1 || iops[8 * w + o] >= c->fmm.nkey) bad("M2L item operator");
+            if (icn[w] < 1 || icn[w] > 64 || ibg[w] < 0 || ibg[w] + icn[w] > L.n_vg) bad("M2L item range");
             covered += icn[w];
+            for (long long q = ibg[w]; q < ibg[w] + icn[w]; ++q) {
+                const int g = cols[q];
+                if (g < 0 || g >= L.n_vg) bad("M2L item column");
+                if (L.m2l_grouped) {
+                    for (int o = 0; o < 8; ++o)
+                        if (vgs[8 * (long long)g + o] >= 0 && iops[8 * w + o] < 0) bad("M2L child without operator");
+                } else {
+                    if (iops[8 * w] != (lev[vtgt[g]] - 2) * 316 + vcls[g]) bad("M2L entry operator");
+                    for (int o = 1; o < 8; ++o)
+                        if (iops[8 * w + o] != -1) bad("M2L entry octant");
+                }
+            }
         }
-        if (covered != L.n_v) bad("M2L items do not cover V");
-        std::vector<char> sv(L.n_v, 0);
-        for (long long q = 0; q < L.n_v; ++q) {
-            if (pairs[q] < 0 || pairs[q] >= L.n_v || sv[pairs[q]]) bad("M2L pair permutation");
-            sv[pairs[q]] = 1;
+        if (covered != L.n_vg) bad("M2L items do not cover the groups");
+        std::vector<char> sv(L.n_vg, 0);
+        for (long long q = 0; q < L.n_vg; ++q) {
+            if (sv[cols[q]]) bad("M2L group permutation");
+            sv[cols[q]] = 1;
+        }
+        if (L.m2l_grouped) {
+            if (vgp[0] != 0 || vgp[nb] != L.n_vg) bad("M2L group ptr");
+            for (long long B = 0; B < nb; ++B) {
+                long long ent = 0;
+                for (long long g = vgp[B]; g < vgp[B + 1]; ++g)
+                    for (int o = 0; o < 8; ++o) {
+                        const int sb = vgs[8 * g + o];
+                        if (sb < -1 || sb >= nb) bad("M2L group child");
+                        ent += sb >= 0;
+                    }
+                if (ent != vp[B + 1] - vp[B]) bad("M2L groups do not cover V");
+            }
         }
     }
     auto nptr = host_copy(c->near.ptr, n + 1, s);
@@ -939,6 +976,8 @@ afmpb_status afmpb_tree_info(afmpb_ctx *ctx, afmpb_tree_sizes *out) {
         out->n_m2l_pairs = ctx->lists.n_v;
         out->order_p = ctx->prm.order_p;
         out->leaf_cap = ctx->prm.leaf_cap;
+        out->n_m2l_slots = ctx->lists.n_vg * ctx->lists.m2l_split;
+        out->m2l_layout = ctx->lists.m2l_grouped ? 2 : 1;
     });
 }
 

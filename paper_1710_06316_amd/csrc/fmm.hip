@@ -462,8 +462,9 @@ __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *p
 // 16 x 16 output tiles and runs v_mfma_*_16x16x4 over the (zero-padded) K
 // dimension.  Operands: A = translation operator rows (read from cache),
 // B = gathered expansions in LDS ([KK][CC]).
-//   MODE 0  M2L  one operator per work item (level, offset class);
-//                column c = one V entry; result -> Z (bucket order)
+//   MODE 0  M2L, per-entry layout: one operator per work item (level,
+//                offset class); column c = one V entry; result -> its
+//                slot of Z (the grouped layout runs in k_m2l below)
 //   MODE 1  M2M  eight operators (child octants) accumulated;
 //                column c = one parent box; result -> M[parent]
 //   MODE 2  L2L  eight operators, shared input L[parent];
@@ -478,11 +479,13 @@ struct TransArgs {
     int KZ;                      // M2L: slot length of one result (K rounded up to 16)
     long long nkey, PM;
     // M2L
-    const int *item_key, *item_begin, *item_count, *pairs, *vidx;
+    const int *item_ops, *item_begin, *item_count, *cols, *vgsrc;
+    int vstride;                 // M2L: entries per group in vgsrc (8, or 1 per entry)
     // M2M / L2L
     long long lb, le;            // boxes of the parent level
     long long ncap;              // mode 1: capacity (boxes) of one octant slice of the scratch
-    int n_items;                 // mode 0: number of work items
+    int n_items;                 // M2L: number of work items
+    int nsplit;                  // M2L: blocks (and result slots) per group
     int KC;                      // bf16 M2L: 32-deep k-chunks
     long long PMB;               // bf16 M2L: elements per packed matrix (each part)
     const int *cb, *nc;          // child begin / count
@@ -503,7 +506,7 @@ __device__ inline long long trans_dst(const TransArgs &a, const int *colbox,
                                       const int (*child)[CC], int col, int o, int kern) {
     const int K = a.K;
     if (MODE == 0) {
-        // slot of the V entry (target-major list order)
+        // slot of the group (target-major)
         (void)K;
         return ((long long)colbox[col] * 2 + kern) * a.KZ;
     } else if (MODE == 1) {
@@ -607,77 +610,17 @@ __device__ inline void trans_rows_res(const TransArgs &a, const R (&areg)[KSR], 
     trans_store<R, CC, MODE, NA>(a, acc, out, colbox, child, ncols, o, kern, lane, rt);
 }
 
-template <typename R, int CC, int MODE, int KSR>
-__global__ void __launch_bounds__(512) k_trans(TransArgs a, const R *__restrict__ ops,
-                                               const R *__restrict__ in, R *__restrict__ out,
-                                               int lev) {
-    extern __shared__ unsigned char smem_raw[];
-    R *Ms = reinterpret_cast<R *>(smem_raw);         // [CC][KKp]
-    __shared__ int colbox[CC];                         // mode 0: V entry; 1, 2: parent box
-    __shared__ int srcbox[CC];                         // box whose expansion is column c
-    __shared__ int child[8][CC];                       // modes 1, 2: child of octant o
-    const int K = a.K, KK = a.KK, KS = KK / 4;
-    // operand rows held in LDS: KK, or all KSR k-steps of the resident form
-    const int KR = KSR > 0 ? 4 * KSR : KK;
-    const int KKp = lds_stride(KR, (int)sizeof(R));
-    const int kern = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int o = (MODE == 0) ? 0 : (int)blockIdx.z;  // child octant (modes 1, 2)
-    int ncols;
-    const R *op0;
-    if (MODE == 0) {
-        // Work item w, columns [blockIdx.z * CC, +CC) of its <= 64 entries.
-        // Blocks are dealt to the 8 XCDs in turn (block b runs on XCD b % 8);
-        // XCD x takes the contiguous item range [x per, (x+1) per), so the
-        // items of one (level, class) bucket share their operator in one L2.
-        // gridDim.x = 8 per, so b -> w is a bijection onto [0, 8 per).
-        const int per = (int)(gridDim.x >> 3);
-        const int w = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
-        if (w >= a.n_items) return;                      // uniform for the block
-        const int off = blockIdx.z * CC;
-        ncols = min(CC, a.item_count[w] - off);
-        if (ncols <= 0) return;                          // uniform for the block
-        const int beg = a.item_begin[w] + off;
-        if (tid < CC) {
-            const int q = tid < ncols ? a.pairs[beg + tid] : -1;
-            colbox[tid] = q;
-            srcbox[tid] = q >= 0 ? a.vidx[q] : -1;
-        }
-        op0 = ops + ((long long)kern * a.nkey + a.item_key[w]) * a.PM;
-    } else {
-        const long long c0 = a.lb + (long long)blockIdx.x * CC;
-        ncols = (int)min((long long)CC, a.le - c0);
-        if (tid < CC) {
-            colbox[tid] = tid < ncols ? (int)(c0 + tid) : -1;
-            for (int q = 0; q < 8; ++q) child[q][tid] = -1;
-            if (tid < ncols) {
-                const int P = (int)(c0 + tid);
-                for (int c = a.cb[P]; c < a.cb[P] + a.nc[P]; ++c)
-                    child[(int)(a.prefix[c] & 7ull)][tid] = c;
-            }
-        }
-        op0 = ops + ((((long long)kern * a.nlev + lev) * 8) + o) * a.PM;
-    }
-    // resident form: this wave's operator rows (row tile = wave), issued now
-    // so that their latency overlaps the operand gather
-    R areg[KSR > 0 ? KSR : 1];
-    if constexpr (KSR > 0) {
-        const R *A = op0 + (long long)wave * KS * 64 + lane;
-#pragma unroll
-        // k-steps past the operator's KS are zero in registers: the values
-        // beyond belong to the next matrix (or are unwritten), and although
-        // the matching operand rows in LDS are zero, NaN * 0 would be NaN
-        for (int j = 0; j < KSR; ++j) areg[j] = j < KS ? A[j * 64] : R(0);
-    }
-    __syncthreads();
-    if (MODE != 0 && tid < CC) srcbox[tid] = (MODE == 1) ? child[o][tid] : colbox[tid];
-    __syncthreads();
+// Gathers the B operand of one block: column c (c < 16 nact) of Ms holds
+// rows [0, KR) of the expansion of box srcbox[c] (zero past K and for
+// absent columns).
+template <typename R>
+__device__ inline void gather_cols(const R *__restrict__ in, const int *srcbox, int ncols,
+                                   int nact, int K, int KR, int KKp, int kern, int lane,
+                                   int wave, R *Ms) {
     // gather the B operand column by column (consecutive lanes read
     // consecutive coefficients of one expansion); a wave issues the loads of
     // four columns before it stores any, so their latencies overlap.  Rows
     // past K and missing columns are zero.
-    const int nact = (ncols + 15) / 16;                  // active column tiles
     {
         const int nwave = (int)(blockDim.x >> 6);
         const int ncs = nact * 16;
@@ -714,6 +657,76 @@ __global__ void __launch_bounds__(512) k_trans(TransArgs a, const R *__restrict_
             }
         }
     }
+}
+
+template <typename R, int CC, int MODE, int KSR>
+__global__ void __launch_bounds__(512) k_trans(TransArgs a, const R *__restrict__ ops,
+                                               const R *__restrict__ in, R *__restrict__ out,
+                                               int lev) {
+    extern __shared__ unsigned char smem_raw[];
+    R *Ms = reinterpret_cast<R *>(smem_raw);         // [CC][KKp]
+    __shared__ int colbox[CC];                         // mode 0: V entry; 1, 2: parent box
+    __shared__ int srcbox[CC];                         // box whose expansion is column c
+    __shared__ int child[8][CC];                       // modes 1, 2: child of octant o
+    const int K = a.K, KK = a.KK, KS = KK / 4;
+    // operand rows held in LDS: KK, or all KSR k-steps of the resident form
+    const int KR = KSR > 0 ? 4 * KSR : KK;
+    const int KKp = lds_stride(KR, (int)sizeof(R));
+    const int kern = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int o = (MODE == 0) ? 0 : (int)blockIdx.z;  // child octant (modes 1, 2)
+    int ncols;
+    const R *op0;
+    if (MODE == 0) {
+        // Work item w, columns [blockIdx.z * CC, +CC) of its <= 64 entries.
+        // Blocks are dealt to the 8 XCDs in turn (block b runs on XCD b % 8);
+        // XCD x takes the contiguous item range [x per, (x+1) per), so the
+        // items of one (level, class) bucket share their operator in one L2.
+        // gridDim.x = 8 per, so b -> w is a bijection onto [0, 8 per).
+        const int per = (int)(gridDim.x >> 3);
+        const int w = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+        if (w >= a.n_items) return;                      // uniform for the block
+        const int off = blockIdx.z * CC;
+        ncols = min(CC, a.item_count[w] - off);
+        if (ncols <= 0) return;                          // uniform for the block
+        const int beg = a.item_begin[w] + off;
+        if (tid < CC) {
+            const int q = tid < ncols ? a.cols[beg + tid] : -1;
+            colbox[tid] = q;
+            srcbox[tid] = q >= 0 ? a.vgsrc[q] : -1;
+        }
+        op0 = ops + ((long long)kern * a.nkey + a.item_ops[8 * (long long)w]) * a.PM;
+    } else {
+        const long long c0 = a.lb + (long long)blockIdx.x * CC;
+        ncols = (int)min((long long)CC, a.le - c0);
+        if (tid < CC) {
+            colbox[tid] = tid < ncols ? (int)(c0 + tid) : -1;
+            for (int q = 0; q < 8; ++q) child[q][tid] = -1;
+            if (tid < ncols) {
+                const int P = (int)(c0 + tid);
+                for (int c = a.cb[P]; c < a.cb[P] + a.nc[P]; ++c)
+                    child[(int)(a.prefix[c] & 7ull)][tid] = c;
+            }
+        }
+        op0 = ops + ((((long long)kern * a.nlev + lev) * 8) + o) * a.PM;
+    }
+    // resident form: this wave's operator rows (row tile = wave), issued now
+    // so that their latency overlaps the operand gather
+    R areg[KSR > 0 ? KSR : 1];
+    if constexpr (KSR > 0) {
+        const R *A = op0 + (long long)wave * KS * 64 + lane;
+#pragma unroll
+        // k-steps past the operator's KS are zero in registers: the values
+        // beyond belong to the next matrix (or are unwritten), and although
+        // the matching operand rows in LDS are zero, NaN * 0 would be NaN
+        for (int j = 0; j < KSR; ++j) areg[j] = j < KS ? A[j * 64] : R(0);
+    }
+    __syncthreads();
+    if (MODE != 0 && tid < CC) srcbox[tid] = (MODE == 1) ? child[o][tid] : colbox[tid];
+    __syncthreads();
+    const int nact = (ncols + 15) / 16;                  // active column tiles
+    gather_cols<R>(in, srcbox, ncols, nact, K, KR, KKp, kern, lane, wave, Ms);
     __syncthreads();
     if constexpr (KSR > 0) {
         if constexpr (CC >= 64) {
@@ -734,6 +747,133 @@ __global__ void __launch_bounds__(512) k_trans(TransArgs a, const R *__restrict_
         }
         trans_rows<R, CC, MODE, 1>(a, op0, Ms, KKp, out, colbox, child, ncols, o, kern, lane, wave);
     }
+}
+
+// ---------------------------------------------------------------------------
+// M2L by groups (k_m2l; the bf16 M2L below takes both layouts).  A work item
+// is <= 64 groups of one bucket; every group of the bucket takes the same
+// operator in octant slot c.  Grouped layout: a group is the V entries of
+// one target that are children of one colleague of its parent (bucket:
+// level, colleague offset, target octant).  Per-entry layout: a group is one
+// V entry (bucket: level, offset class; one octant slot).  For each octant
+// slot with an operator the block gathers that child's expansions of its
+// columns into LDS and each wave adds its operator row tile times them to
+// its accumulators, so the sum over a group's children leaves the registers
+// once, into the group's slot of Z.  Operator fragments stream from cache
+// four k-steps ahead.
+// ---------------------------------------------------------------------------
+// Share h of nsplit of an item's octants with operators: ranks [lo, hi)
+// among them, in octant order (an empty share stores zeros).
+__device__ inline void m2l_share(const int *__restrict__ iops, int nsplit, int h, int &lo,
+                                 int &hi) {
+    int n = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) n += iops[c] >= 0;
+    const int per = (n + nsplit - 1) / nsplit;
+    lo = min(n, h * per);
+    hi = min(n, lo + per);
+}
+
+template <typename R, int CC, int NA>
+__device__ inline void m2l_group_rows(const TransArgs &a, const R *__restrict__ ops,
+                                      const R *__restrict__ in, R *__restrict__ out, R *Ms,
+                                      int KKp, const int *colbox, const int (*srcbox)[CC],
+                                      const int *__restrict__ iops, int lo, int hi, int ncols,
+                                      int kern, int lane, int wave) {
+    typedef typename Acc4<R>::T V4;
+    const int K = a.K, KK = a.KK, KS = KK / 4, NRT = (K + 15) / 16;
+    const int nwave = (int)(blockDim.x >> 6);
+    const R *Bp = Ms + (lane & 15) * KKp + (lane >> 4);
+    for (int rt0 = 0; rt0 < NRT; rt0 += nwave) {
+        const int rt = rt0 + wave;
+        if (rt0 > 0) __syncthreads();                    // the last pass's products done
+        V4 acc[NA];
+#pragma unroll
+        for (int ct = 0; ct < NA; ++ct) acc[ct] = V4{0, 0, 0, 0};
+        bool busy = false;                               // an octant was multiplied
+        for (int c = 0, rank = 0; c < 8; ++c) {
+            const int key = __builtin_amdgcn_readfirstlane(iops[c]);   // uniform
+            if (key < 0 || rank++ < lo || rank > hi) continue;         // not this block's
+            if (busy) __syncthreads();                   // products of the last octant done
+            busy = true;
+            gather_cols<R>(in, srcbox[c], ncols, NA, K, KK, KKp, kern, lane, wave, Ms);
+            __syncthreads();
+            if (rt >= NRT) continue;
+            const R *A = ops + ((long long)kern * a.nkey + key) * a.PM +
+                         (long long)rt * KS * 64 + lane;
+            R pre[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pre[j] = A[j * 64];
+            for (int ks = 0; ks < KS; ks += 4) {
+                R cur[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    cur[j] = pre[j];
+                    pre[j] = A[(ks + 4 + j) * 64];       // in bounds: operators carry a tail pad
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (ks + j < KS) {
+#pragma unroll
+                        for (int ct = 0; ct < NA; ++ct)
+                            acc[ct] = mfma16(cur[j], Bp[ct * 16 * KKp + (ks + j) * 4], acc[ct]);
+                    }
+                }
+            }
+        }
+        if (rt < NRT)
+            trans_store<R, CC, 0, NA>(a, acc, out, colbox, nullptr, ncols, 0, kern, lane, rt);
+    }
+}
+
+template <typename R, int CC>
+__global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == sizeof(float) ? 8 : 1)))
+k_m2l(TransArgs a, const R *__restrict__ ops,
+                                              const R *__restrict__ in, R *__restrict__ out) {
+    extern __shared__ unsigned char smem_raw[];
+    R *Ms = reinterpret_cast<R *>(smem_raw);          // [CC][KKp]
+    __shared__ int colbox[CC];                         // group of column c
+    __shared__ int srcbox[8][CC];                      // its child in octant o (or -1)
+    const int KKp = lds_stride(a.KK, (int)sizeof(R));
+    const int kern = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // Work item w, columns [blockIdx.z * CC, +CC) of its <= 64 groups.
+    // Blocks are dealt to the 8 XCDs in turn (block b runs on XCD b % 8);
+    // XCD x takes the contiguous item range [x per, (x+1) per), so items of
+    // one bucket, which share their operators, share one L2.
+    // gridDim.x = 8 per, so b -> w is a bijection onto [0, 8 per).
+    const int per = (int)(gridDim.x >> 3);
+    const int w = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+    if (w >= a.n_items) return;                        // uniform for the block
+    // blockIdx.z = column chunk * nsplit + part: part h takes the h-th share
+    // of the item's octants (in octant order) and writes slot h of each group
+    const int h = (int)blockIdx.z % a.nsplit;
+    const int off = ((int)blockIdx.z / a.nsplit) * CC;
+    const int ncols = min(CC, a.item_count[w] - off);
+    if (ncols <= 0) return;                            // uniform for the block
+    const int beg = a.item_begin[w] + off;
+    const int *iops = a.item_ops + 8 * (long long)w;
+    int lo, hi;
+    m2l_share(iops, a.nsplit, h, lo, hi);
+    if (tid < CC) {
+        const int g = tid < ncols ? a.cols[beg + tid] : -1;
+        colbox[tid] = g >= 0 ? g * a.nsplit + h : -1;
+#pragma unroll
+        for (int o = 0; o < 8; ++o)
+            srcbox[o][tid] = (g >= 0 && iops[o] >= 0) ? a.vgsrc[(long long)g * a.vstride + o] : -1;
+    }
+    __syncthreads();               // column tables visible to every wave
+    const int nact = (ncols + 15) / 16;                // active column tiles
+    if constexpr (CC >= 64) {
+        if (nact == 4) { m2l_group_rows<R, CC, 4>(a, ops, in, out, Ms, KKp, colbox, srcbox, iops, lo, hi, ncols, kern, lane, wave); return; }
+        if (nact == 3) { m2l_group_rows<R, CC, 3>(a, ops, in, out, Ms, KKp, colbox, srcbox, iops, lo, hi, ncols, kern, lane, wave); return; }
+    }
+    if constexpr (CC >= 32) {
+        if (nact == 2) { m2l_group_rows<R, CC, 2>(a, ops, in, out, Ms, KKp, colbox, srcbox, iops, lo, hi, ncols, kern, lane, wave); return; }
+    }
+    m2l_group_rows<R, CC, 1>(a, ops, in, out, Ms, KKp, colbox, srcbox, iops, lo, hi, ncols, kern, lane, wave);
 }
 
 // ---------------------------------------------------------------------------
@@ -769,35 +909,61 @@ __host__ __device__ inline int bf16_stride(int kr) {
     return 8 * u;
 }
 
-template <int NA>
-__device__ inline void m2l_bf16_rows(const TransArgs &a, const u16x8_t *__restrict__ Ah0,
-                                     const u16x8_t *__restrict__ Al0, const unsigned short *Mh,
-                                     const unsigned short *Ml, int KKp, float *__restrict__ out,
-                                     const int *colbox, int ncols, int kern, int lane, int wave) {
-    const int K = a.K, KC = a.KC, NRT = (K + 15) / 16;
+template <int CC, int NA, bool GROUPED>
+__device__ inline void m2l_bf16_group(const TransArgs &a, const u16x8_t *__restrict__ opsh,
+                                      const u16x8_t *__restrict__ opsl,
+                                      const float *__restrict__ in, float *__restrict__ out,
+                                      unsigned short *Mh, unsigned short *Ml, int KKp,
+                                      const int *colbox, const int (*srcbox)[CC],
+                                      const int *__restrict__ iops, int lo, int hi, int ncols,
+                                      int kern, int lane, int wave) {
+    const int K = a.K, KC = a.KC, KR = 32 * KC, NRT = (K + 15) / 16;
     const int nwave = (int)(blockDim.x >> 6);
     const int boff = (lane & 15) * KKp + 8 * (lane >> 4);
-    for (int rt = wave; rt < NRT; rt += nwave) {
-        const u16x8_t *Ah = Ah0 + (long long)rt * KC * 64 + lane;
-        const u16x8_t *Al = Al0 + (long long)rt * KC * 64 + lane;
+    for (int rt0 = 0; rt0 < NRT; rt0 += nwave) {
+        const int rt = rt0 + wave;
+        if (rt0 > 0) __syncthreads();                    // the last pass's products done
         f4v acc[NA];
 #pragma unroll
         for (int ct = 0; ct < NA; ++ct) acc[ct] = f4v{0, 0, 0, 0};
-        u16x8_t ph = Ah[0], pl = Al[0];
-        for (int kc = 0; kc < KC; ++kc) {
-            const u16x8_t ah = ph, al = pl;
-            ph = Ah[(kc + 1) * 64];        // in bounds: operators carry a tail pad
-            pl = Al[(kc + 1) * 64];
+        bool busy = false;                               // an octant was multiplied
+        for (int c = 0, rank = 0; c < (GROUPED ? 8 : 1); ++c) {
+            const int key = __builtin_amdgcn_readfirstlane(iops[c]);
+            if (key < 0 || rank++ < lo || rank > hi) continue;         // not this block's
+            if (busy) __syncthreads();                   // products of the last octant done
+            busy = true;
+            for (int col = wave; col < NA * 16; col += nwave) {
+                const int src = col < ncols ? srcbox[c][col] : -1;
+                const float *cp = in + ((long long)(src < 0 ? 0 : src) * 2 + kern) * K;
+                for (int k = lane; k < KR; k += 64) {
+                    const float v = (src >= 0 && k < K) ? cp[k] : 0.0f;
+                    const unsigned short h = bf16_bits(v);
+                    Mh[col * KKp + k] = h;
+                    Ml[col * KKp + k] = bf16_bits(v - bf16_value(h));
+                }
+            }
+            __syncthreads();
+            if (rt >= NRT) continue;
+            const long long mat = (long long)kern * a.nkey + key;
+            const u16x8_t *Ah = opsh + mat * (a.PMB / 8) + (long long)rt * KC * 64 + lane;
+            const u16x8_t *Al = opsl + mat * (a.PMB / 8) + (long long)rt * KC * 64 + lane;
+            u16x8_t ph = Ah[0], pl = Al[0];
+            for (int kc = 0; kc < KC; ++kc) {
+                const u16x8_t ah = ph, al = pl;
+                ph = Ah[(kc + 1) * 64];        // in bounds: operators carry a tail pad
+                pl = Al[(kc + 1) * 64];
 #pragma unroll
-            for (int ct = 0; ct < NA; ++ct) {
-                const int o = ct * 16 * KKp + boff + 32 * kc;
-                const u16x8_t bh = *reinterpret_cast<const u16x8_t *>(Mh + o);
-                const u16x8_t bl = *reinterpret_cast<const u16x8_t *>(Ml + o);
-                acc[ct] = mfma_bf16(ah, bh, acc[ct]);
-                acc[ct] = mfma_bf16(ah, bl, acc[ct]);
-                acc[ct] = mfma_bf16(al, bh, acc[ct]);
+                for (int ct = 0; ct < NA; ++ct) {
+                    const int o = ct * 16 * KKp + boff + 32 * kc;
+                    const u16x8_t bh = *reinterpret_cast<const u16x8_t *>(Mh + o);
+                    const u16x8_t bl = *reinterpret_cast<const u16x8_t *>(Ml + o);
+                    acc[ct] = mfma_bf16(ah, bh, acc[ct]);
+                    acc[ct] = mfma_bf16(ah, bl, acc[ct]);
+                    acc[ct] = mfma_bf16(al, bh, acc[ct]);
+                }
             }
         }
+        if (rt >= NRT) continue;
 #pragma unroll
         for (int ct = 0; ct < NA; ++ct) {
             const int col = ct * 16 + (lane & 15);
@@ -808,17 +974,17 @@ __device__ inline void m2l_bf16_rows(const TransArgs &a, const u16x8_t *__restri
     }
 }
 
-// One block per work item (as the FP32 M2L, XCD-contiguous); waves take the
-// operator's row tiles in turn, fragments loaded one chunk ahead.
-template <int CC>
-__global__ void __launch_bounds__(512) k_m2l_bf16(TransArgs a, const u16x8_t *__restrict__ opsh,
-                                                  const u16x8_t *__restrict__ opsl,
-                                                  const float *__restrict__ in,
-                                                  float *__restrict__ out) {
+// One block per work item (as the FP32 M2L: groups, XCD-contiguous items);
+// waves take the operators' row tiles, fragments loaded one chunk ahead.
+template <int CC, bool GROUPED>
+__global__ void __launch_bounds__(1024) k_m2l_bf16(TransArgs a, const u16x8_t *__restrict__ opsh,
+                                                   const u16x8_t *__restrict__ opsl,
+                                                   const float *__restrict__ in,
+                                                   float *__restrict__ out) {
     extern __shared__ __align__(16) unsigned char smem_bf[];
     __shared__ int colbox[CC];
-    __shared__ int srcbox[CC];
-    const int K = a.K, KR = 32 * a.KC, KKp = bf16_stride(KR);
+    __shared__ int srcbox[8][CC];
+    const int KR = 32 * a.KC, KKp = bf16_stride(KR);
     unsigned short *Mh = reinterpret_cast<unsigned short *>(smem_bf);    // [CC][KKp]
     unsigned short *Ml = Mh + CC * KKp;
     const int kern = blockIdx.y;
@@ -827,58 +993,79 @@ __global__ void __launch_bounds__(512) k_m2l_bf16(TransArgs a, const u16x8_t *__
     const int per = (int)(gridDim.x >> 3);
     const int w = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
     if (w >= a.n_items) return;
-    const int off = blockIdx.z * CC;
+    // blockIdx.z = column chunk * nsplit + part: part h takes the h-th share
+    // of the item's octants (in octant order) and writes slot h of each group
+    const int h = (int)blockIdx.z % a.nsplit;
+    const int off = ((int)blockIdx.z / a.nsplit) * CC;
     const int ncols = min(CC, a.item_count[w] - off);
-    if (ncols <= 0) return;
+    if (ncols <= 0) return;                            // uniform for the block
     const int beg = a.item_begin[w] + off;
+    const int *iops = a.item_ops + 8 * (long long)w;
+    int lo, hi;
+    m2l_share(iops, a.nsplit, h, lo, hi);
     if (tid < CC) {
-        const int q = tid < ncols ? a.pairs[beg + tid] : -1;
-        colbox[tid] = q;
-        srcbox[tid] = q >= 0 ? a.vidx[q] : -1;
+        const int g = tid < ncols ? a.cols[beg + tid] : -1;
+        colbox[tid] = g >= 0 ? g * a.nsplit + h : -1;
+#pragma unroll
+        for (int o = 0; o < (GROUPED ? 8 : 1); ++o)
+            srcbox[o][tid] = (g >= 0 && iops[o] >= 0) ? a.vgsrc[(long long)g * a.vstride + o] : -1;
     }
-    __syncthreads();
+    __syncthreads();               // column tables visible to every wave
     const int nact = (ncols + 15) / 16;
-    {
-        const int nwave = (int)(blockDim.x >> 6);
-        for (int c = wave; c < nact * 16; c += nwave) {
-            const int src = c < ncols ? srcbox[c] : -1;
-            const float *col = in + ((long long)(src < 0 ? 0 : src) * 2 + kern) * K;
-            for (int k = lane; k < KR; k += 64) {
-                const float v = (src >= 0 && k < K) ? col[k] : 0.0f;
-                const unsigned short h = bf16_bits(v);
-                Mh[c * KKp + k] = h;
-                Ml[c * KKp + k] = bf16_bits(v - bf16_value(h));
-            }
-        }
-    }
-    __syncthreads();
-    const long long mat = (long long)kern * a.nkey + a.item_key[w];
-    const u16x8_t *Ah = opsh + mat * (a.PMB / 8), *Al = opsl + mat * (a.PMB / 8);
     if constexpr (CC >= 64) {
-        if (nact == 4) { m2l_bf16_rows<4>(a, Ah, Al, Mh, Ml, KKp, out, colbox, ncols, kern, lane, wave); return; }
-        if (nact == 3) { m2l_bf16_rows<3>(a, Ah, Al, Mh, Ml, KKp, out, colbox, ncols, kern, lane, wave); return; }
+        if (nact == 4) { m2l_bf16_group<CC, 4, GROUPED>(a, opsh, opsl, in, out, Mh, Ml, KKp, colbox, srcbox, iops, lo, hi, ncols, kern, lane, wave); return; }
+        if (nact == 3) { m2l_bf16_group<CC, 3, GROUPED>(a, opsh, opsl, in, out, Mh, Ml, KKp, colbox, srcbox, iops, lo, hi, ncols, kern, lane, wave); return; }
     }
     if constexpr (CC >= 32) {
-        if (nact == 2) { m2l_bf16_rows<2>(a, Ah, Al, Mh, Ml, KKp, out, colbox, ncols, kern, lane, wave); return; }
+        if (nact == 2) { m2l_bf16_group<CC, 2, GROUPED>(a, opsh, opsl, in, out, Mh, Ml, KKp, colbox, srcbox, iops, lo, hi, ncols, kern, lane, wave); return; }
     }
-    m2l_bf16_rows<1>(a, Ah, Al, Mh, Ml, KKp, out, colbox, ncols, kern, lane, wave);
+    m2l_bf16_group<CC, 1, GROUPED>(a, opsh, opsl, in, out, Mh, Ml, KKp, colbox, srcbox, iops, lo, hi, ncols, kern, lane, wave);
 }
 
-void launch_m2l_bf16(const TransArgs &ta, unsigned gx, const u16x8_t *opsh, const u16x8_t *opsl,
-                     const float *in, float *out, hipStream_t s) {
-    const int nrt = (ta.K + 15) / 16, passes = (nrt + 7) / 8;
-    const unsigned nthr = 64u * (unsigned)((nrt + passes - 1) / passes);
+// threads per M2L block: one wave per operator row tile, at most 16 (larger
+// orders take the row tiles in balanced passes)
+inline unsigned m2l_threads(int K) {
+    const int nrt = (K + 15) / 16, passes = (nrt + 15) / 16;
+    return 64u * (unsigned)((nrt + passes - 1) / passes);
+}
+
+void launch_m2l_bf16(const TransArgs &ta, unsigned gx, bool grouped, const u16x8_t *opsh,
+                     const u16x8_t *opsl, const float *in, float *out, hipStream_t s) {
+    const unsigned nthr = m2l_threads(ta.K), ns = (unsigned)ta.nsplit;
     (void)blocks_ok(gx, nthr);
     const size_t kkp = (size_t)bf16_stride(32 * ta.KC);
     auto shmem = [&](int cc) { return 2 * kkp * cc * sizeof(unsigned short); };
     const size_t lim = 60 * 1024;
     if (shmem(64) <= lim) {
-        k_m2l_bf16<64><<<dim3(gx, 2, 1), nthr, shmem(64), s>>>(ta, opsh, opsl, in, out);
+        if (grouped) k_m2l_bf16<64, true><<<dim3(gx, 2, 1 * ns), nthr, shmem(64), s>>>(ta, opsh, opsl, in, out);
+        else k_m2l_bf16<64, false><<<dim3(gx, 2, 1 * ns), nthr, shmem(64), s>>>(ta, opsh, opsl, in, out);
     } else if (shmem(32) <= lim) {
-        k_m2l_bf16<32><<<dim3(gx, 2, 2), nthr, shmem(32), s>>>(ta, opsh, opsl, in, out);
+        if (grouped) k_m2l_bf16<32, true><<<dim3(gx, 2, 2 * ns), nthr, shmem(32), s>>>(ta, opsh, opsl, in, out);
+        else k_m2l_bf16<32, false><<<dim3(gx, 2, 2 * ns), nthr, shmem(32), s>>>(ta, opsh, opsl, in, out);
     } else {
         require(shmem(16) <= lim, ST_INVALID, "expansion order too large for the bf16 M2L");
-        k_m2l_bf16<16><<<dim3(gx, 2, 4), nthr, shmem(16), s>>>(ta, opsh, opsl, in, out);
+        if (grouped) k_m2l_bf16<16, true><<<dim3(gx, 2, 4 * ns), nthr, shmem(16), s>>>(ta, opsh, opsl, in, out);
+        else k_m2l_bf16<16, false><<<dim3(gx, 2, 4 * ns), nthr, shmem(16), s>>>(ta, opsh, opsl, in, out);
+    }
+    KCHK();
+}
+
+// Grouped FP32 / FP64 M2L (k_m2l): the widest column block that fits the
+// LDS budget
+template <typename R>
+void launch_m2l(const TransArgs &ta, unsigned gx, const R *ops, const R *in, R *out,
+                hipStream_t s) {
+    const unsigned nthr = m2l_threads(ta.K), ns = (unsigned)ta.nsplit;
+    (void)blocks_ok(gx, nthr);
+    const size_t lim = 60 * 1024;
+    auto shmem = [&](int cc) { return (size_t)lds_stride(ta.KK, (int)sizeof(R)) * cc * sizeof(R); };
+    if (shmem(64) <= lim) {
+        k_m2l<R, 64><<<dim3(gx, 2, 1 * ns), nthr, shmem(64), s>>>(ta, ops, in, out);
+    } else if (shmem(32) <= lim) {
+        k_m2l<R, 32><<<dim3(gx, 2, 2 * ns), nthr, shmem(32), s>>>(ta, ops, in, out);
+    } else {
+        require(shmem(16) <= lim, ST_INVALID, "expansion order too large for the translation kernels");
+        k_m2l<R, 16><<<dim3(gx, 2, 4 * ns), nthr, shmem(16), s>>>(ta, ops, in, out);
     }
     KCHK();
 }
@@ -948,13 +1135,13 @@ void launch_trans_k(const TransArgs &ta, dim3 g, unsigned nthr, const R *ops, co
 }
 
 // M2M / L2L with up to 8 row tiles and 32 k-steps (p <= 10): one wave per
-// row tile with its operator rows in registers; otherwise (and for M2L) the
-// streaming form with at most 8 waves in balanced passes.
+// row tile with its operator rows in registers; otherwise (and for the
+// per-entry M2L) the streaming form with at most 8 waves in balanced passes.
 template <typename R, int MODE>
 void launch_trans(const TransArgs &ta, dim3 grid_items, const R *ops, const R *in, R *out,
                   int lev, hipStream_t s) {
     const int nrt = (ta.K + 15) / 16, ks = ta.KK / 4;
-    // (M2L streams its operators: measured faster there than the resident form)
+    // (the per-entry M2L streams its operators: measured faster there)
     if (MODE != 0 && nrt <= 8 && ks <= 32) {
         const unsigned nthr = 64u * (unsigned)nrt;
         if (ks <= 16) launch_trans_k<R, MODE, 16>(ta, grid_items, nthr, ops, in, out, lev, s);
@@ -967,13 +1154,14 @@ void launch_trans(const TransArgs &ta, dim3 grid_items, const R *ops, const R *i
     }
 }
 
-// L[B] = sum of the M2L products of the entries of V(B), stored in list
-// order as slots [v_ptr[B], v_ptr[B+1]) of Z (2 KZ values each: kernel 0,
-// then kernel 1, each K values and a zero pad).  Four waves take every
-// fourth slot, reading 16 bytes per lane and four slots per step; their
-// partial sums are added in wave order.
+// L[B] = sum of the M2L results of the groups of V(B), stored target-major
+// as slots [ns vg_ptr[B], ns vg_ptr[B+1]) of Z (ns per group, 2 KZ values
+// each: kernel 0, then kernel 1, each K values and a zero pad).  Four waves
+// take every fourth slot, reading 16 bytes per lane and four slots per step;
+// their partial sums are added in wave order.
 template <typename R>
-__global__ void __launch_bounds__(256) k_m2l_reduce(int K, int KZ, long long nbox, const int *vptr,
+__global__ void __launch_bounds__(256) k_m2l_reduce(int K, int KZ, int ns, long long nbox,
+                                                    const int *vptr,
                                                     const R *__restrict__ Z, R *__restrict__ L) {
     constexpr int VB = 16 / (int)sizeof(R);            // elements per 16-byte vector
     typedef R V __attribute__((ext_vector_type(VB)));
@@ -984,7 +1172,7 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(int K, int KZ, long long nbo
     if (box >= nbox) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int W = 2 * KZ, NV = W / VB;                 // KZ is a multiple of 16
-    const long long q0 = vptr[box], q1 = vptr[box + 1];
+    const long long q0 = (long long)ns * vptr[box], q1 = (long long)ns * vptr[box + 1];
     V acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = V{};
@@ -1299,11 +1487,13 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     ta.PM = F.PM;
     ta.nlev = F.nlev;
     ta.nkey = F.nkey;
-    ta.item_key = L.m2l_item_key.p;
+    ta.item_ops = L.m2l_item_ops.p;
     ta.item_begin = L.m2l_item_begin.p;
     ta.item_count = L.m2l_item_count.p;
-    ta.pairs = L.m2l_pairs.p;
-    ta.vidx = L.v_idx.p;
+    ta.cols = L.m2l_cols.p;
+    ta.vgsrc = L.m2l_grouped ? L.vg_src.p : L.v_idx.p;
+    ta.vstride = L.m2l_grouped ? 8 : 1;
+    ta.nsplit = L.m2l_split;
     ta.cb = t.child_begin.p;
     ta.nc = t.n_child.p;
     ta.prefix = t.prefix.p;
@@ -1328,19 +1518,23 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
             if (w.bf16_m2l) {
                 ta.KC = F.KC;
                 ta.PMB = F.PMB;
-                launch_m2l_bf16(ta, gx, reinterpret_cast<const u16x8_t *>(F.Tbh.p),
+                launch_m2l_bf16(ta, gx, L.m2l_grouped, reinterpret_cast<const u16x8_t *>(F.Tbh.p),
                                 reinterpret_cast<const u16x8_t *>(F.Tbl.p), w.M, w.Z, s);
+            } else if (L.m2l_grouped) {
+                launch_m2l<R>(ta, gx, Ops<R>::T(F), w.M, w.Z, s);
             } else {
                 launch_trans<R, 0>(ta, dim3(gx, 2), Ops<R>::T(F), w.M, w.Z, 0, s);
             }
+        } else if (L.m2l_grouped) {
+            launch_m2l<R>(ta, gx, Ops<R>::T(F), w.M, w.Z, s);
         } else {
             launch_trans<R, 0>(ta, dim3(gx, 2), Ops<R>::T(F), w.M, w.Z, 0, s);
         }
     }
     {
         ProfScope ps(prof, "m2l_reduce", s);
-        k_m2l_reduce<R><<<blocks_ok(t.nbox, 256), 256, 0, s>>>(K, F.KZ, t.nbox, L.v_ptr.p, w.Z,
-                                                                w.Lc);
+        k_m2l_reduce<R><<<blocks_ok(t.nbox, 256), 256, 0, s>>>(
+            K, F.KZ, L.m2l_split, t.nbox, L.m2l_grouped ? L.vg_ptr.p : L.v_ptr.p, w.Z, w.Lc);
         KCHK();
     }
     {

@@ -57,14 +57,26 @@ struct Lists {
     // consecutive leaves with <= 64 points together (a larger leaf alone)
     DBuf<int> pm_leaf, pm_first, pm_count;
     long long n_pm = 0;
-    // M2L: V entries grouped by (level, offset class) into chunks of <= 64.
     DBuf<int> v_tgt;                   // [n_v] target box of each V entry
-    DBuf<int> m2l_pairs;               // [n_v] V-entry indices grouped by bucket
-    DBuf<int> m2l_item_key, m2l_item_begin, m2l_item_count;
-    long long n_m2l_items = 0;
+    // M2L groups: per-entry layout (m2l_grouped = false): group g is V entry g
+    // (its source v_idx[g], result slots in list order, [v_ptr[B],
+    // v_ptr[B+1]) for target B).  Grouped layout: the V entries of one target
+    // that are children of one colleague of its parent, numbered target-major
+    // ([vg_ptr[B], vg_ptr[B+1])), vg_src[8 g + c] the child in octant c (-1 if
+    // absent).  Items: <= 64 groups of one bucket listed in m2l_cols
+    // [m2l_item_begin, + m2l_item_count); m2l_item_ops[8 w + c] is the
+    // operator key (level, offset class) of octant slot c, or -1.  Grouped
+    // items may share their octants among m2l_split blocks, each with its own
+    // result slot per group (slots g * m2l_split + part).
+    DBuf<int> vg_ptr, vg_src, m2l_cols;
+    DBuf<int> m2l_item_ops, m2l_item_begin, m2l_item_count;
+    long long n_vg = 0, n_m2l_items = 0;
+    int m2l_split = 1;
+    bool m2l_grouped = false;
     std::vector<int> levels_with_v;    // levels that have V entries
 };
 
-void build_lists(const Tree &t, Lists &L, hipStream_t s);
+// M2L layout: 1 per entry, 2 grouped, 0 chosen by the number of V entries.
+void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s);
 
 }  // namespace afmpb

@@ -12,6 +12,13 @@ namespace {
 
 constexpr int MAXLEVEL = 21;
 constexpr int MAXCOLL = 26;
+// M2L blocks (items x kernels x octant shares) wanted per launch
+constexpr long long M2L_FILL_BLOCKS = 4096;
+// Grouped M2L from this many V entries on.  Grouping writes ~6x fewer
+// result slots but multiplies ~1.4x more padded columns (absent children)
+// and balances less evenly over the XCDs; measured on one MI355X it loses
+// at 0.22 M entries (FP32 and FP64) and wins at 7.2 M (matvec -10%).
+constexpr long long M2L_GROUP_MIN_ENTRIES = 2ll << 20;
 constexpr int DFS_STACK = 128;
 
 // ----------------------------- split ---------------------------------------
@@ -250,6 +257,18 @@ __global__ void k_list_fill(TreeView t, long long nbox, const int *pu, const int
 
 // Offset class of C relative to B: rank of (anchor_C - anchor_B)/side in
 // [-3,3]^3 minus [-1,1]^3, ascending lexicographic (dx, dy, dz).
+// Rank of the offset (o0, o1, o2) in [-3,3]^3 minus [-1,1]^3, lexicographic.
+__host__ __device__ inline int offset_class(int o0, int o1, int o2) {
+    const int full = ((o0 + 3) * 7 + (o1 + 3)) * 7 + (o2 + 3);
+    // number of excluded (|o|_inf <= 1) positions that precede `full`
+    int excl = 0;
+    for (int x = -1; x <= 1; ++x)
+        for (int y = -1; y <= 1; ++y)
+            for (int z = -1; z <= 1; ++z)
+                if (((x + 3) * 7 + (y + 3)) * 7 + (z + 3) < full) ++excl;
+    return full - excl;
+}
+
 __global__ void k_v_class(TreeView t, long long nbox, const int *vptr, const int *vidx,
                           int *vcls, int *vtgt) {
     long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -262,16 +281,61 @@ __global__ void k_v_class(TreeView t, long long nbox, const int *vptr, const int
         anchor_of(t, vidx[q], ac);
         int d[3];
         for (int a = 0; a < 3; ++a) d[a] = (int)((ac[a] - ab[a]) / side);
-        int full = ((d[0] + 3) * 7 + (d[1] + 3)) * 7 + (d[2] + 3);
-        // number of excluded (|d|_inf <= 1) positions that precede `full`
-        int excl = 0;
-        for (int x = -1; x <= 1; ++x)
-            for (int y = -1; y <= 1; ++y)
-                for (int z = -1; z <= 1; ++z)
-                    if (((x + 3) * 7 + (y + 3)) * 7 + (z + 3) < full) ++excl;
-        vcls[q] = full - excl;
+        vcls[q] = offset_class(d[0], d[1], d[2]);
         vtgt[q] = (int)B;
     }
+}
+
+// M2L groups: the entries of V(B) that are children of one colleague C of
+// B's parent P.  They are contiguous in the ascending list (siblings have
+// consecutive box indices).  A group's bucket is (level, offset d = C - P in
+// [-1,1]^3, octant b of B); the child in octant c sits at offset 2 d + c - b
+// from B, so one bucket has one operator per child octant.  Buckets are
+// ordered by d before b: the 8 buckets of one d use only 27 offsets, so
+// consecutive work items share their operators in cache.
+__global__ void k_vg_count(long long nbox, const int *parent, const int *vptr, const int *vidx,
+                           int *cnt) {
+    long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nbox) return;
+    int n = 0;
+    for (int q = vptr[B]; q < vptr[B + 1]; ++q)
+        if (q == vptr[B] || parent[vidx[q]] != parent[vidx[q - 1]]) ++n;
+    cnt[B] = n;
+}
+
+__global__ void k_vg_fill(TreeView t, long long nbox, const int *vptr, const int *vidx,
+                          const int *vgptr, int *src, unsigned long long *key, int *idx,
+                          int *err) {
+    long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nbox) return;
+    long long ab[3];
+    anchor_of(t, (int)B, ab);
+    const long long side = 1ll << (MAXLEVEL - t.lev[B]);
+    const int b = (int)(t.prefix[B] & 7ull);
+    int g = vgptr[B] - 1;
+    for (int q = vptr[B]; q < vptr[B + 1]; ++q) {
+        const int sb = vidx[q];
+        const int c = (int)(t.prefix[sb] & 7ull);
+        if (q == vptr[B] || t.parent[sb] != t.parent[vidx[q - 1]]) {
+            ++g;
+            if (g >= vgptr[B + 1]) { atomicOr(err, 8); return; }
+            for (int j = 0; j < 8; ++j) src[8 * (long long)g + j] = -1;
+            long long ac[3];
+            anchor_of(t, sb, ac);
+            int dk = 0;
+            for (int a = 0; a < 3; ++a) {
+                const int o = (int)((ac[a] - ab[a]) / side);
+                const int d2 = o + ((b >> a) & 1) - ((c >> a) & 1);
+                if (d2 < -2 || d2 > 2 || (d2 & 1)) { atomicOr(err, 8); return; }
+                dk = 3 * dk + d2 / 2 + 1;
+            }
+            key[g] = (unsigned long long)((t.lev[B] - 2) * 216 + dk * 8 + b);
+            idx[g] = g;
+        }
+        if (src[8 * (long long)g + c] != -1) { atomicOr(err, 8); return; }
+        src[8 * (long long)g + c] = sb;
+    }
+    if (g + 1 != vgptr[B + 1]) atomicOr(err, 8);
 }
 
 __global__ void k_x_count(long long nbox, const int *wptr, const int *widx, int *cnt) {
@@ -432,7 +496,7 @@ void build_tree(const unsigned long long *keys, long long n, int cap, const doub
     HIPCHK(hipStreamSynchronize(s));
 }
 
-void build_lists(const Tree &t, Lists &L, hipStream_t s) {
+void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s) {
     const long long nb = t.nbox;
     L.coll.alloc((size_t)nb * MAXCOLL);
     L.ncoll.alloc(nb);
@@ -605,39 +669,106 @@ void build_lists(const Tree &t, Lists &L, hipStream_t s) {
         L.pm_count.upload(pmc.data(), pmc.size(), s);
         HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
     }
-    // M2L buckets by (level, class), chunks of <= 64 entries
+    // M2L work items.  Per entry: items of <= 64 V entries of one (level,
+    // offset class), each entry its own group with its one operator in
+    // octant slot 0 and its own result slot (target-major list order).
+    // Grouped (large trees): groups bucketed by (level, colleague offset,
+    // octant) into items of <= 64.
     const long long nv = L.n_v;
-    L.m2l_pairs.alloc(nv);
     L.levels_with_v.clear();
     L.n_m2l_items = 0;
-    if (nv > 0) {
+    L.n_vg = 0;
+    L.m2l_split = 1;
+    L.m2l_grouped = m2l_layout == 0 ? nv >= M2L_GROUP_MIN_ENTRIES : m2l_layout == 2;
+    if (nv == 0) {
+        L.vg_ptr.alloc(nb + 1);
+        L.vg_ptr.zero(nb + 1, s);
+    } else if (!L.m2l_grouped) {
+        L.n_vg = nv;
+        L.m2l_cols.alloc(nv);
         DBuf<unsigned long long> keys(nv), tk(nv);
         DBuf<int> tvv(nv);
         k_m2l_keys<<<grid_for(nv, 256), 256, 0, s>>>(nv, L.v_tgt.p, L.v_cls.p, t.level.p,
-                                                     keys.p, L.m2l_pairs.p);
+                                                     keys.p, L.m2l_cols.p);
         KCHK();
-        radix_sort_pairs(keys.p, L.m2l_pairs.p, tk.p, tvv.p, nv, 16, s);
+        radix_sort_pairs(keys.p, L.m2l_cols.p, tk.p, tvv.p, nv, 16, s);
         std::vector<unsigned long long> hk(nv);
         keys.download(hk.data(), nv, s);
         HIPCHK(hipStreamSynchronize(s));
-        std::vector<int> ik, ib, ic;
+        std::vector<int> iops, ib, ic;
         long long i = 0;
         while (i < nv) {
             long long j = i;
             while (j < nv && hk[j] == hk[i] && j - i < 64) ++j;
-            ik.push_back((int)hk[i]);
+            iops.push_back((int)hk[i]);
+            for (int c = 1; c < 8; ++c) iops.push_back(-1);
             ib.push_back((int)i);
             ic.push_back((int)(j - i));
-            int lev = (int)(hk[i] / 316) + 2;
+            const int lev = (int)(hk[i] / 316) + 2;
             if (L.levels_with_v.empty() || L.levels_with_v.back() != lev)
                 L.levels_with_v.push_back(lev);
             i = j;
         }
-        L.n_m2l_items = (long long)ik.size();
-        L.m2l_item_key.alloc(ik.size());
-        L.m2l_item_begin.alloc(ik.size());
-        L.m2l_item_count.alloc(ik.size());
-        L.m2l_item_key.upload(ik.data(), ik.size(), s);
+        L.n_m2l_items = (long long)ib.size();
+        L.m2l_item_ops.alloc(iops.size());
+        L.m2l_item_begin.alloc(ib.size());
+        L.m2l_item_count.alloc(ib.size());
+        L.m2l_item_ops.upload(iops.data(), iops.size(), s);
+        L.m2l_item_begin.upload(ib.data(), ib.size(), s);
+        L.m2l_item_count.upload(ic.data(), ic.size(), s);
+        HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
+    } else {
+        L.vg_ptr.alloc(nb + 1);
+        DBuf<int> cg(nb + 1);
+        err.zero(1, s);
+        k_vg_count<<<grid_for(nb, 128), 128, 0, s>>>(nb, t.parent.p, L.v_ptr.p, L.v_idx.p, cg.p);
+        KCHK();
+        exclusive_scan_i32(cg.p, L.vg_ptr.p, nb, s);
+        const long long ng = read_scalar(L.vg_ptr.p + nb, s);
+        L.n_vg = ng;
+        L.vg_src.alloc((size_t)8 * ng);
+        L.m2l_cols.alloc(ng);
+        DBuf<unsigned long long> keys(ng), tk(ng);
+        DBuf<int> tvv(ng);
+        k_vg_fill<<<grid_for(nb, 128), 128, 0, s>>>(tv, nb, L.v_ptr.p, L.v_idx.p, L.vg_ptr.p,
+                                                    L.vg_src.p, keys.p, L.m2l_cols.p, err.p);
+        KCHK();
+        require(read_scalar(err.p, s) == 0, ST_DEVICE, "M2L groups inconsistent with V lists");
+        radix_sort_pairs(keys.p, L.m2l_cols.p, tk.p, tvv.p, ng, 16, s);
+        std::vector<unsigned long long> hk(ng);
+        keys.download(hk.data(), ng, s);
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<int> iops, ib, ic;
+        long long i = 0;
+        while (i < ng) {
+            long long j = i;
+            while (j < ng && hk[j] == hk[i] && j - i < 64) ++j;
+            const int key = (int)hk[i], lev = key / 216 + 2, dk = (key % 216) / 8, b = key % 8;
+            const int d[3] = {dk / 9 - 1, (dk / 3) % 3 - 1, dk % 3 - 1};
+            for (int c = 0; c < 8; ++c) {
+                int o[3], far = 0;
+                for (int a = 0; a < 3; ++a) {
+                    o[a] = 2 * d[a] + ((c >> a) & 1) - ((b >> a) & 1);
+                    far |= o[a] < -1 || o[a] > 1;
+                }
+                iops.push_back(far ? (lev - 2) * 316 + offset_class(o[0], o[1], o[2]) : -1);
+            }
+            ib.push_back((int)i);
+            ic.push_back((int)(j - i));
+            if (L.levels_with_v.empty() || L.levels_with_v.back() != lev)
+                L.levels_with_v.push_back(lev);
+            i = j;
+        }
+        L.n_m2l_items = (long long)ib.size();
+        // few items (a small tree): share each item's octants among up to 4
+        // blocks so that the launch still fills the chip
+        L.m2l_split = 1;
+        while (L.m2l_split < 4 && L.n_m2l_items * 2 * L.m2l_split < M2L_FILL_BLOCKS)
+            L.m2l_split *= 2;
+        L.m2l_item_ops.alloc(iops.size());
+        L.m2l_item_begin.alloc(ib.size());
+        L.m2l_item_count.alloc(ib.size());
+        L.m2l_item_ops.upload(iops.data(), iops.size(), s);
         L.m2l_item_begin.upload(ib.data(), ib.size(), s);
         L.m2l_item_count.upload(ic.data(), ic.size(), s);
         HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies

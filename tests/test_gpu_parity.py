@@ -148,6 +148,36 @@ def test_fmm_matvec_matches_oracle_and_converges_in_p(name):
     assert errs[4] > errs[8] > errs[10] > errs[12]
 
 
+@pytest.mark.parametrize("name,cap,p", [("born4", 32, 8), ("star4", 16, 10), ("star4", 5, 14)])
+def test_m2l_layouts_agree_and_match_oracle(name, cap, p):
+    """Both M2L work layouts, one result slot per V entry (1) and one per
+    (target, colleague of its parent) with the colleague's children summed in
+    registers (2), in every precision: the same sums up to rounding order,
+    and as close to the oracle as each other.  Small trees share an item's
+    octants among several blocks (some shares empty), p = 14 takes 15 row
+    tiles per operator."""
+    import paper_1710_06316_amd as A
+    mol = MOLS[name]()
+    x = np.random.default_rng(6).normal(size=2 * mol.n_nodes)
+    ref = _oracle_op(mol).matvec(x)
+    agree = {A.AFMPB_FP64: 1e-13, A.AFMPB_FP32_REFINED: 1e-5, A.AFMPB_FP32_BF16M2L_REFINED: 1e-5}
+    for prec, tol in agree.items():
+        ys, errs = {}, {}
+        for layout in (1, 2):
+            s = _solver(mol, order_p=p, leaf_cap=cap, precision=prec, m2l_layout=layout)
+            info = s.tree_info()
+            assert info["m2l_layout"] == layout and info["n_v"] > 0
+            if layout == 1:
+                assert info["n_m2l_slots"] == info["n_m2l_pairs"]
+            ys[layout] = s.matvec(x)
+            errs[layout] = _rel(ys[layout], ref)
+            s.close()
+        d = _rel(ys[2], ys[1])
+        _say(f"{name} p={p} precision={prec} layouts differ {d:.2e}, oracle errors {errs}")
+        assert d < tol
+        assert errs[2] <= 1.05 * errs[1] + tol and errs[2] < 1e-4
+
+
 def test_fmm_matvec_kappa_zero_and_identity_case():
     mol = MOLS["star3"]()
     x = np.random.default_rng(5).normal(size=2 * mol.n_nodes)
