@@ -26,14 +26,23 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per unit (measurement section).
-P2P_FLOPS_PER_PAIR = 60            # canonical count, FMA = 2, transcendentals excluded
+# Algorithmic work per unit: P2P 60 flops per (target, source) pair (canonical
+# count, FMA = 2, transcendentals excluded); M2L 2 K^2 flops per V pair and
+# kernel (4 K^2 for the Laplace and screened kernels together).
+P2P_FLOPS_PER_PAIR = 60
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0     # dense bf16 matrix rate
 PEAK_HBM_GBS = 8000.0
+
+# Leaf capacity per workload: the fastest FP32-refined p = 10 matvec of a
+# sweep on one MI355X (globular: 0.486 / 0.436 / 0.409 / 0.413 ms at leaf
+# 64 / 128 / 192 / 256; complex: 8.32 / 5.86 / 6.54 ms at 64 / 128 / 192).
+# Larger leaves move work from the far-field chain to P2P, which runs on the
+# second stream beside it.
+LEAF_BEST = {"globular": 192, "complex_100k": 128}
 
 
 def parse():
@@ -45,7 +54,8 @@ def parse():
                     help="fp64; fp32 (FP32 FMM, FP64 refinement); bf16 (as fp32 with "
                          "bf16-split M2L)")
     ap.add_argument("--order", type=int, default=10)
-    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--leaf", type=int, default=0,
+                    help="leaf capacity; 0 takes the workload's measured best (LEAF_BEST)")
     ap.add_argument("--workload", choices=["globular", "complex_100k"], default="globular",
                     help="globular (headline) or the 100k-atom complex (~1M nodes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -158,26 +168,35 @@ def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host, do_
             "setup_ms": setup_ms, "solve": solve, "y_host": y_host}
 
 
-def measured_traffic(kernel, order, precision, workload="globular"):
+TRAFFIC_PROFILES = {
+    # (kernel, workload, precision, order, leaf): committed counter summary
+    ("p2p", "globular", "fp32", 10, 192): "p2p_globular_5000_fp32_p10_leaf192_hbm_traffic.md",
+    ("m2l", "globular", "fp32", 10, 192): "m2l_globular_5000_fp32_p10_leaf192_hbm_traffic.md",
+}
+
+
+def measured_traffic(kernel, order, precision, workload="globular", leaf=0):
     """HBM bytes per launch of `kernel` from the committed counter summary of
-    the same workload and configuration, or None (other configuration, or the
-    kernel source changed since the counters were taken)."""
+    the same workload and configuration, or None (no summary for that
+    configuration, or the kernel source changed since the counters were
+    taken)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "m2l_globular_5000_fp32_p10_hbm_traffic.md")
-    if (kernel != "m2l" or order != 10 or precision != "fp32" or workload != "globular"
-            or not os.path.exists(path)):
+    name = TRAFFIC_PROFILES.get((kernel, workload, precision, order, leaf))
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if path is None or not os.path.exists(path):
         return None
     for ln in open(path):
         if ln.startswith("traffic-json:"):
             rec = json.loads(ln.split(":", 1)[1])
-            src = os.path.join(ROOT, rec["source"])
-            if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
-                return None
+            for src, sha in zip(rec["sources"], rec["sources_sha256"]):
+                f = os.path.join(ROOT, src)
+                if hashlib.sha256(open(f, "rb").read()).hexdigest() != sha:
+                    return None
             return rec["bytes_per_launch"]
     return None
 
 
-def roofline(r, order, precision, workload="globular"):
+def roofline(r, order, precision, workload="globular", leaf=0):
     """Roofline entries for P2P (vector ALU) and M2L (matrix cores); the
     dominant kernel of the step (largest total time) is the headline one."""
     info, prof = r["info"], r["prof"]
@@ -202,7 +221,7 @@ def roofline(r, order, precision, workload="globular"):
         achieved = flops / per_step / avg_s / 1e12
         roofs[name] = {"kernel": name, "bound": bound, "achieved": achieved, "peak": pk,
                        "unit": "TFLOP/s", "frac": achieved / pk,
-                       "traffic": measured_traffic(name, order, precision, workload),
+                       "traffic": measured_traffic(name, order, precision, workload, leaf),
                        "flops_per_launch": flops / per_step, "launches_per_step": per_step,
                        "avg_ms": avg_s * 1e3}
     dom = r.get("dominant") or max(prof.items(), key=lambda kv: kv[1][0])[0]
@@ -317,6 +336,8 @@ def serving_child(a):
 
 def main():
     a = parse()
+    if a.leaf == 0:
+        a.leaf = LEAF_BEST[a.workload]
     if a.serve_only:
         import paper_1710_06316_amd as A
         print(json.dumps(serving(A, None, a.serve_requests, a.serve_check, a.serve_budget_gb,
@@ -324,7 +345,8 @@ def main():
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                                   "multi-GPU sharding is a design only (see DESIGN.md)"}))
+                                   "sharding one molecule or a request stream over several "
+                                   "GPUs is designed but not built"}))
         sys.exit(2)
     import torch
 
@@ -337,7 +359,7 @@ def main():
     x_host = np.random.default_rng(99).normal(size=2 * n)
     r = run_config(A, torch, mol, a.precision, a.order, a.leaf, a.steps, a.warmup, x_host,
                    not a.no_solve)
-    roof, roofs, dom = roofline(r, a.order, a.precision, a.workload)
+    roof, roofs, dom = roofline(r, a.order, a.precision, a.workload, a.leaf)
     info = r["info"]
     line = {
         "metric": "FMM matvec Munknowns/s", "value": r["value"], "unit": "Munknowns/s",
@@ -367,7 +389,7 @@ def main():
         line["fp64_plain"] = {"value": r64["value"], "ms_per_step": r64["ms"],
                               "kernels_ms_per_step": {k: v[0] / a.steps
                                                       for k, v in r64["prof"].items()},
-                              "roofline_all": roofline(r64, a.order, "fp64", a.workload)[1],
+                              "roofline_all": roofline(r64, a.order, "fp64", a.workload, a.leaf)[1],
                               "solve": r64["solve"]}
         y_gpu[f"fp64_p{a.order}"] = r64["y_host"]
     if a.serve_requests > 0:

@@ -373,29 +373,38 @@ struct PmItem {
     }
 };
 
-// P2M: one block per item, wave w computes the expansions of kernel w.  Each
+// P2M: one block per item; wave w computes the expansions of kernel w % 2
+// over the 64-point chunks c = w / 2, w / 2 + NCH, ... of the item.  Each
 // lane evaluates the regular basis at one source point (about its own
 // leaf's centre); the coefficients are emitted 16 at a time into LDS
 // (W[slot][point]), and the per-leaf sums over points are one product on the
 // matrix cores: W (16 x 64) times the 0/1 indicator of point-in-leaf
 // (64 x 4, padded to 16 columns), 16 k-steps of four points.  The products
-// by 1 and 0 are exact and the accumulation order is fixed (deterministic).
-template <typename R>
-__global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *pm_leaf,
-                                             const int *pm_first, const int *pm_count,
-                                             const R *px, const R *py, const R *pz,
-                                             const R *pnx, const R *pny, const R *pnz,
-                                             const R *sf, const R *sh, R inv_ebar, R *M,
-                                             int nlev) {
-    __shared__ R Wv[2][16][65];
-    __shared__ int kslot[2][16];
+// by 1 and 0 are exact.  An item of one chunk writes M directly; a larger
+// leaf (several chunks) sums its chunks' partial expansions in chunk order
+// after a barrier (deterministic, the order of a serial pass).
+template <typename R, int NCH>
+__global__ void __launch_bounds__(128 * NCH) k_p2m(BasisDev B, TreeDev T, const int *pm_leaf,
+                                                   const int *pm_first, const int *pm_count,
+                                                   const R *px, const R *py, const R *pz,
+                                                   const R *pnx, const R *pny, const R *pnz,
+                                                   const R *sf, const R *sh, R inv_ebar, R *M,
+                                                   int nlev) {
+    __shared__ R Wv[NCH][2][16][65];
+    __shared__ int kslot[NCH][2][16];
     extern __shared__ __align__(16) unsigned char tab_raw[];
     const BasisTab<R> tab = stage_basis<R>(B, nlev, tab_raw);
+    // partial expansions of the chunks [NCH][2][K], after the basis tables
+    R *part = reinterpret_cast<R *>(tab_raw + basis_tab_bytes(B.P, nlev, sizeof(R)));
     const PmItem it(pm_leaf, pm_first, pm_count, T, blockIdx.x);
     const int lane = threadIdx.x & 63;
-    const int kern = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int kern = wave & 1, ch = wave >> 1;
     const int K = B.K;
-    for (int c0 = 0; c0 < it.tot; c0 += 64) {
+    const bool multi = it.tot > 64;                    // uniform for the block
+    R (*W)[65] = Wv[ch][kern];
+    int *ks_slot = kslot[ch][kern];
+    for (int c0 = 64 * ch; c0 < it.tot; c0 += 64 * NCH) {
         const int q = c0 + lane;
         const bool ok = q < it.tot;
         const int g = it.leaf_of(ok ? q : 0);
@@ -423,19 +432,21 @@ __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *p
 #pragma unroll
             for (int ks = 0; ks < 16; ++ks) {
                 const int pt = 4 * ks + kq;
-                acc = mfma16(Wv[kern][j][pt], (pt >= lo && pt < hi) ? R(1) : R(0), acc);
+                acc = mfma16(W[j][pt], (pt >= lo && pt < hi) ? R(1) : R(0), acc);
             }
             // D[i][j]: the sum of slot i over the points of leaf j
             if (j < it.cnt && max(lo, 0) < min(hi, 64)) {
                 const int lg = pm_leaf[it.first + j];
-                if (T.level[lg] >= 2) {
-                    R *Mb = M + ((long long)lg * 2 + kern) * K;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int slot = drow<R>(lane, r);
-                        if (slot < nslot) {
-                            const int k = kslot[kern][slot];
-                            Mb[k] = (c0 == 0) ? acc[r] : Mb[k] + acc[r];
+                for (int r = 0; r < 4; ++r) {
+                    const int slot = drow<R>(lane, r);
+                    if (slot < nslot) {
+                        const int k = ks_slot[slot];
+                        if (multi) {                     // one leaf (j = 0): this wave's partial
+                            R *pk = part + (ch * 2 + kern) * K + k;
+                            *pk = (c0 == 64 * ch) ? acc[r] : *pk + acc[r];
+                        } else if (T.level[lg] >= 2) {
+                            M[((long long)lg * 2 + kern) * K + k] = acc[r];
                         }
                     }
                 }
@@ -447,12 +458,25 @@ __global__ void __launch_bounds__(128) k_p2m(BasisDev B, TreeDev T, const int *p
         regular_basis_tab<R, Dual<R>>(B, tab, kern, lev, Dual<R>(vx, nx), Dual<R>(vy, ny),
                                       Dual<R>(vz, nz), [&](int k, Dual<R> r) {
                                       const int sl = cnt & 15;
-                                      Wv[kern][sl][lane] = qv * r.v + dip * r.d;
-                                      if (lane == 0) kslot[kern][sl] = k;
+                                      W[sl][lane] = qv * r.v + dip * r.d;
+                                      if (lane == 0) ks_slot[sl] = k;
                                       ++cnt;
                                       if ((cnt & 15) == 0) flush(16);
                                   });
         if (cnt & 15) flush(cnt & 15);
+    }
+    if (!multi) return;                                // uniform for the block
+    __syncthreads();
+    // a leaf of several chunks (it.cnt == 1): sum the waves' partials in
+    // chunk order
+    const int leaf = pm_leaf[it.first];
+    if (T.level[leaf] < 2) return;
+    const int nch = min(NCH, (it.tot + 63) / 64);
+    for (int idx = threadIdx.x; idx < 2 * K; idx += blockDim.x) {
+        const int kn = idx / K, k = idx - kn * K;
+        R acc = part[kn * K + k];
+        for (int c = 1; c < nch; ++c) acc += part[(c * 2 + kn) * K + k];
+        M[((long long)leaf * 2 + kn) * K + k] = acc;
     }
 }
 
@@ -1474,10 +1498,29 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     {
         ProfScope ps(prof, "p2m", s);
         // P2M keeps the generic table recurrence: the unrolled orders need
-        // up to 185 VGPRs here (two waves per SIMD) and run slower
-        k_p2m<R><<<blocks_ok(L.n_pm, 128), 128, basis_tab_bytes(F.P, F.nlev, sizeof(R)), s>>>(
-            B, T, L.pm_leaf.p, L.pm_first.p, L.pm_count.p, px, py, pz, pnx, pny, pnz, sf, sh,
-            R(inv_ebar), w.M, F.nlev);
+        // up to 185 VGPRs here (two waves per SIMD) and run slower;
+        // one wave per kernel and 64-point chunk of the largest item: up to
+        // four chunks at once for FP32, two for FP64, within 60 KB of LDS
+        const size_t lds = basis_tab_bytes(F.P, F.nlev, sizeof(R));
+        auto lds_total = [&](int nc) {
+            return (size_t)nc * 2 * 16 * (65 * sizeof(R) + sizeof(int)) + lds +
+                   (size_t)nc * 2 * K * sizeof(R);
+        };
+        int nc = (int)std::min<long long>((L.pm_max_points + 63) / 64, sizeof(R) == 4 ? 4 : 2);
+        if (nc == 3) nc = 4;
+        while (nc > 1 && lds_total(nc) > 60 * 1024) nc /= 2;
+        auto go = [&](auto kfn, int ncb) {
+            kfn<<<blocks_ok(L.n_pm, 128 * ncb), 128 * ncb, lds + (size_t)ncb * 2 * K * sizeof(R), s>>>(
+                B, T, L.pm_leaf.p, L.pm_first.p, L.pm_count.p, px, py, pz, pnx, pny, pnz, sf, sh,
+                R(inv_ebar), w.M, F.nlev);
+        };
+        if (nc <= 1) {
+            go(k_p2m<R, 1>, 1);
+        } else if (nc == 2) {
+            go(k_p2m<R, 2>, 2);
+        } else {
+            if constexpr (sizeof(R) == sizeof(float)) go(k_p2m<R, 4>, 4);
+        }
         KCHK();
     }
     TransArgs ta{};

@@ -56,7 +56,7 @@ struct Lists {
     // P2M / L2P work: leaves in point order, packed into items of <= 4
     // consecutive leaves with <= 64 points together (a larger leaf alone)
     DBuf<int> pm_leaf, pm_first, pm_count;
-    long long n_pm = 0;
+    long long n_pm = 0, pm_max_points = 0;
     DBuf<int> v_tgt;                   // [n_v] target box of each V entry
     // M2L groups: per-entry layout (m2l_grouped = false): group g is V entry g
     // (its source v_idx[g], result slots in list order, [v_ptr[B],

@@ -660,6 +660,7 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s) {
                 }
             pmf.push_back((int)i);
             pmc.push_back(cnt);
+            L.pm_max_points = std::max(L.pm_max_points, (long long)pts);
             i += cnt;
         }
         L.n_pm = (long long)pmf.size();
