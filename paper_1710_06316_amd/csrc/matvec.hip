@@ -5,6 +5,8 @@
 //           multiplications" per pair);
 //   combine -- y_f = alpha f + P2P_f - Phi_L + Phi_Y + near_f,
 //              y_h = alpha h + P2P_h - dPhi_L/dn + dPhi_Y/dn / ebar + near_h.
+#include <type_traits>
+
 #include "kernels.h"
 #include "matvec.h"
 #include "prof.h"
@@ -77,13 +79,15 @@ __global__ void __launch_bounds__(64) k_p2p(
     const R x = nd.x[ii], y = nd.y[ii], z = nd.z[ii];
     const R n0x = nd.nx[ii], n0y = nd.ny[ii], n0z = nd.nz[ii];
     double af = 0.0, ah = 0.0;
-    // one source pair (T row jj) against this lane's target
-    auto pair = [&](int jj, bool ok, R &bf, R &bh) {
+    // one source pair (T row jj) against this lane's target; MASKED: the
+    // pair may be the target itself or past the tile (then it adds nothing)
+    auto pair = [&](auto masked, int jj, bool ok, R &bf, R &bh) {
+        constexpr bool MASKED = decltype(masked)::value;
         const R rx = x - T[jj][0], ry = y - T[jj][1], rz = z - T[jj][2];
         const R snx = T[jj][3], sny = T[jj][4], snz = T[jj][5];
         const R sfv = T[jj][6], shv = T[jj][7];
         R r2 = (rx * rx + ry * ry) + rz * rz;
-        r2 = ok ? r2 : R(1);
+        if constexpr (MASKED) r2 = ok ? r2 : R(1);
         const R ir = Fast<R>::rsq(r2);
         const R rr = r2 * ir;
         const R s = kappa * rr;
@@ -115,8 +119,13 @@ __global__ void __launch_bounds__(64) k_p2p(
         const R B = Rn * ir3 * (inv_ebar - e1);
         const R Cc = Rn0 * ir3 * (e1 * inv_ebar - R(1));
         const R D = inv_ebar * ir3 * (n0n * fa - Rn0 * Rn * fb * ir * ir);
-        bf += ok ? (B * sfv - A * shv) : R(0);
-        bh += ok ? (D * sfv - Cc * shv) : R(0);
+        if constexpr (MASKED) {
+            bf += ok ? (B * sfv - A * shv) : R(0);
+            bh += ok ? (D * sfv - Cc * shv) : R(0);
+        } else {
+            bf += B * sfv - A * shv;
+            bh += D * sfv - Cc * shv;
+        }
     };
     // Source tiles of 64 points, walked over the chunk's ranges; the next
     // tile is loaded into registers while the current one is evaluated.
@@ -152,13 +161,22 @@ __global__ void __launch_bounds__(64) k_p2p(
         R bf = R(0), bh = R(0);
         // two sources per trip, added in source order; jb + rep <= 63 (jb is a
         // multiple of f below cnt <= 64 and f | 64); the second row index is
-        // clamped into the tile when it is past cnt (then masked)
-        for (int jb = 0; jb < cnt; jb += 2 * f) {
-            const int ja = jb + rep, jc = jb + f + rep;
-            const bool oka = act && ja < cnt && s0c + ja != i;
-            const bool okc = act && jc < cnt && s0c + jc != i;
-            pair(ja, oka, bf, bh);
-            pair(min(jc, 63), okc, bf, bh);
+        // clamped into the tile when it is past cnt (then masked).  A full
+        // tile that holds none of the group's targets needs no mask (the
+        // lanes past the group's targets are discarded by the reduction).
+        if (cnt == 64 && (s0c >= te || s0c + 64 <= tb)) {       // uniform
+            for (int jb = 0; jb < 64; jb += 2 * f) {
+                pair(std::false_type{}, jb + rep, true, bf, bh);
+                pair(std::false_type{}, jb + f + rep, true, bf, bh);
+            }
+        } else {
+            for (int jb = 0; jb < cnt; jb += 2 * f) {
+                const int ja = jb + rep, jc = jb + f + rep;
+                const bool oka = act && ja < cnt && s0c + ja != i;
+                const bool okc = act && jc < cnt && s0c + jc != i;
+                pair(std::true_type{}, ja, oka, bf, bh);
+                pair(std::true_type{}, min(jc, 63), okc, bf, bh);
+            }
         }
         af += (double)bf;
         ah += (double)bh;
