@@ -289,6 +289,9 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     if (c->p2p_part.n < (size_t)c->lists.n_chunks * 128)
         c->p2p_part.alloc((size_t)std::max(c->lists.n_chunks, 1ll) * 128);
     mp.part = c->p2p_part.p;
+    if (c->p2p_rpart.n < (size_t)2 * std::max(c->lists.n_rev, 1ll))
+        c->p2p_rpart.alloc((size_t)2 * std::max(c->lists.n_rev, 1ll));
+    mp.rpart = c->p2p_rpart.p;
     long long widest = 1;
     for (int l = 0; l < c->tree.nlev; ++l)
         widest = std::max(widest, c->tree.level_start[l + 1] - c->tree.level_start[l]);
@@ -397,6 +400,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
         c->fmm = Fmm();
         c->p2p64 = DBuf<double>();
         c->p2p_part = DBuf<double>();
+        c->p2p_rpart = DBuf<double>();
         build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa,
                             prm.precision == AFMPB_FP32_BF16M2L_REFINED, c->fmm, s);
         mark();   // translation operators

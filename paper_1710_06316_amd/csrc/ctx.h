@@ -36,7 +36,7 @@ struct afmpb_ctx {
     Lists lists;
     NearSet near;
     Fmm fmm;
-    DBuf<double> w64, far64, p2p64, p2p_part;
+    DBuf<double> w64, far64, p2p64, p2p_part, p2p_rpart;
     DBuf<float> w32, far32;
     MatvecPlan<double> mp64;
     MatvecPlan<float> mp32;

@@ -53,6 +53,13 @@ struct Lists {
     DBuf<int> grp_ptr, grp_tbeg, grp_tend;  // [n_groups+1], [n_groups], [n_groups]
     DBuf<int> ch_grp;                    // [n_chunks] owning group
     long long n_chunks = 0, n_groups = 0, n_rng = 0;
+    // Each unordered pair of point sets is evaluated once: a reverse chunk
+    // (ch_rev[c] >= 0) also adds the targets' contributions to its sources,
+    // stream position k of the chunk going to reverse slot ch_rev[c] + k;
+    // ch_rev[c] = -1 for a leaf's own points (one-directional).  The reverse
+    // slots of point p are rev_idx[rev_ptr[p] .. rev_ptr[p+1]), in chunk order.
+    DBuf<int> ch_rev, rev_ptr, rev_idx;
+    long long n_rev = 0;
     // P2M / L2P work: leaves in point order, packed into items of <= 4
     // consecutive leaves with <= 64 points together (a larger leaf alone)
     DBuf<int> pm_leaf, pm_first, pm_count;

@@ -25,6 +25,7 @@ struct MatvecPlan {
     R *sf = nullptr, *sh = nullptr;
     double *pf = nullptr, *ph = nullptr;   // P2P sums (double in both precisions)
     double *part = nullptr;                // P2P chunk partial sums [chunks][2][64]
+    double *rpart = nullptr;               // P2P reverse partial sums [reverse slots][2]
     const R *delta = nullptr;              // near corrections [nnz][4], working precision
     hipStream_t side = nullptr;            // near field runs here, between fork and join
     hipEvent_t fork = nullptr, join = nullptr;

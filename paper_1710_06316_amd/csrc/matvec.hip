@@ -57,15 +57,22 @@ struct P2PSeries {
 // 64 at a time in LDS (coalesced loads, zero fill past the range); the copies
 // are added in copy order and the chunk's partial sums go to part[chunk][2][64],
 // which k_p2p_reduce adds per target in chunk order (deterministic).
+// A reverse chunk (rev[c] >= 0) also evaluates every pair the other way: at
+// step k lane (copy q, target ti) meets source row q + f ((ti + k) mod W), so
+// the lanes of one step touch distinct rows, whose sums over the tile go to
+// the reverse slots rev[c] + (stream position) of rpart[slot][2].
 template <typename R>
 __global__ void __launch_bounds__(64) k_p2p(
     const int *__restrict__ ch_lo, const int *__restrict__ ch_hi, const int *__restrict__ ch_grp,
     const int *__restrict__ grp_tbeg, const int *__restrict__ grp_tend,
-    const int *__restrict__ rng_b, const int *__restrict__ rng_e, NodeR<R> nd,
-    const R *__restrict__ sf, const R *__restrict__ sh, R kappa, R inv_ebar,
-    double *__restrict__ part) {
+    const int *__restrict__ rng_b, const int *__restrict__ rng_e, const int *__restrict__ rev,
+    NodeR<R> nd, const R *__restrict__ sf, const R *__restrict__ sh, R kappa, R inv_ebar,
+    double *__restrict__ part, double *__restrict__ rpart) {
     constexpr P2PSeries S;
     __shared__ R T[64][8];
+    // reverse sums of the tile's sources, even and odd steps apart (the two
+    // updates of one trip cannot alias, so they overlap)
+    __shared__ R RV0[64][2], RV1[64][2];
     __shared__ double red[2][64];
     const int lane = threadIdx.x;
     const int c = blockIdx.x;
@@ -78,11 +85,14 @@ __global__ void __launch_bounds__(64) k_p2p(
     const int ii = act ? i : tb;
     const R x = nd.x[ii], y = nd.y[ii], z = nd.z[ii];
     const R n0x = nd.nx[ii], n0y = nd.ny[ii], n0z = nd.nz[ii];
+    // this lane's target as a source of the reverse pairs (zero when inactive)
+    const R tsf = act ? sf[ii] : R(0), tsh = act ? sh[ii] : R(0);
+    const int roff = rev[c];                          // uniform; -1: one-directional
     double af = 0.0, ah = 0.0;
     // one source pair (T row jj) against this lane's target; MASKED: the
     // pair may be the target itself or past the tile (then it adds nothing)
-    auto pair = [&](auto masked, int jj, bool ok, R &bf, R &bh) {
-        constexpr bool MASKED = decltype(masked)::value;
+    auto pair = [&](auto masked, auto both, int jj, bool ok, R &bf, R &bh, R &rf, R &rh) {
+        constexpr bool MASKED = decltype(masked)::value, BOTH = decltype(both)::value;
         const R rx = x - T[jj][0], ry = y - T[jj][1], rz = z - T[jj][2];
         const R snx = T[jj][3], sny = T[jj][4], snz = T[jj][5];
         const R sfv = T[jj][6], shv = T[jj][7];
@@ -126,6 +136,14 @@ __global__ void __launch_bounds__(64) k_p2p(
             bf += B * sfv - A * shv;
             bh += D * sfv - Cc * shv;
         }
+        if constexpr (BOTH) {
+            // the pair the other way: r -> -r swaps the roles of the two
+            // normals (Rn -> -Rn0, Rn0 -> -Rn); A and D are unchanged
+            const R Br = -Rn0 * ir3 * (inv_ebar - e1);
+            const R Cr = -Rn * ir3 * (e1 * inv_ebar - R(1));
+            rf = MASKED && !ok ? R(0) : Br * tsf - A * tsh;
+            rh = MASKED && !ok ? R(0) : D * tsf - Cr * tsh;
+        }
     };
     // Source tiles of 64 points, walked over the chunk's ranges; the next
     // tile is loaded into registers while the current one is evaluated.
@@ -143,10 +161,16 @@ __global__ void __launch_bounds__(64) k_p2p(
         v[6] = in ? sf[j] : R(0);    v[7] = in ? sh[j] : R(0);
     };
     if (r < rhi) fetch(s0, ce);
+    int pos = 0;                                      // stream position of the tile
+    R rdum0, rdum1;
     while (r < rhi) {
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < 8; ++q) T[lane][q] = v[q];
+        RV0[lane][0] = R(0);
+        RV0[lane][1] = R(0);
+        RV1[lane][0] = R(0);
+        RV1[lane][1] = R(0);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -164,20 +188,50 @@ __global__ void __launch_bounds__(64) k_p2p(
         // clamped into the tile when it is past cnt (then masked).  A full
         // tile that holds none of the group's targets needs no mask (the
         // lanes past the group's targets are discarded by the reduction).
-        if (cnt == 64 && (s0c >= te || s0c + 64 <= tb)) {       // uniform
+        if (roff >= 0) {                                          // uniform
+            // reverse chunk (sources never include the group's targets);
+            // inactive lanes add nothing the other way (zero strengths)
+            auto rot = [&](auto masked, int k, R (*RV)[2]) {
+                const int jrow = rep + f * ((ti + k) & (W - 1));
+                R rf, rh;
+                pair(masked, std::true_type{}, jrow, jrow < cnt, bf, bh, rf, rh);
+                RV[jrow][0] += rf;
+                RV[jrow][1] += rh;
+            };
+            if (cnt == 64) {
+                for (int k = 0; k < W; k += 2) {
+                    rot(std::false_type{}, k, RV0);
+                    rot(std::false_type{}, k + 1, RV1);
+                }
+            } else {
+                for (int k = 0; k < W; k += 2) {
+                    rot(std::true_type{}, k, RV0);
+                    rot(std::true_type{}, k + 1, RV1);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < cnt) {
+                double *o = rpart + 2 * ((long long)roff + pos + lane);
+                o[0] = (double)(RV0[lane][0] + RV1[lane][0]);
+                o[1] = (double)(RV0[lane][1] + RV1[lane][1]);
+            }
+        } else if (cnt == 64 && (s0c >= te || s0c + 64 <= tb)) { // uniform
             for (int jb = 0; jb < 64; jb += 2 * f) {
-                pair(std::false_type{}, jb + rep, true, bf, bh);
-                pair(std::false_type{}, jb + f + rep, true, bf, bh);
+                pair(std::false_type{}, std::false_type{}, jb + rep, true, bf, bh, rdum0, rdum1);
+                pair(std::false_type{}, std::false_type{}, jb + f + rep, true, bf, bh, rdum0, rdum1);
             }
         } else {
             for (int jb = 0; jb < cnt; jb += 2 * f) {
                 const int ja = jb + rep, jc = jb + f + rep;
                 const bool oka = act && ja < cnt && s0c + ja != i;
                 const bool okc = act && jc < cnt && s0c + jc != i;
-                pair(std::true_type{}, ja, oka, bf, bh);
-                pair(std::true_type{}, min(jc, 63), okc, bf, bh);
+                pair(std::true_type{}, std::false_type{}, ja, oka, bf, bh, rdum0, rdum1);
+                pair(std::true_type{}, std::false_type{}, min(jc, 63), okc, bf, bh, rdum0, rdum1);
             }
         }
+        pos += cnt;
         af += (double)bf;
         ah += (double)bh;
     }
@@ -201,6 +255,9 @@ __global__ void __launch_bounds__(64) k_p2p_reduce(const int *__restrict__ grp_p
                                                    const int *__restrict__ grp_tbeg,
                                                    const int *__restrict__ grp_tend,
                                                    const double *__restrict__ part,
+                                                   const int *__restrict__ rev_ptr,
+                                                   const int *__restrict__ rev_idx,
+                                                   const double *__restrict__ rpart,
                                                    double *__restrict__ out_f,
                                                    double *__restrict__ out_h) {
     const int g = blockIdx.x, lane = threadIdx.x;
@@ -210,6 +267,12 @@ __global__ void __launch_bounds__(64) k_p2p_reduce(const int *__restrict__ grp_p
     for (int c = grp_ptr[g]; c < grp_ptr[g + 1]; ++c) {
         tf += part[((long long)c * 2) * 64 + lane];
         th += part[((long long)c * 2 + 1) * 64 + lane];
+    }
+    // the pairs evaluated the other way, in chunk order
+    for (int q = rev_ptr[i]; q < rev_ptr[i + 1]; ++q) {
+        const long long sl = rev_idx[q];
+        tf += rpart[2 * sl];
+        th += rpart[2 * sl + 1];
     }
     out_f[i] = tf * INV_4PI;
     out_h[i] = th * INV_4PI;
@@ -329,10 +392,11 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
         const Lists &L = *mp.lists;
         k_p2p<R><<<blocks_ok(L.n_chunks, 64), 64, 0, mp.side>>>(
             L.ch_lo.p, L.ch_hi.p, L.ch_grp.p, L.grp_tbeg.p, L.grp_tend.p, L.rng_b.p, L.rng_e.p,
-            mp.nd, mp.sf, mp.sh, R(mp.kappa), R(mp.inv_ebar), mp.part);
+            L.ch_rev.p, mp.nd, mp.sf, mp.sh, R(mp.kappa), R(mp.inv_ebar), mp.part, mp.rpart);
         KCHK();
-        k_p2p_reduce<<<blocks_ok(L.n_groups, 64), 64, 0, mp.side>>>(L.grp_ptr.p, L.grp_tbeg.p,
-                                                                L.grp_tend.p, mp.part, mp.pf, mp.ph);
+        k_p2p_reduce<<<blocks_ok(L.n_groups, 64), 64, 0, mp.side>>>(
+            L.grp_ptr.p, L.grp_tbeg.p, L.grp_tend.p, mp.part, L.rev_ptr.p, L.rev_idx.p, mp.rpart,
+            mp.pf, mp.ph);
         KCHK();
     }
     {

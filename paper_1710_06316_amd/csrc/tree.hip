@@ -581,36 +581,36 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s) {
     KCHK();
     require(read_scalar(err.p, s) == 0, ST_DEVICE, "P2P task fill out of range");
     {
-        // balanced P2P chunks: per leaf, the source boxes' point ranges (adjacent
-        // ranges merged), cut into spans of at most P2P_CHUNK points per lane
-        // copy; every (target group, span) is one work item
+        // Balanced P2P chunks.  The point pairs of the U, W and X lists are
+        // symmetric (U(B) holds C iff U(C) holds B; X is the transpose of W),
+        // so every unordered pair of point sets is evaluated once: leaf B
+        // takes its own points (one-directional, the pair p = t excluded),
+        // the leaves of U(B) after B and the boxes of W(B); those are
+        // reverse chunks, whose sources also receive the targets'
+        // contributions (the X-list side of W, and the other side of U).
+        // Source point ranges (touching ranges merged) are cut into spans of
+        // at most P2P_CHUNK points per lane copy; every (target group, span)
+        // is one work item.
         constexpr int P2P_CHUNK = 256;
-        std::vector<int> sptr(nl + 1), src(L.n_p2p_src), leaf(nl), ptb_h(nb), pte_h(nb);
-        L.p2p_ptr.download(sptr.data(), nl + 1, s);
-        L.p2p_src.download(src.data(), L.n_p2p_src, s);
+        std::vector<int> leaf(nl), ptb_h(nb), pte_h(nb);
+        std::vector<int> uptr(nb + 1), uidx(std::max(L.n_u, 1ll)), wptr(nb + 1), widx(std::max(L.n_w, 1ll));
         L.leaf_ids.download(leaf.data(), nl, s);
         t.pt_begin.download(ptb_h.data(), nb, s);
         t.pt_end.download(pte_h.data(), nb, s);
+        L.u_ptr.download(uptr.data(), nb + 1, s);
+        L.u_idx.download(uidx.data(), L.n_u, s);
+        L.w_ptr.download(wptr.data(), nb + 1, s);
+        L.w_idx.download(widx.data(), L.n_w, s);
         HIPCHK(hipStreamSynchronize(s));
-        std::vector<int> rb, re, clo, chi, cgrp, gptr, gtb, gte;
+        const long long npts = pte_h[0];
+        std::vector<int> rb, re, clo, chi, cgrp, gptr, gtb, gte, crev;
         std::vector<std::pair<int, int>> r;
-        for (long long i = 0; i < nl; ++i) {
-            r.clear();
-            for (int q = sptr[i]; q < sptr[i + 1]; ++q) r.emplace_back(ptb_h[src[q]], pte_h[src[q]]);
-            std::sort(r.begin(), r.end());
-            // merge touching ranges, then cut into spans of <= P2P_CHUNK points
-            std::vector<std::pair<int, int>> m;
-            for (auto &x : r) {
-                if (!m.empty() && x.first <= m.back().second) m.back().second = std::max(m.back().second, x.second);
-                else m.push_back(x);
-            }
-            const long long r0 = (long long)rb.size();
-            const int B = leaf[i];
-            // replicated lanes take proportionally more sources per chunk
-            const long long budget =
-                (long long)P2P_CHUNK * p2p_replicas(std::min(64, pte_h[B] - ptb_h[B]));
+        long long nrev = 0, pairs = 0;
+        // cut merged ranges into spans of <= budget points: returns the span
+        // boundaries (indices into rb/re)
+        auto spans = [&](std::vector<std::pair<int, int>> &m, long long budget) {
+            std::vector<long long> cut{(long long)rb.size()};
             long long acc = 0;
-            std::vector<long long> cut{r0};
             for (auto &x : m) {
                 int b = x.first;
                 while (b < x.second) {
@@ -623,24 +623,89 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s) {
                 }
             }
             if ((long long)rb.size() > cut.back()) cut.push_back((long long)rb.size());
+            return cut;
+        };
+        auto npts_of = [&](long long lo, long long hi) {
+            long long c = 0;
+            for (long long k = lo; k < hi; ++k) c += re[k] - rb[k];
+            return c;
+        };
+        for (long long i = 0; i < nl; ++i) {
+            const int B = leaf[i];
+            // replicated lanes take proportionally more sources per chunk
+            const long long budget =
+                (long long)P2P_CHUNK * p2p_replicas(std::min(64, pte_h[B] - ptb_h[B]));
+            std::vector<std::pair<int, int>> self{{ptb_h[B], pte_h[B]}};
+            const std::vector<long long> cs = spans(self, budget);
+            r.clear();
+            for (int q = uptr[B]; q < uptr[B + 1]; ++q)
+                if (uidx[q] > B) r.emplace_back(ptb_h[uidx[q]], pte_h[uidx[q]]);
+            for (int q = wptr[B]; q < wptr[B + 1]; ++q) r.emplace_back(ptb_h[widx[q]], pte_h[widx[q]]);
+            std::sort(r.begin(), r.end());
+            std::vector<std::pair<int, int>> m;
+            for (auto &x : r) {
+                if (!m.empty() && x.first <= m.back().second) m.back().second = std::max(m.back().second, x.second);
+                else m.push_back(x);
+            }
+            const std::vector<long long> cr = spans(m, budget);
             for (int tb = ptb_h[B]; tb < pte_h[B]; tb += 64) {
+                const int te = std::min(tb + 64, pte_h[B]);
                 gptr.push_back((int)clo.size());
                 gtb.push_back(tb);
-                gte.push_back(std::min(tb + 64, pte_h[B]));
-                for (size_t k = 0; k + 1 < cut.size(); ++k) {
-                    clo.push_back((int)cut[k]);
-                    chi.push_back((int)cut[k + 1]);
+                gte.push_back(te);
+                pairs += (long long)(te - tb) * (pte_h[B] - ptb_h[B] - 1);
+                for (size_t k = 0; k + 1 < cs.size(); ++k) {
+                    clo.push_back((int)cs[k]);
+                    chi.push_back((int)cs[k + 1]);
                     cgrp.push_back((int)gtb.size() - 1);
+                    crev.push_back(-1);
+                }
+                for (size_t k = 0; k + 1 < cr.size(); ++k) {
+                    const long long np = npts_of(cr[k], cr[k + 1]);
+                    clo.push_back((int)cr[k]);
+                    chi.push_back((int)cr[k + 1]);
+                    cgrp.push_back((int)gtb.size() - 1);
+                    crev.push_back((int)nrev);
+                    nrev += np;
+                    pairs += 2 * (long long)(te - tb) * np;
                 }
             }
         }
         gptr.push_back((int)clo.size());
-        require(rb.size() < (1ull << 31) && clo.size() < (1ull << 31), ST_INVALID, "too many P2P chunks");
+        require(rb.size() < (1ull << 31) && clo.size() < (1ull << 31) && nrev < (1ll << 31),
+                ST_INVALID, "too many P2P chunks");
+        require(pairs == L.n_p2p_pairs, ST_DEVICE,
+                "P2P tasks do not cover the U/W/X point pairs exactly once");
+        // reverse slots of every point, in chunk order (CSR over points)
+        {
+            std::vector<int> cnt(npts + 1, 0), rptr(npts + 1), ridx(std::max(nrev, 1ll));
+            for (size_t c = 0; c < clo.size(); ++c)
+                if (crev[c] >= 0)
+                    for (int k = clo[c]; k < chi[c]; ++k)
+                        for (int p = rb[k]; p < re[k]; ++p) ++cnt[p];
+            rptr[0] = 0;
+            for (long long p = 0; p < npts; ++p) rptr[p + 1] = rptr[p] + cnt[p];
+            std::vector<int> cur(rptr.begin(), rptr.end() - 1);
+            for (size_t c = 0; c < clo.size(); ++c) {
+                if (crev[c] < 0) continue;
+                int slot = crev[c];
+                for (int k = clo[c]; k < chi[c]; ++k)
+                    for (int p = rb[k]; p < re[k]; ++p) ridx[cur[p]++] = slot++;
+            }
+            L.n_rev = nrev;
+            L.rev_ptr.alloc(npts + 1);
+            L.rev_idx.alloc(ridx.size());
+            L.rev_ptr.upload(rptr.data(), rptr.size(), s);
+            L.rev_idx.upload(ridx.data(), ridx.size(), s);
+            HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
+        }
         L.n_rng = (long long)rb.size();
         L.n_chunks = (long long)clo.size();
         L.n_groups = (long long)gtb.size();
         L.rng_b.alloc(L.n_rng); L.rng_e.alloc(L.n_rng);
         L.ch_lo.alloc(L.n_chunks); L.ch_hi.alloc(L.n_chunks); L.ch_grp.alloc(L.n_chunks);
+        L.ch_rev.alloc(L.n_chunks);
+        L.ch_rev.upload(crev.data(), crev.size(), s);
         L.grp_ptr.alloc(L.n_groups + 1); L.grp_tbeg.alloc(L.n_groups); L.grp_tend.alloc(L.n_groups);
         L.rng_b.upload(rb.data(), rb.size(), s); L.rng_e.upload(re.data(), re.size(), s);
         L.ch_lo.upload(clo.data(), clo.size(), s); L.ch_hi.upload(chi.data(), chi.size(), s);
