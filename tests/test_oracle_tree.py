@@ -89,6 +89,40 @@ def test_lists_cover_every_pair_exactly_once(n, cap, seed):
             assert leaf[C]
 
 
+@pytest.mark.parametrize("n,cap,seed", [(200, 4, 4), (1200, 12, 5), (4000, 24, 6)])
+def test_direct_pairs_decompose_into_symmetric_tasks(n, cap, seed):
+    """The direct (P2P) point pairs of the U, W and X lists are symmetric, so
+    each unordered pair of point sets can be evaluated once: a leaf's own
+    points (one way, p != t), the leaves of U(B) after B and the boxes of
+    W(B), each credited both ways, give every ordered pair of U(B) u W(B) u
+    X(A) (A = B and its ancestors) exactly once."""
+    x = _clustered(n, seed)
+    t = T.build_tree(x, cap)
+    L = T.build_lists(t)
+    leaf = np.nonzero(t.is_leaf())[0]
+    direct = np.zeros((n, n), np.int64)        # the lists' ordered pairs
+    tasks = np.zeros((n, n), np.int64)         # the symmetric tasks' ordered pairs
+    for B in leaf:
+        P = slice(t.pt_begin[B], t.pt_end[B])
+        srcs = set(L.U[B]) | set(L.W[B])
+        A = B
+        while A >= 0:
+            srcs |= set(L.X[A])
+            A = t.parent[A]
+        for C in srcs:
+            direct[P, t.pt_begin[C]:t.pt_end[C]] += 1
+        tasks[P, P] += 1
+        for C in [c for c in L.U[B] if c > B] + list(L.W[B]):
+            S = slice(t.pt_begin[C], t.pt_end[C])
+            tasks[P, S] += 1
+            tasks[S, P] += 1
+    np.fill_diagonal(direct, 0)
+    np.fill_diagonal(tasks, 0)
+    assert direct.max() == 1 and tasks.max() == 1
+    assert (direct == tasks).all()
+    assert (direct == direct.T).all()
+
+
 def test_offset_class_ranking():
     assert T.offset_class((-3, -3, -3)) == 0
     assert T.offset_class((3, 3, 3)) == 315
