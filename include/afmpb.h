@@ -290,9 +290,9 @@ typedef struct {
 } afmpb_server_counts;
 
 /* Starts a server on `device` with setup_threads threads that build admitted
- * requests and one stepping thread.  setup_threads must be 1 in this build:
- * parallel setup is switched off until a host crash seen with several setup
- * threads is understood (AFMPB_E_INVALID otherwise).  params as for
+ * requests and one stepping thread.  setup_threads must be 1: parallel setup
+ * is switched off until a host crash seen with several setup threads is
+ * understood (AFMPB_E_INVALID otherwise).  params as for
  * afmpb_set_molecule, except that order_p == 0 / leaf_cap == 0 select per
  * request from the tuning table.  Errors: AFMPB_E_INVALID. */
 afmpb_status afmpb_server_create(const afmpb_params *params,
