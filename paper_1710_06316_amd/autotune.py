@@ -33,7 +33,7 @@ def _solve(A, mol, **params):
     return E, dt, bool(info.converged)
 
 
-def tune(levels=(3, 4, 5, 6), samples=2, leafs=(16, 32, 64, 128), orders=(6, 8, 10),
+def tune(levels=(3, 4, 5, 6), samples=2, leafs=(16, 32, 64, 128, 192, 256), orders=(6, 8, 10),
          precision=1, tol=2e-5, seed0=9000, log=print):
     import paper_1710_06316_amd as A
     root = os.path.dirname(HERE)
