@@ -518,6 +518,29 @@ void check_setup(afmpb_ctx *c) {
             if (gp[g + 1] <= gp[g]) bad("P2P group without chunks");
             if (gb[g] < 0 || ge[g] > n || gb[g] >= ge[g] || ge[g] - gb[g] > 64) bad("P2P group targets");
         }
+        // reverse chunks: each chunk's source stream owns the slots
+        // [rev[c], rev[c] + its points); every point's slot list is a set of
+        // distinct slots, together all of them
+        auto crv = host_copy(L.ch_rev, L.n_chunks, s);
+        auto rp = host_copy(L.rev_ptr, n + 1, s);
+        auto ri = host_copy(L.rev_idx, std::max(L.n_rev, 1ll), s);
+        c->sync();
+        for (long long k = 0; k < L.n_chunks; ++k) {
+            if (crv[k] < -1) bad("P2P reverse chunk");
+            if (crv[k] < 0) continue;
+            long long np = 0;
+            for (int q = clo[k]; q < chi[k]; ++q) np += re[q] - rb[q];
+            if (crv[k] + np > L.n_rev) bad("P2P reverse slots");
+        }
+        if (rp[0] != 0 || rp[n] != L.n_rev) bad("P2P reverse ptr");
+        std::vector<char> used(std::max(L.n_rev, 1ll), 0);
+        for (long long p = 0; p < n; ++p) {
+            if (rp[p + 1] < rp[p]) bad("P2P reverse ptr");
+            for (long long q = rp[p]; q < rp[p + 1]; ++q) {
+                if (ri[q] < 0 || ri[q] >= L.n_rev || used[ri[q]]) bad("P2P reverse slot list");
+                used[ri[q]] = 1;
+            }
+        }
     }
     {
         // P2M / L2P items: every leaf once, <= 4 leaves and <= 64 points per
