@@ -263,13 +263,49 @@ __global__ void __launch_bounds__(64) k_p2p_reduce(const int *__restrict__ grp_p
     const int g = blockIdx.x, lane = threadIdx.x;
     const int i = grp_tbeg[g] + lane;
     if (i >= grp_tend[g]) return;
+    // loads are issued RB entries ahead of the additions, which stay in
+    // chunk order (few waves per SIMD: the sum is bound by load latency)
+    constexpr int RB = 8;
     double tf = 0.0, th = 0.0;
-    for (int c = grp_ptr[g]; c < grp_ptr[g + 1]; ++c) {
+    int c = grp_ptr[g];
+    const int c1 = grp_ptr[g + 1];
+    for (; c + RB <= c1; c += RB) {
+        double vf[RB], vh[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            vf[k] = part[((long long)(c + k) * 2) * 64 + lane];
+            vh[k] = part[((long long)(c + k) * 2 + 1) * 64 + lane];
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            tf += vf[k];
+            th += vh[k];
+        }
+    }
+    for (; c < c1; ++c) {
         tf += part[((long long)c * 2) * 64 + lane];
         th += part[((long long)c * 2 + 1) * 64 + lane];
     }
     // the pairs evaluated the other way, in chunk order
-    for (int q = rev_ptr[i]; q < rev_ptr[i + 1]; ++q) {
+    int q = rev_ptr[i];
+    const int q1 = rev_ptr[i + 1];
+    for (; q + RB <= q1; q += RB) {
+        long long sl[RB];
+        double vf[RB], vh[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) sl[k] = rev_idx[q + k];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            vf[k] = rpart[2 * sl[k]];
+            vh[k] = rpart[2 * sl[k] + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            tf += vf[k];
+            th += vh[k];
+        }
+    }
+    for (; q < q1; ++q) {
         const long long sl = rev_idx[q];
         tf += rpart[2 * sl];
         th += rpart[2 * sl + 1];
