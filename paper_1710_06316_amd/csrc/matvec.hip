@@ -323,25 +323,26 @@ __global__ void k_gather_sources(const double *__restrict__ x, const double *__r
     sh[i] = R(area[i] * x[n + i]);
 }
 
-// Near correction: one group of 8 lanes per row (two entries in flight per
-// lane), lane partial sums added by a fixed butterfly; the row's sums are
-// added to the P2P sums.
+// Near correction: one group of 16 lanes per row (two entries in flight per
+// lane, so a row of ~70 entries takes ~3 dependent index/gather trips), lane
+// partial sums added by a fixed butterfly; the row's sums are added to the
+// P2P sums.
 template <typename R>
 __global__ void k_near_apply(long long n, const double *__restrict__ x,
                              const long long *__restrict__ nptr, const int *__restrict__ ncol,
                              const R *__restrict__ nd, double *__restrict__ pf,
                              double *__restrict__ ph) {
     long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long p = gid >> 3;
-    int sub = (int)(gid & 7);
+    long long p = gid >> 4;
+    int sub = (int)(gid & 15);
     double cf = 0.0, ch = 0.0, cf2 = 0.0, ch2 = 0.0;
     if (p < n) {
         const long long e1 = nptr[p + 1];
         long long e = nptr[p] + sub;
-        for (; e + 8 < e1; e += 16) {
-            const int t = ncol[e], t2 = ncol[e + 8];
+        for (; e + 16 < e1; e += 32) {
+            const int t = ncol[e], t2 = ncol[e + 16];
             const double f = x[t], h = x[n + t], f2 = x[t2], h2 = x[n + t2];
-            const R *d = nd + 4 * e, *d2 = nd + 4 * (e + 8);
+            const R *d = nd + 4 * e, *d2 = nd + 4 * (e + 16);
             cf += (double)d[1] * f - (double)d[0] * h;
             ch += (double)d[3] * f - (double)d[2] * h;
             cf2 += (double)d2[1] * f2 - (double)d2[0] * h2;
@@ -358,9 +359,9 @@ __global__ void k_near_apply(long long n, const double *__restrict__ x,
     cf += cf2;
     ch += ch2;
 #pragma unroll
-    for (int o = 4; o > 0; o >>= 1) {
-        cf += __shfl_xor(cf, o, 8);
-        ch += __shfl_xor(ch, o, 8);
+    for (int o = 8; o > 0; o >>= 1) {
+        cf += __shfl_xor(cf, o, 16);
+        ch += __shfl_xor(ch, o, 16);
     }
     if (p < n && sub == 0) {
         pf[p] += cf;
@@ -437,7 +438,7 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
     }
     {
         ProfScope ps(prof, "near", mp.side);
-        k_near_apply<R><<<grid_for(8 * n, 256), 256, 0, mp.side>>>(
+        k_near_apply<R><<<grid_for(16 * n, 256), 256, 0, mp.side>>>(
             n, x, mp.near->ptr.p, mp.near->col.p, mp.delta, mp.pf, mp.ph);
         KCHK();
     }
