@@ -123,12 +123,17 @@ __global__ void __launch_bounds__(64) k_p2p(
         const R Rn = (rx * snx + ry * sny) + rz * snz;
         const R Rn0 = (rx * n0x + ry * n0y) + rz * n0z;
         const R n0n = (n0x * snx + n0y * sny) + n0z * snz;
-        const R ir3 = ir * ir * ir;
+        const R ir2 = ir * ir;
+        const R ir3 = ir2 * ir;
         const R e1 = e * (R(1) + s);
         const R A = om * ir;
-        const R B = Rn * ir3 * (inv_ebar - e1);
-        const R Cc = Rn0 * ir3 * (e1 * inv_ebar - R(1));
-        const R D = inv_ebar * ir3 * (n0n * fa - Rn0 * Rn * fb * ir * ir);
+        // B = Rn Pb, Cc = Rn0 Pc (the factors are shared with the pair the
+        // other way)
+        const R Pb = ir3 * (inv_ebar - e1);
+        const R Pc = ir3 * (e1 * inv_ebar - R(1));
+        const R B = Rn * Pb;
+        const R Cc = Rn0 * Pc;
+        const R D = (inv_ebar * ir3) * (n0n * fa - (Rn0 * Rn) * (fb * ir2));
         if constexpr (MASKED) {
             bf += ok ? (B * sfv - A * shv) : R(0);
             bh += ok ? (D * sfv - Cc * shv) : R(0);
@@ -139,8 +144,8 @@ __global__ void __launch_bounds__(64) k_p2p(
         if constexpr (BOTH) {
             // the pair the other way: r -> -r swaps the roles of the two
             // normals (Rn -> -Rn0, Rn0 -> -Rn); A and D are unchanged
-            const R Br = -Rn0 * ir3 * (inv_ebar - e1);
-            const R Cr = -Rn * ir3 * (e1 * inv_ebar - R(1));
+            const R Br = -Rn0 * Pb;
+            const R Cr = -Rn * Pc;
             rf = MASKED && !ok ? R(0) : Br * tsf - A * tsh;
             rh = MASKED && !ok ? R(0) : D * tsf - Cr * tsh;
         }
@@ -324,7 +329,7 @@ __global__ void k_gather_sources(const double *__restrict__ x, const double *__r
 }
 
 // Near correction: one group of 16 lanes per row (two entries in flight per
-// lane, so a row of ~70 entries takes ~3 dependent index/gather trips), lane
+// lane, so a row of ~110 entries takes ~4 dependent index/gather trips), lane
 // partial sums added by a fixed butterfly; the row's sums are added to the
 // P2P sums.
 template <typename R>
