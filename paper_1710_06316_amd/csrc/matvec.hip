@@ -62,7 +62,7 @@ struct P2PSeries {
 // the lanes of one step touch distinct rows, whose sums over the tile go to
 // the reverse slots rev[c] + (stream position) of rpart[slot][2].
 template <typename R>
-__global__ void __launch_bounds__(64) k_p2p(
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 1 : 3))) k_p2p(
     const int *__restrict__ ch_lo, const int *__restrict__ ch_hi, const int *__restrict__ ch_grp,
     const int *__restrict__ grp_tbeg, const int *__restrict__ grp_tend,
     const int *__restrict__ rng_b, const int *__restrict__ rng_e, const int *__restrict__ rev,
@@ -89,8 +89,9 @@ __global__ void __launch_bounds__(64) k_p2p(
     const R tsf = act ? sf[ii] : R(0), tsh = act ? sh[ii] : R(0);
     const int roff = rev[c];                          // uniform; -1: one-directional
     double af = 0.0, ah = 0.0;
-    // one source pair (T row jj) against this lane's target; MASKED: the
-    // pair may be the target itself or past the tile (then it adds nothing)
+    // one source pair (T row jj) against this lane's target, added to bf, bh
+    // (and, BOTH, the pair the other way to rf, rh); MASKED: the pair may be
+    // the target itself or past the tile (then it adds nothing)
     auto pair = [&](auto masked, auto both, int jj, bool ok, R &bf, R &bh, R &rf, R &rh) {
         constexpr bool MASKED = decltype(masked)::value, BOTH = decltype(both)::value;
         const R rx = x - T[jj][0], ry = y - T[jj][1], rz = z - T[jj][2];
@@ -134,20 +135,23 @@ __global__ void __launch_bounds__(64) k_p2p(
         const R B = Rn * Pb;
         const R Cc = Rn0 * Pc;
         const R D = (inv_ebar * ir3) * (n0n * fa - (Rn0 * Rn) * (fb * ir2));
+        // the terms are added one at a time (two fused multiply-adds each)
         if constexpr (MASKED) {
-            bf += ok ? (B * sfv - A * shv) : R(0);
-            bh += ok ? (D * sfv - Cc * shv) : R(0);
+            bf = ok ? (bf + B * sfv) - A * shv : bf;
+            bh = ok ? (bh + D * sfv) - Cc * shv : bh;
         } else {
-            bf += B * sfv - A * shv;
-            bh += D * sfv - Cc * shv;
+            bf = (bf + B * sfv) - A * shv;
+            bh = (bh + D * sfv) - Cc * shv;
         }
         if constexpr (BOTH) {
-            // the pair the other way: r -> -r swaps the roles of the two
-            // normals (Rn -> -Rn0, Rn0 -> -Rn); A and D are unchanged
+            // the pair the other way, added to rf, rh: r -> -r swaps the roles
+            // of the two normals (Rn -> -Rn0, Rn0 -> -Rn); A and D are unchanged
             const R Br = -Rn0 * Pb;
             const R Cr = -Rn * Pc;
-            rf = MASKED && !ok ? R(0) : Br * tsf - A * tsh;
-            rh = MASKED && !ok ? R(0) : D * tsf - Cr * tsh;
+            if (!MASKED || ok) {
+                rf = (rf + Br * tsf) - A * tsh;
+                rh = (rh + D * tsf) - Cr * tsh;
+            }
         }
     };
     // Source tiles of 64 points, walked over the chunk's ranges; the next
@@ -198,10 +202,10 @@ __global__ void __launch_bounds__(64) k_p2p(
             // inactive lanes add nothing the other way (zero strengths)
             auto rot = [&](auto masked, int k, R (*RV)[2]) {
                 const int jrow = rep + f * ((ti + k) & (W - 1));
-                R rf, rh;
+                R rf = RV[jrow][0], rh = RV[jrow][1];
                 pair(masked, std::true_type{}, jrow, jrow < cnt, bf, bh, rf, rh);
-                RV[jrow][0] += rf;
-                RV[jrow][1] += rh;
+                RV[jrow][0] = rf;
+                RV[jrow][1] = rh;
             };
             if (cnt == 64) {
                 for (int k = 0; k < W; k += 2) {
