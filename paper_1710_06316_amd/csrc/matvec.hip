@@ -129,12 +129,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(
         const R e1 = e * (R(1) + s);
         const R A = om * ir;
         // B = Rn Pb, Cc = Rn0 Pc (the factors are shared with the pair the
-        // other way)
-        const R Pb = ir3 * (inv_ebar - e1);
-        const R Pc = ir3 * (e1 * inv_ebar - R(1));
+        // other way); Pb = ir3 (1/ebar - e1), Pc = ir3 (e1/ebar - 1), one
+        // fused multiply-add each
+        const R ir3e = inv_ebar * ir3;
+        const R Pb = ir3e - ir3 * e1;
+        const R Pc = e1 * ir3e - ir3;
         const R B = Rn * Pb;
         const R Cc = Rn0 * Pc;
-        const R D = (inv_ebar * ir3) * (n0n * fa - (Rn0 * Rn) * (fb * ir2));
+        const R D = ir3e * (n0n * fa - (Rn0 * Rn) * (fb * ir2));
         // the terms are added one at a time (two fused multiply-adds each)
         if constexpr (MASKED) {
             bf = ok ? (bf + B * sfv) - A * shv : bf;
