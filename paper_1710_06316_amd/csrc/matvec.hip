@@ -61,8 +61,11 @@ struct P2PSeries {
 // step k lane (copy q, target ti) meets source row q + f ((ti + k) mod W), so
 // the lanes of one step touch distinct rows, whose sums over the tile go to
 // the reverse slots rev[c] + (stream position) of rpart[slot][2].
+// FP64: at least 3 waves per SIMD (168 VGPRs; left free, the compiler takes
+// 174, which leaves room for only 2).
 template <typename R>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 1 : 3))) k_p2p(
+__global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 1 : 3))) k_p2p(
     const int *__restrict__ ch_lo, const int *__restrict__ ch_hi, const int *__restrict__ ch_grp,
     const int *__restrict__ grp_tbeg, const int *__restrict__ grp_tend,
     const int *__restrict__ rng_b, const int *__restrict__ rng_e, const int *__restrict__ rev,
