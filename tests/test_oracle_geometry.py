@@ -87,3 +87,88 @@ def test_near_set_is_symmetric_contains_self_and_is_about_the_two_ring():
     np.fill_diagonal(ref, True)
     assert (ref == S).all()
     assert 10 < S.sum(1).mean() < 40
+
+
+# ---------------------------------------------------------------------------
+# Patch radius rho_t (Figure 1: the patch of node t is bounded by the edge
+# midpoints and triangle centroids around t; rho_t is the farthest of them).
+# Values worked by hand, on shapes chosen so that a radius taken from the
+# midpoints only, from the centroids only, or from the full edges fails.
+# ---------------------------------------------------------------------------
+
+def _octahedron():
+    v = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
+    t = []
+    for sx in (0, 1):
+        for sy in (2, 3):
+            for sz in (4, 5):
+                f = [sx, sy, sz]
+                if np.cross(v[sy] - v[sx], v[sz] - v[sx]) @ v[f].mean(0) < 0:
+                    f = [sx, sz, sy]
+                t.append(f)
+    return v, np.array(t, np.int32)
+
+
+def _bipyramid():
+    """Triangular bipyramid: ring of 3 vertices at radius 1 in z = 0 (angles
+    90, 210, 330 degrees), apices at z = +4 and z = -4."""
+    ang = np.deg2rad([90.0, 210.0, 330.0])
+    ring = np.stack([np.cos(ang), np.sin(ang), np.zeros(3)], 1)
+    v = np.vstack([ring, [[0, 0, 4.0]], [[0, 0, -4.0]]])
+    t = []
+    for i in range(3):
+        j = (i + 1) % 3
+        t.append([i, j, 3])            # ring counter-clockwise seen from above
+        t.append([j, i, 4])
+    return v, np.array(t, np.int32)
+
+
+def test_patch_radius_octahedron_hand_worked():
+    # unit octahedron: edges sqrt(2); midpoint at sqrt(2)/2 (rho^2 = 1/2), the
+    # centroid (1/3, 1/3, 1/3) of a face at squared distance 4/9 + 1/9 + 1/9 =
+    # 2/3 from (1, 0, 0): the centroids decide, rho^2 = 2/3 at every node
+    v, t = _octahedron()
+    O.validate_mesh(v, t)
+    g = O.geometry(v, t)
+    assert np.allclose(g.rho2, 2.0 / 3.0, rtol=1e-15, atol=0)
+
+
+def test_patch_radius_icosahedron_hand_worked():
+    # vertices (0, +-1, +-phi) and cyclic: edge 2; equilateral faces, so the
+    # centroid (a / sqrt(3) = 2 / sqrt(3)) is farther than a midpoint (1):
+    # rho^2 = 4/3 at every node
+    v, t = W.icosphere(0, 1.0)
+    v = v * np.sqrt(1.0 + ((1.0 + np.sqrt(5.0)) / 2.0) ** 2)   # back to edge 2
+    g = O.geometry(v, t)
+    edge = np.linalg.norm(v[t[:, 0]] - v[t[:, 1]], axis=1)
+    assert np.allclose(edge, 2.0, rtol=1e-14)
+    assert np.allclose(g.rho2, 4.0 / 3.0, rtol=1e-14, atol=0)
+
+
+def test_patch_radius_irregular_fan_hand_worked():
+    # ring node (0, 1, 0): its edge to an apex has length sqrt(17), midpoint
+    # at sqrt(17)/2 (rho^2 = 17/4); the centroid of (ring0, ring1, apex) is
+    # (-sqrt(3)/6, 1/6, 4/3), squared distance 3/36 + 25/36 + 64/36 = 23/9
+    # < 17/4, and the ring edge midpoint lies at sqrt(3)/2: the midpoint to the
+    # apex decides.  Apex (0, 0, 4): midpoints at sqrt(17)/2 again, the same
+    # centroid at 1/12 + 1/36 + 64/9 = 65/9 > 17/4: the centroid decides.
+    v, t = _bipyramid()
+    O.validate_mesh(v, t)
+    g = O.geometry(v, t)
+    assert np.allclose(g.rho2[:3], 17.0 / 4.0, rtol=1e-14, atol=0)
+    assert np.allclose(g.rho2[3:], 65.0 / 9.0, rtol=1e-14, atol=0)
+
+
+def test_near_set_hand_worked_on_the_fan():
+    # ring-ring distance sqrt(3) (d^2 = 3), ring-apex sqrt(17) (d^2 = 17),
+    # apex-apex 8 (d^2 = 64).  With eta = 1 the rule d^2 < eta^2 max(rho^2):
+    # ring-ring 3 < 17/4 near; ring-apex 17 >= 65/9 far; apex-apex far.
+    # With eta = 2: ring-apex 17 < 4 * 65/9 near, apex-apex 64 >= 4 * 65/9 far.
+    v, t = _bipyramid()
+    g = O.geometry(v, t)
+    _, ptr, col = O.near_set(g, 1.0)
+    rows1 = [list(col[ptr[i]:ptr[i + 1]]) for i in range(5)]
+    assert rows1 == [[0, 1, 2], [0, 1, 2], [0, 1, 2], [3], [4]]
+    _, ptr, col = O.near_set(g, 2.0)
+    rows2 = [list(col[ptr[i]:ptr[i + 1]]) for i in range(5)]
+    assert rows2 == [[0, 1, 2, 3, 4]] * 3 + [[0, 1, 2, 3], [0, 1, 2, 4]]
