@@ -61,9 +61,12 @@ typedef enum {
 
 typedef enum {
     AFMPB_FP64 = 0,              /* every kernel in double precision                   */
-    AFMPB_FP32_REFINED = 1,      /* FMM/P2P in single precision with compensated sums,
-                                    near correction, Arnoldi, residuals and energy in
-                                    double; iterative refinement restores the residual */
+    AFMPB_FP32_REFINED = 1,      /* FMM translations and P2P pair terms in single
+                                    precision; P2P sums each 64-source tile in single
+                                    and adds a target's tiles in double; near
+                                    corrections stored in single, applied in double;
+                                    Arnoldi, residuals and energy in double; iterative
+                                    refinement restores the residual               */
     AFMPB_FP32_BF16M2L_REFINED = 2 /* as AFMPB_FP32_REFINED, with the M2L products taken
                                     as three bf16 products of split operands (hi*hi +
                                     hi*lo + lo*hi, FP32 accumulation) on the bf16

@@ -657,7 +657,8 @@ double host_dot(afmpb_ctx *c, const double *a, const double *b, long long len) {
 // Gram-Schmidt with one reorthogonalisation pass (two block projections per
 // step), Givens rotations on the host; stopping rule Eq. (7).
 Gmres gmres(afmpb_ctx *c, const double *b, double *x, bool x_zero, double rel_tol,
-            double abs_tol, int m, int max_restarts, bool fp64_matvec) {
+            double abs_tol, int m, int max_restarts, bool fp64_matvec,
+            bool final_residual = true) {
     const long long len = 2 * c->n;
     hipStream_t s = c->stream;
     if (c->krylov_m < m) {
@@ -739,7 +740,9 @@ Gmres gmres(afmpb_ctx *c, const double *b, double *x, bool x_zero, double rel_to
         c->sync();
         if (done) { g.converged = true; break; }
     }
-    // true residual in FP64
+    // true residual in FP64 (an inner solve of the refinement loop leaves it
+    // to the caller, which forms the residual of the updated outer iterate)
+    if (!final_residual) return g;
     c->matvec_m(x, c->tmp.p, true);
     axpby(1.0, b, -1.0, c->tmp.p, len, c->tmp.p, s);
     double rn = std::sqrt(host_dot(c, c->tmp.p, c->tmp.p, len));
@@ -751,12 +754,8 @@ double energy_of(afmpb_ctx *ctx, const double *x_morton) {
     if (ctx->na == 0) return 0.0;
     reaction_potential(ctx->nodes(), ctx->n, x_morton, ctx->ax.p, ctx->na, ctx->ebar,
                        ctx->phi_at.p, ctx->stream);
-    std::vector<double> phi(ctx->na), q(ctx->na);
-    ctx->phi_at.download(phi.data(), ctx->na, ctx->stream);
-    ctx->aq.download(q.data(), ctx->na, ctx->stream);
-    ctx->sync();
-    double sum = 0.0;
-    for (long long k = 0; k < ctx->na; ++k) sum += q[k] * phi[k];
+    // sum_k q_k phi_k reduced on the device in a fixed block order
+    const double sum = host_dot(ctx, ctx->aq.p, ctx->phi_at.p, ctx->na);
     return 0.5 * sum * unit_scale();
 }
 
@@ -928,7 +927,7 @@ afmpb_status afmpb_solve(afmpb_ctx *ctx, const double *x0, double *f, double *h,
             for (int it = 0; it < 8 && rn > tol; ++it) {
                 double inner_rel = std::max(tol / rn, 1e-6);
                 Gmres gi = gmres(ctx, r.p, d.p, true, inner_rel, 0.0, p.restart, p.max_restarts,
-                                 false);
+                                 false, false);
                 g.iterations += gi.iterations;
                 g.restarts += gi.restarts;
                 g.inner += gi.inner;

@@ -24,17 +24,23 @@ draw order.
 """
 from __future__ import annotations
 
+import ctypes
 import itertools
 import math
+import os
+import subprocess
 from dataclasses import dataclass, field
 
 import numpy as np
 
 __all__ = [
     "Molecule", "icosphere", "born_ion", "saw_atoms", "gaussian_surface",
-    "globular", "complex_100k", "star_request", "check_closed_manifold",
-    "random_rigid_motion",
+    "gaussian_surface_native", "shell_atoms", "globular", "complex_100k",
+    "capsid_shell", "star_request", "check_closed_manifold", "random_rigid_motion",
 ]
+
+# grid spacing of the capsid-scale shell's isosurface (A)
+CAPSID_H_GRID = 2.5
 
 
 @dataclass
@@ -415,6 +421,125 @@ def complex_100k(seed: int = 3, n_atoms: int = 100000, r_max: float = 90.0,
     pos, rad, q = saw_atoms(n_atoms, r_max, seed)
     V, T, meta = gaussian_surface(pos, rad, h_grid)
     return Molecule(name=f"complex_{n_atoms}", xyz=V, tri=T, atom_xyz=pos,
+                    charge=q, radius=rad, meta=dict(meta, seed=seed))
+
+
+# ---------------------------------------------------------------------------
+# Native generators (workloads/meshgen.cpp) for multi-million-atom inputs
+# ---------------------------------------------------------------------------
+
+_MG_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "meshgen.cpp")
+_MG_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmeshgen.so")
+_mg = None
+
+
+def build_native(force: bool = False) -> str:
+    """Compile meshgen.cpp (g++, OpenMP, no fused multiply-add)."""
+    if force or not os.path.exists(_MG_LIB) or (
+            os.path.getmtime(_MG_LIB) < os.path.getmtime(_MG_SRC)):
+        tmp = _MG_LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off",
+                               "-fPIC", "-shared", "-o", tmp, _MG_SRC])
+        os.replace(tmp, _MG_LIB)
+    return _MG_LIB
+
+
+def _native():
+    global _mg
+    if _mg is None:
+        build_native()
+        L = ctypes.CDLL(_MG_LIB)
+        dp, lp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)
+        c_long, c_double = ctypes.c_long, ctypes.c_double
+        L.mg_accept_min_sep.argtypes = [c_long, dp, c_double, c_long, lp]
+        L.mg_accept_min_sep.restype = c_long
+        L.mg_density.argtypes = [c_long, dp, dp, dp, c_double, c_long, c_long, c_long,
+                                 c_double, c_double, dp]
+        L.mg_march.argtypes = [dp, c_long, c_long, c_long, dp, c_double, c_double, lp, lp]
+        L.mg_march_fetch.argtypes = [dp, ctypes.POINTER(ctypes.c_int32)]
+        _mg = L
+    return _mg
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def gaussian_surface_native(atoms, radii, h_grid: float, beta: float = 2.0,
+                            pad: float = 5.0, level: float = 1.0, clamp: float = 0.25):
+    """``gaussian_surface`` computed by the native generator (same grid,
+    density, tetrahedra, vertex numbering, clamp and orientation)."""
+    L = _native()
+    atoms = np.ascontiguousarray(atoms, dtype=np.float64)
+    radii = np.ascontiguousarray(radii, dtype=np.float64)
+    lo = atoms.min(0) - pad
+    hi = atoms.max(0) + pad
+    shape = tuple(int(math.ceil((hi[a] - lo[a]) / h_grid)) + 1 for a in range(3))
+    lo = np.ascontiguousarray(lo)
+    F = np.empty(shape, dtype=np.float64)
+    L.mg_density(len(atoms), _dptr(atoms), _dptr(radii), _dptr(lo), float(h_grid),
+                 shape[0], shape[1], shape[2], float(beta), 3.0, _dptr(F))
+    F -= level
+    F[F == 0.0] = 1e-300          # no grid value exactly on the level set
+    nv, nt = ctypes.c_long(), ctypes.c_long()
+    L.mg_march(_dptr(F), shape[0], shape[1], shape[2], _dptr(lo), float(h_grid),
+               float(clamp), ctypes.byref(nv), ctypes.byref(nt))
+    del F
+    V = np.empty((nv.value, 3), np.float64)
+    T = np.empty((nt.value, 3), np.int32)
+    L.mg_march_fetch(_dptr(V), T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    A = _tri_area(V, T)
+    if (A < 1e-12 * A.mean()).any():       # not met with the quarter-edge clamp
+        T = _collapse_degenerate(V, T.astype(np.int64))
+        V, T = _compact(V, T)
+        T = T.astype(np.int32)
+    return V, T, {"grid_shape": shape, "h_grid": h_grid, "beta": beta}
+
+
+def _ico_directions():
+    v, _ = _icosahedron()
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def shell_atoms(n: int, r_in: float, r_out: float, seed: int, min_sep: float = 1.2,
+                batch: int = 2_000_000):
+    """Atoms uniform in r^3 between r_in^3 and r_out^3, uniform in
+    direction, thinned by the icosahedral modulation w(u) = 0.5 + 0.5
+    max_i (u . v_i)^16 over the 12 vertex directions v_i, with a minimum
+    separation (candidates accepted in draw order).  Radii ~ U(1.2, 2.0),
+    charges ~ N(0, 0.4) (no shift).  Candidates are drawn in batches of
+    ``batch`` (normal directions, uniform r^3, uniform thinning variate)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    vdir = _ico_directions()
+    kept = []
+    total = 0
+    while True:
+        u = _unit_vectors(rng, batch)
+        r = np.cbrt(rng.uniform(r_in ** 3, r_out ** 3, batch))
+        w = 0.5 + 0.5 * np.max(u @ vdir.T, axis=1) ** 16
+        thin = rng.uniform(0.0, 1.0, batch) < w
+        kept.append((u[thin] * r[thin, None]))
+        cand = np.ascontiguousarray(np.concatenate(kept))
+        idx = np.empty(n, dtype=np.int64)
+        total = _native().mg_accept_min_sep(len(cand), _dptr(cand), float(min_sep), n,
+                                            idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
+        if total >= n:
+            break
+    pos = cand[idx[:n]]
+    radius = rng.uniform(1.2, 2.0, n)
+    q = rng.normal(0.0, 0.4, n)
+    return pos, radius, q
+
+
+def capsid_shell(seed: int = 5, n_atoms: int = 1_100_000, r_in: float = 220.0,
+                 r_out: float = 280.0, h_grid: float = CAPSID_H_GRID):
+    """Config 'virus-capsid-scale shell': ~1.1M atoms in a spherical shell
+    of radii 220-280 A with icosahedral density modulation, Gaussian
+    isosurface by marching tetrahedra (native generator) on a grid whose
+    spacing puts the surface near ~20M triangles (~10M nodes)."""
+    pos, rad, q = shell_atoms(n_atoms, r_in, r_out, seed)
+    V, T, meta = gaussian_surface_native(pos, rad, h_grid)
+    return Molecule(name=f"capsid_shell_{n_atoms}", xyz=V, tri=T, atom_xyz=pos,
                     charge=q, radius=rad, meta=dict(meta, seed=seed))
 
 
