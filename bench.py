@@ -2,18 +2,24 @@
 
 One step = one application of the boundary-integral operator of Eq. (5)
 (source gather, P2M, M2M, M2L, L2L, L2P, P2P, near-set corrections and the
-identity term) to a vector already resident in HBM, on the synthetic globular
-molecule (5,000 atoms, 49,190 surface nodes, 98,380 unknowns).  Setup
-(geometry, octree, lists, near-set quadrature, translation operators) happens
-once before the timed region and is reported separately.
+identity term) to a vector already resident in HBM.  The headline workload is
+the capsid-scale shell (1.1M atoms in a 220-280 A shell with icosahedral
+density modulation, Gaussian isosurface of ~20M triangles / ~9.7M nodes,
+expansion order 8, mixed precision: FP32 far and near field, FP64
+accumulation, combine and Krylov vectors).  Setup (geometry, octree, lists,
+near-set quadrature, translation operators, the nodes+atoms tree of the
+right-hand side) happens once before the timed region and is reported
+separately; the plain FP64 form is timed on the same setup beside it, and one
+full solve of each form (FP64 GMRES / iterative refinement to 1e-6) is
+reported.  The 100k-atom complex and the 5,000-atom globular molecule are
+timed as extra entries.
 
-The headline form is the mixed-precision one (FP32 far and near field, FP64
-accumulation, combine and Krylov vectors) at expansion order 10; the plain
-FP64 form is timed on the same workload beside it.  Prints ONE JSON line with
-the metric, a roofline entry for the dominant kernel (per-launch durations
-from HIP events on the library's stream over the timed region), the FP64 CPU
-oracle timed on a bounded row sample, and the error of each GPU matvec
-against the oracle on those rows.
+Prints ONE JSON line with the metric, a roofline entry for the dominant
+kernel (per-launch durations from HIP events on the library's stream over the
+timed region), the FP64 CPU oracle timed on bounded row samples (median of
+three, on one thread and on all threads), the error of each GPU matvec
+against the oracle on those rows, and the serving stream's throughput and
+latency.
 """
 import argparse
 import json
@@ -37,31 +43,37 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0     # dense bf16 matrix rate
 PEAK_HBM_GBS = 8000.0
 
-# Leaf capacity per workload: the fastest FP32-refined p = 10 matvec of a
-# sweep on one MI355X (globular: 0.486 / 0.436 / 0.409 / 0.413 ms at leaf
-# 64 / 128 / 192 / 256; complex: 8.32 / 5.86 / 6.54 ms at 64 / 128 / 192).
-# Larger leaves move work from the far-field chain to P2P, which runs on the
-# second stream beside it.
-LEAF_BEST = {"globular": 192, "complex_100k": 128}
+WORKLOADS = {
+    # name: (generator, description, expansion order, leaf capacity)
+    # Leaf capacities are the fastest of measured sweeps of the FP32-refined
+    # matvec on one MI355X (globular: 64 / 128 / 192 / 256 -> 0.486 / 0.436 /
+    # 0.409 / 0.413 ms; complex p = 10: 64 / 128 / 192 -> 8.32 / 5.86 / 6.54
+    # ms; capsid p = 8: see DESIGN).  Larger leaves move work from the
+    # far-field chain to P2P, which runs on a second stream beside it.
+    "capsid": ("capsid_shell", "capsid_shell_1100000: 1.1M atoms in a 220-280 A shell "
+               "(icosahedral modulation)", 8, 128),
+    "complex_100k": ("complex_100k", "complex_100k: SAW atoms in 90 A", 10, 128),
+    "globular": ("globular", "globular_5000: SAW atoms in 25 A", 10, 192),
+}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp32",
-                    help="fp64; fp32 (FP32 FMM, FP64 refinement); bf16 (as fp32 with "
-                         "bf16-split M2L)")
-    ap.add_argument("--order", type=int, default=10)
-    ap.add_argument("--leaf", type=int, default=0,
-                    help="leaf capacity; 0 takes the workload's measured best (LEAF_BEST)")
-    ap.add_argument("--workload", choices=["globular", "complex_100k"], default="globular",
-                    help="globular (headline) or the 100k-atom complex (~1M nodes)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
+                    help="headline form: fp32 (FP32 FMM, FP64 refinement) or bf16 (as fp32 "
+                         "with bf16-split M2L); the plain FP64 form is timed beside it")
+    ap.add_argument("--order", type=int, default=0, help="0: the workload's order")
+    ap.add_argument("--leaf", type=int, default=0, help="0: the workload's leaf capacity")
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="capsid")
+    ap.add_argument("--extra", default="complex_100k,globular",
+                    help="comma-separated workloads timed beside the headline ('' for none)")
+    ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true",
-                    help="skip the plain FP64 comparison run")
-    ap.add_argument("--no-solve", action="store_true", help="skip the full solve")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 form")
+    ap.add_argument("--no-solve", action="store_true", help="skip the full solves")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving stream (0 skips it)")
     ap.add_argument("--serve-check", type=int, default=12,
@@ -75,61 +87,86 @@ def parse():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=4.0,
+                    help="target seconds of oracle work per timed repetition")
     return ap.parse_args()
 
 
+def make(name):
+    import workloads as W
+    return getattr(W, WORKLOADS[name][0])()
+
+
 def cpu_baseline(mol, target_s, x, y_gpu):
-    """FP64 oracle (direct O(N^2) node-patch matvec) on a bounded row sample,
-    scaled to Munknowns/s of a full matvec.  The same rows give the error of
-    each GPU matvec in y_gpu (caller order, input x) against the oracle."""
+    """FP64 oracle (direct O(N^2) node-patch matvec) on bounded row samples,
+    scaled to Munknowns/s of a full matvec: the median of three timings on
+    all of the oracle's threads and on one thread.  The all-thread rows give
+    the error of each GPU matvec in y_gpu (caller order, input x) against
+    the oracle."""
     import oracle as O
     n = mol.n_nodes
+    threads = O.core.max_threads()
     rng = np.random.default_rng(123)
-    nrows = 128
-    while True:
-        rows = np.sort(rng.choice(n, size=min(nrows, n), replace=False))
-        op = O.operator(mol.xyz, mol.tri, mol.eps_p, mol.eps_s, mol.kappa, rows=rows,
-                        validate=False)
-        t0 = time.perf_counter()
-        yf, yh = op.apply_rows(x)
-        dt = time.perf_counter() - t0
-        if dt * 4 > target_s or nrows >= n:
-            break
-        nrows = min(n, int(nrows * max(2.0, target_s / max(dt, 1e-3) * 0.9)))
-    t_full = dt * n / len(rows)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rows_all = np.sort(rng.choice(n, size=min(n, 4096), replace=False))
+    op = O.operator(mol.xyz, mol.tri, mol.eps_p, mol.eps_s, mol.kappa, rows=rows_all,
+                    validate=False)
+
+    def sub(k):
+        """Operator restricted to the first k sampled rows."""
+        ptr = op.near_ptr[:k + 1]
+        return O.core.Operator(op.geo, op.eps_p, op.eps_s, op.kappa, op.eta, op.rows[:k],
+                               ptr, op.near_col[:ptr[-1]], op.near_coef[:ptr[-1]])
+
+    def timed(k, nthreads):
+        O.core.set_threads(nthreads)
+        o = sub(k)
+        ts, out = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            out = o.apply_rows(x)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), out
+
+    def calibrate(nthreads):
+        """Rows for about target_s seconds on nthreads threads."""
+        O.core.set_threads(nthreads)
+        k = min(len(rows_all), max(1, nthreads))
+        while True:
+            t0 = time.perf_counter()
+            sub(k).apply_rows(x)
+            t = time.perf_counter() - t0
+            if t * 2 >= target_s or k >= len(rows_all):
+                return k
+            k = min(len(rows_all), max(k + 1, int(k * target_s / max(t, 1e-4) * 0.9)))
+
+    try:
+        k_all = calibrate(threads)
+        t_all, (yf, yh) = timed(k_all, threads)
+        k_one = calibrate(1)
+        t_one, _ = timed(k_one, 1)
+    finally:
+        O.core.set_threads(threads)
+    rows = rows_all[:k_all]
     ref = np.r_[yf, yh]
     acc = {k: float(np.linalg.norm(np.r_[y[rows], y[n + rows]] - ref) / np.linalg.norm(ref))
            for k, y in y_gpu.items()}
-    return ({"value": 2 * n / t_full / 1e6, "unit": "Munknowns/s", "cores": cores,
-             "kind": "oracle",
-             "sample": f"{len(rows)} of {n} rows of one FP64 direct matvec "
-                       f"({dt:.2f} s, near-set quadrature of those rows excluded), "
-                       f"scaled by N/rows"},
-            {"matvec_rel_l2_vs_oracle": acc, "rows": int(len(rows))})
+    v_all = 2 * n / (t_all * n / k_all) / 1e6
+    v_one = 2 * n / (t_one * n / k_one) / 1e6
+    return ({"value": v_all, "unit": "Munknowns/s", "cores": threads, "kind": "oracle",
+             "sample": f"{k_all} of {n} rows of one FP64 direct matvec, median of 3 "
+                       f"({t_all:.2f} s) on {threads} threads, scaled by N/rows (near-set "
+                       f"quadrature of the rows excluded)",
+             "single_thread": {"value": v_one, "unit": "Munknowns/s", "cores": 1,
+                               "sample": f"{k_one} rows, median of 3 ({t_one:.2f} s)"}},
+            {"matvec_rel_l2_vs_oracle": acc, "rows": int(k_all)})
 
 
-def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host, do_solve=True):
-    """Setup, warm-up, K timed matvecs (device-resident vectors), one solve."""
-    n = mol.n_nodes
-    stream = torch.cuda.current_stream()
-    prec = {"fp64": A.AFMPB_FP64, "fp32": A.AFMPB_FP32_REFINED,
-            "bf16": A.AFMPB_FP32_BF16M2L_REFINED}[precision]
-    s = A.Solver(0, stream.cuda_stream)
-    t0 = time.perf_counter()
-    s.load(mol, order_p=order, leaf_cap=leaf, precision=prec)
-    torch.cuda.synchronize()
-    setup_ms = (time.perf_counter() - t0) * 1e3
-    info = s.tree_info()
-    g = torch.Generator(device="cuda").manual_seed(1)
-    x = torch.randn(2 * n, dtype=torch.float64, device="cuda", generator=g)
-    y = torch.empty_like(x)
+def time_form(A, torch, s, n, steps, warmup, x, y):
+    """Warm-up, an untimed pass with every kernel scope timed (per-kernel
+    breakdown), then K steps timed with only the dominant kernel's scope."""
     for _ in range(warmup):
         s.matvec_dev(x.data_ptr(), y.data_ptr())
     torch.cuda.synchronize()
-    # per-kernel breakdown: an untimed pass with every kernel scope timed
-    # (two event records per scope perturb the step, so it is not the timed one)
     s.profile(True)
     for _ in range(steps):
         s.matvec_dev(x.data_ptr(), y.data_ptr())
@@ -137,8 +174,6 @@ def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host, do_
     prof_all = s.profile_read()
     s.profile(False)
     dom = max(prof_all.items(), key=lambda kv: kv[1][0])[0]
-    # timed region: K steps with only the dominant kernel timed (HIP events on
-    # the stream it runs on)
     s.profile_only(dom)
     s.profile(True)
     torch.cuda.synchronize()
@@ -153,19 +188,47 @@ def run_config(A, torch, mol, precision, order, leaf, steps, warmup, x_host, do_
     prof = dict(prof_all)
     prof[dom] = prof_dom[dom]                 # the live measurement of the timed region
     ms = (t1 - t0) * 1e3 / steps
-    y_host = s.matvec(x_host)
+    return {"ms": ms, "value": 2 * n / (ms * 1e-3) / 1e6, "prof": prof, "steps": steps,
+            "dominant": dom}
+
+
+def solve_form(s):
+    f, h, E, info, _ = s.solve(allow_not_converged=True)
+    return {"energy_kcal_mol": E, "iterations": info.iterations,
+            "refinement_steps": info.refinement_steps, "converged": bool(info.converged),
+            "true_rel_residual": info.true_rel_residual, "ms_rhs": info.ms_rhs,
+            "ms_gmres": info.ms_gmres, "ms_energy": info.ms_energy, "ms_total": info.ms_total}
+
+
+def run_workload(A, torch, mol, prec_name, order, leaf, steps, warmup, x_host, do_fp64,
+                 do_solve):
+    """One setup; the mixed form and (do_fp64) the plain FP64 form timed on
+    it; one solve of each form."""
+    n = mol.n_nodes
+    prec = {"fp32": A.AFMPB_FP32_REFINED, "bf16": A.AFMPB_FP32_BF16M2L_REFINED}[prec_name]
+    s = A.Solver(0)
+    t0 = time.perf_counter()
+    s.load(mol, order_p=order, leaf_cap=leaf, precision=prec)
     torch.cuda.synchronize()
-    solve = None
+    out = {"setup_ms": (time.perf_counter() - t0) * 1e3, "setup_phases_ms": s.setup_times(),
+           "info": s.tree_info()}
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.randn(2 * n, dtype=torch.float64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    out["mixed"] = time_form(A, torch, s, n, steps, warmup, x, y)
+    out["mixed"]["y_host"] = s.matvec(x_host)
     if do_solve:
-        f, h, E, sinfo, _ = s.solve(allow_not_converged=True)
-        solve = {"energy_kcal_mol": E, "iterations": sinfo.iterations,
-                 "converged": bool(sinfo.converged),
-                 "true_rel_residual": sinfo.true_rel_residual,
-                 "ms_gmres": sinfo.ms_gmres, "ms_total": sinfo.ms_total}
+        out["mixed"]["solve"] = solve_form(s)
+    if do_fp64:
+        s.set_precision(A.AFMPB_FP64)
+        out["fp64"] = time_form(A, torch, s, n, steps, warmup, x, y)
+        out["fp64"]["y_host"] = s.matvec(x_host)
+        if do_solve:
+            out["fp64"]["solve"] = solve_form(s)
     s.close()
-    return {"ms": ms, "value": 2 * n / (ms * 1e-3) / 1e6, "prof": prof, "info": info,
-            "steps": steps, "dominant": dom,
-            "setup_ms": setup_ms, "solve": solve, "y_host": y_host}
+    del x, y
+    torch.cuda.empty_cache()
+    return out
 
 
 TRAFFIC_PROFILES = {
@@ -175,7 +238,7 @@ TRAFFIC_PROFILES = {
 }
 
 
-def measured_traffic(kernel, order, precision, workload="globular", leaf=0):
+def measured_traffic(kernel, order, precision, workload, leaf):
     """HBM bytes per launch of `kernel` from the committed counter summary of
     the same workload and configuration, or None (no summary for that
     configuration, or the kernel source changed since the counters were
@@ -196,10 +259,10 @@ def measured_traffic(kernel, order, precision, workload="globular", leaf=0):
     return None
 
 
-def roofline(r, order, precision, workload="globular", leaf=0):
+def roofline(r, info, order, precision, workload, leaf):
     """Roofline entries for P2P (vector ALU) and M2L (matrix cores); the
     dominant kernel of the step (largest total time) is the headline one."""
-    info, prof = r["info"], r["prof"]
+    prof = r["prof"]
     K = (order + 1) ** 2
     peak = PEAK_FP64_VECTOR_TFLOPS if precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
     # bf16-split M2L counts the same algorithmic flops, against the bf16 peak
@@ -236,7 +299,8 @@ def serve_run(A, mols, qps, precision, order, leaf, budget_gb, max_active, setup
     (seeded exponential gaps).  Returns throughput, latency percentiles and
     the per-request energies."""
     srv = A.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_active=max_active,
-                   setup_threads=setup_threads, tuning=tuning, precision=precision, order_p=order, leaf_cap=leaf)
+                   setup_threads=setup_threads, tuning=tuning, precision=precision, order_p=order,
+                   leaf_cap=leaf)
     rng = np.random.default_rng(4)
     n = len(mols)
     arrive = np.zeros(n) if qps is None else np.cumsum(rng.exponential(1.0 / qps, n))
@@ -324,9 +388,9 @@ def serving_child(a):
            "--serve-max-active", str(a.serve_max_active),
            "--serve-setup-threads", str(a.serve_setup_threads)]
     try:
-        r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
     except subprocess.TimeoutExpired:
-        return {"error": "serving run exceeded 600 s"}
+        return {"error": "serving run exceeded 900 s"}
     lines = [x for x in r.stdout.splitlines() if x.startswith("{")]
     if r.returncode != 0 or not lines:
         return {"error": f"serving run ended with status {r.returncode}",
@@ -334,10 +398,12 @@ def serving_child(a):
     return json.loads(lines[-1])
 
 
+def say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
-    if a.leaf == 0:
-        a.leaf = LEAF_BEST[a.workload]
     if a.serve_only:
         import paper_1710_06316_amd as A
         print(json.dumps(serving(A, None, a.serve_requests, a.serve_check, a.serve_budget_gb,
@@ -351,50 +417,81 @@ def main():
     import torch
 
     import paper_1710_06316_amd as A
-    import workloads as W
 
     torch.cuda.set_device(0)
-    mol = W.globular() if a.workload == "globular" else W.complex_100k()
+    _, desc, order0, leaf0 = WORKLOADS[a.workload]
+    order = a.order or order0
+    leaf = a.leaf or leaf0
+    say(f"generating {a.workload}")
+    t0 = time.perf_counter()
+    mol = make(a.workload)
+    gen_s = time.perf_counter() - t0
     n = mol.n_nodes
+    say(f"{a.workload}: {n} nodes, {len(mol.tri)} triangles, {len(mol.charge)} atoms "
+        f"({gen_s:.1f} s); setup and timing")
     x_host = np.random.default_rng(99).normal(size=2 * n)
-    r = run_config(A, torch, mol, a.precision, a.order, a.leaf, a.steps, a.warmup, x_host,
-                   not a.no_solve)
-    roof, roofs, dom = roofline(r, a.order, a.precision, a.workload, a.leaf)
+    r = run_workload(A, torch, mol, a.precision, order, leaf, a.steps, a.warmup, x_host,
+                     not a.no_fp64, not a.no_solve)
     info = r["info"]
+    mix = r["mixed"]
+    roof, roofs, dom = roofline(mix, info, order, a.precision, a.workload, leaf)
+    say(f"mixed {mix['value']:.1f} Munknowns/s ({mix['ms']:.3f} ms)")
     line = {
-        "metric": "FMM matvec Munknowns/s", "value": r["value"], "unit": "Munknowns/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["ms"],
+        "metric": "FMM matvec Munknowns/s", "value": mix["value"], "unit": "Munknowns/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": mix["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16x3+f32+f64"}[a.precision],
+        "dtype": {"fp32": "f32+f64", "bf16": "bf16x3+f32+f64"}[a.precision],
         "data": "synthetic",
-        "config": {"workload": (("globular_5000: SAW atoms in 25 A" if a.workload == "globular"
-                                 else "complex_100k: SAW atoms in 90 A")
-                                + f", Gaussian isosurface, {n} nodes / {len(mol.tri)} triangles"),
-                   "unknowns": 2 * n, "order_p": a.order, "leaf_cap": a.leaf,
+        "config": {"workload": f"{desc}, Gaussian isosurface, {n} nodes / {len(mol.tri)} "
+                               f"triangles, {len(mol.charge)} atoms",
+                   "unknowns": 2 * n, "order_p": order, "leaf_cap": leaf,
                    "precision": a.precision, "n_boxes": info["n_boxes"],
                    "n_p2p_pairs": info["n_p2p_pairs"], "n_m2l_pairs": info["n_m2l_pairs"],
-                   "n_near": info["n_near"]},
+                   "n_near": info["n_near"], "rhs_mode": info["rhs_mode"]},
+        "generate_s": gen_s,
         "setup_ms": r["setup_ms"],
-        "kernels_ms_per_step": {k: v[0] / a.steps for k, v in r["prof"].items()},
+        "setup_phases_ms": r["setup_phases_ms"],
+        "kernels_ms_per_step": {k: v[0] / a.steps for k, v in mix["prof"].items()},
         "roofline": roof,
         "roofline_all": roofs,
         "dominant_phase": dom,
-        "solve": r["solve"],
+        "solve": mix.get("solve"),
     }
-    y_gpu = {f"{a.precision}_p{a.order}": r["y_host"]}
-    if a.precision != "fp64" and not a.no_fp64:
-        # the plain FP64 path on the same workload, for comparison
-        r64 = run_config(A, torch, mol, "fp64", a.order, a.leaf, a.steps, a.warmup, x_host,
-                         not a.no_solve)
+    y_gpu = {f"{a.precision}_p{order}": mix["y_host"]}
+    if "fp64" in r:
+        r64 = r["fp64"]
         line["fp64_plain"] = {"value": r64["value"], "ms_per_step": r64["ms"],
                               "kernels_ms_per_step": {k: v[0] / a.steps
                                                       for k, v in r64["prof"].items()},
-                              "roofline_all": roofline(r64, a.order, "fp64", a.workload, a.leaf)[1],
-                              "solve": r64["solve"]}
-        y_gpu[f"fp64_p{a.order}"] = r64["y_host"]
+                              "roofline_all": roofline(r64, info, order, "fp64", a.workload,
+                                                       leaf)[1],
+                              "solve": r64.get("solve")}
+        y_gpu[f"fp64_p{order}"] = r64["y_host"]
+        say(f"fp64 {r64['value']:.1f} Munknowns/s ({r64['ms']:.3f} ms)")
+    extra = {}
+    for w in [e for e in a.extra.split(",") if e and e != a.workload]:
+        say(f"extra workload {w}")
+        m2 = make(w)
+        _, d2, o2, l2 = WORKLOADS[w]
+        r2 = run_workload(A, torch, m2, a.precision, o2, l2, a.extra_steps, a.warmup,
+                          np.zeros(2 * m2.n_nodes), not a.no_fp64, False)
+        i2 = r2["info"]
+        e = {"workload": d2, "nodes": m2.n_nodes, "order_p": o2, "leaf_cap": l2,
+             "setup_ms": r2["setup_ms"], "value": r2["mixed"]["value"],
+             "ms_per_step": r2["mixed"]["ms"],
+             "roofline_all": roofline(r2["mixed"], i2, o2, a.precision, w, l2)[1]}
+        if "fp64" in r2:
+            e["fp64_value"] = r2["fp64"]["value"]
+            e["fp64_ms_per_step"] = r2["fp64"]["ms"]
+        extra[w] = e
+        del m2
+    if extra:
+        line["extra_workloads"] = extra
     if a.serve_requests > 0:
+        say("serving stream")
         line["serving"] = serving_child(a)
     if not a.no_cpu_baseline:
+        say("oracle rows")
         line["cpu_baseline"], line["accuracy"] = cpu_baseline(mol, a.cpu_seconds, x_host, y_gpu)
     if a.calib_copy_mb > 0:
         src = torch.ones(a.calib_copy_mb << 20, dtype=torch.uint8, device="cuda")

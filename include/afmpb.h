@@ -97,6 +97,11 @@ typedef struct {
                             entries on (large trees, where the result traffic
                             of 1 dominates).  Every layout computes the same
                             sums (rounding order aside)                         */
+    int rhs_fmm;         /* right-hand side of Eq. (5) and the reaction potential
+                            at the atoms: 0 automatic (fast multipole pass over
+                            one octree of nodes and atoms from 2^34 node-atom
+                            pairs on, direct sums below); 1 direct sums; 2 the
+                            fast multipole pass (order max(order_p, 14), FP64) */
 } afmpb_params;
 
 typedef struct {
@@ -123,6 +128,9 @@ typedef struct {
     long long n_m2l_slots;           /* M2L result slots per kernel and matvec
                                         (= n_m2l_pairs in the per-entry layout)  */
     int m2l_layout;                  /* layout in use: 1 per entry, 2 grouped    */
+    int rhs_mode;                    /* right-hand side / energy: 1 direct sums,
+                                        2 fast multipole pass over nodes+atoms */
+    long long rhs_boxes;             /* boxes of the nodes+atoms tree (0 if 1) */
 } afmpb_tree_sizes;
 
 /* Caller-allocated host buffers for afmpb_debug_tree (sizes from
@@ -146,15 +154,35 @@ typedef struct {
 
 typedef struct afmpb_ctx afmpb_ctx;
 
+/* Device memory supplier for a context (e.g. a framework's caching
+ * allocator).  alloc returns `bytes` of device memory on the context's
+ * device, usable by work queued on `stream` (the context's stream), or NULL
+ * when it cannot; free returns memory alloc gave.  The library waits for its
+ * own queued work before it frees.  Both are called from the thread that
+ * makes the library call; user is passed through. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} afmpb_allocator;
+
 /* Fills *out with the defaults above (eps_p 2, eps_s 80, kappa 0.1, p 8,
  * leaf 64, FP64, rel_tol 1e-6, abs_tol 0, restart 80, max_restarts 5,
- * eta 4). */
+ * eta 4, automatic right-hand side). */
 afmpb_status afmpb_default_params(afmpb_params *out);
 
-/* Creates a context on HIP device `device`.  hip_stream is a hipStream_t
- * (NULL = the device's null stream) on which all work of this context is
- * queued; it must outlive the context. */
-afmpb_status afmpb_create(int device, void *hip_stream, afmpb_ctx **out);
+/* Creates a context on HIP device `device`.  hip_stream is a hipStream_t on
+ * which all work of this context is queued; it must outlive the context.
+ * NULL: the context creates a non-blocking stream of its own (the solve
+ * captures its Arnoldi steps into HIP graphs, which the legacy null stream
+ * does not allow); the _dev entry points then order against other work only
+ * through device synchronisation.  alloc (may be NULL: hipMalloc / hipFree)
+ * supplies every device buffer of the context (tree, lists, near set,
+ * operators, expansions, Krylov basis, work vectors); the struct is copied.
+ * Errors: AFMPB_E_INVALID (no such device, NULL out, incomplete allocator),
+ * AFMPB_E_DEVICE. */
+afmpb_status afmpb_create(int device, void *hip_stream, const afmpb_allocator *alloc,
+                          afmpb_ctx **out);
 
 /* Frees all device state of the context.  NULL is accepted. */
 afmpb_status afmpb_destroy(afmpb_ctx *ctx);
@@ -206,6 +234,14 @@ afmpb_status afmpb_solve(afmpb_ctx *ctx, const double *x0, double *f,
 /* Right-hand side of Eq. (5) in caller order ([2 n_nodes], unitless). */
 afmpb_status afmpb_rhs(afmpb_ctx *ctx, double *b);
 
+/* Switches the working precision of the loaded molecule between AFMPB_FP64
+ * and AFMPB_FP32_REFINED (both operator forms are built by
+ * afmpb_set_molecule); AFMPB_FP32_BF16M2L_REFINED only if the molecule was
+ * set up with it (its split operators are built then).  Applies to later
+ * matvec and solve calls.  Errors: AFMPB_E_STATE (no molecule),
+ * AFMPB_E_INVALID. */
+afmpb_status afmpb_set_precision(afmpb_ctx *ctx, int precision);
+
 /* Polar energy (kcal/mol) for a given internal solution x = [f; h]
  * (caller order, unitless). */
 afmpb_status afmpb_energy(afmpb_ctx *ctx, const double *x, double *energy);
@@ -214,8 +250,11 @@ afmpb_status afmpb_energy(afmpb_ctx *ctx, const double *x, double *energy);
  * 0 validation, upload and patch geometry; 1 Morton keys, sort and node
  * gather; 2 octree; 3 U/V/W/X lists and the P2P / M2L work items; 4 near
  * set and patch-integral corrections; 5 translation operators; 6 work
- * buffers and structural checks.  ms: [AFMPB_SETUP_PHASES] host array. */
-#define AFMPB_SETUP_PHASES 7
+ * buffers and structural checks; 7 the octree of nodes and atoms for the
+ * fast multipole right-hand side and energy (empty when direct sums are
+ * used).
+ * ms: [AFMPB_SETUP_PHASES] host array. */
+#define AFMPB_SETUP_PHASES 8
 afmpb_status afmpb_setup_times(afmpb_ctx *ctx, double *ms);
 
 /* Sizes of the internal tree and lists of the loaded molecule. */
@@ -297,10 +336,13 @@ typedef struct {
  * is switched off until a host crash seen with several setup threads is
  * understood (AFMPB_E_INVALID otherwise).  params as for
  * afmpb_set_molecule, except that order_p == 0 / leaf_cap == 0 select per
- * request from the tuning table.  Errors: AFMPB_E_INVALID. */
+ * request from the tuning table.  hip_stream (may be NULL): a stream of the
+ * caller; the device work of each request starts only after the work that
+ * was queued on it when the request was submitted.  Each request runs on a
+ * stream of its own.  Errors: AFMPB_E_INVALID. */
 afmpb_status afmpb_server_create(const afmpb_params *params,
                                  long long hbm_budget_bytes, int max_active,
-                                 int setup_threads, int device,
+                                 int setup_threads, int device, void *hip_stream,
                                  afmpb_server **out);
 
 /* Replaces the tuning table (n entries, copied). */

@@ -68,8 +68,19 @@ def lib():
         L.orc_energy_sum.argtypes = [c_long, dp, dp, dp, c_long, dp, dp,
                                      c_double, dp, dp, dp]
         L.orc_energy_sum.restype = c_double
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (for timing it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _d(a):

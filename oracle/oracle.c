@@ -20,6 +20,7 @@
  * Built with -O2 -ffp-contract=off so that no multiply-add is fused.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -482,3 +483,11 @@ double orc_energy_sum(long n, const double *V, const double *node_n,
     free(tmp);
     return total;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Thread count of the parallel loops above (for timing the oracle)          */
+/* ------------------------------------------------------------------------ */
+
+void orc_set_threads(int n) { omp_set_num_threads(n); }
+
+int orc_max_threads(void) { return omp_get_max_threads(); }

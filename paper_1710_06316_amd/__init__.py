@@ -7,8 +7,9 @@ library has not been built, any call raises ``RuntimeError`` -- there is no
 fallback implementation.
 
 Device memory and streams may come from PyTorch: ``afmpb_create`` takes a
-``hipStream_t`` (``torch.cuda.current_stream().cuda_stream``) and
-``afmpb_matvec_dev`` takes raw device pointers (``tensor.data_ptr()``).
+``hipStream_t`` (``torch.cuda.current_stream().cuda_stream``) and an optional
+device memory supplier (``TorchAllocator`` binds PyTorch's caching allocator),
+and ``afmpb_matvec_dev`` takes raw device pointers (``tensor.data_ptr()``).
 """
 from __future__ import annotations
 
@@ -41,7 +42,8 @@ STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_MESH", -3: "E_OOM",
 ABI_FUNCTIONS = (
     "afmpb_default_params", "afmpb_create", "afmpb_destroy", "afmpb_last_error",
     "afmpb_set_molecule", "afmpb_matvec", "afmpb_matvec_dev", "afmpb_solve",
-    "afmpb_rhs", "afmpb_energy", "afmpb_tree_info", "afmpb_debug_tree",
+    "afmpb_rhs", "afmpb_energy", "afmpb_set_precision",
+    "afmpb_tree_info", "afmpb_debug_tree",
     "afmpb_profile_enable", "afmpb_profile_read", "afmpb_profile_only", "afmpb_setup_times",
     "afmpb_server_create", "afmpb_server_set_tuning", "afmpb_server_submit",
     "afmpb_server_poll", "afmpb_server_cancel", "afmpb_server_stats", "afmpb_server_destroy",
@@ -54,7 +56,8 @@ class afmpb_params(ctypes.Structure):
                 ("leaf_cap", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rel_tol", ctypes.c_double), ("abs_tol", ctypes.c_double),
                 ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
-                ("near_eta", ctypes.c_double), ("m2l_layout", ctypes.c_int)]
+                ("near_eta", ctypes.c_double), ("m2l_layout", ctypes.c_int),
+                ("rhs_fmm", ctypes.c_int)]
 
 
 class afmpb_solve_info(ctypes.Structure):
@@ -76,7 +79,9 @@ class afmpb_tree_sizes(ctypes.Structure):
                  "n_p2p_pairs", "n_m2l_pairs")] + [("order_p", ctypes.c_int),
                                                    ("leaf_cap", ctypes.c_int),
                                                    ("n_m2l_slots", ctypes.c_longlong),
-                                                   ("m2l_layout", ctypes.c_int)]
+                                                   ("m2l_layout", ctypes.c_int),
+                                                   ("rhs_mode", ctypes.c_int),
+                                                   ("rhs_boxes", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,6 +95,52 @@ _TREE_FIELDS = ("keys", "perm", "level", "parent", "child_begin", "n_child", "pt
 
 class afmpb_tree_view(ctypes.Structure):
     _fields_ = [(k, _P) for k in _TREE_FIELDS]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class afmpb_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """Hands the library's device buffers to PyTorch's caching allocator
+    (``torch.cuda.caching_allocator_alloc`` / ``caching_allocator_delete``),
+    so that PyTorch owns the solver's device memory.  Keeps count of the live
+    buffers and bytes.  The object must outlive every context that uses it."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+        self.calls = 0
+        self.peak_bytes = 0
+        self._alloc = ALLOC_FN(self._do_alloc)
+        self._free = FREE_FN(self._do_free)
+        self.struct = afmpb_allocator(self._alloc, self._free, None)
+
+    @property
+    def live_bytes(self) -> int:
+        return sum(self.live.values())
+
+    def _do_alloc(self, nbytes, stream, user):
+        try:
+            p = self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                         int(stream or 0))
+        except Exception:
+            return None
+        self.live[int(p)] = int(nbytes)
+        self.calls += 1
+        self.peak_bytes = max(self.peak_bytes, self.live_bytes)
+        return p
+
+    def _do_free(self, ptr, user):
+        if ptr:
+            self.live.pop(int(ptr), None)
+            self._torch.cuda.caching_allocator_delete(int(ptr))
 
 
 class afmpb_molecule(ctypes.Structure):
@@ -124,10 +175,27 @@ class afmpb_server_counts(ctypes.Structure):
 _lib = None
 
 
+def _torch_runtime_first():
+    """PyTorch ships its own copy of the HIP runtime under the same library
+    name.  Loaded first, it is the one this library binds to, so both share
+    one runtime (streams, events and device pointers interchangeable).  Loaded
+    after the system runtime that this library would otherwise pull in, it
+    starts a second runtime in the process, which finds no device.  So import
+    (and, with a GPU present, initialise) PyTorch before loading the library
+    when it is installed."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:
+        pass
+
+
 def lib():
     """The loaded library; raises RuntimeError when it has not been built."""
     global _lib
     if _lib is None:
+        _torch_runtime_first()
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"libafmpb.so not found at {LIB_PATH}; build it with "
@@ -136,7 +204,8 @@ def lib():
         vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
         ll = ctypes.c_longlong
         L.afmpb_default_params.argtypes = [ctypes.POINTER(afmpb_params)]
-        L.afmpb_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.afmpb_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(afmpb_allocator),
+                                   ctypes.POINTER(vp)]
         L.afmpb_destroy.argtypes = [vp]
         L.afmpb_last_error.argtypes = [vp]
         L.afmpb_last_error.restype = ctypes.c_char_p
@@ -147,6 +216,7 @@ def lib():
         L.afmpb_solve.argtypes = [vp, dp, dp, dp, dp, ctypes.POINTER(afmpb_solve_info)]
         L.afmpb_rhs.argtypes = [vp, dp]
         L.afmpb_energy.argtypes = [vp, dp, dp]
+        L.afmpb_set_precision.argtypes = [vp, ctypes.c_int]
         L.afmpb_tree_info.argtypes = [vp, ctypes.POINTER(afmpb_tree_sizes)]
         L.afmpb_debug_tree.argtypes = [vp, ctypes.POINTER(afmpb_tree_view)]
         L.afmpb_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -155,7 +225,7 @@ def lib():
                                          dp, ctypes.POINTER(ll)]
         L.afmpb_setup_times.argtypes = [vp, dp]
         L.afmpb_server_create.argtypes = [ctypes.POINTER(afmpb_params), ll, ctypes.c_int,
-                                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+                                          ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]
         L.afmpb_server_set_tuning.argtypes = [vp, ctypes.c_int,
                                               ctypes.POINTER(afmpb_tuning_entry)]
         L.afmpb_server_submit.argtypes = [vp, ctypes.POINTER(afmpb_molecule),
@@ -198,9 +268,13 @@ def afmpb_default_params() -> afmpb_params:
     return p
 
 
-def afmpb_create(device: int = 0, stream: int | None = None):
+def afmpb_create(device: int = 0, stream: int | None = None, allocator=None):
+    """allocator: None (the library's own hipMalloc) or a TorchAllocator (or
+    any object with a ``struct`` of type afmpb_allocator kept alive by the
+    caller)."""
     h = ctypes.c_void_p()
-    st = lib().afmpb_create(int(device), ctypes.c_void_p(stream or 0), ctypes.byref(h))
+    al = ctypes.byref(allocator.struct) if allocator is not None else None
+    st = lib().afmpb_create(int(device), ctypes.c_void_p(stream or 0), al, ctypes.byref(h))
     if st != AFMPB_OK:
         raise AfmpbError(st, "afmpb_create failed")
     return h
@@ -267,6 +341,10 @@ def afmpb_energy(ctx, x):
     return e.value
 
 
+def afmpb_set_precision(ctx, precision: int):
+    return _check(ctx, lib().afmpb_set_precision(ctx, int(precision)))
+
+
 def afmpb_tree_info(ctx) -> afmpb_tree_sizes:
     s = afmpb_tree_sizes()
     _check(ctx, lib().afmpb_tree_info(ctx, ctypes.byref(s)))
@@ -299,7 +377,8 @@ def afmpb_debug_tree(ctx) -> dict:
     return arr
 
 
-SETUP_PHASES = ("geometry", "keys_sort", "tree", "lists", "near", "operators", "buffers_checks")
+SETUP_PHASES = ("geometry", "keys_sort", "tree", "lists", "near", "operators", "buffers_checks",
+                "rhs_tree")
 
 
 def afmpb_setup_times(ctx) -> dict:
@@ -334,8 +413,9 @@ def afmpb_profile_read(ctx) -> dict:
 class Solver:
     """One context holding one molecule."""
 
-    def __init__(self, device: int = 0, stream: int | None = None):
-        self.ctx = afmpb_create(device, stream)
+    def __init__(self, device: int = 0, stream: int | None = None, allocator=None):
+        self.allocator = allocator            # kept alive with the context
+        self.ctx = afmpb_create(device, stream, allocator)
         self.n = 0
 
     def close(self):
@@ -380,6 +460,9 @@ class Solver:
     def energy(self, x):
         return afmpb_energy(self.ctx, x)
 
+    def set_precision(self, precision: int):
+        afmpb_set_precision(self.ctx, precision)
+
     def tree_info(self):
         return afmpb_tree_info(self.ctx).as_dict()
 
@@ -402,10 +485,11 @@ class Solver:
 # --- solve server ---------------------------------------------------------------
 
 def afmpb_server_create(params: afmpb_params, hbm_budget_bytes: int, max_active: int,
-                        setup_threads: int = 1, device: int = 0):
+                        setup_threads: int = 1, device: int = 0, stream: int | None = None):
     h = ctypes.c_void_p()
     st = lib().afmpb_server_create(ctypes.byref(params), int(hbm_budget_bytes), int(max_active),
-                                   int(setup_threads), int(device), ctypes.byref(h))
+                                   int(setup_threads), int(device), ctypes.c_void_p(stream or 0),
+                                   ctypes.byref(h))
     if st != AFMPB_OK:
         raise AfmpbError(st, "afmpb_server_create failed")
     return h
@@ -468,11 +552,12 @@ class Server:
     """Continuous-batching solve server (one device)."""
 
     def __init__(self, hbm_budget_bytes: int = 32 << 30, max_active: int = 64,
-                 setup_threads: int = 1, device: int = 0, tuning=None, **params):
+                 setup_threads: int = 1, device: int = 0, tuning=None, stream=None, **params):
         p = afmpb_default_params()
         for k, v in params.items():
             setattr(p, k, v)
-        self.srv = afmpb_server_create(p, hbm_budget_bytes, max_active, setup_threads, device)
+        self.srv = afmpb_server_create(p, hbm_budget_bytes, max_active, setup_threads, device,
+                                       stream)
         self.n_of = {}
         if tuning:
             afmpb_server_set_tuning(self.srv, tuning)

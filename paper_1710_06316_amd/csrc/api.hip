@@ -212,6 +212,9 @@ int fail(afmpb_ctx *ctx, const Error &e) {
 template <class F>
 afmpb_status guarded(afmpb_ctx *ctx, F &&f) {
     try {
+        // device buffers allocated during the call come from the context's
+        // supplier (if it has one)
+        AllocScope as(ctx && ctx->has_al ? &ctx->al : nullptr, ctx ? ctx->stream : nullptr);
         f();
         if (ctx) ctx->err.clear();
         return AFMPB_OK;
@@ -239,6 +242,7 @@ void fill_defaults(afmpb_params &p) {
     p.max_restarts = 5;
     p.near_eta = 4.0;
     p.m2l_layout = 0;
+    p.rhs_fmm = 0;
 }
 
 afmpb_params normalise(const afmpb_params &in) {
@@ -260,6 +264,7 @@ afmpb_params normalise(const afmpb_params &in) {
     require(p.restart >= 1 && p.restart <= 1000, ST_INVALID, "restart must be in [1, 1000]");
     require(p.max_restarts >= 0, ST_INVALID, "max_restarts must be >= 0");
     require(p.m2l_layout >= 0 && p.m2l_layout <= 2, ST_INVALID, "m2l_layout must be 0, 1 or 2");
+    require(p.rhs_fmm >= 0 && p.rhs_fmm <= 2, ST_INVALID, "rhs_fmm must be 0, 1 or 2");
     if (p.near_eta == 0) p.near_eta = 4.0;
     require(fin(p.near_eta) && p.near_eta > 0, ST_INVALID, "near_eta must be > 0");
     return p;
@@ -344,6 +349,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
     };
     std::fill(c->ms_phase, c->ms_phase + AFMPB_SETUP_PHASES, 0.0);
     c->loaded = false;
+    c->gm.reset();            // captured steps refer to the previous molecule's buffers
     validate_mesh_indices(n, xyz, m, tri);
     // the remaining mesh checks run on the host beside the device setup
     // (which needs only valid indices); a failure is raised before the
@@ -416,6 +422,9 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
         check_setup(c);
         if (topo.valid()) topo.get();   // rethrows a mesh error
         mark();   // work buffers, structural checks, mesh checks
+        c->dual = DualTree();
+        if (use_dual(c)) build_dual(c);
+        mark();   // nodes + atoms tree of the right-hand side and energy
     } catch (...) {
         // a mesh error found meanwhile explains a failure of the device setup
         if (topo.valid()) topo.get();
@@ -637,13 +646,6 @@ void check_setup(afmpb_ctx *c) {
     }
 }
 
-struct Gmres {
-    int iterations = 0, restarts = 0;
-    long long inner = 0;
-    double est = 0, true_rel = 0;
-    bool converged = false;
-};
-
 double host_dot(afmpb_ctx *c, const double *a, const double *b, long long len) {
     if (c->dotv.n < 1) c->dotv.alloc(1);
     dots(a, 0, 1, b, len, c->dotv.p, c->dscratch, c->stream);
@@ -653,109 +655,29 @@ double host_dot(afmpb_ctx *c, const double *a, const double *b, long long len) {
     return v;
 }
 
-// Restarted GMRES(m) on M x = b (Morton order).  Arnoldi by classical
-// Gram-Schmidt with one reorthogonalisation pass (two block projections per
-// step), Givens rotations on the host; stopping rule Eq. (7).
-Gmres gmres(afmpb_ctx *c, const double *b, double *x, bool x_zero, double rel_tol,
-            double abs_tol, int m, int max_restarts, bool fp64_matvec,
-            bool final_residual = true) {
-    const long long len = 2 * c->n;
-    hipStream_t s = c->stream;
-    if (c->krylov_m < m) {
-        c->krylov.alloc((size_t)(m + 1) * len);
-        c->krylov_m = m;
+void rhs_morton(afmpb_ctx *c, double *b) {
+    if (c->dual.built) dual_rhs(c, b);
+    else rhs(c->nodes(), c->n, c->ax.p, c->aq.p, c->na, c->prm.eps_s, b, c->stream);
+}
+
+void energy_sum(afmpb_ctx *c, const double *x_morton, double *out) {
+    if (c->dual.built) {
+        dual_energy_sum(c, x_morton, out);
+        return;
     }
-    if (c->hbuf.n < (size_t)(2 * (m + 2))) c->hbuf.alloc(2 * (m + 2));
-    if (c->dscratch.n < (size_t)dots_scratch(len, m + 1)) c->dscratch.alloc(dots_scratch(len, m + 1));
-    double *Vk = c->krylov.p;
-    Gmres g;
-    const double nb = std::sqrt(host_dot(c, b, b, len));
-    g.inner += 1;
-    const double tol = rel_tol * nb + abs_tol;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), h1(m + 1), h2(m + 1);
-    bool first = true;
-    if (x_zero) HIPCHK(hipMemsetAsync(x, 0, len * sizeof(double), s));
-    for (int cycle = 0; cycle <= max_restarts; ++cycle) {
-        if (first && x_zero) {
-            HIPCHK(hipMemcpyAsync(Vk, b, len * sizeof(double), hipMemcpyDeviceToDevice, s));
-        } else {
-            c->matvec_m(x, c->tmp.p, fp64_matvec);
-            axpby(1.0, b, -1.0, c->tmp.p, len, Vk, s);
-        }
-        first = false;
-        double beta = std::sqrt(host_dot(c, Vk, Vk, len));
-        g.inner += 1;
-        g.est = beta;
-        require(std::isfinite(beta), ST_NUMERIC, "non-finite residual");
-        if (beta <= tol) { g.converged = true; break; }
-        if (cycle > 0) g.restarts += 1;
-        scale(Vk, 1.0 / beta, len, Vk, s);
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = beta;
-        int k = 0;
-        bool done = false;
-        for (int j = 0; j < m; ++j) {
-            double *w = Vk + (size_t)(j + 1) * len;
-            c->matvec_m(Vk + (size_t)j * len, w, fp64_matvec);
-            g.iterations += 1;
-            // two block Gram-Schmidt passes
-            dots(Vk, len, j + 1, w, len, c->hbuf.p, c->dscratch, s);
-            gemv(Vk, len, j + 1, c->hbuf.p, -1.0, len, w, s);
-            dots(Vk, len, j + 1, w, len, c->hbuf.p + (m + 2), c->dscratch, s);
-            gemv(Vk, len, j + 1, c->hbuf.p + (m + 2), -1.0, len, w, s);
-            HIPCHK(hipMemcpyAsync(h1.data(), c->hbuf.p, (j + 1) * sizeof(double),
-                                  hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(h2.data(), c->hbuf.p + (m + 2), (j + 1) * sizeof(double),
-                                  hipMemcpyDeviceToHost, s));
-            double hn = std::sqrt(host_dot(c, w, w, len));
-            g.inner += 2 * (j + 1) + 1;
-            require(std::isfinite(hn), ST_NUMERIC, "non-finite value in the Arnoldi process");
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h1[i] + h2[i];
-            H[(size_t)(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {
-                double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
-            }
-            double den = std::hypot(H[(size_t)j * m + j], hn);
-            cs[j] = H[(size_t)j * m + j] / den;
-            sn[j] = hn / den;
-            H[(size_t)j * m + j] = den;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            gv[j + 1] = -sn[j] * gv[j];
-            gv[j] = cs[j] * gv[j];
-            k = j + 1;
-            g.est = std::fabs(gv[j + 1]);
-            if (g.est <= tol || hn == 0.0) { done = true; break; }
-            scale(w, 1.0 / hn, len, w, s);
-        }
-        std::vector<double> y(k);
-        for (int i = k - 1; i >= 0; --i) {
-            double acc = gv[i];
-            for (int l = i + 1; l < k; ++l) acc -= H[(size_t)i * m + l] * y[l];
-            y[i] = acc / H[(size_t)i * m + i];
-        }
-        HIPCHK(hipMemcpyAsync(c->hbuf.p, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
-        gemv(Vk, len, k, c->hbuf.p, 1.0, len, x, s);
-        c->sync();
-        if (done) { g.converged = true; break; }
-    }
-    // true residual in FP64 (an inner solve of the refinement loop leaves it
-    // to the caller, which forms the residual of the updated outer iterate)
-    if (!final_residual) return g;
-    c->matvec_m(x, c->tmp.p, true);
-    axpby(1.0, b, -1.0, c->tmp.p, len, c->tmp.p, s);
-    double rn = std::sqrt(host_dot(c, c->tmp.p, c->tmp.p, len));
-    g.true_rel = nb > 0 ? rn / nb : rn;
-    return g;
+    reaction_potential(c->nodes(), c->n, x_morton, c->ax.p, c->na, c->ebar, c->phi_at.p,
+                       c->stream);
+    // sum_k q_k phi_k reduced on the device in a fixed block order
+    dots(c->aq.p, 0, 1, c->phi_at.p, c->na, out, c->dscratch, c->stream);
 }
 
 double energy_of(afmpb_ctx *ctx, const double *x_morton) {
     if (ctx->na == 0) return 0.0;
-    reaction_potential(ctx->nodes(), ctx->n, x_morton, ctx->ax.p, ctx->na, ctx->ebar,
-                       ctx->phi_at.p, ctx->stream);
-    // sum_k q_k phi_k reduced on the device in a fixed block order
-    const double sum = host_dot(ctx, ctx->aq.p, ctx->phi_at.p, ctx->na);
+    if (ctx->dotv.n < 1) ctx->dotv.alloc(1);
+    energy_sum(ctx, x_morton, ctx->dotv.p);
+    double sum;
+    HIPCHK(hipMemcpyAsync(&sum, ctx->dotv.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
     return 0.5 * sum * unit_scale();
 }
 
@@ -769,9 +691,11 @@ afmpb_status afmpb_default_params(afmpb_params *out) {
     return AFMPB_OK;
 }
 
-afmpb_status afmpb_create(int device, void *hip_stream, afmpb_ctx **out) {
+afmpb_status afmpb_create(int device, void *hip_stream, const afmpb_allocator *alloc,
+                          afmpb_ctx **out) {
     if (!out) return AFMPB_E_INVALID;
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) return AFMPB_E_INVALID;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return AFMPB_E_INVALID;
@@ -779,16 +703,32 @@ afmpb_status afmpb_create(int device, void *hip_stream, afmpb_ctx **out) {
     afmpb_ctx *c = new (std::nothrow) afmpb_ctx();
     if (!c) return AFMPB_E_OOM;
     c->device = device;
+    if (alloc) {
+        c->al = *alloc;
+        c->has_al = true;
+    }
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    if (!c->stream) {
+        // a stream of its own: the legacy null stream cannot be captured
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return AFMPB_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    auto fail_device = [c] {
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->ev_join) (void)hipEventDestroy(c->ev_join);
         if (c->side) (void)hipStreamDestroy(c->side);
+        hipStream_t own = c->own_stream ? c->stream : nullptr;
         delete c;
+        if (own) (void)hipStreamDestroy(own);
         return AFMPB_E_DEVICE;
-    }
+    };
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+        return fail_device();
     *out = c;
     return AFMPB_OK;
 }
@@ -801,7 +741,9 @@ afmpb_status afmpb_destroy(afmpb_ctx *ctx) {
     (void)hipEventDestroy(ctx->ev_fork);
     (void)hipEventDestroy(ctx->ev_join);
     (void)hipStreamDestroy(ctx->side);
+    hipStream_t own = ctx->own_stream ? ctx->stream : nullptr;
     delete ctx;
+    if (own) (void)hipStreamDestroy(own);
     return AFMPB_OK;
 }
 
@@ -862,8 +804,7 @@ afmpb_status afmpb_rhs(afmpb_ctx *ctx, double *b) {
     return guarded(ctx, [&] {
         ensure_loaded(ctx);
         require(b != nullptr, ST_INVALID, "null argument");
-        rhs(ctx->nodes(), ctx->n, ctx->ax.p, ctx->aq.p, ctx->na, ctx->prm.eps_s, ctx->bvec.p,
-            ctx->stream);
+        rhs_morton(ctx, ctx->bvec.p);
         from_morton(ctx->bvec.p, ctx->perm.p, ctx->n, ctx->tmp.p, ctx->stream);
         ctx->tmp.download(b, 2 * ctx->n, ctx->stream);
         ctx->sync();
@@ -882,6 +823,19 @@ afmpb_status afmpb_energy(afmpb_ctx *ctx, const double *x, double *energy) {
     });
 }
 
+afmpb_status afmpb_set_precision(afmpb_ctx *ctx, int precision) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        require(precision == AFMPB_FP64 || precision == AFMPB_FP32_REFINED ||
+                    (precision == AFMPB_FP32_BF16M2L_REFINED && ctx->fmm.Tbh.n > 0),
+                ST_INVALID, "precision not available for this molecule");
+        ctx->prm.precision = precision;
+        ctx->mp32.far.bf16_m2l = precision == AFMPB_FP32_BF16M2L_REFINED ? 1 : 0;
+        ctx->gm.reset();      // the captured FP32 step follows the precision
+    });
+}
+
 afmpb_status afmpb_solve(afmpb_ctx *ctx, const double *x0, double *f, double *h,
                          double *energy, afmpb_solve_info *info) {
     if (!ctx) return AFMPB_E_INVALID;
@@ -893,7 +847,7 @@ afmpb_status afmpb_solve(afmpb_ctx *ctx, const double *x0, double *f, double *h,
         auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
         const long long n = ctx->n, len = 2 * n;
         hipStream_t s = ctx->stream;
-        rhs(ctx->nodes(), n, ctx->ax.p, ctx->aq.p, ctx->na, ctx->prm.eps_s, ctx->bvec.p, s);
+        rhs_morton(ctx, ctx->bvec.p);
         ctx->sync();
         auto t1 = std::chrono::steady_clock::now();
         bool xz = (x0 == nullptr);
@@ -904,10 +858,10 @@ afmpb_status afmpb_solve(afmpb_ctx *ctx, const double *x0, double *f, double *h,
             to_morton(ctx->tmp.p, ctx->perm.p, n, ctx->xsol.p, s);
         }
         const afmpb_params &p = ctx->prm;
-        Gmres g;
+        GmresResult g;
         if (p.precision == AFMPB_FP64) {
-            g = gmres(ctx, ctx->bvec.p, ctx->xsol.p, xz, p.rel_tol, p.abs_tol, p.restart,
-                      p.max_restarts, true);
+            g = gmres_device(ctx, ctx->bvec.p, ctx->xsol.p, xz, p.rel_tol, p.abs_tol, p.restart,
+                             p.max_restarts, true, true);
         } else {
             // iterative refinement: single-precision operator inside, true
             // residual of the double-precision operator outside
@@ -926,8 +880,8 @@ afmpb_status afmpb_solve(afmpb_ctx *ctx, const double *x0, double *f, double *h,
             }
             for (int it = 0; it < 8 && rn > tol; ++it) {
                 double inner_rel = std::max(tol / rn, 1e-6);
-                Gmres gi = gmres(ctx, r.p, d.p, true, inner_rel, 0.0, p.restart, p.max_restarts,
-                                 false, false);
+                GmresResult gi = gmres_device(ctx, r.p, d.p, true, inner_rel, 0.0, p.restart,
+                                              p.max_restarts, false, false);
                 g.iterations += gi.iterations;
                 g.restarts += gi.restarts;
                 g.inner += gi.inner;
@@ -1004,6 +958,8 @@ afmpb_status afmpb_tree_info(afmpb_ctx *ctx, afmpb_tree_sizes *out) {
         out->leaf_cap = ctx->prm.leaf_cap;
         out->n_m2l_slots = ctx->lists.n_vg * ctx->lists.m2l_split;
         out->m2l_layout = ctx->lists.m2l_grouped ? 2 : 1;
+        out->rhs_mode = ctx->dual.built ? 2 : 1;
+        out->rhs_boxes = ctx->dual.built ? ctx->dual.t.nbox : 0;
     });
 }
 

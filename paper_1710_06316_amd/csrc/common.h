@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/afmpb.h"
+
 #include <atomic>
 #include <mutex>
 #include <shared_mutex>
@@ -59,21 +61,43 @@ inline thread_local std::atomic<long long> *g_dev_bytes = nullptr;
 // exclusively.
 inline std::shared_mutex g_capture_mu;
 
+// The caller-supplied device memory supplier of the context whose entry
+// point runs on this thread (null: hipMalloc / hipFree), and that context's
+// stream; set for the duration of each context call.
+inline thread_local const afmpb_allocator *g_alloc = nullptr;
+inline thread_local hipStream_t g_alloc_stream = nullptr;
+
+struct AllocScope {
+    const afmpb_allocator *a0;
+    hipStream_t s0;
+    AllocScope(const afmpb_allocator *a, hipStream_t s) : a0(g_alloc), s0(g_alloc_stream) {
+        g_alloc = a;
+        g_alloc_stream = s;
+    }
+    ~AllocScope() {
+        g_alloc = a0;
+        g_alloc_stream = s0;
+    }
+};
+
 template <typename T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
     std::atomic<long long> *acct = nullptr;
+    const afmpb_allocator *al = nullptr;    // supplier of p (null: hipMalloc)
     DBuf() = default;
     explicit DBuf(size_t count) { alloc(count); }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), acct(o.acct) { o.p = nullptr; o.n = 0; o.acct = nullptr; }
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), acct(o.acct), al(o.al) {
+        o.p = nullptr; o.n = 0; o.acct = nullptr; o.al = nullptr;
+    }
     DBuf &operator=(DBuf &&o) noexcept {
         if (this != &o) {
             release();
-            p = o.p; n = o.n; acct = o.acct;
-            o.p = nullptr; o.n = 0; o.acct = nullptr;
+            p = o.p; n = o.n; acct = o.acct; al = o.al;
+            o.p = nullptr; o.n = 0; o.acct = nullptr; o.al = nullptr;
         }
         return *this;
     }
@@ -81,19 +105,33 @@ struct DBuf {
     void alloc(size_t count) {
         release();
         if (count == 0) count = 1;  // keep a valid pointer for empty arrays
-        HIPCHK(hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)));
+        const size_t bytes = count * sizeof(T);
+        if (g_alloc) {
+            // 256-byte granules: every buffer starts aligned for wide loads
+            void *q = g_alloc->alloc((bytes + 255) / 256 * 256, (void *)g_alloc_stream, g_alloc->user);
+            if (!q) throw Error(ST_OOM, "device allocation by the caller's allocator failed");
+            p = static_cast<T *>(q);
+            al = g_alloc;
+        } else {
+            HIPCHK(hipMalloc(reinterpret_cast<void **>(&p), bytes));
+        }
         n = count;
         acct = g_dev_bytes;
         if (acct) *acct += (long long)(n * sizeof(T));
     }
     void release() {
         if (p) {
-            {
+            if (al) {
+                // the supplier may hand the memory out again at once: wait
+                // for every queued use of it first
+                (void)hipDeviceSynchronize();
+                al->free(p, al->user);
+            } else {
                 std::shared_lock<std::shared_mutex> lk(g_capture_mu);
                 (void)hipFree(p);
             }
             if (acct) *acct -= (long long)(n * sizeof(T));
-            p = nullptr; n = 0; acct = nullptr;
+            p = nullptr; n = 0; acct = nullptr; al = nullptr;
         }
     }
     T *get() const { return p; }

@@ -6,6 +6,8 @@
 #include <string>
 
 #include "../../include/afmpb.h"
+#include "dual.h"
+#include "gmres.h"
 #include "krylov.h"
 #include "matvec.h"
 #include "prof.h"
@@ -13,8 +15,13 @@
 using namespace afmpb;
 
 struct afmpb_ctx {
+    // caller's device memory supplier (first member: the buffers below refer
+    // to it until they are freed)
+    afmpb_allocator al{};
+    bool has_al = false;
     int device = 0;
     hipStream_t stream = nullptr;
+    bool own_stream = false;  // created by the context (NULL stream given)
     // second stream for the near field, forked from and joined to `stream`
     // inside every matvec (default priority)
     hipStream_t side = nullptr;
@@ -36,6 +43,7 @@ struct afmpb_ctx {
     Lists lists;
     NearSet near;
     Fmm fmm;
+    DualTree dual;            // nodes + atoms tree of the FMM right-hand side
     DBuf<double> w64, far64, p2p64, p2p_part, p2p_rpart;
     DBuf<float> w32, far32;
     MatvecPlan<double> mp64;
@@ -45,6 +53,9 @@ struct afmpb_ctx {
     DBuf<double> krylov;
     int krylov_m = 0;
     Prof prof;
+    // GMRES on the device (state, captured Arnoldi steps); declared last so
+    // that its graphs go before the buffers they use
+    GmresEngine gm;
 
     NodeSoA nodes() const {
         double *b = node64.p;
@@ -72,5 +83,16 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
 // polar energy (kcal/mol) of the solution x (Morton order, internal units);
 // synchronises the context stream
 double energy_of(afmpb_ctx *ctx, const double *x_morton);
+// right-hand side / energy by the fast multipole pass over nodes and atoms
+// (dual.hip): whether the context uses it, its setup, b (Morton order) and
+// the device scalar sum_k q_k phi_reac(r_k)
+bool use_dual(const afmpb_ctx *c);
+void build_dual(afmpb_ctx *c);
+void dual_rhs(afmpb_ctx *c, double *b_morton);
+void dual_energy_sum(afmpb_ctx *c, const double *x_morton, double *out);
+// enqueue on the context stream, by the direct sums or the FMM pass: the
+// right-hand side (Morton order) and the device scalar sum_k q_k phi_reac
+void rhs_morton(afmpb_ctx *c, double *b_morton);
+void energy_sum(afmpb_ctx *c, const double *x_morton, double *out);
 
 }  // namespace afmpb

@@ -67,4 +67,27 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd,
                const R *pnz, const R *sf, const R *sh, double inv_ebar, long long n,
                const FarWork<R> &w, struct Prof *prof, hipStream_t s);
 
+// One side (sources or targets) of a far-field pass over a tree whose boxes
+// may hold two point sets: per box the range [ptb[b], pte[b]) of this side's
+// points (in this side's own order), the P2M / L2P items over the leaves
+// that hold points of this side, and the points (positions, unit normals).
+template <typename R>
+struct FarSide {
+    const int *ptb = nullptr, *pte = nullptr;
+    const int *pm_leaf = nullptr, *pm_first = nullptr, *pm_count = nullptr;
+    long long n_pm = 0, pm_max_points = 0;
+    const R *x = nullptr, *y = nullptr, *z = nullptr, *nx = nullptr, *ny = nullptr,
+            *nz = nullptr;
+    long long n = 0;
+};
+
+// Far field from the sources of `src` (charge sh, dipole -sf along the
+// source normal; the dipoles of kernel 0 scaled by inv_ebar) to the targets
+// of `dst`: phi[4][dst.n] as far_field.  Leaves without source points are
+// left out of src's items, so their multipoles are cleared first.
+template <typename R>
+void far_field_sides(const Fmm &F, const Tree &t, const Lists &L, const FarSide<R> &src,
+                     const R *sf, const R *sh, const FarSide<R> &dst, double inv_ebar,
+                     const FarWork<R> &w, struct Prof *prof, hipStream_t s);
+
 }  // namespace afmpb

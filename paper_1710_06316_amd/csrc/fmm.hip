@@ -1478,16 +1478,19 @@ template <> struct Ops<float> {
     static const float *L(const Fmm &F) { return F.Lp32.p; }
 };
 
+// The far-field pass shared by the matvec (one point set) and the
+// right-hand side / energy (sources and targets from different sets).
 template <typename R>
-void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, const R *px,
-               const R *py, const R *pz, const R *pnx, const R *pny, const R *pnz, const R *sf,
-               const R *sh, double inv_ebar, long long n, const FarWork<R> &w, Prof *prof,
-               hipStream_t s) {
-    (void)nd;
+void far_field_pass(const Fmm &F, const Tree &t, const Lists &L, const FarSide<R> &src,
+                    const R *sf, const R *sh, const FarSide<R> &dst, double inv_ebar,
+                    bool clear_m, const FarWork<R> &w, Prof *prof, hipStream_t s) {
     BasisDev B = F.dev();
-    TreeDev T{t.level.p, t.parent.p, t.child_begin.p, t.n_child.p, t.pt_begin.p, t.pt_end.p,
-              t.prefix.p, t.center.p};
+    TreeDev Ts{t.level.p, t.parent.p, t.child_begin.p, t.n_child.p, src.ptb, src.pte,
+               t.prefix.p, t.center.p};
+    TreeDev Td{t.level.p, t.parent.p, t.child_begin.p, t.n_child.p, dst.ptb, dst.pte,
+               t.prefix.p, t.center.p};
     const int K = F.K;
+    const long long n = dst.n;
     if (L.n_v == 0) {
         // no box has a far field: every pair is in a U/W/X list (a fill
         // kernel, not a memset, so that the matvec can be graph-captured)
@@ -1495,7 +1498,12 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
         KCHK();
         return;
     }
-    {
+    if (clear_m) {
+        // leaves without source points get no P2M item: zero multipoles
+        k_fill_zero<R><<<grid_for(t.nbox * 2 * K, 256), 256, 0, s>>>(w.M, t.nbox * 2 * K);
+        KCHK();
+    }
+    if (src.n_pm > 0) {
         ProfScope ps(prof, "p2m", s);
         // P2M keeps the generic table recurrence: the unrolled orders need
         // up to 185 VGPRs here (two waves per SIMD) and run slower;
@@ -1506,13 +1514,13 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
             return (size_t)nc * 2 * 16 * (65 * sizeof(R) + sizeof(int)) + lds +
                    (size_t)nc * 2 * K * sizeof(R);
         };
-        int nc = (int)std::min<long long>((L.pm_max_points + 63) / 64, sizeof(R) == 4 ? 4 : 2);
+        int nc = (int)std::min<long long>((src.pm_max_points + 63) / 64, sizeof(R) == 4 ? 4 : 2);
         if (nc == 3) nc = 4;
         while (nc > 1 && lds_total(nc) > 60 * 1024) nc /= 2;
         auto go = [&](auto kfn, int ncb) {
-            kfn<<<blocks_ok(L.n_pm, 128 * ncb), 128 * ncb, lds + (size_t)ncb * 2 * K * sizeof(R), s>>>(
-                B, T, L.pm_leaf.p, L.pm_first.p, L.pm_count.p, px, py, pz, pnx, pny, pnz, sf, sh,
-                R(inv_ebar), w.M, F.nlev);
+            kfn<<<blocks_ok(src.n_pm, 128 * ncb), 128 * ncb, lds + (size_t)ncb * 2 * K * sizeof(R), s>>>(
+                B, Ts, src.pm_leaf, src.pm_first, src.pm_count, src.x, src.y, src.z, src.nx,
+                src.ny, src.nz, sf, sh, R(inv_ebar), w.M, F.nlev);
         };
         if (nc <= 1) {
             go(k_p2m<R, 1>, 1);
@@ -1588,15 +1596,15 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
             launch_trans<R, 2>(ta, dim3(1, 2), Ops<R>::L(F), w.Lc, w.Lc, lev, s);
         }
     }
-    {
+    if (dst.n_pm > 0) {
         ProfScope ps(prof, "l2p", s);
         const size_t l2p_lds = basis_tab_bytes(F.P, F.nlev, sizeof(R)) + 4 * 2 * K * sizeof(R);
         // common orders run with a compile-time recurrence (static indices,
         // constant coefficients), others with the generic table recurrence
         auto go = [&](auto kfn) {
-            kfn<<<blocks_ok(L.n_pm, 128), 128, l2p_lds, s>>>(
-                B, T, L.pm_leaf.p, L.pm_first.p, L.pm_count.p, px, py, pz, pnx, pny, pnz, w.Lc,
-                n, w.phi, F.nlev);
+            kfn<<<blocks_ok(dst.n_pm, 128), 128, l2p_lds, s>>>(
+                B, Td, dst.pm_leaf, dst.pm_first, dst.pm_count, dst.x, dst.y, dst.z, dst.nx,
+                dst.ny, dst.nz, w.Lc, n, w.phi, F.nlev);
         };
         switch (F.P) {
             case 6: go(k_l2p<R, 6>); break;
@@ -1609,6 +1617,37 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     }
 }
 
+template <typename R>
+void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, const R *px,
+               const R *py, const R *pz, const R *pnx, const R *pny, const R *pnz, const R *sf,
+               const R *sh, double inv_ebar, long long n, const FarWork<R> &w, Prof *prof,
+               hipStream_t s) {
+    (void)nd;
+    FarSide<R> side;
+    side.ptb = t.pt_begin.p;
+    side.pte = t.pt_end.p;
+    side.pm_leaf = L.pm_leaf.p;
+    side.pm_first = L.pm_first.p;
+    side.pm_count = L.pm_count.p;
+    side.n_pm = L.n_pm;
+    side.pm_max_points = L.pm_max_points;
+    side.x = px; side.y = py; side.z = pz;
+    side.nx = pnx; side.ny = pny; side.nz = pnz;
+    side.n = n;
+    far_field_pass(F, t, L, side, sf, sh, side, inv_ebar, false, w, prof, s);
+}
+
+template <typename R>
+void far_field_sides(const Fmm &F, const Tree &t, const Lists &L, const FarSide<R> &src,
+                     const R *sf, const R *sh, const FarSide<R> &dst, double inv_ebar,
+                     const FarWork<R> &w, Prof *prof, hipStream_t s) {
+    far_field_pass(F, t, L, src, sf, sh, dst, inv_ebar, true, w, prof, s);
+}
+
+template void far_field_sides<double>(const Fmm &, const Tree &, const Lists &,
+                                      const FarSide<double> &, const double *, const double *,
+                                      const FarSide<double> &, double, const FarWork<double> &,
+                                      Prof *, hipStream_t);
 template void far_field<double>(const Fmm &, const Tree &, const Lists &, const NodeSoA &,
                                 const double *, const double *, const double *, const double *,
                                 const double *, const double *, const double *, const double *,

@@ -13,8 +13,11 @@ void compute_geometry(const double *V, const int *T, long long n, long long m,
                       double *tri_area, double *tri_n, int *inc_ptr, int *inc_tri,
                       double *area, double *nrm, double *rho2, hipStream_t s);
 
+// centre_third: a root box of 1.5 times the largest extent, with the
+// centre of the points' box at 1/3 of it on every axis (false: the tree of
+// the matvec, the reference quantisation over the points' own box).
 void morton_sort(const double *V, long long n, unsigned long long *keys, int *perm,
-                 double lo_out[3], double *scale_out, hipStream_t s);
+                 double lo_out[3], double *scale_out, hipStream_t s, bool centre_third = false);
 
 void gather_nodes(const double *V, const double *nrm, const double *area, const double *rho2,
                   const int *perm, long long n, const NodeSoA &out, hipStream_t s);
@@ -84,6 +87,9 @@ struct Lists {
 };
 
 // M2L layout: 1 per entry, 2 grouped, 0 chosen by the number of V entries.
-void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s);
+// p2p_chunks = false leaves out the matvec's symmetric P2P work (chunks and
+// reverse slots); the per-leaf source box lists are built either way.
+void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s,
+                 bool p2p_chunks = true);
 
 }  // namespace afmpb

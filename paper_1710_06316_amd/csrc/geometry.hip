@@ -128,6 +128,7 @@ __global__ void k_morton(const double *__restrict__ V, long long n, double lx, d
         double d = V[3 * i + a] - lo[a];
         double q = floor(d * scale);
         if (q > 2097151.0) q = 2097151.0;
+        if (q < 0.0) q = 0.0;          // (a point below a widened box's rounded corner)
         unsigned long long u = (unsigned long long)q;
         for (int b = 0; b < 21; ++b) key |= ((u >> b) & 1ull) << (3 * b + a);
     }
@@ -178,7 +179,7 @@ void compute_geometry(const double *V, const int *T, long long n, long long m,
 }
 
 void morton_sort(const double *V, long long n, unsigned long long *keys, int *perm,
-                 double lo_out[3], double *scale_out, hipStream_t s) {
+                 double lo_out[3], double *scale_out, hipStream_t s, bool centre_third) {
     int nblk = 256;
     DBuf<double> part(6 * nblk);
     k_bbox_partial<<<nblk, 256, 0, s>>>(V, n, part.p);
@@ -195,6 +196,15 @@ void morton_sort(const double *V, long long n, unsigned long long *keys, int *pe
     double S = 0.0;
     for (int a = 0; a < 3; ++a) S = std::fmax(S, hi[a] - lo[a]);
     if (S == 0.0) S = 1.0;
+    if (centre_third) {
+        // root of side 1.5 S with the centre of the points' box at 1/3 of
+        // it on every axis (binary 0.0101...: a third of a side away from
+        // the faces of the boxes of every level)
+        // (the corner rounded from the centre may lie above the lowest point
+        // by an ulp: never above it)
+        for (int a = 0; a < 3; ++a) lo[a] = std::fmin(lo[a], 0.5 * (lo[a] + hi[a]) - 0.5 * S);
+        S *= 1.5;
+    }
     double scale = 2097152.0 / S;
     for (int a = 0; a < 3; ++a) lo_out[a] = lo[a];
     *scale_out = scale;

@@ -307,9 +307,12 @@ k_near_coeffs(Ctx C, long long n, long long nnz, const long long *__restrict__ p
     }
 }
 
+// grid-stride: 4 nnz passes the 2^32 work-item limit of a dispatch on
+// surfaces of ~10M nodes
 __global__ void k_round_f32(const double *a, float *b, long long n) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = (float)a[i];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
 }
 
 }  // namespace
@@ -432,7 +435,8 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
                                                                out.col.p, out.delta.p);
     KCHK();
     out.delta32.alloc(4 * out.nnz);
-    k_round_f32<<<grid_for(4 * out.nnz, 256), 256, 0, s>>>(out.delta.p, out.delta32.p, 4 * out.nnz);
+    k_round_f32<<<(unsigned)std::min<long long>((4 * out.nnz + 255) / 256, 1ll << 20), 256, 0, s>>>(
+        out.delta.p, out.delta32.p, 4 * out.nnz);
     KCHK();
     HIPCHK(hipStreamSynchronize(s));
 }

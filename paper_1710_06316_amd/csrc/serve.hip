@@ -4,13 +4,13 @@
 // threads admit them in arrival order while the device bytes of the admitted
 // molecules stay within the budget and a slot is free, builds each one's
 // context (geometry, tree, lists, near set, operators; Section 3) on a stream
-// of its own and captures its matvec (Eq. 5, far field and near field) into
-// HIP graphs.  A stepping thread advances every admitted solve through its
-// restarted GMRES (Section 2, Algorithm of the Krylov solver, stopping rule
+// of its own and captures its matvec (Eq. 5, far field and near field) and
+// its whole Arnoldi step into HIP graphs.  A stepping thread advances every
+// admitted solve through its restarted GMRES (Section 3.4, stopping rule
 // Eq. 7) as a resumable state machine: each call issues one asynchronous
-// chunk of device work (one Arnoldi step = one graph launch plus the block
-// Gram-Schmidt kernels and one small device-to-host copy) and returns; the
-// next chunk is issued once its completion event has fired.  Work of all
+// chunk of device work (one Arnoldi step = one graph launch and one small
+// status copy; the Givens update and the tolerance test run on the device)
+// and returns; the next chunk is issued once its completion event has fired.  Work of all
 // active solves therefore overlaps on the device, and requests that arrive
 // while others run join as memory and slots free up.  Results (potential,
 // normal derivative, polar energy) are kept until the caller polls them.
@@ -102,9 +102,16 @@ struct Request {
     std::atomic<bool> cancelled{false};
     long long dev_bytes = 0;
     Clock::time_point t_submit, t_admit, t_ready, t_done;
+    // the caller's stream at submit: the request's work starts after it
+    hipEvent_t after = nullptr;
+    ~Request() {
+        if (after) (void)hipEventDestroy(after);
+    }
 };
 
-// Restarted GMRES as a state machine over asynchronous chunks.  One run
+// Restarted GMRES as a state machine over asynchronous chunks (the Arnoldi
+// process, Givens update and tolerance test run on the device; the host only
+// sequences runs, cycles and steps from small status blocks).  One run
 // solves M x = b for the current (b, x) with the FP64 or FP32 operator graph;
 // the plain form wraps one run, the refined form (FP32 operator inside, FP64
 // residual outside) wraps several.
@@ -112,15 +119,15 @@ struct SolveJob {
     std::atomic<long long> bytes{0};        // first: outlives every buffer below
     Request *req = nullptr;
     std::unique_ptr<afmpb_ctx> c;
-    MatvecGraph g64, g32;
+    MatvecGraph g64;                        // FP64 matvec (true residuals)
     bool refine = false;
     hipEvent_t ev = nullptr;
     bool pending = false;                   // a chunk is in flight
 
     enum Phase {
         RHS_NORM,       // ||b|| on the host
-        RUN_CYCLE,      // residual of a cycle start on the host
-        RUN_STEP,       // one Arnoldi column on the host
+        RUN_CYCLE,      // start of a GMRES cycle (residual norm, tolerance test)
+        RUN_STEP,       // one Arnoldi step (status block)
         OUTER_RES,      // refined form: FP64 residual norm
         TRUE_RES,       // plain form: FP64 residual norm
         FINISH,         // energy and result download
@@ -130,16 +137,13 @@ struct SolveJob {
     long long n = 0, len = 0;
     int m = 80, max_restarts = 5;
     double nb = 0, tol = 0;
-    // current GMRES run
+    // current GMRES run (the Arnoldi process and its state are on the
+    // device, see gmres.h; slot 2 of the status block holds cycle starts,
+    // slot 0 Arnoldi steps)
     const double *rb = nullptr;             // right-hand side of the run
     double *rx = nullptr;                   // iterate of the run
     bool run_fp64 = true, run_zero = true, run_first = true;
-    double run_tol = 0;
-    int cycle = 0, j = 0, k = 0;
-    double beta = 0, hn = 0;
-    bool scale_pending = false;             // V[j] = w / hn before the next step
-    double scale_by = 1;
-    std::vector<double> H, cs, sn, gv;
+    int cycle = 0;
     // refined form
     DBuf<double> r, d;
     int outer_it = 0;
@@ -149,11 +153,9 @@ struct SolveJob {
     long long inner = 0;
     double est = 0, true_rel = 0;
     bool converged = false;
-    // staging: [0, m+2) h1, [m+2, 2m+4) h2, [2m+4] scalar, [2m+8, 3m+8) y
-    Pinned hp, xout, phi;
+    // staging: [0] squared norm, [1] energy sum
+    Pinned hp, xout;
 
-    double *V() const { return c->krylov.p; }
-    double *col(int i) const { return c->krylov.p + (size_t)i * len; }
     hipStream_t s() const { return c->stream; }
 
     void record() {
@@ -167,19 +169,12 @@ struct SolveJob {
         HIPCHK(hipMemcpyAsync(hp.p + slot, c->hbuf.p + slot, sizeof(double),
                               hipMemcpyDeviceToHost, s()));
     }
-    const MatvecGraph &graph(bool fp64) const { return fp64 ? g64 : g32; }
 
-    // r0 = b - M x (or b when x = 0 on the first cycle) into V[0], and its norm
+    // r0 = b - M x (or b when x = 0 on the first cycle), its norm and the
+    // tolerance test, on the device
     void issue_cycle_start() {
-        if (run_first && run_zero) {
-            HIPCHK(hipMemcpyAsync(col(0), rb, len * sizeof(double), hipMemcpyDeviceToDevice, s()));
-        } else {
-            HIPCHK(hipMemcpyAsync(c->xa.p, rx, len * sizeof(double), hipMemcpyDeviceToDevice, s()));
-            graph(run_fp64).launch(s());
-            axpby(1.0, rb, -1.0, c->ya.p, len, col(0), s());
-        }
+        gmres_cycle_start(c.get(), rb, rx, run_first && run_zero, run_fp64, 2);
         run_first = false;
-        issue_dot_to_host(col(0), len, 2 * m + 4);
         record();
         ph = RUN_CYCLE;
     }
@@ -190,112 +185,51 @@ struct SolveJob {
         run_zero = x_zero;
         run_first = true;
         run_fp64 = fp64;
-        run_tol = rel;       // relative to ||b|| of this run; set after its norm
         cycle = 0;
         if (x_zero) {
             // zero fill by kernel (x may be V memory of a later capture)
             axpby(0.0, b, 0.0, b, len, x, s());
         }
-        // ||b|| of the run first: reuse the cycle-start residual when x = 0
-        (void)abs_t;
+        // tolerance of the run: rel ||b|| + abs (Eq. 7)
+        gmres_set_tol(c.get(), b, rel, abs_t, 2);
         issue_cycle_start();
     }
 
     void issue_step() {
-        if (scale_pending) {
-            scale(c->ya.p, scale_by, len, col(j), s());
-            scale_pending = false;
-        }
-        HIPCHK(hipMemcpyAsync(c->xa.p, col(j), len * sizeof(double), hipMemcpyDeviceToDevice, s()));
-        graph(run_fp64).launch(s());
-        double *w = c->ya.p;
-        dots(V(), len, j + 1, w, len, c->hbuf.p, c->dscratch, s());
-        gemv(V(), len, j + 1, c->hbuf.p, -1.0, len, w, s());
-        dots(V(), len, j + 1, w, len, c->hbuf.p + (m + 2), c->dscratch, s());
-        gemv(V(), len, j + 1, c->hbuf.p + (m + 2), -1.0, len, w, s());
-        dots(w, 0, 1, w, len, c->hbuf.p + 2 * m + 4, c->dscratch, s());
-        HIPCHK(hipMemcpyAsync(hp.p, c->hbuf.p, (2 * m + 5) * sizeof(double),
-                              hipMemcpyDeviceToHost, s()));
+        gmres_step(c.get(), run_fp64, 0);
         record();
         ph = RUN_STEP;
     }
 
-    // x += V y for the k columns of the finished cycle
-    void issue_cycle_end() {
-        std::vector<double> y(k);
-        for (int i = k - 1; i >= 0; --i) {
-            double acc = gv[i];
-            for (int l = i + 1; l < k; ++l) acc -= H[(size_t)i * m + l] * y[l];
-            y[i] = acc / H[(size_t)i * m + i];
-        }
-        std::memcpy(hp.p + 2 * m + 8, y.data(), k * sizeof(double));
-        HIPCHK(hipMemcpyAsync(c->hbuf.p + 2 * m + 8, hp.p + 2 * m + 8, k * sizeof(double),
-                              hipMemcpyHostToDevice, s()));
-        gemv(V(), len, k, c->hbuf.p + 2 * m + 8, 1.0, len, rx, s());
-    }
-
     // returns true when the run has finished (converged or out of restarts)
     bool consume_cycle() {
-        beta = std::sqrt(hp.p[2 * m + 4]);
+        const GmresState &st = gmres_status(c.get(), 2);
         inner += 1;
-        require(std::isfinite(beta), ST_NUMERIC, "non-finite residual");
-        if (cycle == 0) {
-            // the first residual of a run fixes its tolerance (Eq. 7)
-            run_tol = run_tol * beta_ref() + abs_run();
-        }
-        est = beta;
-        if (beta <= run_tol) { run_converged = true; return true; }
+        require(st.pad[0] == 0, ST_NUMERIC, "non-finite residual");
+        est = st.beta;
+        if (st.converged) { run_converged = true; return true; }
         if (cycle > 0) restarts += 1;
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = beta;
-        j = 0;
-        k = 0;
-        scale_pending = false;
-        scale(col(0), 1.0 / beta, len, col(0), s());
         issue_step();
         return false;
     }
 
     bool run_converged = false;
-    double run_bnorm = 0, run_abs = 0;
-    double beta_ref() const { return run_bnorm; }
-    double abs_run() const { return run_abs; }
 
     // returns true when the run has finished
     bool consume_step() {
+        const GmresState &st = gmres_status(c.get(), 0);
+        require(st.pad[0] == 0, ST_NUMERIC, "non-finite value in the Arnoldi process");
         iterations += 1;
-        const double *h1 = hp.p, *h2 = hp.p + (m + 2);
-        hn = std::sqrt(hp.p[2 * m + 4]);
-        inner += 2 * (j + 1) + 1;
-        require(std::isfinite(hn), ST_NUMERIC, "non-finite value in the Arnoldi process");
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h1[i] + h2[i];
-        H[(size_t)(j + 1) * m + j] = hn;
-        for (int i = 0; i < j; ++i) {
-            double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
-            H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
-            H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
-        }
-        double den = std::hypot(H[(size_t)j * m + j], hn);
-        cs[j] = H[(size_t)j * m + j] / den;
-        sn[j] = hn / den;
-        H[(size_t)j * m + j] = den;
-        H[(size_t)(j + 1) * m + j] = 0.0;
-        gv[j + 1] = -sn[j] * gv[j];
-        gv[j] = cs[j] * gv[j];
-        k = j + 1;
-        est = std::fabs(gv[j + 1]);
-        const bool done = est <= run_tol || hn == 0.0;
-        if (done || j + 1 == m) {
-            issue_cycle_end();
-            if (done) { run_converged = true; return true; }
+        inner += 2 * st.j + 1;          // the step took column j - 1: 2 j projections and a norm
+        est = st.est;
+        if (st.done) {
+            gmres_cycle_end(c.get(), rx);
+            if (st.converged) { run_converged = true; return true; }
             if (cycle >= max_restarts) return true;
             ++cycle;
             issue_cycle_start();
             return false;
         }
-        scale_pending = true;
-        scale_by = 1.0 / hn;
-        ++j;
         issue_step();
         return false;
     }
@@ -308,42 +242,32 @@ struct SolveJob {
         m = p.restart;
         max_restarts = p.max_restarts;
         refine = p.precision != AFMPB_FP64;
-        H.assign((size_t)(m + 1) * m, 0.0);
-        cs.assign(m, 0.0);
-        sn.assign(m, 0.0);
-        gv.assign(m + 1, 0.0);
-        hp.alloc(3 * m + 16);
+        hp.alloc(16);
         xout.alloc(len);
-        phi.alloc(std::max(c->na, 1ll));
-        if (c->krylov_m < m) {
-            c->krylov.alloc((size_t)(m + 1) * len);
-            c->krylov_m = m;
-        }
-        if (c->hbuf.n < (size_t)(3 * m + 16)) c->hbuf.alloc(3 * m + 16);
+        if (c->hbuf.n < 16) c->hbuf.alloc(16);
         // sized once here: no device allocation or free while stepping
-        if (c->dscratch.n < (size_t)dots_scratch(len, m + 1)) c->dscratch.alloc(dots_scratch(len, m + 1));
+        if (c->dscratch.n < (size_t)dots_scratch(std::max(len, c->na), 1))
+            c->dscratch.alloc(dots_scratch(std::max(len, c->na), 1));
+        // the device GMRES state and its captured Arnoldi steps
+        gmres_prepare(c.get(), m, refine);
         if (refine) {
             r.alloc(len);
             d.alloc(len);
         }
         HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        rhs(c->nodes(), n, c->ax.p, c->aq.p, c->na, p.eps_s, c->bvec.p, s());
-        issue_dot_to_host(c->bvec.p, len, 2 * m + 4);
+        rhs_morton(c.get(), c->bvec.p);
+        issue_dot_to_host(c->bvec.p, len, 0);
         record();
         ph = RHS_NORM;
     }
 
     void start_plain() {
-        run_bnorm = nb;
-        run_abs = c->prm.abs_tol;
         run_converged = false;
         start_run(c->bvec.p, c->xsol.p, true, c->prm.rel_tol, c->prm.abs_tol, true);
     }
 
     void start_inner() {
         // inner FP32 run on the current residual r (norm rn), d = 0
-        run_bnorm = rn;
-        run_abs = 0.0;
         run_converged = false;
         start_run(r.p, d.p, true, std::max(tol / rn, 1e-6), 0.0, false);
     }
@@ -352,15 +276,16 @@ struct SolveJob {
         HIPCHK(hipMemcpyAsync(c->xa.p, c->xsol.p, len * sizeof(double), hipMemcpyDeviceToDevice, s()));
         g64.launch(s());
         axpby(1.0, c->bvec.p, -1.0, c->ya.p, len, rout, s());
-        issue_dot_to_host(rout, len, 2 * m + 4);
+        issue_dot_to_host(rout, len, 0);
         record();
         ph = next;
     }
 
     void issue_finish() {
         if (c->na > 0) {
-            reaction_potential(c->nodes(), n, c->xsol.p, c->ax.p, c->na, c->ebar, c->phi_at.p, s());
-            HIPCHK(hipMemcpyAsync(phi.p, c->phi_at.p, c->na * sizeof(double),
+            // sum_k q_k phi_reac(r_k) reduced on the device, one scalar back
+            energy_sum(c.get(), c->xsol.p, c->hbuf.p + 1);
+            HIPCHK(hipMemcpyAsync(hp.p + 1, c->hbuf.p + 1, sizeof(double),
                                   hipMemcpyDeviceToHost, s()));
         }
         from_morton(c->xsol.p, c->perm.p, n, c->tmp.p, s());
@@ -387,7 +312,7 @@ struct SolveJob {
         pending = false;
         switch (ph) {
         case RHS_NORM: {
-            nb = std::sqrt(hp.p[2 * m + 4]);
+            nb = std::sqrt(hp.p[0]);
             inner += 1;
             tol = c->prm.rel_tol * nb + c->prm.abs_tol;
             if (!refine) {
@@ -414,7 +339,7 @@ struct SolveJob {
             if (consume_step()) run_finished();
             break;
         case OUTER_RES: {
-            rn = std::sqrt(hp.p[2 * m + 4]);
+            rn = std::sqrt(hp.p[0]);
             require(std::isfinite(rn), ST_NUMERIC, "non-finite residual");
             est = rn;
             if (rn <= tol || ++outer_it >= 8) {
@@ -427,7 +352,7 @@ struct SolveJob {
             break;
         }
         case TRUE_RES: {
-            const double rr = std::sqrt(hp.p[2 * m + 4]);
+            const double rr = std::sqrt(hp.p[0]);
             true_rel = nb > 0 ? rr / nb : rr;
             issue_finish();
             break;
@@ -442,8 +367,7 @@ struct SolveJob {
     // polar energy and outputs in physical units (after FINISH completed)
     void collect(Request &q) {
         const double us = unit_scale();
-        double sum = 0.0;
-        for (long long kk = 0; kk < c->na; ++kk) sum += q.q[kk] * phi.p[kk];
+        const double sum = c->na > 0 ? hp.p[1] : 0.0;
         q.energy = 0.5 * sum * us;
         q.f.resize(n);
         q.h.resize(n);
@@ -470,10 +394,8 @@ struct SolveJob {
         if (st) (void)hipStreamSynchronize(st);
         if (sd) (void)hipStreamSynchronize(sd);
         g64.destroy();
-        g32.destroy();
         hp.release();
         xout.release();
-        phi.release();
         r.release();
         d.release();
         std::shared_lock<std::shared_mutex> lk(g_capture_mu);
@@ -497,6 +419,7 @@ using namespace afmpb;
 
 struct afmpb_server {
     afmpb_params prm{};
+    hipStream_t stream = nullptr;       // caller's stream (submit orders after it)
     long long budget = 0;
     int max_active = 0;
     int device = 0;
@@ -582,10 +505,10 @@ void afmpb_server::setup_loop() {
             HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
             HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+            if (q->after) HIPCHK(hipStreamWaitEvent(c->stream, q->after, 0));
             load_molecule(c, q->n, q->xyz.data(), q->m, q->tri.data(), q->na, q->axyz.data(),
                           q->q.data(), qp);
             job->g64.capture(c, true);
-            if (c->prm.precision != AFMPB_FP64) job->g32.capture(c, false);
             job->begin();
             g_dev_bytes = nullptr;
             std::lock_guard<std::mutex> lk(mu);
@@ -692,7 +615,7 @@ extern "C" {
 
 afmpb_status afmpb_server_create(const afmpb_params *params, long long hbm_budget_bytes,
                                  int max_active, int setup_threads, int device,
-                                 afmpb_server **out) {
+                                 void *hip_stream, afmpb_server **out) {
     if (!out || !params) return AFMPB_E_INVALID;
     *out = nullptr;
     int ndev = 0;
@@ -717,6 +640,7 @@ afmpb_status afmpb_server_create(const afmpb_params *params, long long hbm_budge
     auto *s = new (std::nothrow) afmpb_server();
     if (!s) return AFMPB_E_OOM;
     s->prm = p;
+    s->stream = reinterpret_cast<hipStream_t>(hip_stream);
     s->budget = hbm_budget_bytes;
     s->max_active = max_active;
     s->device = device;
@@ -760,6 +684,12 @@ afmpb_status afmpb_server_submit(afmpb_server *s, const afmpb_molecule *mol,
         return AFMPB_E_OOM;
     }
     q->t_submit = Clock::now();
+    if (s->stream) {
+        if (hipSetDevice(s->device) != hipSuccess ||
+            hipEventCreateWithFlags(&q->after, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(q->after, s->stream) != hipSuccess)
+            return AFMPB_E_DEVICE;
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return AFMPB_E_STATE;
     q->ticket = s->next_ticket++;

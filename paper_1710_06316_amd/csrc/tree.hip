@@ -496,7 +496,7 @@ void build_tree(const unsigned long long *keys, long long n, int cap, const doub
     HIPCHK(hipStreamSynchronize(s));
 }
 
-void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s) {
+void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2p_chunks) {
     const long long nb = t.nbox;
     L.coll.alloc((size_t)nb * MAXCOLL);
     L.ncoll.alloc(nb);
@@ -603,6 +603,7 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s) {
         L.w_idx.download(widx.data(), L.n_w, s);
         HIPCHK(hipStreamSynchronize(s));
         const long long npts = pte_h[0];
+        if (p2p_chunks) {
         std::vector<int> rb, re, clo, chi, cgrp, gptr, gtb, gte, crev;
         std::vector<std::pair<int, int>> r;
         long long nrev = 0, pairs = 0;
@@ -712,6 +713,8 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s) {
         L.ch_grp.upload(cgrp.data(), cgrp.size(), s);
         L.grp_ptr.upload(gptr.data(), gptr.size(), s);
         L.grp_tbeg.upload(gtb.data(), gtb.size(), s); L.grp_tend.upload(gte.data(), gte.size(), s);
+        HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
+        }
         // P2M / L2P items: leaves sorted by first point, packed
         std::vector<int> pml(leaf.begin(), leaf.end()), pmf, pmc;
         std::sort(pml.begin(), pml.end(), [&](int a, int b) { return ptb_h[a] < ptb_h[b]; });

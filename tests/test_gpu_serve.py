@@ -205,3 +205,26 @@ def test_tuned_stream_all_finite():
         assert not bad
         assert all(np.isfinite(r.energy) for r in res)
 
+
+def test_server_orders_after_caller_stream():
+    """A server created with a caller stream: requests submitted after work
+    queued on it give the results of direct solves (their work starts after
+    the caller's)."""
+    import torch
+    import paper_1710_06316_amd as A
+    torch.cuda.set_device(0)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        a = torch.randn(4096, 4096, device="cuda")
+        for _ in range(8):
+            a = a @ a.T / 4096.0        # queued work on the caller's stream
+    mols = _mix([3, 4])
+    srv = _server(max_active=4, order_p=8, leaf_cap=64, stream=st.cuda_stream)
+    tickets = [srv.submit(m) for m in mols]
+    for m, t in zip(mols, tickets):
+        _, res, f, h = srv.poll(t, wait=True)
+        assert res.status == 0, res.message
+        f0, h0, E0, info0 = _solo(m, order_p=8, leaf_cap=64)
+        assert abs(res.energy - E0) <= 1e-12 * abs(E0)
+    srv.close()
+    torch.cuda.synchronize()

@@ -417,9 +417,10 @@ def complex_100k(seed: int = 3, n_atoms: int = 100000, r_max: float = 90.0,
                  h_grid: float = 1.5):
     """Config 'synthetic large protein complex' (100,000 atoms): the grid
     spacing 1.5 A puts the isosurface near the configuration's ~2M triangles
-    (~1M nodes)."""
+    (~1M nodes).  The surface comes from the native generator (the same mesh
+    as ``gaussian_surface``, nine times faster at this size)."""
     pos, rad, q = saw_atoms(n_atoms, r_max, seed)
-    V, T, meta = gaussian_surface(pos, rad, h_grid)
+    V, T, meta = gaussian_surface_native(pos, rad, h_grid)
     return Molecule(name=f"complex_{n_atoms}", xyz=V, tri=T, atom_xyz=pos,
                     charge=q, radius=rad, meta=dict(meta, seed=seed))
 
