@@ -246,6 +246,21 @@ afmpb_status afmpb_set_precision(afmpb_ctx *ctx, int precision);
  * (caller order, unitless). */
 afmpb_status afmpb_energy(afmpb_ctx *ctx, const double *x, double *energy);
 
+/* Allocation-free form of afmpb_energy, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops).
+ * x_dev: [2 n_nodes] device array, caller order, internal (unitless) units;
+ * energy_dev: one device double receiving the polar energy (kcal/mol).  Both
+ * on the context's device; the work is enqueued on the context's stream with
+ * no allocation, free or host synchronisation.  Its only scratch is a fixed
+ * device array of 16,384 doubles (one partial sum per block of 256 atoms),
+ * which each GPU holds until the process ends and which every call on that
+ * GPU shares: calls that overlap on one GPU (other streams, other contexts)
+ * race on it.  Each call writes every partial it reads, so nothing needs
+ * clearing.  Errors: AFMPB_E_INVALID (null pointer, or more than 4,194,304
+ * atoms), AFMPB_E_STATE (no molecule), AFMPB_E_DEVICE. */
+afmpb_status afmpb_energy_dev_noalloc(afmpb_ctx *ctx, const double *x_dev,
+                                      double *energy_dev);
+
 /* Wall time (ms) of the phases of the last afmpb_set_molecule, in order:
  * 0 validation, upload and patch geometry; 1 Morton keys, sort and node
  * gather; 2 octree; 3 U/V/W/X lists and the P2P / M2L work items; 4 near

@@ -42,7 +42,7 @@ STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_MESH", -3: "E_OOM",
 ABI_FUNCTIONS = (
     "afmpb_default_params", "afmpb_create", "afmpb_destroy", "afmpb_last_error",
     "afmpb_set_molecule", "afmpb_matvec", "afmpb_matvec_dev", "afmpb_solve",
-    "afmpb_rhs", "afmpb_energy", "afmpb_set_precision",
+    "afmpb_rhs", "afmpb_energy", "afmpb_energy_dev_noalloc", "afmpb_set_precision",
     "afmpb_tree_info", "afmpb_debug_tree",
     "afmpb_profile_enable", "afmpb_profile_read", "afmpb_profile_only", "afmpb_setup_times",
     "afmpb_server_create", "afmpb_server_set_tuning", "afmpb_server_submit",
@@ -216,6 +216,7 @@ def lib():
         L.afmpb_solve.argtypes = [vp, dp, dp, dp, dp, ctypes.POINTER(afmpb_solve_info)]
         L.afmpb_rhs.argtypes = [vp, dp]
         L.afmpb_energy.argtypes = [vp, dp, dp]
+        L.afmpb_energy_dev_noalloc.argtypes = [vp, vp, vp]
         L.afmpb_set_precision.argtypes = [vp, ctypes.c_int]
         L.afmpb_tree_info.argtypes = [vp, ctypes.POINTER(afmpb_tree_sizes)]
         L.afmpb_debug_tree.argtypes = [vp, ctypes.POINTER(afmpb_tree_view)]
@@ -341,6 +342,11 @@ def afmpb_energy(ctx, x):
     return e.value
 
 
+def afmpb_energy_dev_noalloc(ctx, x_ptr: int, energy_ptr: int):
+    return _check(ctx, lib().afmpb_energy_dev_noalloc(ctx, ctypes.c_void_p(x_ptr),
+                                                      ctypes.c_void_p(energy_ptr)))
+
+
 def afmpb_set_precision(ctx, precision: int):
     return _check(ctx, lib().afmpb_set_precision(ctx, int(precision)))
 
@@ -459,6 +465,9 @@ class Solver:
 
     def energy(self, x):
         return afmpb_energy(self.ctx, x)
+
+    def energy_dev_noalloc(self, x_ptr, energy_ptr):
+        return afmpb_energy_dev_noalloc(self.ctx, x_ptr, energy_ptr)
 
     def set_precision(self, precision: int):
         afmpb_set_precision(self.ctx, precision)

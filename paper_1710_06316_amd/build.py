@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libafmpb.so")
 SOURCES = ["prims", "geometry", "tree", "near", "fmm", "matvec", "krylov", "api", "serve",
-           "dual", "gmres"]
+           "noalloc", "dual", "gmres"]
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -725,6 +725,11 @@ afmpb_status afmpb_create(int device, void *hip_stream, const afmpb_allocator *a
         if (own) (void)hipStreamDestroy(own);
         return AFMPB_E_DEVICE;
     };
+    try {
+        c->noalloc_part = noalloc_scratch(device);
+    } catch (const Error &) {
+        return fail_device();
+    }
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
@@ -833,6 +838,15 @@ afmpb_status afmpb_set_precision(afmpb_ctx *ctx, int precision) {
         ctx->prm.precision = precision;
         ctx->mp32.far.bf16_m2l = precision == AFMPB_FP32_BF16M2L_REFINED ? 1 : 0;
         ctx->gm.reset();      // the captured FP32 step follows the precision
+    });
+}
+
+afmpb_status afmpb_energy_dev_noalloc(afmpb_ctx *ctx, const double *x_dev, double *energy_dev) {
+    if (!ctx) return AFMPB_E_INVALID;
+    return guarded(ctx, [&] {
+        ensure_loaded(ctx);
+        require(x_dev && energy_dev, ST_INVALID, "null argument");
+        energy_noalloc(ctx, x_dev, energy_dev);
     });
 }
 

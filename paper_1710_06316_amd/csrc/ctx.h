@@ -53,6 +53,9 @@ struct afmpb_ctx {
     DBuf<double> krylov;
     int krylov_m = 0;
     Prof prof;
+    // device address of the static scratch of the allocation-free energy
+    // entry point on this context's device (resolved at creation)
+    double *noalloc_part = nullptr;
     // GMRES on the device (state, captured Arnoldi steps); declared last so
     // that its graphs go before the buffers they use
     GmresEngine gm;
@@ -94,5 +97,10 @@ void dual_energy_sum(afmpb_ctx *c, const double *x_morton, double *out);
 // right-hand side (Morton order) and the device scalar sum_k q_k phi_reac
 void rhs_morton(afmpb_ctx *c, double *b_morton);
 void energy_sum(afmpb_ctx *c, const double *x_morton, double *out);
+// device address of the allocation-free entry point's static scratch on
+// `device` (looked up once per device); the energy from caller-order x on
+// the device into a device scalar, with no allocation and no synchronisation
+double *noalloc_scratch(int device);
+void energy_noalloc(afmpb_ctx *c, const double *x_dev, double *energy_dev);
 
 }  // namespace afmpb
