@@ -329,6 +329,29 @@ def test_warm_start_matches_oracle(precision):
     assert _rel(f, ref.f) < 1e-4 and _rel(h, ref.h) < 1e-4
 
 
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_globular_energy_matches_oracle_reference(precision):
+    """Solvation energy of the 49,190-node molecule (5,000 atoms) against the
+    oracle's solve stored by tests/golden/make_oracle_energies.py (1e-4, the
+    energy gate), plain FP64 and FP32 with FP64 refinement."""
+    ref = _golden("oracle_globular_5000.json")["energy_kcal_mol"]
+    mol = MOLS["globular"]()
+    s = _solver(mol, order_p=10, leaf_cap=192, precision=precision)
+    f, h, E, info, _ = s.solve()
+    s.close()
+    _say(f"globular precision={precision}: E={E:.6f} oracle={ref:.6f} "
+         f"rel={abs(E - ref) / abs(ref):.2e} iters={info.iterations}")
+    assert info.converged and info.true_rel_residual < 2e-6
+    assert abs(E - ref) <= 1e-4 * abs(ref)
+
+
 def test_globular_sampled_rows():
     mol = W.globular()
     n = mol.n_nodes

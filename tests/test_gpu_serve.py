@@ -228,3 +228,33 @@ def test_server_orders_after_caller_stream():
         assert abs(res.energy - E0) <= 1e-12 * abs(E0)
     srv.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_served_energies_match_oracle_references(precision):
+    """Requests of the benchmark's stream (up to 10,242 nodes) served with
+    the tuning table's leaf capacity and order: every energy within 1e-4 of
+    the oracle's solve of the same request (tests/golden)."""
+    import json
+    import os
+    import paper_1710_06316_amd as A
+    from paper_1710_06316_amd import autotune
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "oracle_star_stream.json")
+    with open(path) as fh:
+        golden = {r["index"]: r["energy_kcal_mol"] for r in json.load(fh)["requests"]}
+    idx = sorted(golden)[:24]
+    assert len(idx) >= 8
+    mols = [W.star_request(i) for i in idx]
+    srv = _server(hbm_budget_bytes=32 << 30, max_active=16, tuning=autotune.load_table(),
+                  precision=precision, order_p=0, leaf_cap=0)
+    tickets = [srv.submit(m) for m in mols]
+    res = [srv.poll(t, wait=True)[1] for t in tickets]
+    srv.close()
+    errs = {}
+    for i, m, r in zip(idx, mols, res):
+        assert r.status == 0, r.message
+        errs[i] = abs(r.energy - golden[i]) / abs(golden[i])
+    _say(f"served vs oracle (precision {precision}): max {max(errs.values()):.2e} over "
+         f"{len(errs)} requests of {sorted(set(m.n_nodes for m in mols))} nodes")
+    assert max(errs.values()) <= 1e-4
