@@ -102,6 +102,13 @@ typedef struct {
                             one octree of nodes and atoms from 2^34 node-atom
                             pairs on, direct sums below); 1 direct sums; 2 the
                             fast multipole pass (order max(order_p, 14), FP64) */
+    int overlap;         /* near-field schedule inside a matvec, beside the
+                            far-field chain on a second stream: 0 automatic
+                            (2 from 2^20 nodes on, else 1); 1 P2P, then the
+                            near-set correction, both started with the chain;
+                            2 the near-set correction beside P2M, then P2P
+                            after P2M has finished (beside the translations).
+                            Both give bit-identical products                   */
 } afmpb_params;
 
 typedef struct {
@@ -168,7 +175,7 @@ typedef struct {
 
 /* Fills *out with the defaults above (eps_p 2, eps_s 80, kappa 0.1, p 8,
  * leaf 64, FP64, rel_tol 1e-6, abs_tol 0, restart 80, max_restarts 5,
- * eta 4, automatic right-hand side). */
+ * eta 4, automatic right-hand side and schedule). */
 afmpb_status afmpb_default_params(afmpb_params *out);
 
 /* Creates a context on HIP device `device`.  hip_stream is a hipStream_t on

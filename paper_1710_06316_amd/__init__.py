@@ -57,7 +57,7 @@ class afmpb_params(ctypes.Structure):
                 ("rel_tol", ctypes.c_double), ("abs_tol", ctypes.c_double),
                 ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
                 ("near_eta", ctypes.c_double), ("m2l_layout", ctypes.c_int),
-                ("rhs_fmm", ctypes.c_int)]
+                ("rhs_fmm", ctypes.c_int), ("overlap", ctypes.c_int)]
 
 
 class afmpb_solve_info(ctypes.Structure):

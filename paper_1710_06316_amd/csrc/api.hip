@@ -243,6 +243,7 @@ void fill_defaults(afmpb_params &p) {
     p.near_eta = 4.0;
     p.m2l_layout = 0;
     p.rhs_fmm = 0;
+    p.overlap = 0;
 }
 
 afmpb_params normalise(const afmpb_params &in) {
@@ -265,6 +266,7 @@ afmpb_params normalise(const afmpb_params &in) {
     require(p.max_restarts >= 0, ST_INVALID, "max_restarts must be >= 0");
     require(p.m2l_layout >= 0 && p.m2l_layout <= 2, ST_INVALID, "m2l_layout must be 0, 1 or 2");
     require(p.rhs_fmm >= 0 && p.rhs_fmm <= 2, ST_INVALID, "rhs_fmm must be 0, 1 or 2");
+    require(p.overlap >= 0 && p.overlap <= 2, ST_INVALID, "overlap must be 0, 1 or 2");
     if (p.near_eta == 0) p.near_eta = 4.0;
     require(fin(p.near_eta) && p.near_eta > 0, ST_INVALID, "near_eta must be > 0");
     return p;
@@ -311,6 +313,7 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.side = c->side;
     mp.fork = c->ev_fork;
     mp.join = c->ev_join;
+    mp.late_p2p = c->prm.overlap == 2 || (c->prm.overlap == 0 && n >= LATE_P2P_MIN_NODES);
     if constexpr (sizeof(R) == sizeof(double)) mp.delta = c->near.delta.p;
     else mp.delta = c->near.delta32.p;
     mp.nd64 = c->nodes();
@@ -329,6 +332,7 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.far.Z = f + 4 * nb * K;         // 16-byte aligned: 4 nb K elements precede it
     mp.far.phi = f + 4 * nb * K + std::max(ng, 1ll) * 2 * KZ;
     mp.far.Mt = mp.far.phi + 4 * n;
+    mp.far.p2m_done = mp.late_p2p ? c->ev_p2m : nullptr;
     mp.far.bf16_m2l = (sizeof(R) == sizeof(float) &&
                        c->prm.precision == AFMPB_FP32_BF16M2L_REFINED) ? 1 : 0;
 }
@@ -719,6 +723,7 @@ afmpb_status afmpb_create(int device, void *hip_stream, const afmpb_allocator *a
     auto fail_device = [c] {
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+        if (c->ev_p2m) (void)hipEventDestroy(c->ev_p2m);
         if (c->side) (void)hipStreamDestroy(c->side);
         hipStream_t own = c->own_stream ? c->stream : nullptr;
         delete c;
@@ -730,9 +735,11 @@ afmpb_status afmpb_create(int device, void *hip_stream, const afmpb_allocator *a
     } catch (const Error &) {
         return fail_device();
     }
+
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_p2m, hipEventDisableTiming) != hipSuccess)
         return fail_device();
     *out = c;
     return AFMPB_OK;
@@ -745,6 +752,7 @@ afmpb_status afmpb_destroy(afmpb_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->side);
     (void)hipEventDestroy(ctx->ev_fork);
     (void)hipEventDestroy(ctx->ev_join);
+    (void)hipEventDestroy(ctx->ev_p2m);
     (void)hipStreamDestroy(ctx->side);
     hipStream_t own = ctx->own_stream ? ctx->stream : nullptr;
     delete ctx;

@@ -118,6 +118,66 @@ __device__ inline void for_each_regular_p(S x, S y, S z, const NT *norm, F &&emi
     }
 }
 
+// for_each_regular_p without the orthonormalisation factors and restricted
+// to the orders m = M0..M1: emits the raw solid harmonics (k, n, q) with
+// R_k = norm[k] q, for a caller that applies the factors once to a sum over
+// many points (and may split the orders m among several lanes).
+template <int P, int M0, int M1, typename R, typename S, typename F>
+__device__ inline void for_each_solid_p(S x, S y, S z, F &&emit) {
+    S r2 = (x * x + y * y) + z * z;
+    S cm(R(1)), sm(R(0));
+    R dfact = R(1);
+#pragma unroll
+    for (int m = 0; m <= M1; ++m) {
+        if (m >= M0) {
+            S pc = cm * dfact, ps = sm * dfact;
+            S qc(R(0)), qs(R(0));
+#pragma unroll
+            for (int n = m; n <= P; ++n) {
+                if (n > m) {
+                    const R a = R((2.0 * n - 1.0) / (n - m)), b = R((n + m - 1.0) / (n - m));
+                    S nc = a * (z * pc) - b * (r2 * qc);
+                    S ns = a * (z * ps) - b * (r2 * qs);
+                    qc = pc; qs = ps;
+                    pc = nc; ps = ns;
+                }
+                const int k0 = n * n + n;
+                if (m == 0) {
+                    emit(k0, n, pc);
+                } else {
+                    emit(k0 + m, n, pc);
+                    emit(k0 - m, n, ps);
+                }
+            }
+        }
+        if (m < M1) {
+            S c2 = cm * x - sm * y;
+            sm = cm * y + sm * x;
+            cm = c2;
+            dfact *= R(2 * m + 1);
+        }
+    }
+}
+
+// Number of harmonics of orders m = M0..M1 up to degree P.
+constexpr int solid_count(int P, int M0, int M1) {
+    int c = 0;
+    for (int m = M0; m <= M1; ++m) c += (m == 0 ? 1 : 2) * (P + 1 - m);
+    return c;
+}
+
+// The first order h of the second of two ranges 0..h-1, h..P, chosen so that
+// the larger of the two holds as few harmonics as possible.
+constexpr int solid_split(int P) {
+    int best = 1, bmax = 1 << 30;
+    for (int h = 1; h <= P; ++h) {
+        const int a = solid_count(P, 0, h - 1), b = solid_count(P, h, P);
+        const int mx = a > b ? a : b;
+        if (mx < bmax) { bmax = mx; best = h; }
+    }
+    return best;
+}
+
 // g_n(x) = i_n(x) / x^n for n = 0..P as functions of t = x^2: series for
 // n = P and P-1, then the downward recurrence g_{n-1} = t g_{n+1} + (2n+1) g_n.
 // inv_dfact[n] = 1/(2n+1)!!; ser[k] = 1/(2 k (2n+2k+1)) is the ratio of

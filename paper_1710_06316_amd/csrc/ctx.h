@@ -25,7 +25,7 @@ struct afmpb_ctx {
     // second stream for the near field, forked from and joined to `stream`
     // inside every matvec (default priority)
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_p2m = nullptr;
     std::string err;
     bool loaded = false;
     afmpb_params prm{};

@@ -25,6 +25,8 @@ struct DualTree {
     DBuf<int> atom_caller;               // [na] dual atom position -> caller index
     DBuf<int> nptb, npte, aptb, apte;    // [nbox] node / atom range of each box
     DBuf<int> npm_leaf, npm_first, npm_count, apm_leaf, apm_first, apm_count;
+    DBuf<int> npm_bysize, apm_bysize;    // item leaves by decreasing point count
+    long long n_npm_leaves = 0, n_apm_leaves = 0;
     long long n_npm = 0, npm_max = 0, n_apm = 0, apm_max = 0;
     DBuf<double> nodes;                  // [6][n] x y z nx ny nz, dual node order
     DBuf<double> atoms;                  // [6][na] x y z and zero normals

@@ -203,12 +203,14 @@ std::vector<T> down(const DBuf<T> &b, size_t n, hipStream_t s) {
 // together; a larger leaf alone); leaves without points of the set omitted.
 void side_items(const std::vector<int> &leaf, const std::vector<int> &pb,
                 const std::vector<int> &pe, DBuf<int> &pm_leaf, DBuf<int> &pm_first,
-                DBuf<int> &pm_count, long long &n_pm, long long &pm_max, hipStream_t s) {
+                DBuf<int> &pm_count, long long &n_pm, long long &pm_max,
+                DBuf<int> &pm_bysize, long long &n_leaves, hipStream_t s) {
     std::vector<int> pml, pmf, pmc;
     for (int b : leaf)
         if (pe[b] > pb[b]) pml.push_back(b);
     std::sort(pml.begin(), pml.end(), [&](int a, int b) { return pb[a] < pb[b]; });
     const long long nl = (long long)pml.size();
+    n_leaves = nl;
     pm_max = 0;
     for (long long i = 0; i < nl;) {
         int cnt = 1, pts = pe[pml[i]] - pb[pml[i]];
@@ -223,12 +225,17 @@ void side_items(const std::vector<int> &leaf, const std::vector<int> &pb,
         i += cnt;
     }
     n_pm = (long long)pmf.size();
+    std::vector<int> pbs(pml);
+    std::stable_sort(pbs.begin(), pbs.end(),
+                     [&](int a, int b) { return pe[a] - pb[a] > pe[b] - pb[b]; });
     pm_leaf.alloc(std::max(nl, 1ll));
     pm_first.alloc(std::max(n_pm, 1ll));
     pm_count.alloc(std::max(n_pm, 1ll));
+    pm_bysize.alloc(std::max(nl, 1ll));
     pm_leaf.upload(pml.data(), pml.size(), s);
     pm_first.upload(pmf.data(), pmf.size(), s);
     pm_count.upload(pmc.data(), pmc.size(), s);
+    pm_bysize.upload(pbs.data(), pbs.size(), s);
     HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -265,6 +272,8 @@ FarSide<double> side_of(const DualTree &D, bool atoms) {
     f.pm_count = atoms ? D.apm_count.p : D.npm_count.p;
     f.n_pm = atoms ? D.n_apm : D.n_npm;
     f.pm_max_points = atoms ? D.apm_max : D.npm_max;
+    f.pm_bysize = atoms ? D.apm_bysize.p : D.npm_bysize.p;
+    f.n_pm_leaves = atoms ? D.n_apm_leaves : D.n_npm_leaves;
     f.x = p; f.y = p + m; f.z = p + 2 * m;
     f.nx = p + 3 * m; f.ny = p + 4 * m; f.nz = p + 5 * m;
     f.n = m;
@@ -352,8 +361,10 @@ void build_dual(afmpb_ctx *c) {
                     "right-hand side tree: P2P lists");
         }
         for (int b : src) require(b >= 0 && b < nb, ST_DEVICE, "right-hand side tree: P2P source box");
-        side_items(leaf, nbh, neh, D.npm_leaf, D.npm_first, D.npm_count, D.n_npm, D.npm_max, s);
-        side_items(leaf, abh, aeh, D.apm_leaf, D.apm_first, D.apm_count, D.n_apm, D.apm_max, s);
+        side_items(leaf, nbh, neh, D.npm_leaf, D.npm_first, D.npm_count, D.n_npm, D.npm_max,
+                   D.npm_bysize, D.n_npm_leaves, s);
+        side_items(leaf, abh, aeh, D.apm_leaf, D.apm_first, D.apm_count, D.n_apm, D.apm_max,
+                   D.apm_bysize, D.n_apm_leaves, s);
         side_groups(leaf, nbh, neh, D.gn_leaf, D.gn_b, D.gn_e, D.n_gn, s);
         side_groups(leaf, abh, aeh, D.ga_leaf, D.ga_b, D.ga_e, D.n_ga, s);
     }

@@ -59,6 +59,7 @@ struct FarWork {
     R *M, *Lc, *Z, *phi;       // [nbox][2][K], [nbox][2][K], [n_v][2][KZ], [4][n]
     R *Mt;                     // [8][widest level][2][K] per-octant M2M products
     int bf16_m2l = 0;          // FP32 path: M2L as three bf16 products (split operands)
+    hipEvent_t p2m_done = nullptr;   // recorded once the multipole expansions are formed
 };
 
 template <typename R>
@@ -76,6 +77,8 @@ struct FarSide {
     const int *ptb = nullptr, *pte = nullptr;
     const int *pm_leaf = nullptr, *pm_first = nullptr, *pm_count = nullptr;
     long long n_pm = 0, pm_max_points = 0;
+    const int *pm_bysize = nullptr;   // the item leaves by decreasing point count
+    long long n_pm_leaves = 0;
     const R *x = nullptr, *y = nullptr, *z = nullptr, *nx = nullptr, *ny = nullptr,
             *nz = nullptr;
     long long n = 0;

@@ -480,6 +480,103 @@ __global__ void __launch_bounds__(128 * NCH) k_p2m(BasisDev B, TreeDev T, const 
     }
 }
 
+// P2M by accumulation in registers (compile-time order PC): S adjacent lanes
+// share one leaf and each sums the expansion of every S-th point of it (a
+// fixed strided subset) in registers; the S partial expansions are then
+// added across the lanes by a fixed butterfly.  The point loop has no LDS
+// traffic and no barrier.  The orthonormalisation factors and, for the
+// screened kernel, 1/g_n(kappa s) are constant over a leaf and are applied
+// once to the sums.  Leaves come in order of decreasing point count, so the
+// lanes of a wave run similar trip counts.  blockIdx.y is the kernel; with
+// MS = 2, blockIdx.z picks one of two ranges of orders m (about half of the
+// harmonics each), which halves the accumulators of a lane.
+template <typename R, int PC, int S, int M0, int M1>
+__device__ inline void p2m_acc_range(const BasisDev &B, const TreeDev &T,
+                                     const BasisTab<R> &tab, const int *__restrict__ leaves,
+                                     long long nleaf, const int *__restrict__ ptb,
+                                     const int *__restrict__ pte, const R *px, const R *py,
+                                     const R *pz, const R *pnx, const R *pny, const R *pnz,
+                                     const R *sf, const R *sh, R inv_ebar, R *M) {
+    constexpr int K = (PC + 1) * (PC + 1);
+    constexpr int KS = solid_count(PC, M0, M1);
+    const int kern = blockIdx.y;
+    const long long slot = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / S;
+    const int sub = threadIdx.x % S;
+    const bool live = slot < nleaf;
+    const int leaf = live ? leaves[slot] : 0;
+    const int lev = live ? T.level[leaf] : 0;
+    const int b = live ? ptb[leaf] : 0, e = live ? pte[leaf] : 0;
+    const R cx = R(T.center[3 * leaf]), cy = R(T.center[3 * leaf + 1]);
+    const R cz = R(T.center[3 * leaf + 2]);
+    const R is = R(1.0 / B.side[lev]);
+    const bool scr = kern == 1 && B.screened;         // uniform for the block
+    const R ks = scr ? R(B.kappa * B.side[lev]) : R(0);
+    R acc[KS];
+#pragma unroll
+    for (int j = 0; j < KS; ++j) acc[j] = R(0);
+    for (int i = b + sub; i < e; i += S) {
+        const Dual<R> ux((px[i] - cx) * is, pnx[i] * is), uy((py[i] - cy) * is, pny[i] * is);
+        const Dual<R> uz((pz[i] - cz) * is, pnz[i] * is);
+        const R qv = sh[i], dmag = -sf[i];
+        const R dip = kern == 0 ? dmag * inv_ebar : dmag;
+        int j = 0;                                    // static after unrolling
+        if (!scr) {
+            for_each_solid_p<PC, M0, M1, R>(ux, uy, uz, [&](int, int, Dual<R> r) {
+                acc[j] += qv * r.v + dip * r.d;
+                ++j;
+            });
+        } else {
+            const Dual<R> t = (ks * ks) * ((ux * ux + uy * uy) + uz * uz);
+            Dual<R> g[PC + 1];
+            g_all_p<PC, R, Dual<R>>(t, tab.idf, tab.ser, g);
+            for_each_solid_p<PC, M0, M1, R>(ux, uy, uz, [&](int, int n, Dual<R> r) {
+                const Dual<R> w = r * g[n];
+                acc[j] += qv * w.v + dip * w.d;
+                ++j;
+            });
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+#pragma unroll
+        for (int o = 1; o < S; o <<= 1) acc[j] += __shfl_xor(acc[j], o, 64);
+    }
+    if (!live || sub != 0 || lev < 2) return;
+    R *out = M + ((long long)leaf * 2 + kern) * K;
+    const R *gi = tab.ginv + lev * (PC + 1);
+    int j = 0;
+    // the same (k, n) sequence; the harmonics themselves are dead code here
+    for_each_solid_p<PC, M0, M1, R>(R(0), R(0), R(0), [&](int k, int n, R) {
+        out[k] = acc[j] * (R(B.norm[k]) * (scr ? gi[n] : R(1)));
+        ++j;
+    });
+}
+
+template <typename R, int PC, int S, int MS>
+__global__ void __launch_bounds__(256) k_p2m_acc(BasisDev B, TreeDev T,
+                                                 const int *__restrict__ leaves, long long nleaf,
+                                                 const int *__restrict__ ptb,
+                                                 const int *__restrict__ pte,
+                                                 const R *px, const R *py, const R *pz,
+                                                 const R *pnx, const R *pny, const R *pnz,
+                                                 const R *sf, const R *sh, R inv_ebar, R *M,
+                                                 int nlev) {
+    extern __shared__ __align__(16) unsigned char tab_raw[];
+    const BasisTab<R> tab = stage_basis<R>(B, nlev, tab_raw);
+    if constexpr (MS == 1) {
+        p2m_acc_range<R, PC, S, 0, PC>(B, T, tab, leaves, nleaf, ptb, pte, px, py, pz, pnx, pny,
+                                       pnz, sf, sh, inv_ebar, M);
+    } else {
+        constexpr int H = solid_split(PC);
+        if (blockIdx.z == 0)
+            p2m_acc_range<R, PC, S, 0, H - 1>(B, T, tab, leaves, nleaf, ptb, pte, px, py, pz,
+                                              pnx, pny, pnz, sf, sh, inv_ebar, M);
+        else
+            p2m_acc_range<R, PC, S, H, PC>(B, T, tab, leaves, nleaf, ptb, pte, px, py, pz, pnx,
+                                           pny, pnz, sf, sh, inv_ebar, M);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Batched K x K translations on the matrix cores.  One block (4 waves) owns a
 // set of up to CC output columns; each wave owns a fixed subset of the
@@ -1503,10 +1600,32 @@ void far_field_pass(const Fmm &F, const Tree &t, const Lists &L, const FarSide<R
         k_fill_zero<R><<<grid_for(t.nbox * 2 * K, 256), 256, 0, s>>>(w.M, t.nbox * 2 * K);
         KCHK();
     }
-    if (src.n_pm > 0) {
+    bool p2m_done = false;
+    if (sizeof(R) == sizeof(float) && src.n_pm > 0 && src.pm_bysize) {
+        // FP32, common orders: the accumulating kernel, four lanes per leaf
+        // (FP64 accumulators would leave one wave per SIMD)
+        constexpr int S = 4;
+        auto go = [&](auto kfn, int ms) {
+            ProfScope ps(prof, "p2m", s);
+            const long long lanes = src.n_pm_leaves * S;
+            kfn<<<dim3(blocks_ok((lanes + 255) / 256, 256), 2, ms), 256,
+                  basis_tab_bytes(F.P, F.nlev, sizeof(R)), s>>>(
+                B, Ts, src.pm_bysize, src.n_pm_leaves, src.ptb, src.pte, src.x, src.y, src.z,
+                src.nx, src.ny, src.nz, sf, sh, R(inv_ebar), w.M, F.nlev);
+            KCHK();
+            p2m_done = true;
+        };
+        if constexpr (sizeof(R) == sizeof(float)) {
+            switch (F.P) {
+                case 6: go(k_p2m_acc<R, 6, S, 2>, 2); break;
+                case 8: go(k_p2m_acc<R, 8, S, 2>, 2); break;
+                case 10: go(k_p2m_acc<R, 10, S, 2>, 2); break;
+                default: break;
+            }
+        }
+    }
+    if (src.n_pm > 0 && !p2m_done) {
         ProfScope ps(prof, "p2m", s);
-        // P2M keeps the generic table recurrence: the unrolled orders need
-        // up to 185 VGPRs here (two waves per SIMD) and run slower;
         // one wave per kernel and 64-point chunk of the largest item: up to
         // four chunks at once for FP32, two for FP64, within 60 KB of LDS
         const size_t lds = basis_tab_bytes(F.P, F.nlev, sizeof(R));
@@ -1531,6 +1650,7 @@ void far_field_pass(const Fmm &F, const Tree &t, const Lists &L, const FarSide<R
         }
         KCHK();
     }
+    if (w.p2m_done) HIPCHK(hipEventRecord(w.p2m_done, s));
     TransArgs ta{};
     ta.K = K;
     ta.KK = F.KK;
@@ -1631,6 +1751,8 @@ void far_field(const Fmm &F, const Tree &t, const Lists &L, const NodeSoA &nd, c
     side.pm_count = L.pm_count.p;
     side.n_pm = L.n_pm;
     side.pm_max_points = L.pm_max_points;
+    side.pm_bysize = L.pm_bysize.p;
+    side.n_pm_leaves = L.n_pm_leaves;
     side.x = px; side.y = py; side.z = pz;
     side.nx = pnx; side.ny = pny; side.nz = pnz;
     side.n = n;

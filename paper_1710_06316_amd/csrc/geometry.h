@@ -67,6 +67,10 @@ struct Lists {
     // consecutive leaves with <= 64 points together (a larger leaf alone)
     DBuf<int> pm_leaf, pm_first, pm_count;
     long long n_pm = 0, pm_max_points = 0;
+    // the same leaves by decreasing point count (ties in point order): the
+    // lane order of the accumulating P2M
+    DBuf<int> pm_bysize;
+    long long n_pm_leaves = 0;
     DBuf<int> v_tgt;                   // [n_v] target box of each V entry
     // M2L groups: per-entry layout (m2l_grouped = false): group g is V entry g
     // (its source v_idx[g], result slots in list order, [v_ptr[B],

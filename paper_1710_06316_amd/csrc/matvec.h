@@ -11,6 +11,10 @@ struct NodeR {
     const R *x, *y, *z, *nx, *ny, *nz;
 };
 
+// From this many nodes on, the automatic schedule runs the near-set
+// correction beside P2M and P2P after it (P2P beside P2M slows the chain).
+constexpr long long LATE_P2P_MIN_NODES = 1ll << 20;
+
 template <typename R>
 struct MatvecPlan {
     long long n = 0;
@@ -29,6 +33,8 @@ struct MatvecPlan {
     const R *delta = nullptr;              // near corrections [nnz][4], working precision
     hipStream_t side = nullptr;            // near field runs here, between fork and join
     hipEvent_t fork = nullptr, join = nullptr;
+    // P2P waits for P2M (far.p2m_done); the near correction runs first
+    bool late_p2p = false;
     FarWork<R> far{};
 };
 

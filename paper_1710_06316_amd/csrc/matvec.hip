@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(64) k_p2p_reduce(const int *__restrict__ grp_p
                                                    const int *__restrict__ rev_idx,
                                                    const double *__restrict__ rpart,
                                                    double *__restrict__ out_f,
-                                                   double *__restrict__ out_h) {
+                                                   double *__restrict__ out_h, int add) {
     const int g = blockIdx.x, lane = threadIdx.x;
     const int i = grp_tbeg[g] + lane;
     if (i >= grp_tend[g]) return;
@@ -324,8 +324,15 @@ __global__ void __launch_bounds__(64) k_p2p_reduce(const int *__restrict__ grp_p
         tf += rpart[2 * sl];
         th += rpart[2 * sl + 1];
     }
-    out_f[i] = tf * INV_4PI;
-    out_h[i] = th * INV_4PI;
+    // add: the near-set correction is already there.  The product is rounded
+    // before the addition (no fused multiply-add), so that both schedules
+    // add the same two rounded terms.
+    {
+#pragma clang fp contract(off)
+        const double vf = tf * INV_4PI, vh = th * INV_4PI;
+        out_f[i] = add ? out_f[i] + vf : vf;
+        out_h[i] = add ? out_h[i] + vh : vh;
+    }
 }
 
 template <typename R>
@@ -340,8 +347,8 @@ __global__ void k_gather_sources(const double *__restrict__ x, const double *__r
 // Near correction: one group of 16 lanes per row (two entries in flight per
 // lane, so a row of ~110 entries takes ~4 dependent index/gather trips), lane
 // partial sums added by a fixed butterfly; the row's sums are added to the
-// P2P sums.
-template <typename R>
+// P2P sums (ADD) or stored for P2P to add to.
+template <typename R, bool ADD>
 __global__ void k_near_apply(long long n, const double *__restrict__ x,
                              const long long *__restrict__ nptr, const int *__restrict__ ncol,
                              const R *__restrict__ nd, double *__restrict__ pf,
@@ -378,8 +385,8 @@ __global__ void k_near_apply(long long n, const double *__restrict__ x,
         ch += __shfl_xor(ch, o, 16);
     }
     if (p < n && sub == 0) {
-        pf[p] += cf;
-        ph[p] += ch;
+        pf[p] = ADD ? pf[p] + cf : cf;
+        ph[p] = ADD ? ph[p] + ch : ch;
     }
 }
 
@@ -435,10 +442,13 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
         KCHK();
     }
     // fork: the near field (P2P and patch corrections) depends only on the
-    // gathered sources and x, and runs beside the far-field chain
+    // gathered sources and x, and runs beside the far-field chain.  P2P
+    // issues at full VALU rate and, started with the chain, holds the SIMDs
+    // that P2M waits for; late_p2p puts the memory-bound near correction
+    // beside P2M and P2P beside the translations instead.
     HIPCHK(hipEventRecord(mp.fork, s));
     HIPCHK(hipStreamWaitEvent(mp.side, mp.fork, 0));
-    {
+    auto p2p = [&](int add) {
         ProfScope ps(prof, "p2p", mp.side);
         const Lists &L = *mp.lists;
         k_p2p<R><<<blocks_ok(L.n_chunks, 64), 64, 0, mp.side>>>(
@@ -447,18 +457,30 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
         KCHK();
         k_p2p_reduce<<<blocks_ok(L.n_groups, 64), 64, 0, mp.side>>>(
             L.grp_ptr.p, L.grp_tbeg.p, L.grp_tend.p, mp.part, L.rev_ptr.p, L.rev_idx.p, mp.rpart,
-            mp.pf, mp.ph);
+            mp.pf, mp.ph, add);
         KCHK();
-    }
-    {
+    };
+    auto near = [&](auto add) {
         ProfScope ps(prof, "near", mp.side);
-        k_near_apply<R><<<grid_for(16 * n, 256), 256, 0, mp.side>>>(
+        k_near_apply<R, decltype(add)::value><<<grid_for(16 * n, 256), 256, 0, mp.side>>>(
             n, x, mp.near->ptr.p, mp.near->col.p, mp.delta, mp.pf, mp.ph);
         KCHK();
+    };
+    if (mp.late_p2p) {
+        near(std::false_type{});
+        // far_field records far.p2m_done after P2M, before it returns
+    } else {
+        p2p(0);
+        near(std::true_type{});
+        HIPCHK(hipEventRecord(mp.join, mp.side));
     }
-    HIPCHK(hipEventRecord(mp.join, mp.side));
     far_field<R>(*mp.fmm, *mp.tree, *mp.lists, mp.nd64, mp.nd.x, mp.nd.y, mp.nd.z, mp.nd.nx,
                  mp.nd.ny, mp.nd.nz, mp.sf, mp.sh, mp.inv_ebar, n, mp.far, prof, s);
+    if (mp.late_p2p) {
+        HIPCHK(hipStreamWaitEvent(mp.side, mp.far.p2m_done, 0));
+        p2p(1);
+        HIPCHK(hipEventRecord(mp.join, mp.side));
+    }
     HIPCHK(hipStreamWaitEvent(s, mp.join, 0));
     {
         ProfScope ps(prof, "combine", s);

@@ -401,12 +401,13 @@ struct SolveJob {
         std::shared_lock<std::shared_mutex> lk(g_capture_mu);
         if (ev) (void)hipEventDestroy(ev);
         if (!c) return;
-        hipEvent_t e1 = c->ev_fork, e2 = c->ev_join;
+        hipEvent_t e1 = c->ev_fork, e2 = c->ev_join, e3 = c->ev_p2m;
         lk.unlock();
         c.reset();                              // device buffers of the context
         lk.lock();
         if (e1) (void)hipEventDestroy(e1);
         if (e2) (void)hipEventDestroy(e2);
+        if (e3) (void)hipEventDestroy(e3);
         if (sd) (void)hipStreamDestroy(sd);
         if (st) (void)hipStreamDestroy(st);
     }
@@ -505,6 +506,7 @@ void afmpb_server::setup_loop() {
             HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
             HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&c->ev_p2m, hipEventDisableTiming));
             if (q->after) HIPCHK(hipStreamWaitEvent(c->stream, q->after, 0));
             load_molecule(c, q->n, q->xyz.data(), q->m, q->tri.data(), q->na, q->axyz.data(),
                           q->q.data(), qp);

@@ -732,10 +732,17 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2
             i += cnt;
         }
         L.n_pm = (long long)pmf.size();
+        std::vector<int> pbs(pml);
+        std::stable_sort(pbs.begin(), pbs.end(), [&](int a, int b) {
+            return pte_h[a] - ptb_h[a] > pte_h[b] - ptb_h[b];
+        });
+        L.n_pm_leaves = nl;
         L.pm_leaf.alloc(nl); L.pm_first.alloc(L.n_pm); L.pm_count.alloc(L.n_pm);
+        L.pm_bysize.alloc(std::max(nl, 1ll));
         L.pm_leaf.upload(pml.data(), pml.size(), s);
         L.pm_first.upload(pmf.data(), pmf.size(), s);
         L.pm_count.upload(pmc.data(), pmc.size(), s);
+        L.pm_bysize.upload(pbs.data(), pbs.size(), s);
         HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
     }
     // M2L work items.  Per entry: items of <= 64 V entries of one (level,
