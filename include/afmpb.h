@@ -104,11 +104,13 @@ typedef struct {
                             fast multipole pass (order max(order_p, 14), FP64) */
     int overlap;         /* near-field schedule inside a matvec, beside the
                             far-field chain on a second stream: 0 automatic
-                            (2 from 2^20 nodes on, else 1); 1 P2P, then the
+                            (3 from 2^20 nodes on, else 1); 1 P2P, then the
                             near-set correction, both started with the chain;
                             2 the near-set correction beside P2M, then P2P
-                            after P2M has finished (beside the translations).
-                            Both give bit-identical products                   */
+                            after P2M has finished (beside the translations);
+                            3 one stream, every kernel after the last (for
+                            per-kernel timing).  All give bit-identical
+                            products                                           */
 } afmpb_params;
 
 typedef struct {

@@ -266,7 +266,7 @@ afmpb_params normalise(const afmpb_params &in) {
     require(p.max_restarts >= 0, ST_INVALID, "max_restarts must be >= 0");
     require(p.m2l_layout >= 0 && p.m2l_layout <= 2, ST_INVALID, "m2l_layout must be 0, 1 or 2");
     require(p.rhs_fmm >= 0 && p.rhs_fmm <= 2, ST_INVALID, "rhs_fmm must be 0, 1 or 2");
-    require(p.overlap >= 0 && p.overlap <= 2, ST_INVALID, "overlap must be 0, 1 or 2");
+    require(p.overlap >= 0 && p.overlap <= 3, ST_INVALID, "overlap must be 0, 1, 2 or 3");
     if (p.near_eta == 0) p.near_eta = 4.0;
     require(fin(p.near_eta) && p.near_eta > 0, ST_INVALID, "near_eta must be > 0");
     return p;
@@ -291,7 +291,7 @@ template <typename R>
 void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const R *ndR) {
     const long long n = c->n, K = c->fmm.K, nb = c->tree.nbox;
     const long long ng = c->lists.n_vg * c->lists.m2l_split;   // result slots
-    w.alloc((size_t)2 * n);
+    w.alloc((size_t)4 * n);
     if (c->p2p64.n < (size_t)2 * n) c->p2p64.alloc((size_t)2 * n);
     if (c->p2p_part.n < (size_t)c->lists.n_chunks * 128)
         c->p2p_part.alloc((size_t)std::max(c->lists.n_chunks, 1ll) * 128);
@@ -313,7 +313,9 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.side = c->side;
     mp.fork = c->ev_fork;
     mp.join = c->ev_join;
-    mp.late_p2p = c->prm.overlap == 2 || (c->prm.overlap == 0 && n >= LATE_P2P_MIN_NODES);
+    mp.late_p2p = c->prm.overlap == 2;
+    mp.serial = c->prm.overlap == 3 || (c->prm.overlap == 0 && n >= SERIAL_MIN_NODES);
+    mp.far.p2m_done = mp.late_p2p && !mp.serial ? c->ev_p2m : nullptr;
     if constexpr (sizeof(R) == sizeof(double)) mp.delta = c->near.delta.p;
     else mp.delta = c->near.delta32.p;
     mp.nd64 = c->nodes();
@@ -323,6 +325,7 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.inv_ebar = c->inv_ebar;
     mp.alpha = c->alpha;
     mp.sf = w.p;
+    mp.xp = w.p + 2 * n;
     mp.sh = w.p + n;
     mp.pf = c->p2p64.p;
     mp.ph = c->p2p64.p + n;
@@ -332,7 +335,6 @@ void setup_plan(afmpb_ctx *c, MatvecPlan<R> &mp, DBuf<R> &w, DBuf<R> &far, const
     mp.far.Z = f + 4 * nb * K;         // 16-byte aligned: 4 nb K elements precede it
     mp.far.phi = f + 4 * nb * K + std::max(ng, 1ll) * 2 * KZ;
     mp.far.Mt = mp.far.phi + 4 * n;
-    mp.far.p2m_done = mp.late_p2p ? c->ev_p2m : nullptr;
     mp.far.bf16_m2l = (sizeof(R) == sizeof(float) &&
                        c->prm.precision == AFMPB_FP32_BF16M2L_REFINED) ? 1 : 0;
 }

@@ -11,9 +11,12 @@ struct NodeR {
     const R *x, *y, *z, *nx, *ny, *nz;
 };
 
-// From this many nodes on, the automatic schedule runs the near-set
-// correction beside P2M and P2P after it (P2P beside P2M slows the chain).
-constexpr long long LATE_P2P_MIN_NODES = 1ll << 20;
+// From this many nodes on, the automatic schedule runs every kernel on one
+// stream: the kernels are then large enough to fill the GPU alone, and run
+// beside each other they compete for the same SIMDs and caches (measured on
+// the 9.7M-node shell: 67.1 ms one stream, 68.1-68.4 ms with either
+// two-stream order).
+constexpr long long SERIAL_MIN_NODES = 1ll << 20;
 
 template <typename R>
 struct MatvecPlan {
@@ -27,6 +30,7 @@ struct MatvecPlan {
     const double *area = nullptr;
     double kappa = 0, inv_ebar = 0, alpha = 0;
     R *sf = nullptr, *sh = nullptr;
+    R *xp = nullptr;                       // [n][2] (f, h) in the working precision
     double *pf = nullptr, *ph = nullptr;   // P2P sums (double in both precisions)
     double *part = nullptr;                // P2P chunk partial sums [chunks][2][64]
     double *rpart = nullptr;               // P2P reverse partial sums [reverse slots][2]
@@ -35,6 +39,7 @@ struct MatvecPlan {
     hipEvent_t fork = nullptr, join = nullptr;
     // P2P waits for P2M (far.p2m_done); the near correction runs first
     bool late_p2p = false;
+    bool serial = false;                   // no second stream: every kernel on s
     FarWork<R> far{};
 };
 

@@ -335,58 +335,96 @@ __global__ void __launch_bounds__(64) k_p2p_reduce(const int *__restrict__ grp_p
     }
 }
 
+// Source strengths a f, a h of every node, and (f, h) side by side in the
+// working precision for the near correction's gathers.
 template <typename R>
 __global__ void k_gather_sources(const double *__restrict__ x, const double *__restrict__ area,
-                                 long long n, R *sf, R *sh) {
+                                 long long n, R *sf, R *sh, R *xp) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    sf[i] = R(area[i] * x[i]);
-    sh[i] = R(area[i] * x[n + i]);
+    const double f = x[i], h = x[n + i];
+    sf[i] = R(area[i] * f);
+    sh[i] = R(area[i] * h);
+    xp[2 * i] = R(f);
+    xp[2 * i + 1] = R(h);
 }
 
-// Near correction: one group of 16 lanes per row (two entries in flight per
-// lane, so a row of ~110 entries takes ~4 dependent index/gather trips), lane
-// partial sums added by a fixed butterfly; the row's sums are added to the
-// P2P sums (ADD) or stored for P2P to add to.
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+template <typename R> struct Pair2;
+template <> struct Pair2<float> { typedef float2 T; };
+template <> struct Pair2<double> { typedef double2 T; };
+
+// Near correction: one group of 16 lanes per row, NEAR_INFLIGHT entries in
+// flight per lane.  The coefficients and column indices are read once
+// (non-temporal loads, so that they do not evict the gathered (f, h) pairs
+// from cache); products and sums are in FP64 (a product of two FP32 values
+// is exact there).  Lane partial sums are added by a fixed butterfly; the
+// row's sums are added to the P2P sums (ADD) or stored for P2P to add to.
+// Two entries in flight measured faster than four or eight on the 9.7M-node
+// shell (13.0 / 14.4 / 13.6 ms): the dependent (f, h) gathers, not the
+// streamed coefficients, bound this kernel.
+#ifndef NEAR_INFLIGHT
+#define NEAR_INFLIGHT 2
+#endif
 template <typename R, bool ADD>
-__global__ void k_near_apply(long long n, const double *__restrict__ x,
-                             const long long *__restrict__ nptr, const int *__restrict__ ncol,
-                             const R *__restrict__ nd, double *__restrict__ pf,
-                             double *__restrict__ ph) {
-    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long p = gid >> 4;
-    int sub = (int)(gid & 15);
-    double cf = 0.0, ch = 0.0, cf2 = 0.0, ch2 = 0.0;
+__global__ void __launch_bounds__(256) k_near_apply(
+    long long n, const typename Pair2<R>::T *__restrict__ xp, const long long *__restrict__ nptr,
+    const int *__restrict__ ncol, const R *__restrict__ nd, double *__restrict__ pf,
+    double *__restrict__ ph) {
+    typedef typename Pair2<R>::T P2;
+    constexpr int IN = NEAR_INFLIGHT;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long p = gid >> 4;
+    const int sub = (int)(gid & 15);
+    double cf[IN], ch[IN];
+#pragma unroll
+    for (int q = 0; q < IN; ++q) cf[q] = ch[q] = 0.0;
+    auto term = [&](int q, long long e, int t) {
+        const P2 v = xp[t];
+        R d[4];
+        if constexpr (sizeof(R) == sizeof(float)) {
+            const fvec4 c = __builtin_nontemporal_load(reinterpret_cast<const fvec4 *>(nd + 4 * e));
+            d[0] = c.x; d[1] = c.y; d[2] = c.z; d[3] = c.w;
+        } else {
+            const dvec2 c0 = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(nd + 4 * e));
+            const dvec2 c1 = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(nd + 4 * e + 2));
+            d[0] = c0.x; d[1] = c0.y; d[2] = c1.x; d[3] = c1.y;
+        }
+        const double f = (double)v.x, h = (double)v.y;
+        cf[q] += (double)d[1] * f - (double)d[0] * h;
+        ch[q] += (double)d[3] * f - (double)d[2] * h;
+    };
     if (p < n) {
         const long long e1 = nptr[p + 1];
         long long e = nptr[p] + sub;
-        for (; e + 16 < e1; e += 32) {
-            const int t = ncol[e], t2 = ncol[e + 16];
-            const double f = x[t], h = x[n + t], f2 = x[t2], h2 = x[n + t2];
-            const R *d = nd + 4 * e, *d2 = nd + 4 * (e + 16);
-            cf += (double)d[1] * f - (double)d[0] * h;
-            ch += (double)d[3] * f - (double)d[2] * h;
-            cf2 += (double)d2[1] * f2 - (double)d2[0] * h2;
-            ch2 += (double)d2[3] * f2 - (double)d2[2] * h2;
+        for (; e + 16 * (IN - 1) < e1; e += 16 * IN) {
+            int t[IN];
+#pragma unroll
+            for (int q = 0; q < IN; ++q) t[q] = __builtin_nontemporal_load(ncol + e + 16 * q);
+#pragma unroll
+            for (int q = 0; q < IN; ++q) term(q, e + 16 * q, t[q]);
         }
-        if (e < e1) {
-            const int t = ncol[e];
-            const double f = x[t], h = x[n + t];
-            const R *d = nd + 4 * e;
-            cf += (double)d[1] * f - (double)d[0] * h;
-            ch += (double)d[3] * f - (double)d[2] * h;
-        }
+        // fewer than IN entries left for this lane
+#pragma unroll
+        for (int q = 0; q < IN - 1; ++q)
+            if (e + 16 * q < e1) term(q, e + 16 * q, __builtin_nontemporal_load(ncol + e + 16 * q));
     }
-    cf += cf2;
-    ch += ch2;
+    double sf = 0.0, sh = 0.0;
+#pragma unroll
+    for (int q = 0; q < IN; ++q) {
+        sf += cf[q];
+        sh += ch[q];
+    }
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) {
-        cf += __shfl_xor(cf, o, 16);
-        ch += __shfl_xor(ch, o, 16);
+        sf += __shfl_xor(sf, o, 16);
+        sh += __shfl_xor(sh, o, 16);
     }
     if (p < n && sub == 0) {
-        pf[p] = ADD ? pf[p] + cf : cf;
-        ph[p] = ADD ? ph[p] + ch : ch;
+        pf[p] = ADD ? pf[p] + sf : sf;
+        ph[p] = ADD ? ph[p] + sh : sh;
     }
 }
 
@@ -438,35 +476,44 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
     const long long n = mp.n;
     {
         ProfScope ps(prof, "gather", s);
-        k_gather_sources<R><<<grid_for(n, 256), 256, 0, s>>>(x, mp.area, n, mp.sf, mp.sh);
+        k_gather_sources<R><<<grid_for(n, 256), 256, 0, s>>>(x, mp.area, n, mp.sf, mp.sh,
+                                                             mp.xp);
         KCHK();
     }
     // fork: the near field (P2P and patch corrections) depends only on the
     // gathered sources and x, and runs beside the far-field chain.  P2P
     // issues at full VALU rate and, started with the chain, holds the SIMDs
     // that P2M waits for; late_p2p puts the memory-bound near correction
-    // beside P2M and P2P beside the translations instead.
-    HIPCHK(hipEventRecord(mp.fork, s));
-    HIPCHK(hipStreamWaitEvent(mp.side, mp.fork, 0));
+    // beside P2M and P2P beside the translations instead.  serial: every
+    // kernel on s, one after another.
+    const hipStream_t sd = mp.serial ? s : mp.side;
+    if (!mp.serial) {
+        HIPCHK(hipEventRecord(mp.fork, s));
+        HIPCHK(hipStreamWaitEvent(sd, mp.fork, 0));
+    }
     auto p2p = [&](int add) {
-        ProfScope ps(prof, "p2p", mp.side);
+        ProfScope ps(prof, "p2p", sd);
         const Lists &L = *mp.lists;
-        k_p2p<R><<<blocks_ok(L.n_chunks, 64), 64, 0, mp.side>>>(
+        k_p2p<R><<<blocks_ok(L.n_chunks, 64), 64, 0, sd>>>(
             L.ch_lo.p, L.ch_hi.p, L.ch_grp.p, L.grp_tbeg.p, L.grp_tend.p, L.rng_b.p, L.rng_e.p,
             L.ch_rev.p, mp.nd, mp.sf, mp.sh, R(mp.kappa), R(mp.inv_ebar), mp.part, mp.rpart);
         KCHK();
-        k_p2p_reduce<<<blocks_ok(L.n_groups, 64), 64, 0, mp.side>>>(
+        k_p2p_reduce<<<blocks_ok(L.n_groups, 64), 64, 0, sd>>>(
             L.grp_ptr.p, L.grp_tbeg.p, L.grp_tend.p, mp.part, L.rev_ptr.p, L.rev_idx.p, mp.rpart,
             mp.pf, mp.ph, add);
         KCHK();
     };
     auto near = [&](auto add) {
-        ProfScope ps(prof, "near", mp.side);
-        k_near_apply<R, decltype(add)::value><<<grid_for(16 * n, 256), 256, 0, mp.side>>>(
-            n, x, mp.near->ptr.p, mp.near->col.p, mp.delta, mp.pf, mp.ph);
+        ProfScope ps(prof, "near", sd);
+        k_near_apply<R, decltype(add)::value><<<grid_for(16 * n, 256), 256, 0, sd>>>(
+            n, reinterpret_cast<const typename Pair2<R>::T *>(mp.xp), mp.near->ptr.p,
+            mp.near->col.p, mp.delta, mp.pf, mp.ph);
         KCHK();
     };
-    if (mp.late_p2p) {
+    if (mp.serial) {
+        p2p(0);
+        near(std::true_type{});
+    } else if (mp.late_p2p) {
         near(std::false_type{});
         // far_field records far.p2m_done after P2M, before it returns
     } else {
@@ -476,12 +523,12 @@ void apply_operator(const MatvecPlan<R> &mp, const double *x, double *y, Prof *p
     }
     far_field<R>(*mp.fmm, *mp.tree, *mp.lists, mp.nd64, mp.nd.x, mp.nd.y, mp.nd.z, mp.nd.nx,
                  mp.nd.ny, mp.nd.nz, mp.sf, mp.sh, mp.inv_ebar, n, mp.far, prof, s);
-    if (mp.late_p2p) {
-        HIPCHK(hipStreamWaitEvent(mp.side, mp.far.p2m_done, 0));
+    if (mp.late_p2p && !mp.serial) {
+        HIPCHK(hipStreamWaitEvent(sd, mp.far.p2m_done, 0));
         p2p(1);
-        HIPCHK(hipEventRecord(mp.join, mp.side));
+        HIPCHK(hipEventRecord(mp.join, sd));
     }
-    HIPCHK(hipStreamWaitEvent(s, mp.join, 0));
+    if (!mp.serial) HIPCHK(hipStreamWaitEvent(s, mp.join, 0));
     {
         ProfScope ps(prof, "combine", s);
         k_combine<R><<<grid_for(n, 256), 256, 0, s>>>(n, x, mp.pf, mp.ph, mp.far.phi, mp.alpha,

@@ -233,22 +233,23 @@ def test_m2l_layouts_agree_and_match_oracle(name, cap, p):
 
 @pytest.mark.parametrize("p", [8, 14])
 def test_overlap_schedules_bit_identical(p):
-    """The two near-field schedules (P2P beside the whole far-field chain, or
-    the near-set correction beside P2M and P2P after it) add the same two
-    terms per row, so the products agree bit for bit; both match the oracle."""
+    """The near-field schedules (P2P beside the whole far-field chain, the
+    near-set correction beside P2M and P2P after it, or one stream) add the
+    same two terms per row, so the products agree bit for bit; all match the
+    oracle."""
     import paper_1710_06316_amd as A
     mol = MOLS["globular"]()
     x = np.random.default_rng(8).normal(size=2 * mol.n_nodes)
     ref = _oracle_op(mol).matvec(x)
     for prec in (A.AFMPB_FP64, A.AFMPB_FP32_REFINED):
         ys = {}
-        for overlap in (1, 2):
+        for overlap in (1, 2, 3):
             s = _solver(mol, order_p=p, leaf_cap=128, precision=prec, overlap=overlap)
             ys[overlap] = s.matvec(x)
             s.close()
         err = _rel(ys[2], ref)
         _say(f"p={p} precision={prec} oracle error {err:.2e}")
-        assert np.array_equal(ys[1], ys[2])
+        assert np.array_equal(ys[1], ys[2]) and np.array_equal(ys[1], ys[3])
         assert err < (2e-4 if p == 8 else 1e-5)
 
 
