@@ -93,10 +93,13 @@ typedef struct {
                             V-list entry, items of one (level, offset class);
                             2 one slot per (target, colleague of its parent),
                             all children of the colleague accumulated in
-                            registers.  Automatic takes 2 from 2^21 V-list
-                            entries on (large trees, where the result traffic
-                            of 1 dominates).  Every layout computes the same
-                            sums (rounding order aside)                         */
+                            registers; 3 as 2, with work items of box pairs
+                            (P, colleague C of P): each child of C is read
+                            once for all children of P.  Automatic takes 2
+                            from 2^21 V-list entries on (large trees, where
+                            the result traffic of 1 dominates) and 3 from
+                            2^24.  Every layout computes the same sums
+                            (rounding order aside; 2 and 3 bit for bit)       */
     int rhs_fmm;         /* right-hand side of Eq. (5) and the reaction potential
                             at the atoms: 0 automatic (fast multipole pass over
                             one octree of nodes and atoms from 2^34 node-atom
@@ -136,7 +139,8 @@ typedef struct {
     int order_p, leaf_cap;
     long long n_m2l_slots;           /* M2L result slots per kernel and matvec
                                         (= n_m2l_pairs in the per-entry layout)  */
-    int m2l_layout;                  /* layout in use: 1 per entry, 2 grouped    */
+    int m2l_layout;                  /* layout in use: 1 per entry, 2 grouped,
+                                        3 pairs                              */
     int rhs_mode;                    /* right-hand side / energy: 1 direct sums,
                                         2 fast multipole pass over nodes+atoms */
     long long rhs_boxes;             /* boxes of the nodes+atoms tree (0 if 1) */

@@ -264,7 +264,7 @@ afmpb_params normalise(const afmpb_params &in) {
     if (p.restart == 0) p.restart = 80;
     require(p.restart >= 1 && p.restart <= 1000, ST_INVALID, "restart must be in [1, 1000]");
     require(p.max_restarts >= 0, ST_INVALID, "max_restarts must be >= 0");
-    require(p.m2l_layout >= 0 && p.m2l_layout <= 2, ST_INVALID, "m2l_layout must be 0, 1 or 2");
+    require(p.m2l_layout >= 0 && p.m2l_layout <= 3, ST_INVALID, "m2l_layout must be 0, 1, 2 or 3");
     require(p.rhs_fmm >= 0 && p.rhs_fmm <= 2, ST_INVALID, "rhs_fmm must be 0, 1 or 2");
     require(p.overlap >= 0 && p.overlap <= 3, ST_INVALID, "overlap must be 0, 1, 2 or 3");
     if (p.near_eta == 0) p.near_eta = 4.0;
@@ -981,7 +981,7 @@ afmpb_status afmpb_tree_info(afmpb_ctx *ctx, afmpb_tree_sizes *out) {
         out->order_p = ctx->prm.order_p;
         out->leaf_cap = ctx->prm.leaf_cap;
         out->n_m2l_slots = ctx->lists.n_vg * ctx->lists.m2l_split;
-        out->m2l_layout = ctx->lists.m2l_grouped ? 2 : 1;
+        out->m2l_layout = ctx->lists.m2l_pairs ? 3 : ctx->lists.m2l_grouped ? 2 : 1;
         out->rhs_mode = ctx->dual.built ? 2 : 1;
         out->rhs_boxes = ctx->dual.built ? ctx->dual.t.nbox : 0;
     });

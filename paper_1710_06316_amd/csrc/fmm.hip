@@ -611,6 +611,7 @@ struct TransArgs {
     long long PMB;               // bf16 M2L: elements per packed matrix (each part)
     const int *cb, *nc;          // child begin / count
     const unsigned long long *prefix;
+    const int *pr_src, *pr_slot; // M2L pair layout: sources / result slots per octant
 };
 
 // Row stride (elements) of the gathered expansions in LDS, chosen so that
@@ -997,6 +998,101 @@ k_m2l(TransArgs a, const R *__restrict__ ops,
     m2l_group_rows<R, CC, 1>(a, ops, in, out, Ms, KKp, colbox, srcbox, iops, lo, hi, ncols, kern, lane, wave);
 }
 
+// M2L by pairs of boxes (k_m2l_pairs).  A work item is <= CC pairs (P, C)
+// of one level and one colleague offset; for each source octant c the block
+// gathers child c of every pair's C into LDS once, and the waves multiply it
+// by the operators of all eight target octants, accumulating per (target
+// octant, row tile) in registers (JPW such jobs per wave).  At the end each
+// job's tile goes to the slot of (child b of P, C) of the grouped layout, so
+// that the grouped reduction over colleagues applies unchanged.  Against the
+// grouped layout, each source expansion is read once per pair instead of
+// once per child of P.
+template <typename R, int CC, int NA, int JPW>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
+k_m2l_pairs(TransArgs a, const R *__restrict__ ops, const R *__restrict__ in,
+            R *__restrict__ out) {
+    typedef typename Acc4<R>::T V4;
+    extern __shared__ unsigned char smem_raw[];
+    R *Ms = reinterpret_cast<R *>(smem_raw);          // [CC][KKp]
+    __shared__ int src[8][CC], slot[8][CC], iops[64];
+    const int KKp = lds_stride(a.KK, (int)sizeof(R));
+    const int kern = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwave = (int)(blockDim.x >> 6);
+    // items dealt to the XCDs in contiguous ranges (block b runs on XCD b % 8)
+    const int per = (int)(gridDim.x >> 3);
+    const int w = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+    if (w >= a.n_items) return;                        // uniform for the block
+    // columns [blockIdx.z CC, + CC) of the item's <= 64 pairs
+    const int off = (int)blockIdx.z * CC;
+    const int ncols = min(CC, a.item_count[w] - off);
+    if (ncols <= 0) return;                            // uniform for the block
+    const int beg = a.item_begin[w] + off;
+    for (int i = tid; i < 8 * CC; i += blockDim.x) {
+        const int o = i / CC, col = i % CC;
+        const bool ok = col < ncols;
+        src[o][col] = ok ? a.pr_src[8 * (long long)(beg + col) + o] : -1;
+        slot[o][col] = ok ? a.pr_slot[8 * (long long)(beg + col) + o] : -1;
+    }
+    if (tid < 64) iops[tid] = a.item_ops[64 * (long long)w + tid];
+    __syncthreads();
+    const int K = a.K, KK = a.KK, KS = KK / 4, NRT = (K + 15) / 16;
+    const R *Bp = Ms + (lane & 15) * KKp + (lane >> 4);
+    V4 acc[JPW][NA];
+#pragma unroll
+    for (int q = 0; q < JPW; ++q)
+#pragma unroll
+        for (int ct = 0; ct < NA; ++ct) acc[q][ct] = V4{0, 0, 0, 0};
+    bool busy = false;
+    for (int c = 0; c < 8; ++c) {
+        int any = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) any |= iops[8 * b + c] >= 0;
+        if (!__builtin_amdgcn_readfirstlane(any)) continue;   // uniform
+        if (busy) __syncthreads();                     // products of the last octant done
+        busy = true;
+        gather_cols<R>(in, src[c], ncols, NA, K, KK, KKp, kern, lane, wave, Ms);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < JPW; ++q) {
+            const int j = wave + q * nwave;
+            if (j >= 8 * NRT) continue;               // uniform for the wave
+            const int b = j / NRT, rt = j - b * NRT;
+            const int key = __builtin_amdgcn_readfirstlane(iops[8 * b + c]);
+            if (key < 0) continue;
+            const R *A = ops + ((long long)kern * a.nkey + key) * a.PM +
+                         (long long)rt * KS * 64 + lane;
+            R pre[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pre[u] = A[u * 64];
+            for (int ks = 0; ks < KS; ks += 4) {
+                R cur[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    cur[u] = pre[u];
+                    pre[u] = A[(ks + 4 + u) * 64];     // in bounds: operators carry a tail pad
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (ks + u < KS) {
+#pragma unroll
+                        for (int ct = 0; ct < NA; ++ct)
+                            acc[q][ct] = mfma16(cur[u], Bp[ct * 16 * KKp + (ks + u) * 4], acc[q][ct]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < JPW; ++q) {
+        const int j = wave + q * nwave;
+        if (j >= 8 * NRT) continue;
+        const int b = j / NRT, rt = j - b * NRT;
+        trans_store<R, CC, 0, NA>(a, acc[q], out, slot[b], nullptr, ncols, 0, kern, lane, rt);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // M2L with bf16-split operands on the 16x16x32 bf16 matrix instruction: each
 // FP32 value v = hi + lo with hi = bf16(v), lo = bf16(v - hi); the product
@@ -1189,6 +1285,39 @@ void launch_m2l(const TransArgs &ta, unsigned gx, const R *ops, const R *in, R *
         k_m2l<R, 16><<<dim3(gx, 2, 4 * ns), nthr, shmem(16), s>>>(ta, ops, in, out);
     }
     KCHK();
+}
+
+// M2L in the pair layout: 16 waves, JPW = (8 row-tile count) / 16 jobs per
+// wave; 64 columns up to order 10, above that two blocks of 32 columns per
+// item (accumulator registers).
+// Returns false where the grouped kernel runs instead (orders without an
+// instantiation; FP64 above order 6).
+template <typename R>
+bool launch_m2l_pairs(const TransArgs &ta, unsigned gx, const R *ops, const R *in, R *out,
+                      hipStream_t s) {
+    const int nrt = (ta.K + 15) / 16, jpw = (8 * nrt + 15) / 16;
+    // FP64 accumulators of more than two jobs spill at 128 VGPRs
+    if (sizeof(R) == sizeof(double) && jpw > 2) return false;
+    (void)blocks_ok(gx, 1024);
+    auto shmem = [&](int cc) { return (size_t)lds_stride(ta.KK, (int)sizeof(R)) * cc * sizeof(R); };
+    switch (jpw) {
+        case 2: k_m2l_pairs<R, 64, 4, 2><<<dim3(gx, 2), 1024, shmem(64), s>>>(ta, ops, in, out); break;
+        case 3:
+            if constexpr (sizeof(R) == sizeof(float))
+                k_m2l_pairs<R, 64, 4, 3><<<dim3(gx, 2), 1024, shmem(64), s>>>(ta, ops, in, out);
+            break;
+        case 4:
+            if constexpr (sizeof(R) == sizeof(float))
+                k_m2l_pairs<R, 64, 4, 4><<<dim3(gx, 2), 1024, shmem(64), s>>>(ta, ops, in, out);
+            break;
+        case 8:
+            if constexpr (sizeof(R) == sizeof(float))
+                k_m2l_pairs<R, 32, 2, 8><<<dim3(gx, 2, 2), 1024, shmem(32), s>>>(ta, ops, in, out);
+            break;
+        default: return false;
+    }
+    KCHK();
+    return true;
 }
 
 // packed bf16 parts of the M2L operators (from the FP64 operators)
@@ -1685,7 +1814,20 @@ void far_field_pass(const Fmm &F, const Tree &t, const Lists &L, const FarSide<R
         ta.n_items = (int)L.n_m2l_items;
         // grid padded to a multiple of 8 for the XCD-contiguous item mapping
         const unsigned gx = (unsigned)((L.n_m2l_items + 7) / 8 * 8);
-        if constexpr (sizeof(R) == sizeof(float)) {
+        bool done = false;
+        if (L.m2l_pairs && !w.bf16_m2l) {
+            TransArgs tp = ta;
+            tp.n_items = (int)L.n_pr_items;
+            tp.item_ops = L.pr_item_ops.p;
+            tp.item_begin = L.pr_item_begin.p;
+            tp.item_count = L.pr_item_count.p;
+            tp.pr_src = L.pr_src.p;
+            tp.pr_slot = L.pr_slot.p;
+            const unsigned gp = (unsigned)((L.n_pr_items + 7) / 8 * 8);
+            done = gp > 0 && launch_m2l_pairs<R>(tp, gp, Ops<R>::T(F), w.M, w.Z, s);
+        }
+        if (done) {
+        } else if constexpr (sizeof(R) == sizeof(float)) {
             if (w.bf16_m2l) {
                 ta.KC = F.KC;
                 ta.PMB = F.PMB;

@@ -87,10 +87,20 @@ struct Lists {
     long long n_vg = 0, n_m2l_items = 0;
     int m2l_split = 1;
     bool m2l_grouped = false;
+    // Pair layout (on top of the grouped one): pair q is a box P and one
+    // colleague C of it; pr_src[8 q + c] is child c of C (-1 if absent),
+    // pr_slot[8 q + b] the grouped-layout slot of (child b of P, C) (-1 if
+    // that child has none).  Items: <= 64 pairs of one (level, offset d),
+    // pairs [pr_item_begin, + pr_item_count); pr_item_ops[64 w + 8 b + c]
+    // the operator key of target octant b and source octant c, or -1.
+    bool m2l_pairs = false;
+    DBuf<int> pr_src, pr_slot, pr_item_ops, pr_item_begin, pr_item_count;
+    long long n_pairs = 0, n_pr_items = 0;
     std::vector<int> levels_with_v;    // levels that have V entries
 };
 
-// M2L layout: 1 per entry, 2 grouped, 0 chosen by the number of V entries.
+// M2L layout: 1 per entry, 2 grouped, 3 pairs (with the grouped slots), 0
+// chosen by the number of V entries.
 // p2p_chunks = false leaves out the matvec's symmetric P2P work (chunks and
 // reverse slots); the per-leaf source box lists are built either way.
 void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s,

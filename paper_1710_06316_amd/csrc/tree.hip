@@ -14,6 +14,10 @@ constexpr int MAXLEVEL = 21;
 constexpr int MAXCOLL = 26;
 // M2L blocks (items x kernels x octant shares) wanted per launch
 constexpr long long M2L_FILL_BLOCKS = 4096;
+// automatic layout: pairs of boxes from this many V entries on (FP32 M2L on
+// the 9.7M-node shell, 52 M entries: 26.7 -> 19.3 ms; on the 100k-atom
+// complex, 7 M entries at p = 10: 1.87 -> 2.28 ms)
+constexpr long long M2L_PAIR_MIN_ENTRIES = 1ll << 24;
 // Grouped M2L from this many V entries on.  Grouping writes ~6x fewer
 // result slots but multiplies ~1.4x more padded columns (absent children)
 // and balances less evenly over the XCDs; measured on one MI355X it loses
@@ -338,6 +342,18 @@ __global__ void k_vg_fill(TreeView t, long long nbox, const int *vptr, const int
     if (g + 1 != vgptr[B + 1]) atomicOr(err, 8);
 }
 
+// Pair key of every grouped-layout group (before its keys are sorted):
+// (level, colleague offset) and the target's parent, and (group, octant).
+__global__ void k_pair_keys(long long nbox, const int *parent, const int *vgptr,
+                            const unsigned long long *gkey, unsigned long long *pkey, int *pval) {
+    long long B = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nbox) return;
+    for (int g = vgptr[B]; g < vgptr[B + 1]; ++g) {
+        pkey[g] = (gkey[g] >> 3) * (unsigned long long)nbox + (unsigned long long)parent[B];
+        pval[g] = 8 * g + (int)(gkey[g] & 7ull);
+    }
+}
+
 __global__ void k_x_count(long long nbox, const int *wptr, const int *widx, int *cnt) {
     long long C = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (C >= nbox) return;
@@ -494,6 +510,89 @@ void build_tree(const unsigned long long *keys, long long n, int cap, const doub
     t.side.resize(t.nlev);
     for (int l = 0; l < t.nlev; ++l) t.side[l] = (double)(1ll << (MAXLEVEL - l)) / scale;
     HIPCHK(hipStreamSynchronize(s));
+}
+
+// Operator key of target octant b and source octant c of a pair at
+// colleague offset d (level lev), or -1 when the two children are adjacent.
+static int pair_op(int lev, const int d[3], int b, int c) {
+    int o[3], far = 0;
+    for (int a = 0; a < 3; ++a) {
+        o[a] = 2 * d[a] + ((c >> a) & 1) - ((b >> a) & 1);
+        far |= o[a] < -1 || o[a] > 1;
+    }
+    return far ? (lev - 2) * 316 + offset_class(o[0], o[1], o[2]) : -1;
+}
+
+// Pair layout from the grouped one: groups sorted by (level, colleague
+// offset, parent of the target); a run of equal keys is one pair (P, C),
+// its groups the target octants.  gkey: the groups' keys by group index.
+void build_pairs(const Tree &t, Lists &L, const unsigned long long *gkey, long long ng,
+                 hipStream_t s) {
+    const long long nb = t.nbox;
+    DBuf<unsigned long long> pk(ng), tk(ng);
+    DBuf<int> pv(ng), tv(ng);
+    k_pair_keys<<<grid_for(nb, 128), 128, 0, s>>>(nb, t.parent.p, L.vg_ptr.p, gkey, pk.p, pv.p);
+    KCHK();
+    const unsigned long long maxkey = (unsigned long long)(t.nlev * 27 + 1) * (unsigned long long)nb;
+    int bits = 1;
+    while (bits < 64 && (maxkey >> bits)) ++bits;
+    radix_sort_pairs(pk.p, pv.p, tk.p, tv.p, ng, bits, s);
+    std::vector<unsigned long long> hk(ng);
+    std::vector<int> hv(ng), hs((size_t)8 * ng);
+    pk.download(hk.data(), ng, s);
+    pv.download(hv.data(), ng, s);
+    L.vg_src.download(hs.data(), (size_t)8 * ng, s);
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int> psrc, pslot, iops, ib, ic;
+    long long np = 0;
+    unsigned long long cur = ~0ull;
+    int lev = 0, d[3] = {0, 0, 0};
+    for (long long i = 0; i < ng;) {
+        const unsigned long long ld = hk[i] / (unsigned long long)nb;
+        if (ib.empty() || ld != cur || ic.back() == 64) {       // a new item
+            cur = ld;
+            lev = (int)(ld / 27) + 2;
+            const int dk = (int)(ld % 27);
+            d[0] = dk / 9 - 1; d[1] = (dk / 3) % 3 - 1; d[2] = dk % 3 - 1;
+            ib.push_back((int)np);
+            ic.push_back(0);
+            for (int b = 0; b < 8; ++b)
+                for (int c = 0; c < 8; ++c) iops.push_back(pair_op(lev, d, b, c));
+        }
+        int src[8], slot[8];
+        for (int o = 0; o < 8; ++o) src[o] = slot[o] = -1;
+        long long j = i;
+        for (; j < ng && hk[j] == hk[i]; ++j) {
+            const int g = hv[j] >> 3, b = hv[j] & 7;
+            require(slot[b] < 0, ST_DEVICE, "M2L pairs: two groups of one target octant");
+            slot[b] = g;
+            for (int c = 0; c < 8; ++c) {
+                const int sb = hs[(size_t)8 * g + c];
+                if (sb < 0) continue;
+                require(pair_op(lev, d, b, c) >= 0, ST_DEVICE, "M2L pairs: adjacent V entry");
+                require(src[c] < 0 || src[c] == sb, ST_DEVICE, "M2L pairs: sources disagree");
+                src[c] = sb;
+            }
+        }
+        psrc.insert(psrc.end(), src, src + 8);
+        pslot.insert(pslot.end(), slot, slot + 8);
+        ++np;
+        ++ic.back();
+        i = j;
+    }
+    L.n_pairs = np;
+    L.n_pr_items = (long long)ib.size();
+    L.pr_src.alloc(psrc.size());
+    L.pr_slot.alloc(pslot.size());
+    L.pr_item_ops.alloc(iops.size());
+    L.pr_item_begin.alloc(ib.size());
+    L.pr_item_count.alloc(ic.size());
+    L.pr_src.upload(psrc.data(), psrc.size(), s);
+    L.pr_slot.upload(pslot.data(), pslot.size(), s);
+    L.pr_item_ops.upload(iops.data(), iops.size(), s);
+    L.pr_item_begin.upload(ib.data(), ib.size(), s);
+    L.pr_item_count.upload(ic.data(), ic.size(), s);
+    HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
 }
 
 void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2p_chunks) {
@@ -755,7 +854,9 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2
     L.n_m2l_items = 0;
     L.n_vg = 0;
     L.m2l_split = 1;
-    L.m2l_grouped = m2l_layout == 0 ? nv >= M2L_GROUP_MIN_ENTRIES : m2l_layout == 2;
+    L.m2l_grouped = m2l_layout == 0 ? nv >= M2L_GROUP_MIN_ENTRIES : m2l_layout >= 2;
+    L.m2l_pairs = m2l_layout == 0 ? nv >= M2L_PAIR_MIN_ENTRIES : m2l_layout == 3;
+    L.n_pairs = L.n_pr_items = 0;
     if (nv == 0) {
         L.vg_ptr.alloc(nb + 1);
         L.vg_ptr.zero(nb + 1, s);
@@ -810,6 +911,7 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2
                                                     L.vg_src.p, keys.p, L.m2l_cols.p, err.p);
         KCHK();
         require(read_scalar(err.p, s) == 0, ST_DEVICE, "M2L groups inconsistent with V lists");
+        if (L.m2l_pairs) build_pairs(t, L, keys.p, ng, s);
         radix_sort_pairs(keys.p, L.m2l_cols.p, tk.p, tvv.p, ng, 16, s);
         std::vector<unsigned long long> hk(ng);
         keys.download(hk.data(), ng, s);
@@ -838,8 +940,10 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2
         L.n_m2l_items = (long long)ib.size();
         // few items (a small tree): share each item's octants among up to 4
         // blocks so that the launch still fills the chip
+        // (not with the pair layout, which writes one slot per group)
         L.m2l_split = 1;
-        while (L.m2l_split < 4 && L.n_m2l_items * 2 * L.m2l_split < M2L_FILL_BLOCKS)
+        while (!L.m2l_pairs && L.m2l_split < 4 &&
+               L.n_m2l_items * 2 * L.m2l_split < M2L_FILL_BLOCKS)
             L.m2l_split *= 2;
         L.m2l_item_ops.alloc(iops.size());
         L.m2l_item_begin.alloc(ib.size());
