@@ -74,10 +74,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 form")
     ap.add_argument("--no-solve", action="store_true", help="skip the full solves")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving stream (0 skips it)")
-    ap.add_argument("--serve-check", type=int, default=12,
-                    help="requests checked against the order-14 FP64 solve")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-max-active", type=int, default=32)
     ap.add_argument("--serve-setup-threads", type=int, default=1)
@@ -329,50 +327,77 @@ def serve_run(A, mols, qps, precision, order, leaf, budget_gb, max_active, setup
             "energies": [r.energy for r in res], "ok": ok}
 
 
-def serving(A, torch, n_req, check, budget_gb, max_active, setup_threads):
-    """The serving stream: star-shaped molecules (icosphere levels 3-6),
-    saturated throughput X_sat, then Poisson arrivals at 0.5 and 0.9 X_sat,
-    in the mixed-precision form and the plain FP64 form at the same order.
-    Solves count only when their energy is within 1e-4 of the FP64 order-14
-    GPU solve of the same request (checked on a seeded sample)."""
+def serving_refs(A, mols):
+    """Reference energy of every request: the FP64 oracle's solve (stored by
+    tests/golden/make_oracle_energies.py) for requests of at most 10,242
+    nodes, the FP64 GPU solve at expansion order 14 for the larger ones."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_star_stream.json")
+    golden = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            golden = {r["index"]: r["energy_kcal_mol"] for r in json.load(fh)["requests"]}
+    ref, kind = {}, {}
+    for i, m in enumerate(mols):
+        if i in golden and m.n_nodes <= 10242:
+            ref[i], kind[i] = golden[i], "oracle"
+            continue
+        s = A.Solver(0)
+        s.load(m, order_p=14, precision=A.AFMPB_FP64)
+        ref[i], kind[i] = s.solve()[2], "gpu_fp64_p14"
+        s.close()
+        n_gpu = sum(1 for k in kind.values() if k != "oracle")
+        if n_gpu % 16 == 0:
+            say(f"serving references: {n_gpu} GPU FP64 p=14 solves")
+    return ref, kind
+
+
+def serving(A, torch, n_req, budget_gb, max_active, setup_threads):
+    """The serving stream: star-shaped molecules (icosphere levels 3-6).
+    Saturated throughput X_sat, then Poisson arrivals at 0.5 and 0.9 X_sat,
+    for the mixed-precision and the plain FP64 form with leaf capacity and
+    order from the tuning table; both forms also saturated at p = 8, leaf 64.
+    A solve counts only when its energy is within 1e-4 of its request's
+    reference (the oracle up to 10,242 nodes, the FP64 p = 14 GPU solve
+    above)."""
     import workloads as W
     mols = [W.star_request(i) for i in range(n_req)]
-    rng = np.random.default_rng(44)
-    sample = sorted(rng.choice(n_req, size=min(check, n_req), replace=False).tolist())
-    ref = {}
-    for i in sample:
-        s = A.Solver(0)
-        s.load(mols[i], order_p=14, precision=A.AFMPB_FP64)
-        ref[i] = s.solve()[2]
-        s.close()
+    ref, kind = serving_refs(A, mols)
+    say(f"serving references ready ({sum(1 for k in kind.values() if k == 'oracle')} oracle)")
     out = {"requests": n_req,
            "node_mix": {str(L): sum(1 for m in mols if m.meta["level"] == L) for L in (3, 4, 5, 6)},
-           "reference": f"FP64 p=14 GPU solve on {len(sample)} sampled requests",
+           "reference": {"oracle": sum(1 for k in kind.values() if k == "oracle"),
+                         "gpu_fp64_p14": sum(1 for k in kind.values() if k != "oracle")},
            "budget_gb": budget_gb, "max_active": max_active, "setup_threads": setup_threads}
     from paper_1710_06316_amd import autotune
     table = autotune.load_table()
-    forms = [("fp32_refined", A.AFMPB_FP32_REFINED, 8, 64, None),
-             ("fp64", A.AFMPB_FP64, 8, 64, None)]
+    forms = []
     if table:
-        # the same stream with leaf capacity and order from the tuning table
-        forms.append(("fp32_refined_tuned", A.AFMPB_FP32_REFINED, 0, 0, table))
-    for name, prec, order, leaf, tun in forms:
+        forms += [("fp32_refined_tuned", A.AFMPB_FP32_REFINED, 0, 0, table, True),
+                  ("fp64_tuned", A.AFMPB_FP64, 0, 0, table, True)]
+    forms += [("fp32_refined_p8", A.AFMPB_FP32_REFINED, 8, 64, None, False),
+              ("fp64_p8", A.AFMPB_FP64, 8, 64, None, False)]
+    for name, prec, order, leaf, tun, with_qps in forms:
         runs = {}
         sat = serve_run(A, mols, None, prec, order, leaf, budget_gb, max_active, setup_threads,
                         tun)
         runs["saturated"] = sat
-        for f in (0.5, 0.9):
-            runs[f"qps_{f}"] = serve_run(A, mols, f * sat["solves_per_s"], prec, order, leaf,
-                                         budget_gb, max_active, setup_threads, tun)
-        errs = [abs(sat["energies"][i] - ref[i]) / abs(ref[i]) for i in sample]
+        say(f"serving {name} saturated: {sat['solves_per_s']:.1f} solves/s")
+        if with_qps:
+            for f in (0.5, 0.9):
+                runs[f"qps_{f}"] = serve_run(A, mols, f * sat["solves_per_s"], prec, order, leaf,
+                                             budget_gb, max_active, setup_threads, tun)
+                say(f"serving {name} at {f} of saturation: p50 {runs[f'qps_{f}']['p50_ms']:.1f} ms")
+        errs = [abs(sat["energies"][i] - ref[i]) / abs(ref[i]) for i in range(n_req)]
         for r in runs.values():
-            e = r.pop("energies")
-            r["within_1e-4_sampled"] = int(sum(abs(e[i] - ref[i]) <= 1e-4 * abs(ref[i])
-                                               for i in sample))
-            r.pop("ok")
+            e, ok = r.pop("energies"), r.pop("ok")
+            good = [ok[i] and abs(e[i] - ref[i]) <= 1e-4 * abs(ref[i]) for i in range(n_req)]
+            r["within_1e-4"] = int(sum(good))
+            # throughput counting only the solves within the tolerance
+            r["accurate_solves_per_s"] = r["within_1e-4"] / r["seconds"]
         out[name] = {"order_p": order if order else "tuned",
                      "leaf_cap": leaf if leaf else "tuned",
-                     "max_rel_energy_err_sampled": max(errs), **runs}
+                     "max_rel_energy_err": max(errs),
+                     "median_rel_energy_err": float(np.median(errs)), **runs}
         if tun:
             out[name]["tuning_table"] = [list(t) for t in tun]
     return out
@@ -383,18 +408,18 @@ def serving_child(a):
     printed whatever happens there; its JSON (or the failure) is returned."""
     import subprocess
     cmd = [sys.executable, os.path.abspath(__file__), "--serve-only",
-           "--serve-requests", str(a.serve_requests), "--serve-check", str(a.serve_check),
+           "--serve-requests", str(a.serve_requests),
            "--serve-budget-gb", str(a.serve_budget_gb),
            "--serve-max-active", str(a.serve_max_active),
            "--serve-setup-threads", str(a.serve_setup_threads)]
     try:
-        r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+        # the child's progress lines go straight to this process's stderr
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=None, text=True, timeout=900)
     except subprocess.TimeoutExpired:
         return {"error": "serving run exceeded 900 s"}
     lines = [x for x in r.stdout.splitlines() if x.startswith("{")]
     if r.returncode != 0 or not lines:
-        return {"error": f"serving run ended with status {r.returncode}",
-                "stderr_tail": r.stderr[-400:]}
+        return {"error": f"serving run ended with status {r.returncode}"}
     return json.loads(lines[-1])
 
 
@@ -406,7 +431,7 @@ def main():
     a = parse()
     if a.serve_only:
         import paper_1710_06316_amd as A
-        print(json.dumps(serving(A, None, a.serve_requests, a.serve_check, a.serve_budget_gb,
+        print(json.dumps(serving(A, None, a.serve_requests, a.serve_budget_gb,
                                  a.serve_max_active, a.serve_setup_threads)), flush=True)
         return
     if a.gpus != 1:

@@ -312,7 +312,8 @@ void build_dual(afmpb_ctx *c) {
         morton_sort(pts.p, ntot, keys.p, perm.p, D.lo, &D.scale, s, true);
     }
     build_tree(keys.p, ntot, c->prm.leaf_cap, D.lo, D.scale, D.t, s);
-    build_lists(D.t, D.L, 0, s, false);
+    // (its FP64 M2L at order 14 and above runs the grouped kernel: no pairs)
+    build_lists(D.t, D.L, 0, s, false, false);
     const long long nb = D.t.nbox;
     // node / atom positions in the combined order and per-box ranges
     DBuf<int> flag(ntot + 1), cnode(ntot + 1), node_caller(n), inv_main(n);

@@ -100,10 +100,10 @@ struct Lists {
 };
 
 // M2L layout: 1 per entry, 2 grouped, 3 pairs (with the grouped slots), 0
-// chosen by the number of V entries.
+// chosen by the number of V entries (pairs only where auto_pairs).
 // p2p_chunks = false leaves out the matvec's symmetric P2P work (chunks and
 // reverse slots); the per-leaf source box lists are built either way.
 void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s,
-                 bool p2p_chunks = true);
+                 bool p2p_chunks = true, bool auto_pairs = true);
 
 }  // namespace afmpb

@@ -595,7 +595,8 @@ void build_pairs(const Tree &t, Lists &L, const unsigned long long *gkey, long l
     HIPCHK(hipStreamSynchronize(s));   // host vectors must outlive the copies
 }
 
-void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2p_chunks) {
+void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2p_chunks,
+                 bool auto_pairs) {
     const long long nb = t.nbox;
     L.coll.alloc((size_t)nb * MAXCOLL);
     L.ncoll.alloc(nb);
@@ -855,7 +856,7 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2
     L.n_vg = 0;
     L.m2l_split = 1;
     L.m2l_grouped = m2l_layout == 0 ? nv >= M2L_GROUP_MIN_ENTRIES : m2l_layout >= 2;
-    L.m2l_pairs = m2l_layout == 0 ? nv >= M2L_PAIR_MIN_ENTRIES : m2l_layout == 3;
+    L.m2l_pairs = m2l_layout == 0 ? auto_pairs && nv >= M2L_PAIR_MIN_ENTRIES : m2l_layout == 3;
     L.n_pairs = L.n_pr_items = 0;
     if (nv == 0) {
         L.vg_ptr.alloc(nb + 1);
