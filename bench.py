@@ -231,6 +231,8 @@ def run_workload(A, torch, mol, prec_name, order, leaf, steps, warmup, x_host, d
 
 TRAFFIC_PROFILES = {
     # (kernel, workload, precision, order, leaf): committed counter summary
+    ("p2p", "capsid", "fp32", 8, 128): "p2p_capsid_1100000_fp32_p8_leaf128_hbm_traffic.md",
+    ("m2l", "capsid", "fp32", 8, 128): "m2l_capsid_1100000_fp32_p8_leaf128_hbm_traffic.md",
     ("p2p", "globular", "fp32", 10, 192): "p2p_globular_5000_fp32_p10_leaf192_hbm_traffic.md",
     ("m2l", "globular", "fp32", 10, 192): "m2l_globular_5000_fp32_p10_leaf192_hbm_traffic.md",
 }
