@@ -192,10 +192,30 @@ def time_form(A, torch, s, n, steps, warmup, x, y):
 
 def solve_form(s):
     f, h, E, info, _ = s.solve(allow_not_converged=True)
-    return {"energy_kcal_mol": E, "iterations": info.iterations,
+    return {"energy_kcal_mol": E, "iterations": info.iterations, "restarts": info.restarts,
             "refinement_steps": info.refinement_steps, "converged": bool(info.converged),
             "true_rel_residual": info.true_rel_residual, "ms_rhs": info.ms_rhs,
             "ms_gmres": info.ms_gmres, "ms_energy": info.ms_energy, "ms_total": info.ms_total}
+
+
+def arnoldi_roofline(solve, ms_matvec, n, restart=80):
+    """HBM roofline of the Arnoldi steps of a plain FP64 solve.  Step j (basis
+    vectors v_0..v_j of 2n doubles) reads and writes 4(j+1) + 10 vectors: two
+    Gram-Schmidt passes, each a projection (V and w read) and an update (V and w
+    read, w written), the norm of w, and the new basis vector written with its
+    copy as the next matvec input.  Time: the GMRES phase minus its matvecs
+    (one per step and the final true residual) at the timed matvec rate."""
+    it = solve["iterations"]
+    vec = 2 * n * 8
+    nbytes = sum((4 * (j % restart + 1) + 10) * vec for j in range(it))
+    ms = solve["ms_gmres"] - (it + 1) * ms_matvec
+    if it == 0 or ms <= 0:
+        return None
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": "arnoldi", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+            "bytes_per_solve": nbytes, "steps": it, "avg_ms": ms / it,
+            "method": "GMRES phase minus (steps + 1) timed FP64 matvecs"}
 
 
 def run_workload(A, torch, mol, prec_name, order, leaf, steps, warmup, x_host, do_fp64,
@@ -493,6 +513,8 @@ def main():
                               "roofline_all": roofline(r64, info, order, "fp64", a.workload,
                                                        leaf)[1],
                               "solve": r64.get("solve")}
+        if r64.get("solve"):
+            line["roofline_all"]["arnoldi"] = arnoldi_roofline(r64["solve"], r64["ms"], n)
         y_gpu[f"fp64_p{order}"] = r64["y_host"]
         say(f"fp64 {r64['value']:.1f} Munknowns/s ({r64['ms']:.3f} ms)")
     extra = {}

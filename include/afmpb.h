@@ -274,15 +274,17 @@ afmpb_status afmpb_energy(afmpb_ctx *ctx, const double *x, double *energy);
 afmpb_status afmpb_energy_dev_noalloc(afmpb_ctx *ctx, const double *x_dev,
                                       double *energy_dev);
 
-/* Wall time (ms) of the phases of the last afmpb_set_molecule, in order:
- * 0 validation, upload and patch geometry; 1 Morton keys, sort and node
+/* Wall time (ms) of the phases of the last afmpb_set_molecule: 0
+ * validation, upload and patch geometry; 1 Morton keys, sort and node
  * gather; 2 octree; 3 U/V/W/X lists and the P2P / M2L work items; 4 near
- * set and patch-integral corrections; 5 translation operators; 6 work
+ * set (the patch-integral corrections are then computed on a second stream
+ * while phases 2, 3, 5, 6 and 7 run); 5 translation operators; 6 work
  * buffers and structural checks; 7 the octree of nodes and atoms for the
  * fast multipole right-hand side and energy (empty when direct sums are
- * used).
+ * used); 8 the wait for the patch-integral corrections after all the rest.
+ * Run order: 0, 1, 4, 2, 3, 5, 6, 7, 8.
  * ms: [AFMPB_SETUP_PHASES] host array. */
-#define AFMPB_SETUP_PHASES 8
+#define AFMPB_SETUP_PHASES 9
 afmpb_status afmpb_setup_times(afmpb_ctx *ctx, double *ms);
 
 /* Sizes of the internal tree and lists of the loaded molecule. */

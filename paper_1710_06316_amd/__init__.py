@@ -384,7 +384,7 @@ def afmpb_debug_tree(ctx) -> dict:
 
 
 SETUP_PHASES = ("geometry", "keys_sort", "tree", "lists", "near", "operators", "buffers_checks",
-                "rhs_tree")
+                "rhs_tree", "near_coeffs_wait")
 
 
 def afmpb_setup_times(ctx) -> dict:

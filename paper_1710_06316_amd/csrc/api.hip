@@ -345,12 +345,12 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
                    long long na, const double *axyz, const double *q, const afmpb_params &prm) {
     auto t0 = std::chrono::steady_clock::now();
     auto tp = t0;
-    int ph = 0;
-    // phase end: wait for the device, record the wall time since the last mark
-    auto mark = [&] {
+    // phase end: wait for the context stream, record the wall time since the
+    // last mark as phase ph
+    auto mark = [&](int ph) {
         c->sync();
         auto now = std::chrono::steady_clock::now();
-        c->ms_phase[ph++] = std::chrono::duration<double, std::milli>(now - tp).count();
+        c->ms_phase[ph] = std::chrono::duration<double, std::milli>(now - tp).count();
         tp = now;
     };
     std::fill(c->ms_phase, c->ms_phase + AFMPB_SETUP_PHASES, 0.0);
@@ -386,7 +386,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
         c->area_c.alloc(n); c->nrm_c.alloc(3 * n); c->rho2_c.alloc(n);
         compute_geometry(c->V.p, c->T.p, n, m, c->tri_area.p, c->tri_n.p, c->inc_ptr.p, c->inc_tri.p,
                          c->area_c.p, c->nrm_c.p, c->rho2_c.p, s);
-        mark();   // validation, upload, geometry
+        mark(0);   // validation, upload, geometry
         // a1 Morton keys and sort
         c->keys.alloc(n); c->perm.alloc(n);
         morton_sort(c->V.p, n, c->keys.p, c->perm.p, c->lo, &c->scale, s);
@@ -395,19 +395,24 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
         c->node32.alloc(6 * n);
         k_to_f32<<<grid_for(6 * n, 256), 256, 0, s>>>(c->node64.p, c->node32.p, 6 * n);
         KCHK();
-        mark();   // keys, sort, node gather
+        mark(1);   // keys, sort, node gather
+        // a4 near set; its patch-integral corrections (the largest part of
+        // the setup) run on the second stream beside everything after it,
+        // with device frees held back until they have finished
+        c->near = NearSet();
+        build_near(c->nodes(), n, prm.near_eta, c->V.p, c->T.p, c->tri_n.p, c->inc_ptr.p,
+                   c->inc_tri.p, c->perm.p, prm.kappa, c->ebar, c->near, s);
+        near_coeffs(c->nodes(), n, c->V.p, c->T.p, c->tri_n.p, c->inc_ptr.p, c->inc_tri.p,
+                    c->perm.p, prm.kappa, c->ebar, c->near, c->side);
+        mark(4);   // near set
+        DeferFree held;
         // a2 tree, a3 lists
         c->tree = Tree();
         build_tree(c->keys.p, n, prm.leaf_cap, c->lo, c->scale, c->tree, s);
         c->lists = Lists();
-        mark();   // tree
+        mark(2);   // tree
         build_lists(c->tree, c->lists, prm.m2l_layout, s);
-        mark();   // lists and P2P / M2L work items
-        // a4 near set and corrections
-        c->near = NearSet();
-        build_near(c->nodes(), n, prm.near_eta, c->V.p, c->T.p, c->tri_n.p, c->inc_ptr.p,
-                   c->inc_tri.p, c->perm.p, prm.kappa, c->ebar, c->near, s);
-        mark();   // near set and patch corrections
+        mark(3);   // lists and P2P / M2L work items
         // translation operators
         c->fmm = Fmm();
         c->p2p64 = DBuf<double>();
@@ -415,7 +420,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
         c->p2p_rpart = DBuf<double>();
         build_fmm_operators(c->tree, c->lists, prm.order_p, prm.kappa,
                             prm.precision == AFMPB_FP32_BF16M2L_REFINED, c->fmm, s);
-        mark();   // translation operators
+        mark(5);   // translation operators
         setup_plan<double>(c, c->mp64, c->w64, c->far64, c->node64.p);
         setup_plan<float>(c, c->mp32, c->w32, c->far32, c->node32.p);
         c->xa.alloc(2 * n); c->ya.alloc(2 * n); c->bvec.alloc(2 * n);
@@ -427,10 +432,12 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
         c->sync();
         check_setup(c);
         if (topo.valid()) topo.get();   // rethrows a mesh error
-        mark();   // work buffers, structural checks, mesh checks
+        mark(6);   // work buffers, structural checks, mesh checks
         c->dual = DualTree();
         if (use_dual(c)) build_dual(c);
-        mark();   // nodes + atoms tree of the right-hand side and energy
+        mark(7);   // nodes + atoms tree of the right-hand side and energy
+        HIPCHK(hipStreamSynchronize(c->side));
+        mark(8);   // the rest of the patch-integral corrections
     } catch (...) {
         // a mesh error found meanwhile explains a failure of the device setup
         if (topo.valid()) topo.get();

@@ -80,6 +80,47 @@ struct AllocScope {
     }
 };
 
+// Device memory released while a DeferFree scope is open on this thread is
+// returned when the scope closes, after a device synchronisation, instead of
+// at once: a free waits for the whole device, which would serialise the
+// setup with work left running on another stream meanwhile.
+struct Deferred {
+    void *p;
+    const afmpb_allocator *al;
+    std::atomic<long long> *acct;
+    long long bytes;
+};
+inline thread_local std::vector<Deferred> *g_defer = nullptr;
+
+inline void free_now(void *p, const afmpb_allocator *al) {
+    if (al) {
+        // the supplier may hand the memory out again at once: wait for every
+        // queued use of it first
+        (void)hipDeviceSynchronize();
+        al->free(p, al->user);
+    } else {
+        std::shared_lock<std::shared_mutex> lk(g_capture_mu);
+        (void)hipFree(p);
+    }
+}
+
+struct DeferFree {
+    std::vector<Deferred> list;
+    std::vector<Deferred> *prev;
+    DeferFree() : prev(g_defer) { g_defer = &list; }
+    DeferFree(const DeferFree &) = delete;
+    DeferFree &operator=(const DeferFree &) = delete;
+    ~DeferFree() {
+        g_defer = prev;
+        if (list.empty()) return;
+        (void)hipDeviceSynchronize();
+        for (const Deferred &d : list) {
+            free_now(d.p, d.al);
+            if (d.acct) *d.acct -= d.bytes;
+        }
+    }
+};
+
 template <typename T>
 struct DBuf {
     T *p = nullptr;
@@ -121,16 +162,12 @@ struct DBuf {
     }
     void release() {
         if (p) {
-            if (al) {
-                // the supplier may hand the memory out again at once: wait
-                // for every queued use of it first
-                (void)hipDeviceSynchronize();
-                al->free(p, al->user);
+            if (g_defer) {
+                g_defer->push_back({p, al, acct, (long long)(n * sizeof(T))});
             } else {
-                std::shared_lock<std::shared_mutex> lk(g_capture_mu);
-                (void)hipFree(p);
+                free_now(p, al);
+                if (acct) *acct -= (long long)(n * sizeof(T));
             }
-            if (acct) *acct -= (long long)(n * sizeof(T));
             p = nullptr; n = 0; acct = nullptr; al = nullptr;
         }
     }

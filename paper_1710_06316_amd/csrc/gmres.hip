@@ -463,25 +463,38 @@ GmresResult gmres_device(afmpb_ctx *c, const double *b, double *x, bool x_zero, 
         if (s0.converged) { R.converged = true; break; }
         if (cycle > 0) R.restarts += 1;
         // steps with one step of look-ahead: step k+1 is issued before the
-        // status of step k is read
-        int k = 0;
+        // status of step k is read, unless step k is predicted to end the
+        // cycle (its residual estimate extrapolated geometrically from the
+        // last two reaches the tolerance): a step issued after the last one
+        // still runs its matvec
+        int k = 0, issued = 1;
         gmres_step(c, fp64, 0);
         HIPCHK(hipEventRecord(E.ev[0], s));
         GmresState sk{};
+        double e1 = s0.beta, e2 = 0.0;        // estimates after steps k-1 and k-2
         for (;;) {
             const bool more = k + 1 < m;
-            if (more) {
+            const bool last = e2 > 0.0 && e1 * (e1 / e2) <= s0.tol;
+            if (more && issued == k + 1 && !last) {
                 gmres_step(c, fp64, (k + 1) & 1);
                 HIPCHK(hipEventRecord(E.ev[(k + 1) & 1], s));
+                issued = k + 2;
             }
             HIPCHK(hipEventSynchronize(E.ev[k & 1]));
             sk = E.host[k & 1];
             require(sk.pad[0] == 0, ST_NUMERIC, "non-finite value in the Arnoldi process");
             if (sk.done || !more) {
-                if (more) HIPCHK(hipEventSynchronize(E.ev[(k + 1) & 1]));
+                if (issued > k + 1) HIPCHK(hipEventSynchronize(E.ev[(k + 1) & 1]));
                 break;
             }
+            e2 = e1;
+            e1 = sk.est;
             ++k;
+            if (issued == k) {                // the prediction held the step back
+                gmres_step(c, fp64, k & 1);
+                HIPCHK(hipEventRecord(E.ev[k & 1], s));
+                issued = k + 1;
+            }
         }
         const int steps = sk.j;
         R.iterations += steps;

@@ -405,6 +405,12 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
     }
     k_sort_rows64<<<grid_for(n, 256), 256, 0, s>>>(out.ptr.p, out.col.p, n);
     KCHK();
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+void near_coeffs(const NodeSoA &nd, long long n, const double *V, const int *T,
+                 const double *tri_n, const int *inc_ptr, const int *inc_tri, const int *perm,
+                 double kappa, double ebar, NearSet &out, hipStream_t s) {
     // patch-integral corrections
     Ctx C;
     C.V = V; C.T = T; C.tri_n = tri_n; C.inc_ptr = inc_ptr; C.inc_tri = inc_tri; C.perm = perm;
@@ -424,10 +430,11 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
         r[1] = x16[l & 15];
         r[2] = w16[l >> 4] * w16[l & 15];
     }
-    DBuf<double> rule_d(rule.size());
-    HIPCHK(hipMemcpyAsync(rule_d.p, rule.data(), rule.size() * sizeof(double),
+    out.rule.alloc(rule.size());
+    HIPCHK(hipMemcpyAsync(out.rule.p, rule.data(), rule.size() * sizeof(double),
                           hipMemcpyHostToDevice, s));
-    C.rule = rule_d.p;
+    HIPCHK(hipStreamSynchronize(s));      // the host table must outlive the copy
+    C.rule = out.rule.p;
     out.delta.alloc(4 * out.nnz);
     // one wave per entry, at most 2^22 blocks of 4 waves (the kernel strides)
     const long long nblk = std::min<long long>((out.nnz + 3) / 4, 1ll << 22);
@@ -438,7 +445,6 @@ void build_near(const NodeSoA &nd, long long n, double eta, const double *V, con
     k_round_f32<<<(unsigned)std::min<long long>((4 * out.nnz + 255) / 256, 1ll << 20), 256, 0, s>>>(
         out.delta.p, out.delta32.p, 4 * out.nnz);
     KCHK();
-    HIPCHK(hipStreamSynchronize(s));
 }
 
 }  // namespace afmpb
