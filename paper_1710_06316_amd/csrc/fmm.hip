@@ -1038,12 +1038,20 @@ k_m2l_pairs(TransArgs a, const R *__restrict__ ops, const R *__restrict__ in,
     if (tid < 64) iops[tid] = a.item_ops[64 * (long long)w + tid];
     __syncthreads();
     const int K = a.K, KK = a.KK, KS = KK / 4, NRT = (K + 15) / 16;
+    // K = 16 (NRT - 1) + 1 (orders 6, 8, 14): the last row tile would hold one
+    // row, so that row is a dot product on the vector ALU instead (one
+    // column per lane, waves 8..15 for target octants 0..7), and the matrix
+    // cores take NRT - 1 row tiles
+    const bool tail = K == 16 * (NRT - 1) + 1;
+    const int MRT = tail ? NRT - 1 : NRT;
     const R *Bp = Ms + (lane & 15) * KKp + (lane >> 4);
     V4 acc[JPW][NA];
 #pragma unroll
     for (int q = 0; q < JPW; ++q)
 #pragma unroll
         for (int ct = 0; ct < NA; ++ct) acc[q][ct] = V4{0, 0, 0, 0};
+    R tacc = R(0);                                     // tail row, column `lane`
+    const int tb = wave - 8;                           // tail target octant of this wave
     bool busy = false;
     for (int c = 0; c < 8; ++c) {
         int any = 0;
@@ -1054,11 +1062,21 @@ k_m2l_pairs(TransArgs a, const R *__restrict__ ops, const R *__restrict__ in,
         busy = true;
         gather_cols<R>(in, src[c], ncols, NA, K, KK, KKp, kern, lane, wave, Ms);
         __syncthreads();
+        if (tail && tb >= 0) {                         // uniform for the wave
+            const int key = __builtin_amdgcn_readfirstlane(iops[8 * tb + c]);
+            if (key >= 0 && lane < ncols) {
+                // row K - 1 of the operator: fragment (MRT, k / 4), lane 16 (k % 4)
+                const R *A = ops + ((long long)kern * a.nkey + key) * a.PM +
+                             (long long)MRT * KS * 64;
+                const R *m = Ms + lane * KKp;
+                for (int k = 0; k < K; ++k) tacc += A[(k >> 2) * 64 + (k & 3) * 16] * m[k];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < JPW; ++q) {
             const int j = wave + q * nwave;
-            if (j >= 8 * NRT) continue;               // uniform for the wave
-            const int b = j / NRT, rt = j - b * NRT;
+            if (j >= 8 * MRT) continue;               // uniform for the wave
+            const int b = j / MRT, rt = j - b * MRT;
             const int key = __builtin_amdgcn_readfirstlane(iops[8 * b + c]);
             if (key < 0) continue;
             const R *A = ops + ((long long)kern * a.nkey + key) * a.PM +
@@ -1087,10 +1105,12 @@ k_m2l_pairs(TransArgs a, const R *__restrict__ ops, const R *__restrict__ in,
 #pragma unroll
     for (int q = 0; q < JPW; ++q) {
         const int j = wave + q * nwave;
-        if (j >= 8 * NRT) continue;
-        const int b = j / NRT, rt = j - b * NRT;
+        if (j >= 8 * MRT) continue;
+        const int b = j / MRT, rt = j - b * MRT;
         trans_store<R, CC, 0, NA>(a, acc[q], out, slot[b], nullptr, ncols, 0, kern, lane, rt);
     }
+    if (tail && tb >= 0 && lane < ncols && slot[tb][lane] >= 0)
+        out[((long long)slot[tb][lane] * 2 + kern) * a.KZ + K - 1] = tacc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1295,7 +1315,9 @@ void launch_m2l(const TransArgs &ta, unsigned gx, const R *ops, const R *in, R *
 template <typename R>
 bool launch_m2l_pairs(const TransArgs &ta, unsigned gx, const R *ops, const R *in, R *out,
                       hipStream_t s) {
-    const int nrt = (ta.K + 15) / 16, jpw = (8 * nrt + 15) / 16;
+    const int nrt = (ta.K + 15) / 16;
+    const int mrt = ta.K == 16 * (nrt - 1) + 1 ? nrt - 1 : nrt;   // row tiles on the matrix cores
+    const int jpw = (8 * mrt + 15) / 16;
     // FP64 accumulators of more than two jobs spill at 128 VGPRs
     if (sizeof(R) == sizeof(double) && jpw > 2) return false;
     (void)blocks_ok(gx, 1024);
@@ -1310,6 +1332,7 @@ bool launch_m2l_pairs(const TransArgs &ta, unsigned gx, const R *ops, const R *i
             if constexpr (sizeof(R) == sizeof(float))
                 k_m2l_pairs<R, 64, 4, 4><<<dim3(gx, 2), 1024, shmem(64), s>>>(ta, ops, in, out);
             break;
+        case 7:
         case 8:
             if constexpr (sizeof(R) == sizeof(float))
                 k_m2l_pairs<R, 32, 2, 8><<<dim3(gx, 2, 2), 1024, shmem(32), s>>>(ta, ops, in, out);
