@@ -114,6 +114,17 @@ typedef struct {
                             3 one stream, every kernel after the last (for
                             per-kernel timing).  All give bit-identical
                             products                                           */
+    int wx_expand;       /* W and X lists (Section 3.2): 0 automatic (direct
+                            P2P: on the trees measured, P2P's cost per pair is
+                            below that of the expansions it would replace);
+                            1 every W/X point pair by direct P2P; n >= 2 (order_p
+                            6, 8, 10 or 14) a W entry (leaf B, box C) whose
+                            point counts have a harmonic mean
+                            2|B||C|/(|B|+|C|) >= n is taken by expansions:
+                            C's multipole evaluated at B's points (M2P) and
+                            B's points added to C's local expansion (P2L);
+                            the others stay in P2P.  Truncation error of the
+                            same order as the M2L's                          */
 } afmpb_params;
 
 typedef struct {
@@ -144,6 +155,9 @@ typedef struct {
     int rhs_mode;                    /* right-hand side / energy: 1 direct sums,
                                         2 fast multipole pass over nodes+atoms */
     long long rhs_boxes;             /* boxes of the nodes+atoms tree (0 if 1) */
+    long long n_wx_far;              /* W entries taken by expansions (M2P+P2L) */
+    long long n_wx_pairs;            /* point pairs they stand for (n_p2p_pairs
+                                        excludes them)                        */
 } afmpb_tree_sizes;
 
 /* Caller-allocated host buffers for afmpb_debug_tree (sizes from

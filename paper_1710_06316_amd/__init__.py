@@ -57,7 +57,8 @@ class afmpb_params(ctypes.Structure):
                 ("rel_tol", ctypes.c_double), ("abs_tol", ctypes.c_double),
                 ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
                 ("near_eta", ctypes.c_double), ("m2l_layout", ctypes.c_int),
-                ("rhs_fmm", ctypes.c_int), ("overlap", ctypes.c_int)]
+                ("rhs_fmm", ctypes.c_int), ("overlap", ctypes.c_int),
+                ("wx_expand", ctypes.c_int)]
 
 
 class afmpb_solve_info(ctypes.Structure):
@@ -81,7 +82,9 @@ class afmpb_tree_sizes(ctypes.Structure):
                                                    ("n_m2l_slots", ctypes.c_longlong),
                                                    ("m2l_layout", ctypes.c_int),
                                                    ("rhs_mode", ctypes.c_int),
-                                                   ("rhs_boxes", ctypes.c_longlong)]
+                                                   ("rhs_boxes", ctypes.c_longlong),
+                                                   ("n_wx_far", ctypes.c_longlong),
+                                                   ("n_wx_pairs", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

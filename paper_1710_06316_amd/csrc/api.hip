@@ -244,6 +244,7 @@ void fill_defaults(afmpb_params &p) {
     p.m2l_layout = 0;
     p.rhs_fmm = 0;
     p.overlap = 0;
+    p.wx_expand = 0;
 }
 
 afmpb_params normalise(const afmpb_params &in) {
@@ -267,9 +268,20 @@ afmpb_params normalise(const afmpb_params &in) {
     require(p.m2l_layout >= 0 && p.m2l_layout <= 3, ST_INVALID, "m2l_layout must be 0, 1, 2 or 3");
     require(p.rhs_fmm >= 0 && p.rhs_fmm <= 2, ST_INVALID, "rhs_fmm must be 0, 1 or 2");
     require(p.overlap >= 0 && p.overlap <= 3, ST_INVALID, "overlap must be 0, 1, 2 or 3");
+    require(p.wx_expand >= 0, ST_INVALID, "wx_expand must be >= 0");
+    require(p.wx_expand < 2 || p.order_p == 6 || p.order_p == 8 || p.order_p == 10 ||
+                p.order_p == 14, ST_INVALID, "wx_expand >= 2 needs order_p 6, 8, 10 or 14");
     if (p.near_eta == 0) p.near_eta = 4.0;
     require(fin(p.near_eta) && p.near_eta > 0, ST_INVALID, "near_eta must be > 0");
     return p;
+}
+
+// Harmonic-mean point count from which a W entry is taken by expansions
+// (0: never).  Automatic is never: on the capsid-scale shell (FP32, p = 8,
+// leaf 128) thresholds 24, 48 and 96 moved 49%, 7.8% and 3.9% of the P2P
+// pairs and the matvec took 81.5, 58.6 and 58.3 ms against 58.0 ms direct.
+int wx_threshold(const afmpb_params &p) {
+    return p.wx_expand >= 2 ? p.wx_expand : 0;
 }
 
 void ensure_loaded(afmpb_ctx *c) {
@@ -411,7 +423,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
         build_tree(c->keys.p, n, prm.leaf_cap, c->lo, c->scale, c->tree, s);
         c->lists = Lists();
         mark(2);   // tree
-        build_lists(c->tree, c->lists, prm.m2l_layout, s);
+        build_lists(c->tree, c->lists, prm.m2l_layout, s, true, true, wx_threshold(prm));
         mark(3);   // lists and P2P / M2L work items
         // translation operators
         c->fmm = Fmm();
@@ -991,6 +1003,8 @@ afmpb_status afmpb_tree_info(afmpb_ctx *ctx, afmpb_tree_sizes *out) {
         out->m2l_layout = ctx->lists.m2l_pairs ? 3 : ctx->lists.m2l_grouped ? 2 : 1;
         out->rhs_mode = ctx->dual.built ? 2 : 1;
         out->rhs_boxes = ctx->dual.built ? ctx->dual.t.nbox : 0;
+        out->n_wx_far = ctx->lists.n_wx_far;
+        out->n_wx_pairs = ctx->lists.n_wx_pairs;
     });
 }
 

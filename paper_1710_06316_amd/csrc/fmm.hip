@@ -1526,6 +1526,245 @@ __global__ void __launch_bounds__(128) k_l2p(BasisDev B, TreeDev T, const int *p
     }
 }
 
+// ---------------------------------------------------------------------------
+// W and X lists by expansions (Section 3.2: list 4 by a source-to-local
+// translation, list 3 by a multipole-to-target one).  A W-list box C of leaf
+// B is well separated from B at C's scale, so C's multipole converges at B's
+// points (M2P), and B's points converge in C's local expansion (P2L, the X
+// side).  The weighted singular basis of kernel `kern` at v from the centre
+// of a box of level lev (side s, u = v / s):
+//   Laplace   S_k(v) = R_k(u) |u|^-(2n+1) W_n
+//   screened  S_k(v) = R_k(u) [k_n(kappa s |u|) / k_n(kappa s)] |u|^-n W_n
+// with W_n the expansion weights (the translation operators sample the same
+// functions): the far field of a multipole M is sum_k M_k S_k(x - c), and a
+// source q at y adds q S_k(y - c) to the local expansion about c.
+// ---------------------------------------------------------------------------
+template <typename R> __device__ inline Dual<R> dsqrt(Dual<R> a) {
+    const R r = sqrt(a.v);
+    return {r, a.d / (R(2) * r)};
+}
+template <typename R> __device__ inline Dual<R> drcp(Dual<R> a) {
+    const R r = R(1) / a.v;
+    return {r, -a.d * r * r};
+}
+template <typename R> __device__ inline Dual<R> dexpn(Dual<R> a) {  // exp(-a)
+    const R e = exp(-a.v);
+    return {e, -a.d * e};
+}
+
+// The radial factors rad[n] of S_k (everything but the raw solid harmonic of
+// u and its orthonormalisation factor), for compile-time order PC.  Wl[n],
+// kil[n]: W_n and 1 / k_n(kappa s) of this kernel and level.
+template <int PC, typename R>
+__device__ inline void singular_radial(R kappa_s, const R *Wl, const R *kil, bool scr,
+                                       Dual<R> ux, Dual<R> uy, Dual<R> uz, Dual<R> *rad) {
+    typedef Dual<R> S;
+    const S ru = dsqrt((ux * ux + uy * uy) + uz * uz);
+    const S ir = drcp(ru);
+    if (!scr) {
+        S f = ir;
+        const S ir2 = ir * ir;
+#pragma unroll
+        for (int n = 0; n <= PC; ++n) {
+            rad[n] = f * Wl[n];
+            f = f * ir2;
+        }
+        return;
+    }
+    // k_0 = e^-x / x, k_1 = e^-x (1 + x) / x^2, k_n = k_{n-2} + (2n-1)/x k_{n-1}
+    const S x = ru * kappa_s;
+    const S ix = drcp(x), e = dexpn(x);
+    S km = e * ix, kc = (e * (x + S(R(1)))) * (ix * ix), f(R(1));
+#pragma unroll
+    for (int n = 0; n <= PC; ++n) {
+        S kn;
+        if (n == 0) {
+            kn = km;
+        } else if (n == 1) {
+            kn = kc;
+        } else {
+            const S nx = km + (ix * kc) * R(2 * n - 1);
+            km = kc;
+            kc = nx;
+            kn = kc;
+        }
+        rad[n] = (kn * (kil[n] * Wl[n])) * f;
+        f = f * ir;
+    }
+}
+
+// First order m of part i when the orders 0..P are cut into `parts` runs of
+// about equal harmonic counts (part i: m in [lo(i), lo(i+1))).
+constexpr int solid_part_lo(int P, int parts, int i) {
+    if (i <= 0) return 0;
+    if (i >= parts) return P + 1;
+    const int total = (P + 1) * (P + 1);
+    int acc = 0;
+    for (int m = 0; m <= P; ++m) {
+        if (acc * parts >= i * total) return m;
+        acc += m == 0 ? P + 1 : 2 * (P - m + 1);
+    }
+    return P + 1;
+}
+
+// Per-level tables of one kernel in LDS: W_n and 1 / k_n(kappa s) per level,
+// and the orthonormalisation factors.
+template <typename R>
+__device__ inline void stage_wk(const BasisDev &B, const double *weight, const double *kinv,
+                                int kern, int nlev, int P, R *Wt, R *Kt, R *norm) {
+    for (int i = threadIdx.x; i < nlev * (P + 1); i += blockDim.x) {
+        const int lev = i / (P + 1), nn = i - lev * (P + 1);
+        Wt[i] = R(weight[((long long)kern * 64 + lev) * (P + 1) + nn]);
+        Kt[i] = R(kinv[i]);
+    }
+    for (int k = threadIdx.x; k < (P + 1) * (P + 1); k += blockDim.x) norm[k] = R(B.norm[k]);
+}
+
+// M2P: one 64-point chunk of a target leaf per block, one point per lane;
+// blockIdx.y is the kernel.  For each far W box C of the leaf, C's multipole
+// (times the orthonormalisation factors) is staged in LDS and evaluated at
+// the lane's point, value and derivative along the point's normal; the sums
+// are added to the far-field values L2P wrote.
+template <typename R, int PC>
+__global__ void __launch_bounds__(64) k_m2p(BasisDev B, TreeDev T, const int *__restrict__ item_leaf,
+                                            const int *__restrict__ item_tb,
+                                            const int *__restrict__ fw_ptr,
+                                            const int *__restrict__ fw_idx, const R *px,
+                                            const R *py, const R *pz, const R *pnx, const R *pny,
+                                            const R *pnz, const R *__restrict__ M,
+                                            const double *weight, const double *kinv, long long n,
+                                            R *phi, int nlev) {
+    constexpr int K = (PC + 1) * (PC + 1);
+    __shared__ R Ms[K], norm[K], Wt[64 * (PC + 1)], Kt[64 * (PC + 1)];
+    const int kern = blockIdx.y;
+    const int leaf = item_leaf[blockIdx.x];
+    const int i = item_tb[blockIdx.x] + (int)threadIdx.x;
+    const bool ok = i < T.pte[leaf];
+    stage_wk<R>(B, weight, kinv, kern, nlev, PC, Wt, Kt, norm);
+    const bool scr = kern == 1 && B.screened;
+    const int ii = ok ? i : T.ptb[leaf];
+    const R x = px[ii], y = py[ii], z = pz[ii];
+    const R nx = pnx[ii], ny = pny[ii], nz = pnz[ii];
+    R p = R(0), dp = R(0);
+    for (int q = fw_ptr[leaf]; q < fw_ptr[leaf + 1]; ++q) {
+        const int C = fw_idx[q];
+        __syncthreads();                               // tables staged / last box read
+        for (int k = threadIdx.x; k < K; k += 64)
+            Ms[k] = M[((long long)C * 2 + kern) * K + k] * norm[k];
+        __syncthreads();
+        const int lev = T.level[C];
+        const R is = R(1.0 / B.side[lev]);
+        const Dual<R> ux((x - R(T.center[3 * C])) * is, nx * is);
+        const Dual<R> uy((y - R(T.center[3 * C + 1])) * is, ny * is);
+        const Dual<R> uz((z - R(T.center[3 * C + 2])) * is, nz * is);
+        Dual<R> rad[PC + 1];
+        singular_radial<PC, R>(R(B.kappa * B.side[lev]), Wt + lev * (PC + 1),
+                               Kt + lev * (PC + 1), scr, ux, uy, uz, rad);
+        for_each_solid_p<PC, 0, PC, R>(ux, uy, uz, [&](int k, int nn, Dual<R> r) {
+            const Dual<R> w = r * rad[nn];
+            p += Ms[k] * w.v;
+            dp += Ms[k] * w.d;
+        });
+    }
+    if (ok) {
+        phi[(2 * kern) * n + i] += p;
+        phi[(2 * kern + 1) * n + i] += dp;
+    }
+}
+
+// P2L of the orders m = M0..M1: the block's 64 lanes take the points of the
+// box's far X leaves in turn, each summing q S_k + (dipole) dS_k/dn of its
+// points in registers; a butterfly over the wave adds the lanes, and lane 0
+// adds the sums (times the orthonormalisation factors) to the box's local
+// expansion.
+template <typename R, int PC, int M0, int M1>
+__device__ inline void p2l_range(const BasisDev &B, const TreeDev &T, const R *norm,
+                                 const R *Wl, const R *kil, bool scr, int lev, int C, int kern,
+                                 const int *fx_ptr, const int *fx_idx, const R *px, const R *py,
+                                 const R *pz, const R *pnx, const R *pny, const R *pnz,
+                                 const R *sf, const R *sh, R inv_ebar, R *Lc) {
+    constexpr int K = (PC + 1) * (PC + 1);
+    constexpr int KS = solid_count(PC, M0, M1);
+    const R cx = R(T.center[3 * C]), cy = R(T.center[3 * C + 1]), cz = R(T.center[3 * C + 2]);
+    const R is = R(1.0 / B.side[lev]), kappa_s = R(B.kappa * B.side[lev]);
+    R acc[KS];
+#pragma unroll
+    for (int j = 0; j < KS; ++j) acc[j] = R(0);
+    for (int q = fx_ptr[C]; q < fx_ptr[C + 1]; ++q) {
+        const int Bl = fx_idx[q];
+        for (int i = T.ptb[Bl] + (int)threadIdx.x; i < T.pte[Bl]; i += 64) {
+            const R qv = sh[i], dmag = -sf[i];
+            const R dip = kern == 0 ? dmag * inv_ebar : dmag;
+            const Dual<R> ux((px[i] - cx) * is, pnx[i] * is), uy((py[i] - cy) * is, pny[i] * is);
+            const Dual<R> uz((pz[i] - cz) * is, pnz[i] * is);
+            Dual<R> rad[PC + 1];
+            singular_radial<PC, R>(kappa_s, Wl, kil, scr, ux, uy, uz, rad);
+            int j = 0;                                // static after unrolling
+            for_each_solid_p<PC, M0, M1, R>(ux, uy, uz, [&](int, int nn, Dual<R> r) {
+                const Dual<R> w = r * rad[nn];
+                acc[j] += qv * w.v + dip * w.d;
+                ++j;
+            });
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) acc[j] += __shfl_xor(acc[j], o, 64);
+    }
+    if (threadIdx.x != 0) return;
+    R *out = Lc + ((long long)C * 2 + kern) * K;
+    int j = 0;
+    // the same (k, n) sequence; the harmonics themselves are dead code here
+    for_each_solid_p<PC, M0, M1, R>(R(0), R(0), R(0), [&](int k, int, R) {
+        out[k] += acc[j] * norm[k];
+        ++j;
+    });
+}
+
+template <typename R, int PC, int NPART, int I>
+__device__ inline void p2l_part(int part, const BasisDev &B, const TreeDev &T, const R *norm,
+                                const R *Wl, const R *kil, bool scr, int lev, int C, int kern,
+                                const int *fx_ptr, const int *fx_idx, const R *px, const R *py,
+                                const R *pz, const R *pnx, const R *pny, const R *pnz,
+                                const R *sf, const R *sh, R inv_ebar, R *Lc) {
+    if constexpr (I < NPART) {
+        constexpr int M0 = solid_part_lo(PC, NPART, I), M1 = solid_part_lo(PC, NPART, I + 1) - 1;
+        static_assert(M0 <= M1, "empty order range");
+        if (part == I)
+            p2l_range<R, PC, M0, M1>(B, T, norm, Wl, kil, scr, lev, C, kern, fx_ptr, fx_idx, px,
+                                     py, pz, pnx, pny, pnz, sf, sh, inv_ebar, Lc);
+        else
+            p2l_part<R, PC, NPART, I + 1>(part, B, T, norm, Wl, kil, scr, lev, C, kern, fx_ptr,
+                                          fx_idx, px, py, pz, pnx, pny, pnz, sf, sh, inv_ebar,
+                                          Lc);
+    }
+}
+
+// P2L: one box with far X leaves per block, blockIdx.y the kernel, blockIdx.z
+// one of NPART ranges of orders m (fewer accumulators per lane).  Runs after
+// the M2L sums are in the local expansions and before L2L.
+template <typename R, int PC, int NPART>
+__global__ void __launch_bounds__(64) k_p2l(BasisDev B, TreeDev T, const int *__restrict__ boxes,
+                                            const int *__restrict__ fx_ptr,
+                                            const int *__restrict__ fx_idx, const R *px,
+                                            const R *py, const R *pz, const R *pnx, const R *pny,
+                                            const R *pnz, const R *sf, const R *sh, R inv_ebar,
+                                            const double *weight, const double *kinv, R *Lc,
+                                            int nlev) {
+    constexpr int K = (PC + 1) * (PC + 1);
+    __shared__ R norm[K], Wt[64 * (PC + 1)], Kt[64 * (PC + 1)];
+    const int kern = blockIdx.y;
+    const int C = boxes[blockIdx.x];
+    stage_wk<R>(B, weight, kinv, kern, nlev, PC, Wt, Kt, norm);
+    __syncthreads();
+    const int lev = T.level[C];
+    const bool scr = kern == 1 && B.screened;
+    p2l_part<R, PC, NPART, 0>((int)blockIdx.z, B, T, norm, Wt + lev * (PC + 1),
+                              Kt + lev * (PC + 1), scr, lev, C, kern, fx_ptr, fx_idx, px, py, pz,
+                              pnx, pny, pnz, sf, sh, inv_ebar, Lc);
+}
+
 template <typename R>
 __global__ void k_fill_zero(R *a, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1873,6 +2112,25 @@ void far_field_pass(const Fmm &F, const Tree &t, const Lists &L, const FarSide<R
             K, F.KZ, L.m2l_split, t.nbox, L.m2l_grouped ? L.vg_ptr.p : L.v_ptr.p, w.Z, w.Lc);
         KCHK();
     }
+    if (L.n_p2l_boxes > 0) {
+        // far X leaves into the local expansions (single-tree lists only:
+        // source and target sides are the same points)
+        ProfScope ps(prof, "p2l", s);
+        auto go = [&](auto kfn, int np) {
+            kfn<<<dim3((unsigned)L.n_p2l_boxes, 2, np), 64, 0, s>>>(
+                B, Td, L.p2l_box.p, L.fx_ptr.p, L.fx_idx.p, src.x, src.y, src.z, src.nx, src.ny,
+                src.nz, sf, sh, R(inv_ebar), F.weight.p, F.kinv.p, w.Lc, F.nlev);
+            KCHK();
+        };
+        constexpr bool f32 = sizeof(R) == sizeof(float);
+        switch (F.P) {
+            case 6: go(k_p2l<R, 6, 2>, 2); break;
+            case 8: go(k_p2l<R, 8, f32 ? 2 : 4>, f32 ? 2 : 4); break;
+            case 10: go(k_p2l<R, 10, f32 ? 2 : 4>, f32 ? 2 : 4); break;
+            case 14: go(k_p2l<R, 14, f32 ? 4 : 6>, f32 ? 4 : 6); break;
+            default: throw Error(ST_INVALID, "W/X expansions need order 6, 8, 10 or 14");
+        }
+    }
     {
         ProfScope ps(prof, "l2l", s);
         for (int lev = 2; lev + 1 < t.nlev; ++lev) {
@@ -1899,6 +2157,23 @@ void far_field_pass(const Fmm &F, const Tree &t, const Lists &L, const FarSide<R
             default: go(k_l2p<R, 0>); break;
         }
         KCHK();
+    }
+    if (L.n_m2p_items > 0) {
+        // far W boxes at the leaves' points, added to the L2P values
+        ProfScope ps(prof, "m2p", s);
+        auto go = [&](auto kfn) {
+            kfn<<<dim3((unsigned)L.n_m2p_items, 2), 64, 0, s>>>(
+                B, Td, L.m2p_leaf.p, L.m2p_tb.p, L.fw_ptr.p, L.fw_idx.p, dst.x, dst.y, dst.z,
+                dst.nx, dst.ny, dst.nz, w.M, F.weight.p, F.kinv.p, n, w.phi, F.nlev);
+            KCHK();
+        };
+        switch (F.P) {
+            case 6: go(k_m2p<R, 6>); break;
+            case 8: go(k_m2p<R, 8>); break;
+            case 10: go(k_m2p<R, 10>); break;
+            case 14: go(k_m2p<R, 14>); break;
+            default: throw Error(ST_INVALID, "W/X expansions need order 6, 8, 10 or 14");
+        }
     }
 }
 

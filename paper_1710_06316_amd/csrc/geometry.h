@@ -97,13 +97,24 @@ struct Lists {
     DBuf<int> pr_src, pr_slot, pr_item_ops, pr_item_begin, pr_item_count;
     long long n_pairs = 0, n_pr_items = 0;
     std::vector<int> levels_with_v;    // levels that have V entries
+    // W and X entries by expansions: W entry (B, C) whose point counts have
+    // a harmonic mean of at least wx_tau leaves the P2P work; B's points take
+    // C's multipole (M2P), C's local expansion takes B's points (P2L).
+    // fw_ptr/fw_idx (CSR over boxes): the far W boxes of each leaf;
+    // m2p_leaf/m2p_tb: one item per 64 points of such a leaf; fx_ptr/fx_idx:
+    // the far X leaves of each box; p2l_box: the boxes that have any.
+    int wx_tau = 0;
+    DBuf<int> fw_ptr, fw_idx, m2p_leaf, m2p_tb, fx_ptr, fx_idx, p2l_box;
+    long long n_wx_far = 0, n_wx_pairs = 0, n_m2p_items = 0, n_p2l_boxes = 0;
 };
 
 // M2L layout: 1 per entry, 2 grouped, 3 pairs (with the grouped slots), 0
 // chosen by the number of V entries (pairs only where auto_pairs).
 // p2p_chunks = false leaves out the matvec's symmetric P2P work (chunks and
 // reverse slots); the per-leaf source box lists are built either way.
+// wx_tau > 0 (with p2p_chunks) moves the W/X entries of harmonic-mean point
+// count >= wx_tau to expansions.
 void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s,
-                 bool p2p_chunks = true, bool auto_pairs = true);
+                 bool p2p_chunks = true, bool auto_pairs = true, int wx_tau = 0);
 
 }  // namespace afmpb

@@ -596,7 +596,7 @@ void build_pairs(const Tree &t, Lists &L, const unsigned long long *gkey, long l
 }
 
 void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2p_chunks,
-                 bool auto_pairs) {
+                 bool auto_pairs, int wx_tau) {
     const long long nb = t.nbox;
     L.coll.alloc((size_t)nb * MAXCOLL);
     L.ncoll.alloc(nb);
@@ -705,8 +705,8 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2
         const long long npts = pte_h[0];
         if (p2p_chunks) {
         std::vector<int> rb, re, clo, chi, cgrp, gptr, gtb, gte, crev;
-        std::vector<std::pair<int, int>> r;
-        long long nrev = 0, pairs = 0;
+        std::vector<std::pair<int, int>> r, far;   // far: W entries (B, C) by expansions
+        long long nrev = 0, pairs = 0, far_pairs = 0;
         // cut merged ranges into spans of <= budget points: returns the span
         // boundaries (indices into rb/re)
         auto spans = [&](std::vector<std::pair<int, int>> &m, long long budget) {
@@ -741,7 +741,17 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2
             r.clear();
             for (int q = uptr[B]; q < uptr[B + 1]; ++q)
                 if (uidx[q] > B) r.emplace_back(ptb_h[uidx[q]], pte_h[uidx[q]]);
-            for (int q = wptr[B]; q < wptr[B + 1]; ++q) r.emplace_back(ptb_h[widx[q]], pte_h[widx[q]]);
+            for (int q = wptr[B]; q < wptr[B + 1]; ++q) {
+                const int C = widx[q];
+                const long long nbp = pte_h[B] - ptb_h[B], ncp = pte_h[C] - ptb_h[C];
+                // harmonic mean 2 nb nc / (nb + nc) >= tau
+                if (wx_tau > 0 && ncp > 0 && 2 * nbp * ncp >= (long long)wx_tau * (nbp + ncp)) {
+                    far.emplace_back(B, C);
+                    far_pairs += 2 * nbp * ncp;
+                    continue;
+                }
+                r.emplace_back(ptb_h[C], pte_h[C]);
+            }
             std::sort(r.begin(), r.end());
             std::vector<std::pair<int, int>> m;
             for (auto &x : r) {
@@ -775,8 +785,50 @@ void build_lists(const Tree &t, Lists &L, int m2l_layout, hipStream_t s, bool p2
         gptr.push_back((int)clo.size());
         require(rb.size() < (1ull << 31) && clo.size() < (1ull << 31) && nrev < (1ll << 31),
                 ST_INVALID, "too many P2P chunks");
-        require(pairs == L.n_p2p_pairs, ST_DEVICE,
+        require(pairs + far_pairs == L.n_p2p_pairs, ST_DEVICE,
                 "P2P tasks do not cover the U/W/X point pairs exactly once");
+        L.n_p2p_pairs = pairs;
+        L.wx_tau = wx_tau;
+        L.n_wx_far = (long long)far.size();
+        L.n_wx_pairs = far_pairs;
+        if (!far.empty()) {
+            // M2P side: far W boxes per leaf (the loop visits leaves in
+            // order, so `far` is grouped by B), one item per 64 points
+            std::vector<int> fwp(nb + 1, 0), fwi(far.size()), mleaf, mtb;
+            for (auto &e : far) ++fwp[e.first + 1];
+            for (long long b = 0; b < nb; ++b) fwp[b + 1] += fwp[b];
+            for (size_t q = 0; q < far.size(); ++q) fwi[q] = far[q].second;
+            for (long long b = 0; b < nb; ++b)
+                if (fwp[b + 1] > fwp[b])
+                    for (int tb = ptb_h[b]; tb < pte_h[b]; tb += 64) {
+                        mleaf.push_back((int)b);
+                        mtb.push_back(tb);
+                    }
+            // P2L side: the transpose, far X leaves per box
+            std::vector<std::pair<int, int>> fx(far.size());
+            for (size_t q = 0; q < far.size(); ++q) fx[q] = {far[q].second, far[q].first};
+            std::sort(fx.begin(), fx.end());
+            std::vector<int> fxp(nb + 1, 0), fxi(fx.size()), pbox;
+            for (auto &e : fx) ++fxp[e.first + 1];
+            for (long long b = 0; b < nb; ++b) fxp[b + 1] += fxp[b];
+            for (size_t q = 0; q < fx.size(); ++q) fxi[q] = fx[q].second;
+            for (long long b = 0; b < nb; ++b)
+                if (fxp[b + 1] > fxp[b]) pbox.push_back((int)b);
+            auto put = [&](DBuf<int> &d, const std::vector<int> &h) {
+                d.alloc(h.size());
+                d.upload(h.data(), h.size(), s);
+            };
+            put(L.fw_ptr, fwp);
+            put(L.fw_idx, fwi);
+            put(L.m2p_leaf, mleaf);
+            put(L.m2p_tb, mtb);
+            put(L.fx_ptr, fxp);
+            put(L.fx_idx, fxi);
+            put(L.p2l_box, pbox);
+            L.n_m2p_items = (long long)mleaf.size();
+            L.n_p2l_boxes = (long long)pbox.size();
+            HIPCHK(hipStreamSynchronize(s));
+        }
         // reverse slots of every point, in chunk order (CSR over points)
         {
             std::vector<int> cnt(npts + 1, 0), rptr(npts + 1), ridx(std::max(nrev, 1ll));

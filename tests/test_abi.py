@@ -53,3 +53,30 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(A, "_lib", None)
     with pytest.raises(RuntimeError, match="not found"):
         A.lib()
+
+
+def _struct_fields(name):
+    """Member names of `typedef struct { ... } name;` in the header, in order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    names = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        first, *rest = decl.split(",")
+        names.append(re.findall(r"\w+", first)[-1])
+        names += [re.findall(r"\w+", r)[-1] for r in rest]
+    return names
+
+
+@pytest.mark.parametrize("name", ["afmpb_params", "afmpb_solve_info", "afmpb_tree_sizes",
+                                  "afmpb_tree_view"])
+def test_binding_structs_follow_the_header(name):
+    """The ctypes mirrors of the parameter and result structs list the
+    header's members in the header's order (a missing or reordered member
+    would shift every later field across the boundary)."""
+    import paper_1710_06316_amd as A
+    cls = getattr(A, name)
+    assert [f for f, _ in cls._fields_] == _struct_fields(name)

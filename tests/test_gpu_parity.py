@@ -235,6 +235,76 @@ def test_m2l_layouts_agree_and_match_oracle(name, cap, p):
             assert errs[layout] <= 1.05 * errs[1] + tol and errs[layout] < 1e-4
 
 
+def _far_w(mol, cap, tau):
+    """W entries (B, C) of the CPU tree whose point counts have a harmonic
+    mean >= tau, and the ordered point pairs they stand for."""
+    t = OT.build_tree(mol.xyz, cap)
+    cnt = t.pt_end - t.pt_begin
+    far = pairs = 0
+    for B, ws in enumerate(OT.build_lists(t).W):
+        for C in ws:
+            a, b = int(cnt[B]), int(cnt[C])
+            if b > 0 and 2 * a * b >= tau * (a + b):
+                far += 1
+                pairs += 2 * a * b
+    return far, pairs
+
+
+@pytest.mark.parametrize("name,cap,p", [("born4", 16, 6), ("star4", 16, 8), ("star4", 16, 10),
+                                        ("star4", 5, 14)])
+def test_wx_expansions_match_oracle(name, cap, p):
+    """W/X entries by expansions (C's multipole at B's points, B's points into
+    C's local expansion; Section 3.2) instead of direct pairs: the entries
+    chosen are those of the CPU tree's W lists above the threshold, the P2P
+    work shrinks by exactly their point pairs, and the product stays as close
+    to the oracle as with every W/X pair direct (the expansions converge at
+    least as fast as the M2L's)."""
+    import paper_1710_06316_amd as A
+    mol = MOLS[name]()
+    x = np.random.default_rng(9).normal(size=2 * mol.n_nodes)
+    ref = _oracle_op(mol).matvec(x)
+    far, far_pairs = _far_w(mol, cap, 2)
+    assert far > 0
+    for prec, tol in ((A.AFMPB_FP64, 1e-12), (A.AFMPB_FP32_REFINED, 2e-6)):
+        s = _solver(mol, order_p=p, leaf_cap=cap, precision=prec, wx_expand=1)
+        off = s.tree_info()
+        y_off = s.matvec(x)
+        s.close()
+        s = _solver(mol, order_p=p, leaf_cap=cap, precision=prec, wx_expand=2)
+        on = s.tree_info()
+        y_on = s.matvec(x)
+        s.close()
+        assert off["n_wx_far"] == 0 and off["n_wx_pairs"] == 0
+        assert (on["n_wx_far"], on["n_wx_pairs"]) == (far, far_pairs)
+        assert on["n_p2p_pairs"] + on["n_wx_pairs"] == off["n_p2p_pairs"]
+        e_off, e_on = _rel(y_off, ref), _rel(y_on, ref)
+        _say(f"{name} p={p} precision={prec} W entries by expansions {far}/{off['n_w']}: "
+             f"oracle errors {e_off:.2e} (direct) {e_on:.2e} (expansions)")
+        assert e_on <= 2.0 * e_off + tol and e_on < 1e-4
+
+
+def test_wx_expansions_globular_solve():
+    """On the 49,190-node molecule, W entries of harmonic-mean size >= 16 by
+    expansions: the FP32 matvec and the polar energy of a solve agree with
+    the all-direct run and the oracle."""
+    import paper_1710_06316_amd as A
+    mol = MOLS["globular"]()
+    x = np.random.default_rng(10).normal(size=2 * mol.n_nodes)
+    ref = _oracle_op(mol).matvec(x)
+    ys, es = {}, {}
+    for wx in (1, 16):
+        s = _solver(mol, order_p=8, leaf_cap=64, precision=A.AFMPB_FP32_REFINED, wx_expand=wx)
+        info = s.tree_info()
+        assert (info["n_wx_far"] > 0) == (wx > 1)
+        ys[wx] = s.matvec(x)
+        es[wx] = s.solve()[2]
+        s.close()
+        _say(f"globular wx={wx} far W {info['n_wx_far']} pairs {info['n_wx_pairs']} "
+             f"error {_rel(ys[wx], ref):.2e} energy {es[wx]:.6f}")
+    assert _rel(ys[16], ref) <= 2.0 * _rel(ys[1], ref) + 2e-6
+    assert abs(es[16] - es[1]) <= 1e-5 * abs(es[1])
+
+
 @pytest.mark.parametrize("p", [8, 14])
 def test_overlap_schedules_bit_identical(p):
     """The near-field schedules (P2P beside the whole far-field chain, the
