@@ -9,8 +9,9 @@
 //   D-integrand  (d2G/dn0dn - d2u/dn0dn)/ebar  = [(n0.n) a(s)/r^3 - (R.n0)(R.n) b(s)/r^5]
 //                                                / (4 pi ebar)
 // with s = kappa r, e = e^{-s}, a(s) = 1 - e(1+s), b(s) = 3 - e(3+3s+s^2).
-// a and b are taken from their Taylor series below s = 0.1 and from
-// expm1-based forms above, so the Laplace/screened difference never cancels.
+// a and b are taken from their Taylor series below s = 0.1 and from forms in
+// 1 - e above (1 - e from expm1 below s = 0.5), so the Laplace/screened
+// difference never cancels.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -34,7 +35,7 @@ struct DiffSeries {
 };
 
 template <typename R>
-__device__ inline void diff_factors(R s, R e, R &fa, R &fb) {
+__device__ inline void diff_factors(R s, R e, R em1, R &fa, R &fb) {
     constexpr DiffSeries S;
     if (s < R(0.1)) {
         R pa = R(S.a[10]), pb = R(S.b[10]);
@@ -46,11 +47,23 @@ __device__ inline void diff_factors(R s, R e, R &fa, R &fb) {
         fa = pa * s * s;
         fb = pb * s * s;
     } else {
-        R em1 = -expm1(-s);                  // 1 - e
         fa = em1 - s * e;                    // 1 - e - s e
         fb = R(3) * em1 - e * (R(3) * s + s * s);
     }
 }
+
+// 1/sqrt(x) for x > 0: the hardware estimate refined by Newton's method for
+// the root of y^-2 - x (each step y += y (1 - x y^2) / 2 about doubles the
+// correct bits; two steps from the double-precision estimate, one correction
+// of the residual's second order in the last).
+__device__ inline double inv_sqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(y * e, 0.5, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+__device__ inline float inv_sqrt(float x) { return 1.0f / sqrtf(x); }
 
 // The four integrands (without the patch area / quadrature weight).
 template <typename R>
@@ -62,19 +75,24 @@ template <typename R>
 __device__ inline Abcd<R> abcd_point(R rx, R ry, R rz, R n0x, R n0y, R n0z, R nx, R ny,
                                      R nz, R kappa, R inv_ebar) {
     R r2 = (rx * rx + ry * ry) + rz * rz;
-    R r = sqrt(r2);
-    R ir = R(1) / r;
+    R ir = inv_sqrt(r2);
+    R r = r2 * ir;
     R ir3 = ir * ir * ir;
     R s = kappa * r;
     R e = exp(-s);
+    // 1 - e: from expm1 while e is close to 1, else the plain difference
+    // (which loses no digits once e < e^-0.5)
+    R em1;
+    if (s < R(0.5)) em1 = -expm1(-s);
+    else em1 = R(1) - e;
     R Rn = (rx * nx + ry * ny) + rz * nz;
     R Rn0 = (rx * n0x + ry * n0y) + rz * n0z;
     R n0n = (n0x * nx + n0y * ny) + n0z * nz;
     R fa, fb;
-    diff_factors(s, e, fa, fb);
+    diff_factors(s, e, em1, fa, fb);
     R e1 = e * (R(1) + s);
     Abcd<R> o;
-    o.A = -expm1(-s) * ir * R(INV_4PI);
+    o.A = em1 * ir * R(INV_4PI);
     o.B = Rn * ir3 * R(INV_4PI) * (inv_ebar - e1);
     o.C = -Rn0 * ir3 * R(INV_4PI) * (R(1) - e1 * inv_ebar);
     o.D = (n0n * fa * ir3 - Rn0 * Rn * fb * ir3 * ir * ir) * R(INV_4PI) * inv_ebar;
