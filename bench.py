@@ -48,10 +48,13 @@ WORKLOADS = {
     # Leaf capacities are the fastest of measured sweeps of the FP32-refined
     # matvec on one MI355X (globular: 64 / 128 / 192 / 256 -> 0.486 / 0.436 /
     # 0.409 / 0.413 ms; complex p = 10: 64 / 128 / 192 -> 8.32 / 5.86 / 6.54
-    # ms; capsid p = 8: see DESIGN).  Larger leaves move work from the
-    # far-field chain to P2P, which runs on a second stream beside it.
+    # ms; capsid p = 8: 64 / 96 / 128 / 160 / 192 / 224 / 256 / 320 -> 70.3 /
+    # 67.5 / 57.9 / 54.0 / 53.6 / 54.2 / 54.5 / 56.0 ms with grouped M2L from
+    # leaf 160 on, 51.3 ms at 192 with box pairs; on 24 oracle rows the
+    # order-8 error is 3.0e-5 at leaf 192 and 3.2e-5 at 128).  Larger leaves
+    # move work from the far-field chain to P2P.
     "capsid": ("capsid_shell", "capsid_shell_1100000: 1.1M atoms in a 220-280 A shell "
-               "(icosahedral modulation)", 8, 128),
+               "(icosahedral modulation)", 8, 192),
     "complex_100k": ("complex_100k", "complex_100k: SAW atoms in 90 A", 10, 128),
     "globular": ("globular", "globular_5000: SAW atoms in 25 A", 10, 192),
 }
@@ -251,8 +254,8 @@ def run_workload(A, torch, mol, prec_name, order, leaf, steps, warmup, x_host, d
 
 TRAFFIC_PROFILES = {
     # (kernel, workload, precision, order, leaf): committed counter summary
-    ("p2p", "capsid", "fp32", 8, 128): "p2p_capsid_1100000_fp32_p8_leaf128_hbm_traffic.md",
-    ("m2l", "capsid", "fp32", 8, 128): "m2l_capsid_1100000_fp32_p8_leaf128_hbm_traffic.md",
+    ("p2p", "capsid", "fp32", 8, 192): "p2p_capsid_1100000_fp32_p8_leaf192_hbm_traffic.md",
+    ("m2l", "capsid", "fp32", 8, 192): "m2l_capsid_1100000_fp32_p8_leaf192_hbm_traffic.md",
     ("p2p", "globular", "fp32", 10, 192): "p2p_globular_5000_fp32_p10_leaf192_hbm_traffic.md",
     ("m2l", "globular", "fp32", 10, 192): "m2l_globular_5000_fp32_p10_leaf192_hbm_traffic.md",
 }

@@ -98,7 +98,7 @@ typedef struct {
                             once for all children of P.  Automatic takes 2
                             from 2^21 V-list entries on (large trees, where
                             the result traffic of 1 dominates) and 3 from
-                            2^24.  Every layout computes the same sums
+                            2^23.  Every layout computes the same sums
                             (rounding order aside; 2 and 3 bit for bit)       */
     int rhs_fmm;         /* right-hand side of Eq. (5) and the reaction potential
                             at the atoms: 0 automatic (fast multipole pass over

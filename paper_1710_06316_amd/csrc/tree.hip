@@ -15,9 +15,10 @@ constexpr int MAXCOLL = 26;
 // M2L blocks (items x kernels x octant shares) wanted per launch
 constexpr long long M2L_FILL_BLOCKS = 4096;
 // automatic layout: pairs of boxes from this many V entries on (FP32 M2L on
-// the 9.7M-node shell, 52 M entries: 26.7 -> 19.3 ms; on the 100k-atom
-// complex, 7 M entries at p = 10: 1.87 -> 2.28 ms)
-constexpr long long M2L_PAIR_MIN_ENTRIES = 1ll << 24;
+// the 9.7M-node shell at leaf 128, 52 M entries: 26.7 -> 19.3 ms, and at
+// leaf 192: 7.46 -> 5.25 ms; on the 100k-atom complex, 7 M entries at
+// p = 10: 1.87 -> 2.28 ms)
+constexpr long long M2L_PAIR_MIN_ENTRIES = 1ll << 23;
 // Grouped M2L from this many V entries on.  Grouping writes ~6x fewer
 // result slots but multiplies ~1.4x more padded columns (absent children)
 // and balances less evenly over the XCDs; measured on one MI355X it loses
