@@ -9,9 +9,9 @@
 //   D-integrand  (d2G/dn0dn - d2u/dn0dn)/ebar  = [(n0.n) a(s)/r^3 - (R.n0)(R.n) b(s)/r^5]
 //                                                / (4 pi ebar)
 // with s = kappa r, e = e^{-s}, a(s) = 1 - e(1+s), b(s) = 3 - e(3+3s+s^2).
-// a and b are taken from their Taylor series below s = 0.1 and from forms in
-// 1 - e above (1 - e from expm1 below s = 0.5), so the Laplace/screened
-// difference never cancels.
+// a is taken from its Taylor series below s = 0.1 and from 1 - e - s e above
+// (1 - e from expm1 below s = 0.5), and b = 3 a - s^2 e, so the
+// Laplace/screened difference never cancels.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -19,17 +19,15 @@ namespace afmpb {
 
 constexpr double INV_4PI = 0.079577471545947667884441881686257181;
 
-// Taylor coefficients: a(s) = sum_{k>=2} (-1)^k (k-1) s^k/k!,
-//                      b(s) = -sum_{k>=2} (-1)^k (k-1)(k-3) s^k/k!.
+// Taylor coefficients: a(s) = sum_{k>=2} (-1)^k (k-1) s^k/k!.
 struct DiffSeries {
-    double a[11], b[11];
-    constexpr DiffSeries() : a(), b() {
+    double a[11];
+    constexpr DiffSeries() : a() {
         double fact = 1.0;
         for (int k = 1; k <= 10; ++k) {
             fact *= k;
             double sg = (k & 1) ? -1.0 : 1.0;
             a[k] = (k >= 2) ? sg * (k - 1) / fact : 0.0;
-            b[k] = (k >= 2) ? -sg * (double)((k - 1) * (k - 3)) / fact : 0.0;
         }
     }
 };
@@ -38,18 +36,16 @@ template <typename R>
 __device__ inline void diff_factors(R s, R e, R em1, R &fa, R &fb) {
     constexpr DiffSeries S;
     if (s < R(0.1)) {
-        R pa = R(S.a[10]), pb = R(S.b[10]);
+        R pa = R(S.a[10]);
 #pragma unroll
-        for (int k = 9; k >= 2; --k) {
-            pa = pa * s + R(S.a[k]);
-            pb = pb * s + R(S.b[k]);
-        }
+        for (int k = 9; k >= 2; --k) pa = pa * s + R(S.a[k]);
         fa = pa * s * s;
-        fb = pb * s * s;
     } else {
         fa = em1 - s * e;                    // 1 - e - s e
-        fb = R(3) * em1 - e * (R(3) * s + s * s);
     }
+    // b = 3 a - s^2 e: the two terms cancel to about a third of 3 a as s -> 0
+    // (both a and b ~ s^2/2), so b keeps a relative error of a few times a's
+    fb = R(3) * fa - (s * s) * e;
 }
 
 // 1/sqrt(x) for x > 0: the hardware estimate refined by Newton's method for

@@ -35,17 +35,16 @@ template <> struct Fast<float> {
     static constexpr int NSER = 6;
 };
 
-// Taylor coefficients of om(s) = 1 - e^{-s}, a(s), b(s) (see kernels.h)
+// Taylor coefficients of om(s) = 1 - e^{-s} and a(s) (see kernels.h)
 struct P2PSeries {
-    double om[11], a[11], b[11];
-    constexpr P2PSeries() : om(), a(), b() {
+    double om[11], a[11];
+    constexpr P2PSeries() : om(), a() {
         double fact = 1.0;
         for (int k = 1; k <= 10; ++k) {
             fact *= k;
             double sg = (k & 1) ? -1.0 : 1.0;
             om[k] = -sg / fact;
             a[k] = (k >= 2) ? sg * (k - 1) / fact : 0.0;
-            b[k] = (k >= 2) ? -sg * (double)((k - 1) * (k - 3)) / fact : 0.0;
         }
     }
 };
@@ -106,24 +105,25 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 1 : 3))) k_p2p(
         const R rr = r2 * ir;
         const R s = kappa * rr;
         const R e = Fast<R>::ex(-s);
-        R om, fa, fb;
+        R om, fa;
         if (s < R(0.1)) {
             constexpr int N = Fast<R>::NSER;
-            R po = R(S.om[N]), pa = R(S.a[N]), pb = R(S.b[N]);
+            R po = R(S.om[N]), pa = R(S.a[N]);
 #pragma unroll
             for (int k = N - 1; k >= 2; --k) {
                 po = po * s + R(S.om[k]);
                 pa = pa * s + R(S.a[k]);
-                pb = pb * s + R(S.b[k]);
             }
             om = (po * s + R(1)) * s;
             fa = pa * s * s;
-            fb = pb * s * s;
         } else {
             om = R(1) - e;
             fa = om - s * e;
-            fb = R(3) * om - e * s * (R(3) + s);
         }
+        // b(s) = 3 a(s) - s^2 e outside the divergent branch: the two terms
+        // cancel to about a third of 3 a(s) as s -> 0 (b ~ s^2/2, a ~ s^2/2),
+        // so b keeps a relative error of a few times that of a
+        const R fb = R(3) * fa - (s * s) * e;
         const R Rn = (rx * snx + ry * sny) + rz * snz;
         const R Rn0 = (rx * n0x + ry * n0y) + rz * n0z;
         const R n0n = (n0x * snx + n0y * sny) + n0z * snz;
