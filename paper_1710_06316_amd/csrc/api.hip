@@ -412,8 +412,7 @@ void load_molecule(afmpb_ctx *c, long long n, const double *xyz, long long m, co
         // the setup) run on the second stream beside everything after it,
         // with device frees held back until they have finished
         c->near = NearSet();
-        build_near(c->nodes(), n, prm.near_eta, c->V.p, c->T.p, c->tri_n.p, c->inc_ptr.p,
-                   c->inc_tri.p, c->perm.p, prm.kappa, c->ebar, c->near, s);
+        build_near(c->nodes(), n, prm.near_eta, c->near, s);
         near_coeffs(c->nodes(), n, c->V.p, c->T.p, c->tri_n.p, c->inc_ptr.p, c->inc_tri.p,
                     c->perm.p, prm.kappa, c->ebar, c->near, c->side);
         mark(4);   // near set

@@ -14,9 +14,7 @@ struct NearSet {
 };
 
 // The near set (ptr, col) on stream s; returns with s drained.
-void build_near(const NodeSoA &nd, long long n, double eta, const double *V, const int *T,
-                const double *tri_n, const int *inc_ptr, const int *inc_tri, const int *perm,
-                double kappa, double ebar, NearSet &out, hipStream_t s);
+void build_near(const NodeSoA &nd, long long n, double eta, NearSet &out, hipStream_t s);
 
 // The corrections (delta, delta32) of a built near set, enqueued on stream s
 // without waiting for them: the caller orders later uses after s.

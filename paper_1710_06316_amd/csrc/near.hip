@@ -367,9 +367,7 @@ void gauss_legendre01(int nq, double *x, double *w) {
     }
 }
 
-void build_near(const NodeSoA &nd, long long n, double eta, const double *V, const int *T,
-                const double *tri_n, const int *inc_ptr, const int *inc_tri, const int *perm,
-                double kappa, double ebar, NearSet &out, hipStream_t s) {
+void build_near(const NodeSoA &nd, long long n, double eta, NearSet &out, hipStream_t s) {
     // grid of cell size eta * max(rho), padded by a relative 1e-9
     std::vector<double> hx(n), hy(n), hz(n), hr(n);
     HIPCHK(hipMemcpyAsync(hr.data(), nd.rho2, n * sizeof(double), hipMemcpyDeviceToHost, s));
