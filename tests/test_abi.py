@@ -45,6 +45,8 @@ def test_default_params_without_gpu():
     p = A.afmpb_default_params()
     assert (p.eps_p, p.eps_s, p.kappa, p.order_p, p.leaf_cap) == (2.0, 80.0, 0.1, 8, 64)
     assert (p.restart, p.max_restarts, p.near_eta, p.rel_tol) == (80, 5, 4.0, 1e-6)
+    # implementation choices default to automatic
+    assert (p.m2l_layout, p.rhs_fmm, p.overlap, p.wx_expand) == (0, 0, 0, 0)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
